@@ -1,0 +1,200 @@
+/*
+ * libvsp: TFHE gate bootstrapping and CMUX memory on one AMD Instinct MI355X (gfx950).
+ *
+ * The operations are those the server evaluates in "Virtual Secure Platform: A Five-Stage
+ * Pipeline Processor over TFHE" (arXiv 2010.09410): homomorphic gates over TLWE ciphertexts
+ * (Sec. 2.1.2, "Homomorphic Gates", "Bootstrapping in TFHE") and CMUX-Memory reads and writes
+ * (Sec. 8). The caller (the server party) holds the public bootstrapping key; secret keys
+ * never reach this library.
+ *
+ * Conventions used by every call:
+ *  - Torus elements are uint32_t (the torus R/Z at resolution 2^-32; arithmetic mod 2^32).
+ *  - Parameters are fixed at n = 630, N = 1024, k = 1, l = 3, Bg = 2^6, key switch t = 8,
+ *    base 2^2; vsp_context_create rejects anything else with VSP_E_PARAMS.
+ *  - TLWE (level 0): n + 1 words (a[0..n-1], b). TLWE (level 1): N + 1 words.
+ *    TRLWE: [2][N] (a, then b). TRGSW: [2l][2][N], rows as in Sec. 2.1.2 (rows 0..l-1 carry
+ *    m/Bg^j in a, rows l..2l-1 in b).
+ *  - Messages are encoded as +-1/8 (bit m -> mu(2m - 1), mu = 1/8), Sec. 2.1.2.
+ *  - Pointers named d_* are device memory on the context's device, owned by the caller,
+ *    4-byte aligned, and must cover the sizes stated. Pointers named h_* are host memory.
+ *    The library never frees caller memory. Outputs must not overlap inputs unless a
+ *    call says otherwise (VSP_E_ARG).
+ *  - Calls that take a stream validate their arguments synchronously, then enqueue work
+ *    asynchronously on that stream (a hipStream_t; NULL = the default stream) and return.
+ *    Results are valid after the stream is synchronised. Failures of enqueued work surface
+ *    as VSP_E_HIP from a later call or from vsp_context_sync.
+ *  - A context is not re-entrant: calls on one context must be ordered by the caller
+ *    (one host thread, one stream, or explicit synchronisation). The server serialises
+ *    its own work.
+ *  - Every call returns a vsp_status; nothing unwinds across this interface. The detail
+ *    of the last failure on the calling thread is available from vsp_last_error().
+ */
+#ifndef VSP_H
+#define VSP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t vsp_status;
+#define VSP_OK 0
+#define VSP_E_ARG (-1)      /* null / misaligned / undersized / overlapping / out-of-range argument */
+#define VSP_E_PARAMS (-2)   /* parameter set differs from the compiled one */
+#define VSP_E_NOMEM (-3)    /* device allocation failed */
+#define VSP_E_HIP (-4)      /* HIP runtime or kernel failure */
+#define VSP_E_STATE (-5)    /* object in the wrong state (e.g. destroyed server, unknown ticket) */
+#define VSP_E_CAPACITY (-6) /* server admission refused: request larger than the memory budget */
+
+typedef struct vsp_params {
+  uint32_t n, N, k, l, bg_bits, ks_t, ks_basebit;
+} vsp_params;
+
+/* Gate opcodes. The linear combinations are the standard TFHE ones on the +-1/8 encoding;
+ * NOT negates its first input and needs no bootstrap (Sec. 2.1.2 "Homomorphic Gates"). */
+typedef enum vsp_gate {
+  VSP_NAND = 0, VSP_AND = 1, VSP_OR = 2, VSP_NOR = 3, VSP_XOR = 4, VSP_XNOR = 5,
+  VSP_ANDNOT = 6, /* in0 AND NOT in1 */
+  VSP_ORNOT = 7,  /* in0 OR NOT in1 */
+  VSP_NOT = 8
+} vsp_gate;
+
+/* Launch modes of vsp_gates. */
+#define VSP_BATCHED 0  /* all gates of the call in one launch sequence */
+#define VSP_PER_GATE 1 /* one launch sequence per gate, serialised on the stream */
+
+typedef struct vsp_context vsp_context;
+typedef struct vsp_circuit vsp_circuit;
+typedef struct vsp_server vsp_server;
+
+/* A gate of a circuit: opcode and the wire ids of its inputs (in1 ignored by NOT). Wires
+ * 0..ninputs-1 are the circuit inputs; gate g writes wire ninputs + g. */
+typedef struct vsp_gate_desc {
+  uint32_t op, in0, in1;
+} vsp_gate_desc;
+
+/* Static text of a status code. */
+const char* vsp_status_str(vsp_status s);
+
+/* Detail of the last failure on the calling thread ("" if none). */
+const char* vsp_last_error(void);
+
+/* Create a context on HIP device `device`: validates params, uploads the bootstrapping key
+ * bk_host [n][2l][2][N] (BK[i] = TRGSW_{s1}(s0[i]), Sec. 2.1.2 "Bootstrapping Key") and the
+ * key-switching key ksk_host [N][t][base-1][n+1] (entry [j][p][v-1] = TLWE_{s0}(v s1[j] /
+ * base^(p+1))), converts the bootstrapping key to the NTT domain on the device, and
+ * returns it in *out. Host arrays are copied; the caller keeps them. Synchronous. */
+vsp_status vsp_context_create(const vsp_params* params, const uint32_t* bk_host, const uint32_t* ksk_host,
+                              int device, vsp_context** out);
+
+/* Destroy a context (waits for its device work first). NULL is accepted. */
+vsp_status vsp_context_destroy(vsp_context* ctx);
+
+/* Wait for all work the context enqueued and report any device-side failure. */
+vsp_status vsp_context_sync(vsp_context* ctx);
+
+/* Homomorphic gates (Sec. 2.1.2 "Homomorphic Gates"; the paper's processor evaluates one
+ * per netlist gate, Sec. 2.3): for g < B, d_out[g] = op_g(d_in0[g], d_in1[g]) where each
+ * non-NOT gate is linear combination -> modulus switch -> blind rotation (n CMUX external
+ * products) -> SampleExtract -> identity key switch, giving a fresh TLWE of the gate's
+ * output bit. d_ops [B] (uint8, vsp_gate codes; an invalid code yields an all-zero output
+ * and is reported by vsp_context_sync), d_in0, d_in1, d_out [B][n+1]. B = 0 is a no-op.
+ * mode: VSP_BATCHED or VSP_PER_GATE (same results, bit for bit). */
+vsp_status vsp_gates(vsp_context* ctx, const uint8_t* d_ops, const uint32_t* d_in0, const uint32_t* d_in1,
+                     uint32_t* d_out, uint64_t B, int mode, void* stream);
+
+/* Bootstrapping that returns a TRLWE (Sec. 2.1.2 "Bootstrapping in TFHE", without SE and
+ * IKS): d_out[g] [2][N] is the blind-rotation accumulator of op_g(in0, in1) with the test
+ * vector mu in every coefficient (constant coefficient encodes the gate's output bit).
+ * NOT is rejected (VSP_E_ARG is reported by vsp_context_sync as an invalid op). */
+vsp_status vsp_bootstrap_trlwe(vsp_context* ctx, const uint8_t* d_ops, const uint32_t* d_in0,
+                               const uint32_t* d_in1, uint32_t* d_out, uint64_t B, void* stream);
+
+/* Levelled circuit (the gate-evaluation engine's per-cycle work, Sec. 6.2(d)): gates
+ * [ngates] must be in topological order (each input wire id below the gate's own wire).
+ * Levelises, plans one batched launch per level and captures the level sequence in a HIP
+ * graph. Synchronous. */
+vsp_status vsp_circuit_create(vsp_context* ctx, const vsp_gate_desc* gates, uint64_t ngates, uint64_t ninputs,
+                              vsp_circuit** out);
+
+/* Evaluate the circuit: d_inputs [ninputs][n+1] -> d_wires [ninputs + ngates][n+1] (all
+ * wires, inputs first). Replays the captured graph on `stream`. */
+vsp_status vsp_circuit_run(vsp_circuit* c, const uint32_t* d_inputs, uint32_t* d_wires, void* stream);
+
+/* Same evaluation launching each level eagerly (no graph), recording the device time of
+ * every level into h_level_ms [nlevels] (synchronises the stream). */
+vsp_status vsp_circuit_run_timed(vsp_circuit* c, const uint32_t* d_inputs, uint32_t* d_wires, void* stream,
+                                 float* h_level_ms);
+
+/* Number of levels of the circuit and the width of its widest level. */
+vsp_status vsp_circuit_info(const vsp_circuit* c, uint64_t* nlevels, uint64_t* max_width);
+vsp_status vsp_circuit_destroy(vsp_circuit* c);
+
+/* ROM read by CMUX tree over packed TRLWE cells (Sec. 8.3: LUT with vertical and
+ * horizontal packing). d_rom [P][2][N]: P = 2^(v - log2(N / w)) cells; coefficient w*q + b
+ * of cell h holds bit b of word (N/w)*h + q. d_addr [R][v][2l][2][N]: per read, TRGSW
+ * encryptions of the v address bits, least significant first. The high v - log2(N/w) bits
+ * walk a CMUX tree over the cells, the low log2(N/w) bits rotate the chosen cell by
+ * X^(-w q) with CMUXes, then bit b is KS(SampleExtract_b). d_out [R][w][n+1]. w must divide
+ * N, be a power of two and P >= 1. */
+vsp_status vsp_rom_read(vsp_context* ctx, const uint32_t* d_rom, uint32_t P, const uint32_t* d_addr, uint32_t v,
+                        uint32_t w, uint32_t* d_out, uint64_t R, void* stream);
+
+/* RAM read unit (Sec. 8.2): d_ram [w][2^v][2][N], block i holds bit i of every word in its
+ * constant coefficient. Per read and bit: CMUX tree over the 2^v cells (address bit d
+ * selects at level d, least significant first), SampleExtract_0, key switch.
+ * d_addr [R][v][2l][2][N]; d_out [R][w][n+1]. 1 <= v <= 16. */
+vsp_status vsp_ram_read(vsp_context* ctx, const uint32_t* d_ram, uint32_t v, uint32_t w, const uint32_t* d_addr,
+                        uint32_t* d_out, uint64_t R, void* stream);
+
+/* RAM write (Sec. 8.2, read unit + control unit + write unit): with r_i the read of bit i
+ * at the address, the control unit forms u_i = BR(AND(f, x_i)) + BR(ANDNOT(r_i, f)) +
+ * (0, mu X^0) (HomMUX without SE and IKS); each of the w 2^v write bars (bit i, address A)
+ * chains v CMUXes y <- CMUX(s_d, R[i][A], y) from y = u_i, with s_d = C_d when bit d of A is
+ * 1 and G - C_d otherwise (Sec. 8.2 Remark), and refreshes R[i][A] <- BR(KS(SE_0(y))).
+ * d_ram is updated in place; d_addr [v][2l][2][N]; d_flag [n+1]; d_data [w][n+1]. */
+vsp_status vsp_ram_write(vsp_context* ctx, uint32_t* d_ram, uint32_t v, uint32_t w, const uint32_t* d_addr,
+                         const uint32_t* d_flag, const uint32_t* d_data, void* stream);
+
+/* Continuous-batching server over one context (Bob evaluating many clients' circuits,
+ * Sec. 4.1): admits submitted circuits while their resident wire buffers fit in
+ * mem_budget_bytes of device memory, and each iteration launches one batch of ready
+ * gates taken across all admitted circuits (at most max_batch gates). Runs its own host
+ * thread and stream. */
+vsp_status vsp_server_create(vsp_context* ctx, uint64_t mem_budget_bytes, uint64_t max_batch, vsp_server** out);
+
+/* Submit a circuit (gates as for vsp_circuit_create) with host inputs h_inputs
+ * [ninputs][n+1]; returns a ticket. VSP_E_CAPACITY if the circuit alone exceeds the
+ * memory budget. The input array is copied before the call returns. */
+vsp_status vsp_server_submit(vsp_server* s, const vsp_gate_desc* gates, uint64_t ngates, uint64_t ninputs,
+                             const uint32_t* h_inputs, uint64_t* ticket);
+
+/* Poll a ticket: *done = 1 once finished, and then (if h_wires is not NULL) copies all
+ * wires [ninputs + ngates][n+1] to h_wires and releases the ticket; latency_ms (if not
+ * NULL) receives submit-to-completion time. *done = 0 while queued or running. */
+vsp_status vsp_server_poll(vsp_server* s, uint64_t ticket, uint32_t* h_wires, int* done, double* latency_ms);
+
+/* Counters: gates launched, batches launched, peak resident bytes. */
+vsp_status vsp_server_stats(vsp_server* s, uint64_t* gates, uint64_t* batches, uint64_t* peak_bytes);
+
+/* Stop the server thread (finishing admitted work) and free it. NULL is accepted. */
+vsp_status vsp_server_destroy(vsp_server* s);
+
+/* Test entry: d_out[j] = C_j (ext) x_j for J (TRGSW, TRLWE) pairs, the external product
+ * at the heart of CMUX (Sec. 2.1.2 "CMUX"). d_trgsw [J][2l][2][N], d_x and d_out [J][2][N]. */
+vsp_status vsp_debug_external_product(vsp_context* ctx, const uint32_t* d_trgsw, const uint32_t* d_x,
+                                      uint32_t* d_out, uint64_t J, void* stream);
+
+/* Test entry: d_out[j] = d_a[j] * d_b[j] in Z[X]/(X^N+1) mod 2^32 through the NTT path.
+ * d_a holds small signed integers (|a| <= 2^20, so every exact coefficient stays below
+ * p/2); d_b torus values. Arrays [J][N]. */
+vsp_status vsp_debug_polymul(vsp_context* ctx, const int32_t* d_a, const uint32_t* d_b, uint32_t* d_out,
+                             uint64_t J, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VSP_H */

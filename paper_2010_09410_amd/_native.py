@@ -1,0 +1,205 @@
+"""ctypes binding of libvsp (include/vsp.h): the same entry points, argument marshalling only.
+
+Device pointers are passed as integers (e.g. ``torch.Tensor.data_ptr()``), streams as
+integers (``torch.cuda.current_stream().cuda_stream``) or None. A non-zero status raises
+VspError carrying the library's message. There is no fallback: if libvsp.so is missing,
+importing this module's functions raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvsp.so")
+
+VSP_OK, VSP_E_ARG, VSP_E_PARAMS, VSP_E_NOMEM, VSP_E_HIP, VSP_E_STATE, VSP_E_CAPACITY = 0, -1, -2, -3, -4, -5, -6
+VSP_BATCHED, VSP_PER_GATE = 0, 1
+NAND, AND, OR, NOR, XOR, XNOR, ANDNOT, ORNOT, NOT = range(9)
+
+
+class VspError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: status {status} ({detail})")
+        self.status = status
+
+
+class vsp_params(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_uint32) for k in ("n", "N", "k", "l", "bg_bits", "ks_t", "ks_basebit")]
+
+
+class vsp_gate_desc(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_uint32), ("in0", ctypes.c_uint32), ("in1", ctypes.c_uint32)]
+
+
+DEFAULT_PARAMS = (630, 1024, 1, 3, 6, 8, 2)
+
+_lib = None
+_c = ctypes
+_vp = ctypes.c_void_p
+_u64 = ctypes.c_uint64
+_i32 = ctypes.c_int
+_st = ctypes.c_int32
+
+SIGNATURES = {
+    "vsp_status_str": (ctypes.c_char_p, [_st]),
+    "vsp_last_error": (ctypes.c_char_p, []),
+    "vsp_context_create": (_st, [ctypes.POINTER(vsp_params), _vp, _vp, _i32, ctypes.POINTER(_vp)]),
+    "vsp_context_destroy": (_st, [_vp]),
+    "vsp_context_sync": (_st, [_vp]),
+    "vsp_gates": (_st, [_vp, _vp, _vp, _vp, _vp, _u64, _i32, _vp]),
+    "vsp_bootstrap_trlwe": (_st, [_vp, _vp, _vp, _vp, _vp, _u64, _vp]),
+    "vsp_circuit_create": (_st, [_vp, ctypes.POINTER(vsp_gate_desc), _u64, _u64, ctypes.POINTER(_vp)]),
+    "vsp_circuit_run": (_st, [_vp, _vp, _vp, _vp]),
+    "vsp_circuit_run_timed": (_st, [_vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_float)]),
+    "vsp_circuit_info": (_st, [_vp, ctypes.POINTER(_u64), ctypes.POINTER(_u64)]),
+    "vsp_circuit_destroy": (_st, [_vp]),
+    "vsp_rom_read": (_st, [_vp, _vp, ctypes.c_uint32, _vp, ctypes.c_uint32, ctypes.c_uint32, _vp, _u64, _vp]),
+    "vsp_ram_read": (_st, [_vp, _vp, ctypes.c_uint32, ctypes.c_uint32, _vp, _vp, _u64, _vp]),
+    "vsp_ram_write": (_st, [_vp, _vp, ctypes.c_uint32, ctypes.c_uint32, _vp, _vp, _vp, _vp]),
+    "vsp_server_create": (_st, [_vp, _u64, _u64, ctypes.POINTER(_vp)]),
+    "vsp_server_submit": (_st, [_vp, ctypes.POINTER(vsp_gate_desc), _u64, _u64, _vp, ctypes.POINTER(_u64)]),
+    "vsp_server_poll": (_st, [_vp, _u64, _vp, ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_double)]),
+    "vsp_server_stats": (_st, [_vp, ctypes.POINTER(_u64), ctypes.POINTER(_u64), ctypes.POINTER(_u64)]),
+    "vsp_server_destroy": (_st, [_vp]),
+    "vsp_debug_external_product": (_st, [_vp, _vp, _vp, _vp, _u64, _vp]),
+    "vsp_debug_polymul": (_st, [_vp, _vp, _vp, _vp, _u64, _vp]),
+}
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libvsp (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built (run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name, None)
+            if f is None:
+                continue  # calling it raises AttributeError from the library object
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(status: int, where: str) -> None:
+    if status != VSP_OK:
+        L = lib()
+        raise VspError(status, where, f"{L.vsp_status_str(status).decode()}: {L.vsp_last_error().decode()}")
+
+
+def _call(name, *args):
+    check(getattr(lib(), name)(*args), name)
+
+
+# ------------------------------------------------------------------ entry points
+def vsp_context_create(bk_host, ksk_host, device: int = 0, params=DEFAULT_PARAMS) -> int:
+    """bk_host / ksk_host: C-contiguous uint32 numpy arrays."""
+    p = vsp_params(*params)
+    out = _vp()
+    _call("vsp_context_create", ctypes.byref(p), bk_host.ctypes.data, ksk_host.ctypes.data, device, ctypes.byref(out))
+    return out.value
+
+
+def vsp_context_destroy(ctx: int) -> None:
+    _call("vsp_context_destroy", ctx)
+
+
+def vsp_context_sync(ctx: int) -> None:
+    _call("vsp_context_sync", ctx)
+
+
+def vsp_gates(ctx, d_ops, d_in0, d_in1, d_out, B, mode=VSP_BATCHED, stream=None) -> None:
+    _call("vsp_gates", ctx, d_ops, d_in0, d_in1, d_out, B, mode, stream)
+
+
+def vsp_bootstrap_trlwe(ctx, d_ops, d_in0, d_in1, d_out, B, stream=None) -> None:
+    _call("vsp_bootstrap_trlwe", ctx, d_ops, d_in0, d_in1, d_out, B, stream)
+
+
+def gate_descs(gates) -> ctypes.Array:
+    """(G, 3) integer array of (op, in0, in1) -> vsp_gate_desc[G]."""
+    arr = (vsp_gate_desc * len(gates))()
+    for i, (op, a, b) in enumerate(gates):
+        arr[i].op, arr[i].in0, arr[i].in1 = int(op), int(a), int(b)
+    return arr
+
+
+def vsp_circuit_create(ctx, gates, ninputs: int) -> int:
+    descs = gate_descs(gates)
+    out = _vp()
+    _call("vsp_circuit_create", ctx, descs, len(gates), ninputs, ctypes.byref(out))
+    return out.value
+
+
+def vsp_circuit_run(circ, d_inputs, d_wires, stream=None) -> None:
+    _call("vsp_circuit_run", circ, d_inputs, d_wires, stream)
+
+
+def vsp_circuit_run_timed(circ, d_inputs, d_wires, stream, nlevels: int):
+    ms = (ctypes.c_float * nlevels)()
+    _call("vsp_circuit_run_timed", circ, d_inputs, d_wires, stream, ms)
+    return list(ms)
+
+
+def vsp_circuit_info(circ):
+    a, b = _u64(), _u64()
+    _call("vsp_circuit_info", circ, ctypes.byref(a), ctypes.byref(b))
+    return a.value, b.value
+
+
+def vsp_circuit_destroy(circ) -> None:
+    _call("vsp_circuit_destroy", circ)
+
+
+def vsp_rom_read(ctx, d_rom, P, d_addr, v, w, d_out, R, stream=None) -> None:
+    _call("vsp_rom_read", ctx, d_rom, P, d_addr, v, w, d_out, R, stream)
+
+
+def vsp_ram_read(ctx, d_ram, v, w, d_addr, d_out, R, stream=None) -> None:
+    _call("vsp_ram_read", ctx, d_ram, v, w, d_addr, d_out, R, stream)
+
+
+def vsp_ram_write(ctx, d_ram, v, w, d_addr, d_flag, d_data, stream=None) -> None:
+    _call("vsp_ram_write", ctx, d_ram, v, w, d_addr, d_flag, d_data, stream)
+
+
+def vsp_server_create(ctx, mem_budget_bytes: int, max_batch: int) -> int:
+    out = _vp()
+    _call("vsp_server_create", ctx, mem_budget_bytes, max_batch, ctypes.byref(out))
+    return out.value
+
+
+def vsp_server_submit(srv, gates, ninputs: int, h_inputs) -> int:
+    descs = gate_descs(gates)
+    t = _u64()
+    _call("vsp_server_submit", srv, descs, len(gates), ninputs, h_inputs.ctypes.data, ctypes.byref(t))
+    return t.value
+
+
+def vsp_server_poll(srv, ticket: int, h_wires=None):
+    done = _i32()
+    lat = ctypes.c_double()
+    _call("vsp_server_poll", srv, ticket, None if h_wires is None else h_wires.ctypes.data, ctypes.byref(done),
+          ctypes.byref(lat))
+    return bool(done.value), lat.value
+
+
+def vsp_server_stats(srv):
+    a, b, c = _u64(), _u64(), _u64()
+    _call("vsp_server_stats", srv, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
+    return a.value, b.value, c.value
+
+
+def vsp_server_destroy(srv) -> None:
+    _call("vsp_server_destroy", srv)
+
+
+def vsp_debug_external_product(ctx, d_trgsw, d_x, d_out, J, stream=None) -> None:
+    _call("vsp_debug_external_product", ctx, d_trgsw, d_x, d_out, J, stream)
+
+
+def vsp_debug_polymul(ctx, d_a, d_b, d_out, J, stream=None) -> None:
+    _call("vsp_debug_polymul", ctx, d_a, d_b, d_out, J, stream)

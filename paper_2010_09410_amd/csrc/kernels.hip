@@ -1,0 +1,310 @@
+// Gate-bootstrapping kernels for gfx950: key conversion to the NTT domain, the gate
+// prologue (linear combination + modulus switch), blind rotation with SampleExtract,
+// identity key switching, and test kernels for the external product and polynomial product.
+#include "vsp_internal.h"
+
+namespace vsp {
+
+constexpr int TLWE0 = LWE_N + 1;
+constexpr int TLWE1 = RING_N + 1;
+
+// ------------------------------------------------------------------ key conversion
+// One wave per (item, round k, c'): lanes 0-31 transform row k, lanes 32-63 row k + 3; c' = 0
+// takes the output polynomial the half owns (a for rows 0..2, b for rows 3..5), c' = 1 the other.
+__global__ __launch_bounds__(256) void k_trgsw_to_ntt(const u32* __restrict__ src, u64* __restrict__ dst,
+                                                      const u64* __restrict__ tw, u64 ninv, uint64_t jobs) {
+  __shared__ u64 lds[4 * WAVE_LDS_U64];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint64_t job = (uint64_t)blockIdx.x * 4 + wave;
+  if (job >= jobs) return;
+  const int lane = threadIdx.x & 63, l = lane & 31, h = lane >> 5;
+  const uint64_t item = job / 6;
+  const int rem = (int)(job % 6), k = rem >> 1, cp = rem & 1;
+  const int row = k + GADGET_L * h;
+  const int col = (cp == 0) ? h : 1 - h;
+  const u32* poly = src + ((item * 2 * GADGET_L + row) * 2 + col) * RING_N;
+  u64 v[32];
+#pragma unroll
+  for (int t = 0; t < 32; t++) v[t] = poly[l + 32 * t];
+  u64* reg = lds + wave * WAVE_LDS_U64 + h * TREGION;
+  ntt_forward(v, tw, reg, l);
+  u64* out = dst + item * TRGSW_NTT_U64 + ((size_t)k * 2 + cp) * 32 * 64;
+#pragma unroll
+  for (int s = 0; s < 32; s++) out[s * 64 + lane] = gl_canon(gl_mul(v[s], ninv));
+}
+
+hipError_t launch_trgsw_to_ntt(const vsp_context* ctx, const uint32_t* src, uint64_t* dst, uint64_t count,
+                               hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  const uint64_t jobs = count * 6;
+  const u64 ninv = gl_powmod_const(RING_N, GL_P - 2);
+  hipLaunchKernelGGL(k_trgsw_to_ntt, dim3((unsigned)((jobs + 3) / 4)), dim3(256), 0, st, src, dst, ctx->tw, ninv,
+                     jobs);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ gate prologue
+// Linear combination of a homomorphic gate on the +-1/8 encoding (standard TFHE gates),
+// then modulus switch of every coefficient to Z/2N: round(x 2N / 2^32).
+__device__ __forceinline__ bool gate_linear(uint32_t op, u32 x, u32 y, bool is_b, u32& r) {
+  const u32 E = MU, Q = 2 * MU;
+  switch (op) {
+    case VSP_NAND: r = (is_b ? E : 0u) - x - y; return true;
+    case VSP_AND: r = (is_b ? 0u - E : 0u) + x + y; return true;
+    case VSP_OR: r = (is_b ? E : 0u) + x + y; return true;
+    case VSP_NOR: r = (is_b ? 0u - E : 0u) - x - y; return true;
+    case VSP_XOR: r = (is_b ? Q : 0u) + 2u * (x + y); return true;
+    case VSP_XNOR: r = (is_b ? 0u - Q : 0u) - 2u * (x + y); return true;
+    case VSP_ANDNOT: r = (is_b ? 0u - E : 0u) + x - y; return true;
+    case VSP_ORNOT: r = (is_b ? E : 0u) + x - y; return true;
+    case OP_IDENT: r = x; return true;
+    default: return false;
+  }
+}
+
+__device__ __forceinline__ u32 modswitch_2n(u32 x) { return ((x + (1u << 20)) >> 21) & (2 * RING_N - 1); }
+
+__global__ __launch_bounds__(256) void k_gate_prologue(const uint8_t* __restrict__ ops, uint32_t uniform_op,
+                                                       const u32* __restrict__ in0, const u32* __restrict__ in1,
+                                                       const u32* __restrict__ idx0, const u32* __restrict__ idx1,
+                                                       const u32* __restrict__ idxo, u32* __restrict__ abar,
+                                                       u32* __restrict__ out, int* __restrict__ err, uint64_t B,
+                                                       int allow_not) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= B * TLWE0) return;
+  const uint64_t g = i / TLWE0;
+  const int c = (int)(i - g * TLWE0);
+  const uint32_t op = ops ? ops[g] : uniform_op;
+  const uint64_t r0 = idx0 ? idx0[g] : g, r1 = idx1 ? idx1[g] : g;
+  const u32 x = in0[r0 * TLWE0 + c];
+  const bool one_input = (op == VSP_NOT || op == OP_IDENT || !op_bootstraps(op));
+  const u32 y = one_input ? 0u : in1[r1 * TLWE0 + c];
+  u32 r;
+  if (gate_linear(op, x, y, c == LWE_N, r)) {
+    abar[g * TLWE0 + c] = modswitch_2n(r);
+  } else if (op == VSP_NOT && allow_not) {
+    const uint64_t ro = idxo ? idxo[g] : g;
+    out[ro * TLWE0 + c] = 0u - x;
+  } else {
+    if (out) {
+      const uint64_t ro = idxo ? idxo[g] : g;
+      out[ro * TLWE0 + c] = 0u;
+    }
+    if (c == 0) atomicOr(err, DEVERR_BAD_OP);
+  }
+}
+
+hipError_t launch_gate_prologue(const vsp_context* ctx, const uint8_t* ops, const uint32_t* in0, const uint32_t* in1,
+                                const uint32_t* idx0, const uint32_t* idx1, const uint32_t* idxo, uint32_t* abar,
+                                uint32_t* out, uint64_t B, hipStream_t st, bool allow_not) {
+  if (B == 0) return hipSuccess;
+  const uint64_t n = B * TLWE0;
+  hipLaunchKernelGGL(k_gate_prologue, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ops, 0u, in0, in1, idx0,
+                     idx1, idxo, abar, out, ctx->dev_err, B, allow_not ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_gate_prologue_uniform(const vsp_context* ctx, uint32_t op, const uint32_t* in0, uint32_t* abar,
+                                        uint64_t B, hipStream_t st) {
+  if (B == 0) return hipSuccess;
+  const uint64_t n = B * TLWE0;
+  hipLaunchKernelGGL(k_gate_prologue, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, nullptr, op, in0, in0,
+                     nullptr, nullptr, nullptr, abar, nullptr, ctx->dev_err, B, 0);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ blind rotation
+// One wave per gate. Lanes 0-31 own the accumulator's a polynomial, lanes 32-63 its b
+// polynomial (coefficient l + 32 t in register t). ACC starts as (0, X^{-bbar} tv) with tv = mu
+// everywhere; step i applies ACC <- ACC + BK_i (ext) (X^{abar_i} ACC - ACC) (a CMUX between
+// ACC and its rotation selected by the key bit s0_i), skipped when abar_i = 0 (then the
+// difference is zero and so is the product).
+template <int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void k_blind_rotate(const u64* __restrict__ bkn, const u64* __restrict__ tw,
+                                                             const uint8_t* __restrict__ ops,
+                                                             const u32* __restrict__ abar, u32* __restrict__ tlwe1,
+                                                             u32* __restrict__ trlwe, uint64_t B) {
+  extern __shared__ u64 lds[];  // [2048] twiddles, then WAVES transform regions
+  u64* tws = lds;
+  for (int i = threadIdx.x; i < 2048; i += WAVES * 64) tws[i] = tw[i];
+  __syncthreads();
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint64_t g = (uint64_t)blockIdx.x * WAVES + wave;
+  if (g >= B) return;
+  if (ops && !op_bootstraps(ops[g])) return;
+  const int lane = threadIdx.x & 63, l = lane & 31, h = lane >> 5;
+  const u32* ab = abar + g * TLWE0;
+  const int bbar = (int)ab[LWE_N];
+  const int k0 = (2 * RING_N - bbar) & (2 * RING_N - 1);
+  u32 acc[32];
+#pragma unroll
+  for (int t = 0; t < 32; t++) acc[t] = h ? rotated_testvector(l + 32 * t, k0) : 0u;
+  for (int i = 0; i < LWE_N; i++) {
+    const int a = (int)__builtin_amdgcn_readfirstlane(ab[i]);
+    if (a == 0) continue;
+    const int ln = opaque_lane(lane);
+    u64* rg = lds + 2048 + wave * WAVE_LDS_U64 + (ln >> 5) * TREGION;
+    u32 D[32];
+    rotate_minus(acc, a, rg, ln & 31, D);
+    external_product_acc(D, bkn + (size_t)i * TRGSW_NTT_U64, tws, tws + 1024, rg, ln, acc);
+  }
+  if (trlwe) {
+    u32* o = trlwe + g * 2 * RING_N + h * RING_N;
+#pragma unroll
+    for (int t = 0; t < 32; t++) o[l + 32 * t] = acc[t];
+  }
+  if (tlwe1) {
+    // SampleExtract at 0: a'_0 = A_0, a'_j = -A_{N-j}; b' = B_0.
+    u32* o = tlwe1 + g * TLWE1;
+    if (h == 0) {
+#pragma unroll
+      for (int t = 0; t < 32; t++) {
+        const int j = l + 32 * t;
+        o[(RING_N - j) & (RING_N - 1)] = (j == 0) ? acc[t] : 0u - acc[t];
+      }
+    } else if (l == 0) {
+      o[RING_N] = acc[0];
+    }
+  }
+}
+
+template <int WAVES>
+static void set_br_lds() {
+  static bool done = false;
+  if (!done) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_blind_rotate<WAVES>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (2048 + WAVES * WAVE_LDS_U64) * 8);
+    done = true;
+  }
+}
+
+hipError_t launch_blind_rotate(const vsp_context* ctx, const uint8_t* ops, const uint32_t* abar, uint32_t* tlwe1,
+                               uint32_t* trlwe, uint64_t B, int waves, hipStream_t st) {
+  if (B == 0) return hipSuccess;
+  switch (waves) {
+    case 4: {
+      set_br_lds<4>();
+      const size_t lds = (2048 + 4 * WAVE_LDS_U64) * 8;
+      hipLaunchKernelGGL(k_blind_rotate<4>, dim3((unsigned)((B + 3) / 4)), dim3(256), lds, st, ctx->bkn, ctx->tw,
+                         ops, abar, tlwe1, trlwe, B);
+      break;
+    }
+    default: {
+      set_br_lds<8>();
+      const size_t lds = (2048 + 8 * WAVE_LDS_U64) * 8;
+      hipLaunchKernelGGL(k_blind_rotate<8>, dim3((unsigned)((B + 7) / 8)), dim3(512), lds, st, ctx->bkn, ctx->tw,
+                         ops, abar, tlwe1, trlwe, B);
+      break;
+    }
+  }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ key switching
+// out = (0, b') - sum_{j,p} KSK[j][p][v_{j,p}], v_{j,p} the p-th base-4 digit (most
+// significant first) of a'_j rounded to 16 bits. The device key has a zero row at v = 0 so
+// the loop is branch-free. One workgroup of 256 threads per gate, 3 coefficients per thread.
+__global__ __launch_bounds__(256) void k_keyswitch(const u32* __restrict__ ksk, const uint8_t* __restrict__ ops,
+                                                   const u32* __restrict__ tlwe1, const u32* __restrict__ idxo,
+                                                   u32* __restrict__ out, uint64_t B) {
+  const uint64_t g = blockIdx.x;
+  if (g >= B) return;
+  if (ops && !op_bootstraps(ops[g])) return;
+  const u32* in = tlwe1 + g * TLWE1;
+  const int tid = threadIdx.x;
+  u32 acc0 = 0, acc1 = 0, acc2 = 0;
+  const int c0 = tid, c1 = tid + 256, c2 = tid + 512;
+  const bool has2 = c2 < TLWE0;
+  for (int j = 0; j < RING_N; j++) {
+    const u32 ahat = __builtin_amdgcn_readfirstlane(in[j]) + (1u << 15);
+    const u32* base = ksk + (size_t)j * KS_T * 4 * TLWE0;
+#pragma unroll
+    for (int p = 0; p < KS_T; p++) {
+      const u32 v = (ahat >> (30 - 2 * p)) & 3u;
+      const u32* row = base + (size_t)(p * 4 + v) * TLWE0;
+      acc0 += row[c0];
+      acc1 += row[c1];
+      if (has2) acc2 += row[c2];
+    }
+  }
+  const uint64_t ro = idxo ? idxo[g] : g;
+  u32* o = out + ro * TLWE0;
+  const u32 b = in[RING_N];
+  o[c0] = 0u - acc0;
+  o[c1] = 0u - acc1;
+  if (has2) o[c2] = (c2 == LWE_N ? b : 0u) - acc2;
+}
+
+hipError_t launch_keyswitch(const vsp_context* ctx, const uint8_t* ops, const uint32_t* tlwe1, const uint32_t* idxo,
+                            uint32_t* out, uint64_t B, hipStream_t st) {
+  if (B == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_keyswitch, dim3((unsigned)B), dim3(256), 0, st, ctx->ksk, ops, tlwe1, idxo, out, B);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ test kernels
+__global__ __launch_bounds__(256) void k_ext_product(const u64* __restrict__ Cn, const u32* __restrict__ x,
+                                                     u32* __restrict__ out, const u64* __restrict__ tw, uint64_t J) {
+  __shared__ u64 lds[4 * WAVE_LDS_U64];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint64_t j = (uint64_t)blockIdx.x * 4 + wave;
+  if (j >= J) return;
+  const int lane = threadIdx.x & 63, l = lane & 31, h = lane >> 5;
+  u64* reg = lds + wave * WAVE_LDS_U64 + h * TREGION;
+  const u32* xp = x + j * 2 * RING_N + h * RING_N;
+  u32 D[32], acc[32];
+#pragma unroll
+  for (int t = 0; t < 32; t++) {
+    D[t] = xp[l + 32 * t];
+    acc[t] = 0;
+  }
+  external_product_acc(D, Cn + j * TRGSW_NTT_U64, tw, tw + 1024, reg, lane, acc);
+  u32* o = out + j * 2 * RING_N + h * RING_N;
+#pragma unroll
+  for (int t = 0; t < 32; t++) o[l + 32 * t] = acc[t];
+}
+
+hipError_t launch_ext_product(const vsp_context* ctx, const uint64_t* Cn, const uint32_t* x, uint32_t* out, uint64_t J,
+                              hipStream_t st) {
+  if (J == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ext_product, dim3((unsigned)((J + 3) / 4)), dim3(256), 0, st, Cn, x, out, ctx->tw, J);
+  return hipGetLastError();
+}
+
+// Negacyclic product through the NTT: lanes 0-31 transform a, lanes 32-63 transform b,
+// the pointwise product is formed in lanes 0-31 and transformed back there.
+__global__ __launch_bounds__(256) void k_polymul(const int32_t* __restrict__ a, const u32* __restrict__ b,
+                                                 u32* __restrict__ out, const u64* __restrict__ tw, u64 ninv,
+                                                 uint64_t J) {
+  __shared__ u64 lds[4 * WAVE_LDS_U64];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint64_t j = (uint64_t)blockIdx.x * 4 + wave;
+  if (j >= J) return;
+  const int lane = threadIdx.x & 63, l = lane & 31, h = lane >> 5;
+  u64* reg = lds + wave * WAVE_LDS_U64 + h * TREGION;
+  u64 v[32];
+#pragma unroll
+  for (int t = 0; t < 32; t++)
+    v[t] = h ? (u64)b[j * RING_N + l + 32 * t] : gl_from_i32(a[j * RING_N + l + 32 * t]);
+  ntt_forward(v, tw, reg, l);
+#pragma unroll
+  for (int s = 0; s < 32; s++) {
+    const u64 other = __shfl_xor(v[s], 32);
+    v[s] = gl_mul(gl_mul(v[s], other), ninv);
+  }
+  ntt_inverse(v, tw + 1024, reg, l);
+  if (h == 0) {
+#pragma unroll
+    for (int t = 0; t < 32; t++) out[j * RING_N + l + 32 * t] = gl_lift_u32(gl_canon(v[t]));
+  }
+}
+
+hipError_t launch_polymul(const vsp_context* ctx, const int32_t* a, const uint32_t* b, uint32_t* out, uint64_t J,
+                          hipStream_t st) {
+  if (J == 0) return hipSuccess;
+  const u64 ninv = gl_powmod_const(RING_N, GL_P - 2);
+  hipLaunchKernelGGL(k_polymul, dim3((unsigned)((J + 3) / 4)), dim3(256), 0, st, a, b, out, ctx->tw, ninv, J);
+  return hipGetLastError();
+}
+
+}  // namespace vsp

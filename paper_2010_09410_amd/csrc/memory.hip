@@ -1,0 +1,412 @@
+// CMUX Memory (Sec. 8): ROM reads by a packed LUT (CMUX tree + rotation CMUXes), RAM reads
+// by per-bit CMUX trees, and the RAM write (read unit, control unit, write bars, refresh).
+#include <vector>
+
+#include "vsp_internal.h"
+
+namespace vsp {
+
+constexpr int TRLWE_WORDS = 2 * RING_N;
+constexpr int TRGSW_WORDS = 2 * GADGET_L * 2 * RING_N;
+
+// ------------------------------------------------------------------ kernels
+// One wave per CMUX: out = x0 + C (ext) (x1 - x0).
+__global__ __launch_bounds__(256) void k_cmux_tree_level(const u64* __restrict__ sel, uint64_t sel_r_stride, int selbit,
+                                                         const u32* __restrict__ in, uint64_t s_r, uint64_t s_b,
+                                                         u32* __restrict__ out, uint64_t R, uint64_t nb, uint64_t half,
+                                                         const u64* __restrict__ tw) {
+  __shared__ u64 lds[4 * WAVE_LDS_U64];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint64_t job = (uint64_t)blockIdx.x * 4 + wave;
+  if (job >= R * nb * half) return;
+  const int lane = threadIdx.x & 63, l = lane & 31, h = lane >> 5;
+  const uint64_t m = job % half, rb = job / half, blk = rb % nb, r = rb / nb;
+  const u32* x0 = in + r * s_r + blk * s_b + (2 * m) * TRLWE_WORDS + h * RING_N;
+  const u32* x1 = x0 + TRLWE_WORDS;
+  const u64* C = sel + (r * sel_r_stride + (uint64_t)selbit) * TRGSW_NTT_U64;
+  u64* reg = lds + wave * WAVE_LDS_U64 + h * TREGION;
+  u32 D[32], acc[32];
+#pragma unroll
+  for (int t = 0; t < 32; t++) {
+    const u32 a = x0[l + 32 * t], b = x1[l + 32 * t];
+    acc[t] = a;
+    D[t] = b - a;
+  }
+  external_product_acc(D, C, tw, tw + 1024, reg, lane, acc);
+  u32* o = out + job * TRLWE_WORDS + h * RING_N;
+#pragma unroll
+  for (int t = 0; t < 32; t++) o[l + 32 * t] = acc[t];
+}
+
+// One wave per read: R <- CMUX(C_j, R, X^{-w 2^j} R) = R + C_j (ext) (X^{-w 2^j} R - R), j ascending.
+__global__ __launch_bounds__(256) void k_rom_rotate(const u64* __restrict__ sel, uint64_t sel_r_stride,
+                                                    u32* __restrict__ accbuf, uint64_t R, int rotbits, int w,
+                                                    const u64* __restrict__ tw) {
+  __shared__ u64 lds[4 * WAVE_LDS_U64];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint64_t r = (uint64_t)blockIdx.x * 4 + wave;
+  if (r >= R) return;
+  const int lane = threadIdx.x & 63, l = lane & 31, h = lane >> 5;
+  u64* reg = lds + wave * WAVE_LDS_U64 + h * TREGION;
+  u32* p = accbuf + r * TRLWE_WORDS + h * RING_N;
+  u32 acc[32], D[32];
+#pragma unroll
+  for (int t = 0; t < 32; t++) acc[t] = p[l + 32 * t];
+  for (int j = 0; j < rotbits; j++) {
+    const int k = (2 * RING_N - (w << j)) & (2 * RING_N - 1);
+    rotate_minus(acc, k, reg, l, D);
+    external_product_acc(D, sel + (r * sel_r_stride + (uint64_t)j) * TRGSW_NTT_U64, tw, tw + 1024, reg, lane, acc);
+  }
+#pragma unroll
+  for (int t = 0; t < 32; t++) p[l + 32 * t] = acc[t];
+}
+
+// SampleExtract_h for h < W: out[r][h] (N + 1 words) from in[r] = (A, B).
+__global__ __launch_bounds__(256) void k_sample_extract(const u32* __restrict__ in, u32* __restrict__ out, uint64_t R,
+                                                        int W) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t per = (uint64_t)W * (RING_N + 1);
+  if (i >= R * per) return;
+  const uint64_t r = i / per;
+  const int rem = (int)(i - r * per), hh = rem / (RING_N + 1), j = rem - hh * (RING_N + 1);
+  const u32* c = in + r * TRLWE_WORDS;
+  u32 v;
+  if (j == RING_N) v = c[RING_N + hh];
+  else if (j <= hh) v = c[hh - j];
+  else v = 0u - c[RING_N + hh - j];
+  out[i] = v;
+}
+
+// Control unit output u_i = acc[i] + acc[w + i] + (0, mu X^0).
+__global__ __launch_bounds__(256) void k_ram_control(const u32* __restrict__ acc2, u32* __restrict__ u, int w) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= w * TRLWE_WORDS) return;
+  const int bit = i / TRLWE_WORDS, c = i - bit * TRLWE_WORDS;
+  u[i] = acc2[i] + acc2[(size_t)(w + bit) * TRLWE_WORDS + c] + (c == RING_N ? MU : 0u);
+}
+
+// One wave per write bar (bit i, address A): y = u_i; for d < v: y = CMUX(s_d, R[i][A], y)
+// = R[i][A] + s_d (ext) (y - R[i][A]) with s_d = C_d (bit d of A is 1) or G - C_d (0);
+// then SampleExtract_0(y) into tlwe1[i 2^v + A].
+__global__ __launch_bounds__(256) void k_ram_bars(const u64* __restrict__ sel, const u64* __restrict__ selneg,
+                                                  const u32* __restrict__ ram, const u32* __restrict__ u,
+                                                  u32* __restrict__ tlwe1, int v, int w, const u64* __restrict__ tw) {
+  __shared__ u64 lds[4 * WAVE_LDS_U64];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint64_t bar = (uint64_t)blockIdx.x * 4 + wave;
+  if (bar >= ((uint64_t)w << v)) return;
+  const int lane = threadIdx.x & 63, l = lane & 31, h = lane >> 5;
+  const uint64_t i = bar >> v, A = bar & ((1ull << v) - 1);
+  u64* reg = lds + wave * WAVE_LDS_U64 + h * TREGION;
+  const u32* old = ram + bar * TRLWE_WORDS + h * RING_N;
+  const u32* ui = u + i * TRLWE_WORDS + h * RING_N;
+  u32 o[32], y[32], D[32];
+#pragma unroll
+  for (int t = 0; t < 32; t++) {
+    o[t] = old[l + 32 * t];
+    y[t] = ui[l + 32 * t];
+  }
+  for (int d = 0; d < v; d++) {
+    const u64* C = (((A >> d) & 1) ? sel : selneg) + (size_t)d * TRGSW_NTT_U64;
+#pragma unroll
+    for (int t = 0; t < 32; t++) {
+      D[t] = y[t] - o[t];
+      y[t] = o[t];
+    }
+    external_product_acc(D, C, tw, tw + 1024, reg, lane, y);
+  }
+  u32* out = tlwe1 + bar * (RING_N + 1);
+  if (h == 0) {
+#pragma unroll
+    for (int t = 0; t < 32; t++) {
+      const int j = l + 32 * t;
+      out[(RING_N - j) & (RING_N - 1)] = (j == 0) ? y[t] : 0u - y[t];
+    }
+  } else if (l == 0) {
+    out[RING_N] = y[0];
+  }
+}
+
+// G - C: negate every coefficient of C and add the gadget constants of the trivial TRGSW(1).
+__global__ __launch_bounds__(256) void k_gadget_minus(const u32* __restrict__ C, u32* __restrict__ out, uint64_t count) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count * TRGSW_WORDS) return;
+  const int within = (int)(i % TRGSW_WORDS);
+  const int row = within / TRLWE_WORDS, rem = within % TRLWE_WORDS, col = rem / RING_N, coef = rem % RING_N;
+  u32 g = 0;
+  if (coef == 0) {
+    if (row < GADGET_L && col == 0) g = 1u << (32 - BG_BIT * (row + 1));
+    if (row >= GADGET_L && col == 1) g = 1u << (32 - BG_BIT * (row - GADGET_L + 1));
+  }
+  out[i] = g - C[i];
+}
+
+// Broadcast one TRLWE to R slots.
+__global__ __launch_bounds__(256) void k_broadcast(const u32* __restrict__ src, u32* __restrict__ dst, uint64_t R) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= R * TRLWE_WORDS) return;
+  dst[i] = src[i % TRLWE_WORDS];
+}
+
+// ------------------------------------------------------------------ launchers
+static unsigned blocks_for(uint64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+hipError_t launch_cmux_tree_level(const vsp_context* ctx, const uint64_t* sel, uint64_t sel_r_stride, int selbit,
+                                  const uint32_t* in, uint64_t s_r, uint64_t s_b, uint32_t* out, uint64_t R,
+                                  uint64_t nb, uint64_t W, hipStream_t st) {
+  const uint64_t jobs = R * nb * (W / 2);
+  if (jobs == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cmux_tree_level, dim3(blocks_for(jobs, 4)), dim3(256), 0, st, sel, sel_r_stride, selbit, in,
+                     s_r, s_b, out, R, nb, W / 2, ctx->tw);
+  return hipGetLastError();
+}
+
+hipError_t launch_rom_rotate(const vsp_context* ctx, const uint64_t* sel, uint64_t sel_r_stride, uint32_t* acc,
+                             uint64_t R, int rotbits, int w, hipStream_t st) {
+  if (R == 0 || rotbits == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rom_rotate, dim3(blocks_for(R, 4)), dim3(256), 0, st, sel, sel_r_stride, acc, R, rotbits, w,
+                     ctx->tw);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample_extract(const uint32_t* in, uint32_t* out, uint64_t R, int W, hipStream_t st) {
+  const uint64_t n = R * (uint64_t)W * (RING_N + 1);
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sample_extract, dim3(blocks_for(n, 256)), dim3(256), 0, st, in, out, R, W);
+  return hipGetLastError();
+}
+
+hipError_t launch_ram_control(const uint32_t* acc2, uint32_t* u, int w, hipStream_t st) {
+  hipLaunchKernelGGL(k_ram_control, dim3(blocks_for((uint64_t)w * TRLWE_WORDS, 256)), dim3(256), 0, st, acc2, u, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_ram_bars(const vsp_context* ctx, const uint64_t* sel, const uint64_t* selneg, const uint32_t* ram,
+                           const uint32_t* u, uint32_t* tlwe1, int v, int w, hipStream_t st) {
+  const uint64_t bars = (uint64_t)w << v;
+  hipLaunchKernelGGL(k_ram_bars, dim3(blocks_for(bars, 4)), dim3(256), 0, st, sel, selneg, ram, u, tlwe1, v, w,
+                     ctx->tw);
+  return hipGetLastError();
+}
+
+hipError_t launch_gadget_minus(const uint32_t* C, uint32_t* out, uint64_t count, hipStream_t st) {
+  const uint64_t n = count * TRGSW_WORDS;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gadget_minus, dim3(blocks_for(n, 256)), dim3(256), 0, st, C, out, count);
+  return hipGetLastError();
+}
+
+static hipError_t launch_broadcast(const uint32_t* src, uint32_t* dst, uint64_t R, hipStream_t st) {
+  hipLaunchKernelGGL(k_broadcast, dim3(blocks_for(R * TRLWE_WORDS, 256)), dim3(256), 0, st, src, dst, R);
+  return hipGetLastError();
+}
+
+static int ilog2(uint64_t x) {
+  int r = 0;
+  while ((1ull << r) < x) r++;
+  return r;
+}
+
+// CMUX trees of `levels` levels over `nb` blocks per read (cells [nb][2^levels] shared by all
+// reads, block stride s_b words), address bits `bit0`.. of each read's selectors. Leaves
+// the R * nb results in *result (one of two ping-pong buffers a, b).
+static hipError_t run_trees(const vsp_context* ctx, const uint64_t* sel, uint64_t sel_r_stride, int bit0, int levels,
+                            const uint32_t* cells, uint64_t s_b, uint64_t R, uint64_t nb, uint32_t* a, uint32_t* b,
+                            uint32_t** result, hipStream_t st) {
+  uint64_t W = 1ull << levels;
+  const uint32_t* in = cells;
+  uint64_t s_r = 0, sb = s_b;
+  uint32_t* bufs[2] = {a, b};
+  int cur = 0;
+  for (int d = 0; d < levels; d++) {
+    uint32_t* out = bufs[cur];
+    hipError_t e = launch_cmux_tree_level(ctx, sel, sel_r_stride, bit0 + d, in, s_r, sb, out, R, nb, W, st);
+    if (e != hipSuccess) return e;
+    W /= 2;
+    in = out;
+    sb = W * TRLWE_WORDS;
+    s_r = nb * sb;
+    cur ^= 1;
+  }
+  if (levels == 0) {
+    // a single cell (ROM with one polynomial): give every read its own copy
+    hipError_t e = launch_broadcast(cells, a, R, st);
+    if (e != hipSuccess) return e;
+    *result = a;
+    return hipSuccess;
+  }
+  *result = const_cast<uint32_t*>(in);
+  return hipSuccess;
+}
+
+}  // namespace vsp
+
+using namespace vsp;
+
+extern "C" {
+
+vsp_status vsp_rom_read(vsp_context* ctx, const uint32_t* d_rom, uint32_t P, const uint32_t* d_addr, uint32_t v,
+                        uint32_t w, uint32_t* d_out, uint64_t R, void* stream) {
+  if (ctx == nullptr) return fail(VSP_E_ARG, "context is NULL");
+  if (R == 0) return VSP_OK;
+  if (w == 0 || (w & (w - 1)) || w > (uint32_t)RING_N) return fail(VSP_E_ARG, "w must be a power of two <= N");
+  const int rotbits = ilog2(RING_N / w);
+  if (v < (uint32_t)rotbits || v > 32) return fail(VSP_E_ARG, "v must be at least log2(N / w)");
+  if ((uint64_t)P != (1ull << (v - rotbits))) return fail(VSP_E_ARG, "P must equal 2^(v - log2(N / w))");
+  if (R > (1ull << 24)) return fail(VSP_E_ARG, "R too large");
+  VSP_HIP(hipSetDevice(ctx->device));
+  vsp_status s;
+  const size_t rom_b = (size_t)P * TRLWE_WORDS * 4, addr_b = (size_t)R * v * TRGSW_WORDS * 4,
+               out_b = (size_t)R * w * (LWE_N + 1) * 4;
+  if ((s = check_device_range(ctx, d_rom, rom_b, "d_rom"))) return s;
+  if ((s = check_device_range(ctx, d_addr, addr_b, "d_addr"))) return s;
+  if ((s = check_device_range(ctx, d_out, out_b, "d_out"))) return s;
+  if ((s = check_no_overlap(d_out, out_b, d_rom, rom_b, "d_out and d_rom"))) return s;
+  if ((s = check_no_overlap(d_out, out_b, d_addr, addr_b, "d_out and d_addr"))) return s;
+  const uint64_t half = P > 1 ? P / 2 : 1;
+  if ((s = scratch_reserve(ctx, ctx->ntt_sel, (size_t)R * v * TRGSW_NTT_U64 * 8))) return s;
+  if ((s = scratch_reserve(ctx, ctx->mem_a, (size_t)R * half * TRLWE_WORDS * 4))) return s;
+  if ((s = scratch_reserve(ctx, ctx->mem_b, (size_t)R * half * TRLWE_WORDS * 4))) return s;
+  if ((s = scratch_reserve(ctx, ctx->tlwe1, (size_t)R * w * (RING_N + 1) * 4))) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  uint64_t* sel = static_cast<uint64_t*>(ctx->ntt_sel.ptr);
+  hipError_t e;
+  if ((e = launch_trgsw_to_ntt(ctx, d_addr, sel, R * v, st)) != hipSuccess) return hip_fail(e, "selector conversion");
+  uint32_t* acc = nullptr;
+  if ((e = run_trees(ctx, sel, v, rotbits, (int)(v - rotbits), d_rom, 0, R, 1, static_cast<uint32_t*>(ctx->mem_a.ptr),
+                     static_cast<uint32_t*>(ctx->mem_b.ptr), &acc, st)) != hipSuccess)
+    return hip_fail(e, "ROM tree");
+  if ((e = launch_rom_rotate(ctx, sel, v, acc, R, rotbits, (int)w, st)) != hipSuccess) return hip_fail(e, "ROM rotate");
+  uint32_t* t1 = static_cast<uint32_t*>(ctx->tlwe1.ptr);
+  if ((e = launch_sample_extract(acc, t1, R, (int)w, st)) != hipSuccess) return hip_fail(e, "sample extract");
+  if ((e = launch_keyswitch(ctx, nullptr, t1, nullptr, d_out, R * w, st)) != hipSuccess) return hip_fail(e, "key switch");
+  return VSP_OK;
+}
+
+vsp_status vsp_ram_read(vsp_context* ctx, const uint32_t* d_ram, uint32_t v, uint32_t w, const uint32_t* d_addr,
+                        uint32_t* d_out, uint64_t R, void* stream) {
+  if (ctx == nullptr) return fail(VSP_E_ARG, "context is NULL");
+  if (R == 0) return VSP_OK;
+  if (v < 1 || v > 16) return fail(VSP_E_ARG, "v must be in [1, 16]");
+  if (w < 1 || w > 1024) return fail(VSP_E_ARG, "w must be in [1, 1024]");
+  if (R > (1ull << 20)) return fail(VSP_E_ARG, "R too large");
+  VSP_HIP(hipSetDevice(ctx->device));
+  vsp_status s;
+  const uint64_t cells = (uint64_t)w << v;
+  const size_t ram_b = cells * TRLWE_WORDS * 4, addr_b = (size_t)R * v * TRGSW_WORDS * 4,
+               out_b = (size_t)R * w * (LWE_N + 1) * 4;
+  if ((s = check_device_range(ctx, d_ram, ram_b, "d_ram"))) return s;
+  if ((s = check_device_range(ctx, d_addr, addr_b, "d_addr"))) return s;
+  if ((s = check_device_range(ctx, d_out, out_b, "d_out"))) return s;
+  if ((s = check_no_overlap(d_out, out_b, d_ram, ram_b, "d_out and d_ram"))) return s;
+  if ((s = check_no_overlap(d_out, out_b, d_addr, addr_b, "d_out and d_addr"))) return s;
+  if ((s = scratch_reserve(ctx, ctx->ntt_sel, (size_t)R * v * TRGSW_NTT_U64 * 8))) return s;
+  const size_t level_b = (size_t)R * (cells / 2) * TRLWE_WORDS * 4;
+  if ((s = scratch_reserve(ctx, ctx->mem_a, level_b))) return s;
+  if ((s = scratch_reserve(ctx, ctx->mem_b, level_b))) return s;
+  if ((s = scratch_reserve(ctx, ctx->tlwe1, (size_t)R * w * (RING_N + 1) * 4))) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  uint64_t* sel = static_cast<uint64_t*>(ctx->ntt_sel.ptr);
+  hipError_t e;
+  if ((e = launch_trgsw_to_ntt(ctx, d_addr, sel, R * v, st)) != hipSuccess) return hip_fail(e, "selector conversion");
+  uint32_t* res = nullptr;
+  if ((e = run_trees(ctx, sel, v, 0, (int)v, d_ram, (1ull << v) * TRLWE_WORDS, R, w, static_cast<uint32_t*>(ctx->mem_a.ptr),
+                     static_cast<uint32_t*>(ctx->mem_b.ptr), &res, st)) != hipSuccess)
+    return hip_fail(e, "RAM tree");
+  uint32_t* t1 = static_cast<uint32_t*>(ctx->tlwe1.ptr);
+  if ((e = launch_sample_extract(res, t1, R * w, 1, st)) != hipSuccess) return hip_fail(e, "sample extract");
+  if ((e = launch_keyswitch(ctx, nullptr, t1, nullptr, d_out, R * w, st)) != hipSuccess) return hip_fail(e, "key switch");
+  return VSP_OK;
+}
+
+vsp_status vsp_ram_write(vsp_context* ctx, uint32_t* d_ram, uint32_t v, uint32_t w, const uint32_t* d_addr,
+                         const uint32_t* d_flag, const uint32_t* d_data, void* stream) {
+  if (ctx == nullptr) return fail(VSP_E_ARG, "context is NULL");
+  if (v < 1 || v > 16) return fail(VSP_E_ARG, "v must be in [1, 16]");
+  if (w < 1 || w > 1024) return fail(VSP_E_ARG, "w must be in [1, 1024]");
+  VSP_HIP(hipSetDevice(ctx->device));
+  vsp_status s;
+  const uint64_t cells = (uint64_t)w << v;
+  const size_t T0 = (LWE_N + 1) * 4, T1 = (RING_N + 1) * 4, TR = TRLWE_WORDS * 4;
+  const size_t ram_b = cells * TR, addr_b = (size_t)v * TRGSW_WORDS * 4;
+  if ((s = check_device_range(ctx, d_ram, ram_b, "d_ram"))) return s;
+  if ((s = check_device_range(ctx, d_addr, addr_b, "d_addr"))) return s;
+  if ((s = check_device_range(ctx, d_flag, T0, "d_flag"))) return s;
+  if ((s = check_device_range(ctx, d_data, (size_t)w * T0, "d_data"))) return s;
+  if ((s = check_no_overlap(d_ram, ram_b, d_addr, addr_b, "d_ram and d_addr"))) return s;
+  if ((s = check_no_overlap(d_ram, ram_b, d_flag, T0, "d_ram and d_flag"))) return s;
+  if ((s = check_no_overlap(d_ram, ram_b, d_data, (size_t)w * T0, "d_ram and d_data"))) return s;
+  // scratch: selectors (C and G - C, NTT), torus G - C, read trees, control, bars, refresh
+  if ((s = scratch_reserve(ctx, ctx->ntt_sel, (size_t)2 * v * TRGSW_NTT_U64 * 8))) return s;
+  const size_t tree_b = (cells / 2 > 0 ? cells / 2 : 1) * TR;
+  if ((s = scratch_reserve(ctx, ctx->mem_a, tree_b))) return s;
+  if ((s = scratch_reserve(ctx, ctx->mem_b, tree_b))) return s;
+  // mem_c: [gneg torus v TRGSW][src (1 + 2w) TLWE0][idx 3 * 2w u32][ops 2w][acc2 2w TRLWE][u w TRLWE]
+  const size_t off_src = (size_t)v * TRGSW_WORDS * 4;
+  const size_t off_idx = off_src + (1 + 2 * (size_t)w) * T0;
+  const size_t off_ops = off_idx + 3 * 2 * (size_t)w * 4;
+  const size_t off_acc = (off_ops + 2 * (size_t)w + 255) & ~(size_t)255;
+  const size_t off_u = off_acc + 2 * (size_t)w * TR;
+  const size_t mem_c_b = off_u + (size_t)w * TR;
+  if ((s = scratch_reserve(ctx, ctx->mem_c, mem_c_b))) return s;
+  // mem_d: tlwe0 [cells] then abar [cells]
+  if ((s = scratch_reserve(ctx, ctx->mem_d, cells * T0 * 2))) return s;
+  if ((s = scratch_reserve(ctx, ctx->tlwe1, cells * T1))) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* mc = static_cast<char*>(ctx->mem_c.ptr);
+  uint64_t* sel = static_cast<uint64_t*>(ctx->ntt_sel.ptr);
+  uint64_t* selneg = sel + (size_t)v * TRGSW_NTT_U64;
+  uint32_t* gneg = reinterpret_cast<uint32_t*>(mc);
+  uint32_t* src = reinterpret_cast<uint32_t*>(mc + off_src);
+  uint32_t* idx = reinterpret_cast<uint32_t*>(mc + off_idx);
+  uint8_t* ops = reinterpret_cast<uint8_t*>(mc + off_ops);
+  uint32_t* acc2 = reinterpret_cast<uint32_t*>(mc + off_acc);
+  uint32_t* u = reinterpret_cast<uint32_t*>(mc + off_u);
+  uint32_t* t0 = static_cast<uint32_t*>(ctx->mem_d.ptr);
+  uint32_t* abar = t0 + cells * (LWE_N + 1);
+  uint32_t* t1 = static_cast<uint32_t*>(ctx->tlwe1.ptr);
+  hipError_t e;
+  // selectors
+  if ((e = launch_gadget_minus(d_addr, gneg, v, st)) != hipSuccess) return hip_fail(e, "G - C");
+  if ((e = launch_trgsw_to_ntt(ctx, d_addr, sel, v, st)) != hipSuccess) return hip_fail(e, "selector conversion");
+  if ((e = launch_trgsw_to_ntt(ctx, gneg, selneg, v, st)) != hipSuccess) return hip_fail(e, "selector conversion");
+  // read unit at the address: r_i -> src rows 1 + w + i
+  uint32_t* res = nullptr;
+  if ((e = run_trees(ctx, sel, v, 0, (int)v, d_ram, (1ull << v) * TRLWE_WORDS, 1, w, static_cast<uint32_t*>(ctx->mem_a.ptr),
+                     static_cast<uint32_t*>(ctx->mem_b.ptr), &res, st)) != hipSuccess)
+    return hip_fail(e, "read tree");
+  if ((e = launch_sample_extract(res, t1, w, 1, st)) != hipSuccess) return hip_fail(e, "sample extract");
+  if ((e = launch_keyswitch(ctx, nullptr, t1, nullptr, src + (1 + (size_t)w) * (LWE_N + 1), w, st)) != hipSuccess)
+    return hip_fail(e, "key switch");
+  // control unit: src = [f, x_0..x_{w-1}, r_0..r_{w-1}]; gates AND(f, x_i), ANDNOT(r_i, f)
+  if ((e = hipMemcpyAsync(src, d_flag, T0, hipMemcpyDeviceToDevice, st)) != hipSuccess) return hip_fail(e, "copy flag");
+  if ((e = hipMemcpyAsync(src + (LWE_N + 1), d_data, (size_t)w * T0, hipMemcpyDeviceToDevice, st)) != hipSuccess)
+    return hip_fail(e, "copy data");
+  std::vector<uint32_t> hidx(6 * (size_t)w);
+  std::vector<uint8_t> hops(2 * (size_t)w);
+  for (uint32_t i = 0; i < w; i++) {
+    hidx[i] = 0;                          hidx[2 * w + i] = 1 + i;          // AND(f, x_i)
+    hidx[w + i] = 1 + w + i;              hidx[3 * w + i] = 0;              // ANDNOT(r_i, f)
+    hops[i] = VSP_AND;                    hops[w + i] = VSP_ANDNOT;
+  }
+  if ((e = hipMemcpyAsync(idx, hidx.data(), hidx.size() * 4, hipMemcpyHostToDevice, st)) != hipSuccess)
+    return hip_fail(e, "upload indices");
+  if ((e = hipMemcpyAsync(ops, hops.data(), hops.size(), hipMemcpyHostToDevice, st)) != hipSuccess)
+    return hip_fail(e, "upload ops");
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "sync");  // host vectors go out of scope
+  if ((e = launch_gate_prologue(ctx, ops, src, src, idx, idx + 2 * w, nullptr, abar, nullptr, 2 * (uint64_t)w, st,
+                                false)) != hipSuccess)
+    return hip_fail(e, "control prologue");
+  if ((e = launch_blind_rotate(ctx, ops, abar, nullptr, acc2, 2 * (uint64_t)w, ctx->tune.br_waves, st)) != hipSuccess)
+    return hip_fail(e, "control bootstraps");
+  if ((e = launch_ram_control(acc2, u, (int)w, st)) != hipSuccess) return hip_fail(e, "control combine");
+  // write unit: bars, then refresh every cell with a bootstrap back to TRLWE, in place
+  if ((e = launch_ram_bars(ctx, sel, selneg, d_ram, u, t1, (int)v, (int)w, st)) != hipSuccess) return hip_fail(e, "write bars");
+  if ((e = launch_keyswitch(ctx, nullptr, t1, nullptr, t0, cells, st)) != hipSuccess) return hip_fail(e, "refresh key switch");
+  if ((e = launch_gate_prologue_uniform(ctx, OP_IDENT, t0, abar, cells, st)) != hipSuccess) return hip_fail(e, "refresh prologue");
+  if ((e = launch_blind_rotate(ctx, nullptr, abar, nullptr, d_ram, cells, ctx->tune.br_waves, st)) != hipSuccess)
+    return hip_fail(e, "refresh bootstraps");
+  return VSP_OK;
+}
+
+}  // extern "C"

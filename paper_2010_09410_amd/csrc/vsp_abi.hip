@@ -1,0 +1,306 @@
+// C ABI of libvsp: status codes, the context, batched / per-gate homomorphic gates,
+// TRLWE-output bootstrapping and the test entry points. CMUX memory, circuits and the
+// server have their own files.
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "vsp_internal.h"
+
+namespace vsp {
+
+static thread_local std::string g_last_error;
+
+vsp_status fail(vsp_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+vsp_status hip_fail(hipError_t e, const char* what) {
+  return fail(e == hipErrorOutOfMemory ? VSP_E_NOMEM : VSP_E_HIP,
+              std::string(what) + ": " + hipGetErrorString(e));
+}
+
+vsp_status check_device_range(const vsp_context* ctx, const void* p, size_t bytes, const char* name) {
+  if (p == nullptr) return fail(VSP_E_ARG, std::string(name) + " is NULL");
+  if (reinterpret_cast<uintptr_t>(p) & 3u) return fail(VSP_E_ARG, std::string(name) + " is not 4-byte aligned");
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(VSP_E_ARG, std::string(name) + " is not device memory");
+  }
+  if (attr.type != hipMemoryTypeDevice && !attr.isManaged)
+    return fail(VSP_E_ARG, std::string(name) + " is not device memory");
+  if (attr.device != ctx->device)
+    return fail(VSP_E_ARG, std::string(name) + " lives on another device");
+  hipDeviceptr_t base = nullptr;
+  size_t size = 0;
+  if (hipMemGetAddressRange(&base, &size, const_cast<void*>(p)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(VSP_E_ARG, std::string(name) + ": cannot query its allocation");
+  }
+  const char* b = static_cast<const char*>(base);
+  const char* q = static_cast<const char*>(p);
+  if (q < b || (size_t)(q - b) + bytes > size)
+    return fail(VSP_E_ARG, std::string(name) + " is smaller than the " + std::to_string(bytes) + " bytes needed");
+  return VSP_OK;
+}
+
+vsp_status check_no_overlap(const void* a, size_t abytes, const void* b, size_t bbytes, const char* what) {
+  const char* x = static_cast<const char*>(a);
+  const char* y = static_cast<const char*>(b);
+  if (x < y + bbytes && y < x + abytes) return fail(VSP_E_ARG, std::string(what) + " overlap");
+  return VSP_OK;
+}
+
+vsp_status scratch_reserve(vsp_context* ctx, Scratch& s, size_t bytes) {
+  if (s.bytes >= bytes) return VSP_OK;
+  if (s.ptr) {
+    VSP_HIP(hipDeviceSynchronize());
+    VSP_HIP(hipFree(s.ptr));
+    s.ptr = nullptr;
+    s.bytes = 0;
+  }
+  size_t want = bytes + bytes / 4;
+  VSP_HIP(hipMalloc(&s.ptr, want));
+  s.bytes = want;
+  return VSP_OK;
+}
+
+// ------------------------------------------------------------------ host twiddle tables
+static u64 h_mulmod(u64 a, u64 b) { return (u64)(((unsigned __int128)a * b) % GL_P); }
+static u64 h_powmod(u64 b, u64 e) {
+  u64 r = 1;
+  b %= GL_P;
+  while (e) {
+    if (e & 1) r = h_mulmod(r, b);
+    b = h_mulmod(b, b);
+    e >>= 1;
+  }
+  return r;
+}
+
+// psi: a primitive 2048th root of unity with psi^32 = 8 (so psi_u^32 = 8^{2u+1} = zeta_u).
+// 7 generates the multiplicative group mod p.
+static bool make_tables(std::vector<u64>& tw) {
+  const u64 psi0 = h_powmod(7, (GL_P - 1) / 2048);
+  if (h_powmod(psi0, 1024) != GL_P - 1) return false;
+  const u64 w = h_powmod(psi0, 32);
+  int m = -1;
+  for (int c = 0; c < 64; c++)
+    if (h_powmod(w, c) == 8) { m = c; break; }
+  if (m < 0) return false;
+  const u64 psi = h_powmod(psi0, m);
+  if (h_powmod(psi, 32) != 8 || h_powmod(psi, 1024) != GL_P - 1) return false;
+  tw.assign(2048, 0);
+  for (int j = 0; j < 32; j++)
+    for (int u = 0; u < 32; u++) {
+      const int e = ((2 * u + 1) * j) % 2048;
+      tw[j * 32 + u] = h_powmod(psi, e);
+      tw[1024 + j * 32 + u] = h_powmod(psi, (2048 - e) % 2048);
+    }
+  return true;
+}
+
+static vsp_status check_ctx(const vsp_context* ctx) {
+  if (ctx == nullptr) return fail(VSP_E_ARG, "context is NULL");
+  return VSP_OK;
+}
+
+}  // namespace vsp
+
+using namespace vsp;
+
+extern "C" {
+
+const char* vsp_status_str(vsp_status s) {
+  switch (s) {
+    case VSP_OK: return "ok";
+    case VSP_E_ARG: return "invalid argument";
+    case VSP_E_PARAMS: return "parameter set differs from the compiled one";
+    case VSP_E_NOMEM: return "device allocation failed";
+    case VSP_E_HIP: return "HIP runtime or kernel failure";
+    case VSP_E_STATE: return "object in the wrong state";
+    case VSP_E_CAPACITY: return "request exceeds the memory budget";
+    default: return "unknown status";
+  }
+}
+
+const char* vsp_last_error(void) { return g_last_error.c_str(); }
+
+vsp_status vsp_context_create(const vsp_params* params, const uint32_t* bk_host, const uint32_t* ksk_host, int device,
+                              vsp_context** out) {
+  if (out == nullptr) return fail(VSP_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (params == nullptr || bk_host == nullptr || ksk_host == nullptr)
+    return fail(VSP_E_ARG, "params, bk_host and ksk_host must not be NULL");
+  if (params->n != LWE_N || params->N != RING_N || params->k != 1 || params->l != GADGET_L ||
+      params->bg_bits != BG_BIT || params->ks_t != KS_T || params->ks_basebit != KS_BASEBIT)
+    return fail(VSP_E_PARAMS, "this build supports n=630 N=1024 k=1 l=3 bg_bits=6 ks_t=8 ks_basebit=2 only");
+  int ndev = 0;
+  VSP_HIP(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(VSP_E_ARG, "no such device");
+  VSP_HIP(hipSetDevice(device));
+  std::vector<u64> tw;
+  if (!make_tables(tw)) return fail(VSP_E_HIP, "twiddle table construction failed");
+
+  auto* ctx = new vsp_context();
+  ctx->device = device;
+  auto cleanup = [&](vsp_status s) {
+    vsp_context_destroy(ctx);
+    return s;
+  };
+  const size_t bk_words = (size_t)LWE_N * 2 * GADGET_L * 2 * RING_N;
+  const size_t ksk_rows = (size_t)RING_N * KS_T * 4;
+  hipError_t e;
+  if ((e = hipMalloc(&ctx->bkn, (size_t)LWE_N * TRGSW_NTT_U64 * 8)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc(bk)"));
+  if ((e = hipMalloc(&ctx->ksk, ksk_rows * (LWE_N + 1) * 4)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc(ksk)"));
+  if ((e = hipMalloc(&ctx->tw, tw.size() * 8)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc(tw)"));
+  if ((e = hipMalloc(&ctx->dev_err, 256)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc(err)"));
+  if ((e = hipMemcpy(ctx->tw, tw.data(), tw.size() * 8, hipMemcpyHostToDevice)) != hipSuccess)
+    return cleanup(hip_fail(e, "upload twiddles"));
+  if ((e = hipMemset(ctx->dev_err, 0, 256)) != hipSuccess) return cleanup(hip_fail(e, "clear flags"));
+
+  // Bootstrapping key: torus -> NTT domain on the device.
+  uint32_t* tmp = nullptr;
+  if ((e = hipMalloc(&tmp, bk_words * 4)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc(bk staging)"));
+  e = hipMemcpy(tmp, bk_host, bk_words * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = launch_trgsw_to_ntt(ctx, tmp, ctx->bkn, LWE_N, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  (void)hipFree(tmp);
+  if (e != hipSuccess) return cleanup(hip_fail(e, "bootstrapping-key conversion"));
+
+  // Key-switching key, with a zero row in front of the three digit rows of every (j, p).
+  std::vector<uint32_t> k4(ksk_rows * (LWE_N + 1), 0u);
+  for (size_t jp = 0; jp < (size_t)RING_N * KS_T; jp++)
+    for (int v = 1; v < 4; v++)
+      std::memcpy(&k4[(jp * 4 + v) * (LWE_N + 1)], &ksk_host[(jp * 3 + (v - 1)) * (LWE_N + 1)], (LWE_N + 1) * 4);
+  if ((e = hipMemcpy(ctx->ksk, k4.data(), k4.size() * 4, hipMemcpyHostToDevice)) != hipSuccess)
+    return cleanup(hip_fail(e, "upload ksk"));
+  *out = ctx;
+  return VSP_OK;
+}
+
+vsp_status vsp_context_destroy(vsp_context* ctx) {
+  if (ctx == nullptr) return VSP_OK;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  for (void* p : {(void*)ctx->bkn, (void*)ctx->ksk, (void*)ctx->tw, (void*)ctx->dev_err, ctx->abar.ptr, ctx->tlwe1.ptr,
+                  ctx->ntt_sel.ptr, ctx->mem_a.ptr, ctx->mem_b.ptr, ctx->mem_c.ptr, ctx->mem_d.ptr})
+    if (p) (void)hipFree(p);
+  delete ctx;
+  return VSP_OK;
+}
+
+vsp_status vsp_context_sync(vsp_context* ctx) {
+  vsp_status s = check_ctx(ctx);
+  if (s) return s;
+  VSP_HIP(hipSetDevice(ctx->device));
+  VSP_HIP(hipDeviceSynchronize());
+  int flags = 0;
+  VSP_HIP(hipMemcpy(&flags, ctx->dev_err, sizeof(int), hipMemcpyDeviceToHost));
+  if (flags) {
+    VSP_HIP(hipMemset(ctx->dev_err, 0, sizeof(int)));
+    if (flags & DEVERR_BAD_OP) return fail(VSP_E_ARG, "a gate had an invalid opcode (its output was zeroed)");
+  }
+  return VSP_OK;
+}
+
+static vsp_status gates_impl(vsp_context* ctx, const uint8_t* d_ops, const uint32_t* d_in0, const uint32_t* d_in1,
+                             uint32_t* d_out, uint64_t B, int mode, void* stream, bool trlwe_out) {
+  vsp_status s = check_ctx(ctx);
+  if (s) return s;
+  if (mode != VSP_BATCHED && mode != VSP_PER_GATE) return fail(VSP_E_ARG, "mode must be VSP_BATCHED or VSP_PER_GATE");
+  if (B == 0) return VSP_OK;
+  if (B > (1ull << 31)) return fail(VSP_E_ARG, "B too large");
+  VSP_HIP(hipSetDevice(ctx->device));
+  const size_t tl = (size_t)B * (LWE_N + 1) * 4;
+  const size_t ob = trlwe_out ? (size_t)B * 2 * RING_N * 4 : tl;
+  if ((s = check_device_range(ctx, d_ops, B, "d_ops"))) return s;
+  if ((s = check_device_range(ctx, d_in0, tl, "d_in0"))) return s;
+  if ((s = check_device_range(ctx, d_in1, tl, "d_in1"))) return s;
+  if ((s = check_device_range(ctx, d_out, ob, "d_out"))) return s;
+  if ((s = check_no_overlap(d_out, ob, d_in0, tl, "d_out and d_in0"))) return s;
+  if ((s = check_no_overlap(d_out, ob, d_in1, tl, "d_out and d_in1"))) return s;
+  if ((s = check_no_overlap(d_out, ob, d_ops, B, "d_out and d_ops"))) return s;
+  const uint64_t chunk = (mode == VSP_BATCHED) ? B : 1;
+  if ((s = scratch_reserve(ctx, ctx->abar, chunk * (LWE_N + 1) * 4))) return s;
+  if (!trlwe_out && (s = scratch_reserve(ctx, ctx->tlwe1, chunk * (RING_N + 1) * 4))) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  uint32_t* abar = static_cast<uint32_t*>(ctx->abar.ptr);
+  uint32_t* t1 = static_cast<uint32_t*>(ctx->tlwe1.ptr);
+  for (uint64_t g0 = 0; g0 < B; g0 += chunk) {
+    const uint64_t nb = (B - g0 < chunk) ? B - g0 : chunk;
+    const uint8_t* ops = d_ops + g0;
+    const uint32_t* i0 = d_in0 + g0 * (LWE_N + 1);
+    const uint32_t* i1 = d_in1 + g0 * (LWE_N + 1);
+    hipError_t e;
+    if (trlwe_out) {
+      uint32_t* o = d_out + g0 * 2 * RING_N;
+      // NOT / invalid opcodes are reported through the device flag; their TRLWE stays untouched.
+      if ((e = launch_gate_prologue(ctx, ops, i0, i1, nullptr, nullptr, nullptr, abar, nullptr, nb, st, false)) !=
+          hipSuccess)
+        return hip_fail(e, "gate prologue");
+      if ((e = launch_blind_rotate(ctx, ops, abar, nullptr, o, nb, ctx->tune.br_waves, st)) != hipSuccess)
+        return hip_fail(e, "blind rotation");
+    } else {
+      uint32_t* o = d_out + g0 * (LWE_N + 1);
+      if ((e = launch_gate_prologue(ctx, ops, i0, i1, nullptr, nullptr, nullptr, abar, o, nb, st)) != hipSuccess)
+        return hip_fail(e, "gate prologue");
+      if ((e = launch_blind_rotate(ctx, ops, abar, t1, nullptr, nb, ctx->tune.br_waves, st)) != hipSuccess)
+        return hip_fail(e, "blind rotation");
+      if ((e = launch_keyswitch(ctx, ops, t1, nullptr, o, nb, st)) != hipSuccess) return hip_fail(e, "key switch");
+    }
+  }
+  return VSP_OK;
+}
+
+vsp_status vsp_gates(vsp_context* ctx, const uint8_t* d_ops, const uint32_t* d_in0, const uint32_t* d_in1,
+                     uint32_t* d_out, uint64_t B, int mode, void* stream) {
+  return gates_impl(ctx, d_ops, d_in0, d_in1, d_out, B, mode, stream, false);
+}
+
+vsp_status vsp_bootstrap_trlwe(vsp_context* ctx, const uint8_t* d_ops, const uint32_t* d_in0, const uint32_t* d_in1,
+                               uint32_t* d_out, uint64_t B, void* stream) {
+  return gates_impl(ctx, d_ops, d_in0, d_in1, d_out, B, VSP_BATCHED, stream, true);
+}
+
+vsp_status vsp_debug_external_product(vsp_context* ctx, const uint32_t* d_trgsw, const uint32_t* d_x,
+                                      uint32_t* d_out, uint64_t J, void* stream) {
+  vsp_status s = check_ctx(ctx);
+  if (s) return s;
+  if (J == 0) return VSP_OK;
+  VSP_HIP(hipSetDevice(ctx->device));
+  const size_t cb = (size_t)J * 2 * GADGET_L * 2 * RING_N * 4, xb = (size_t)J * 2 * RING_N * 4;
+  if ((s = check_device_range(ctx, d_trgsw, cb, "d_trgsw"))) return s;
+  if ((s = check_device_range(ctx, d_x, xb, "d_x"))) return s;
+  if ((s = check_device_range(ctx, d_out, xb, "d_out"))) return s;
+  if ((s = check_no_overlap(d_out, xb, d_x, xb, "d_out and d_x"))) return s;
+  if ((s = check_no_overlap(d_out, xb, d_trgsw, cb, "d_out and d_trgsw"))) return s;
+  if ((s = scratch_reserve(ctx, ctx->ntt_sel, (size_t)J * TRGSW_NTT_U64 * 8))) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  uint64_t* cn = static_cast<uint64_t*>(ctx->ntt_sel.ptr);
+  hipError_t e;
+  if ((e = launch_trgsw_to_ntt(ctx, d_trgsw, cn, J, st)) != hipSuccess) return hip_fail(e, "trgsw conversion");
+  if ((e = launch_ext_product(ctx, cn, d_x, d_out, J, st)) != hipSuccess) return hip_fail(e, "external product");
+  return VSP_OK;
+}
+
+vsp_status vsp_debug_polymul(vsp_context* ctx, const int32_t* d_a, const uint32_t* d_b, uint32_t* d_out, uint64_t J,
+                             void* stream) {
+  vsp_status s = check_ctx(ctx);
+  if (s) return s;
+  if (J == 0) return VSP_OK;
+  VSP_HIP(hipSetDevice(ctx->device));
+  const size_t b = (size_t)J * RING_N * 4;
+  if ((s = check_device_range(ctx, d_a, b, "d_a"))) return s;
+  if ((s = check_device_range(ctx, d_b, b, "d_b"))) return s;
+  if ((s = check_device_range(ctx, d_out, b, "d_out"))) return s;
+  if ((s = check_no_overlap(d_out, b, d_a, b, "d_out and d_a"))) return s;
+  if ((s = check_no_overlap(d_out, b, d_b, b, "d_out and d_b"))) return s;
+  hipError_t e = launch_polymul(ctx, d_a, d_b, d_out, J, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "polymul");
+  return VSP_OK;
+}
+
+}  // extern "C"

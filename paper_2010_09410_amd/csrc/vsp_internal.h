@@ -1,0 +1,112 @@
+// Internal declarations of libvsp: the context object, device kernels' launchers, errors.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <mutex>
+#include <string>
+
+#include "../../include/vsp.h"
+#include "ntt.h"
+
+namespace vsp {
+
+// Internal opcode: bootstrap the first input unchanged (refresh of a noisy TLWE).
+constexpr uint8_t OP_IDENT = 16;
+
+__host__ __device__ inline bool op_bootstraps(uint32_t op) { return op < 8 || op == OP_IDENT; }
+
+// Device-side error flags (bits), read back by vsp_context_sync.
+constexpr int DEVERR_BAD_OP = 1;
+
+struct Tuning {
+  int br_waves = 4;      // waves (gates) per workgroup of the blind-rotation kernel (4 or 8)
+  int ks_gates = 1;      // gates per workgroup of the key-switch kernel
+};
+
+// Growable device scratch owned by a context.
+struct Scratch {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+
+struct vsp_context_impl;
+
+}  // namespace vsp
+
+struct vsp_context {
+  int device = 0;
+  uint64_t* bkn = nullptr;        // bootstrapping key, NTT domain: [n][TRGSW_NTT_U64]
+  uint32_t* ksk = nullptr;        // key-switching key [N][t][4][n+1]; digit value 0 points at a zero row
+  uint64_t* tw = nullptr;         // psi_u^j [32][32] then psi_u^-j [32][32]
+  int* dev_err = nullptr;         // device error flags
+  vsp::Scratch abar, tlwe1, ntt_sel, mem_a, mem_b, mem_c, mem_d;
+  vsp::Tuning tune;
+  std::mutex mu;                  // serialises scratch growth
+};
+
+namespace vsp {
+
+// Thread-local error text and status helpers.
+vsp_status fail(vsp_status s, const std::string& msg);
+vsp_status hip_fail(hipError_t e, const char* what);
+#define VSP_HIP(call)                                  \
+  do {                                                 \
+    hipError_t e_ = (call);                            \
+    if (e_ != hipSuccess) return vsp::hip_fail(e_, #call); \
+  } while (0)
+
+// Returns VSP_OK if [p, p + bytes) lies inside one device allocation on ctx's device.
+vsp_status check_device_range(const vsp_context* ctx, const void* p, size_t bytes, const char* name);
+vsp_status check_no_overlap(const void* a, size_t abytes, const void* b, size_t bbytes, const char* what);
+
+// Grows a scratch buffer to at least `bytes` (synchronising the device before freeing).
+vsp_status scratch_reserve(vsp_context* ctx, Scratch& s, size_t bytes);
+
+// ---------------------------------------------------------------- launchers (kernels.hip)
+// Torus TRGSW [count][2l][2][N] -> key layout [count][TRGSW_NTT_U64], scaled by 1/N.
+hipError_t launch_trgsw_to_ntt(const vsp_context* ctx, const uint32_t* src, uint64_t* dst, uint64_t count,
+                               hipStream_t st);
+// Gate linear combination + modulus switch (abar [B][n+1]); NOT / invalid ops write out directly.
+// idx0/idx1/idxo (optional) gather inputs and scatter outputs by wire id (stride n+1).
+// With allow_not false, NOT is reported as an invalid opcode (TRLWE-output bootstrapping).
+hipError_t launch_gate_prologue(const vsp_context* ctx, const uint8_t* ops, const uint32_t* in0, const uint32_t* in1,
+                                const uint32_t* idx0, const uint32_t* idx1, const uint32_t* idxo, uint32_t* abar,
+                                uint32_t* out, uint64_t B, hipStream_t st, bool allow_not = true);
+// The same opcode for every gate, one input (e.g. OP_IDENT for a refresh bootstrap).
+hipError_t launch_gate_prologue_uniform(const vsp_context* ctx, uint32_t op, const uint32_t* in0, uint32_t* abar,
+                                        uint64_t B, hipStream_t st);
+// Blind rotation of B gates (abar from the prologue). Writes SE_0 (TLWE1 [B][N+1]) and/or
+// the accumulator (TRLWE [B][2][N], optionally scattered by trlwe_idx).
+hipError_t launch_blind_rotate(const vsp_context* ctx, const uint8_t* ops, const uint32_t* abar, uint32_t* tlwe1,
+                               uint32_t* trlwe, uint64_t B, int waves, hipStream_t st);
+// Identity key switch TLWE1 [B][N+1] -> TLWE0 [B][n+1] (outputs scattered by idxo if given).
+hipError_t launch_keyswitch(const vsp_context* ctx, const uint8_t* ops, const uint32_t* tlwe1, const uint32_t* idxo,
+                            uint32_t* out, uint64_t B, hipStream_t st);
+// out[j] = C_j (ext) x_j, or with `x0` given: out[j] = x0_j + C_j (ext) (x_j - x0_j).
+hipError_t launch_ext_product(const vsp_context* ctx, const uint64_t* Cn, const uint32_t* x, uint32_t* out,
+                              uint64_t J, hipStream_t st);
+hipError_t launch_polymul(const vsp_context* ctx, const int32_t* a, const uint32_t* b, uint32_t* out, uint64_t J,
+                          hipStream_t st);
+
+// ---------------------------------------------------------------- CMUX memory (memory.hip)
+// One level of CMUX trees: for r < R, blk < nb, m < W/2:
+//   out[(r nb + blk) W/2 + m] = CMUX(sel[r * sel_r_stride + selbit], in[r s_r + blk s_b + 2m], in[.. + 2m + 1]).
+hipError_t launch_cmux_tree_level(const vsp_context* ctx, const uint64_t* sel, uint64_t sel_r_stride, int selbit,
+                                  const uint32_t* in, uint64_t s_r, uint64_t s_b, uint32_t* out, uint64_t R,
+                                  uint64_t nb, uint64_t W, hipStream_t st);
+// R <- CMUX(C_j, R, X^{-w 2^j} R) for j < rotbits, per read.
+hipError_t launch_rom_rotate(const vsp_context* ctx, const uint64_t* sel, uint64_t sel_r_stride, uint32_t* acc,
+                             uint64_t R, int rotbits, int w, hipStream_t st);
+// SampleExtract_h for h < W of each TRLWE: in [R][2][N] -> out [R][W][N+1].
+hipError_t launch_sample_extract(const uint32_t* in, uint32_t* out, uint64_t R, int W, hipStream_t st);
+// u_i = acc_and[i] + acc_andnot[i] + (0, mu X^0).
+hipError_t launch_ram_control(const uint32_t* acc2, uint32_t* u, int w, hipStream_t st);
+// Write bars: SE_0 of the chained CMUX per (bit i, address A) into tlwe1 [w 2^v][N+1].
+hipError_t launch_ram_bars(const vsp_context* ctx, const uint64_t* sel, const uint64_t* selneg, const uint32_t* ram,
+                           const uint32_t* u, uint32_t* tlwe1, int v, int w, hipStream_t st);
+// out = G - C for TRGSW [count][2l][2][N] (torus), the comparison with a constant 0 bit.
+hipError_t launch_gadget_minus(const uint32_t* C, uint32_t* out, uint64_t count, hipStream_t st);
+
+}  // namespace vsp

@@ -1,0 +1,183 @@
+"""torch-facing wrapper of libvsp: device buffers are torch tensors, streams are torch streams.
+
+Torus arrays live on the device as int32 tensors holding the uint32 bit patterns; the
+helpers below convert from and to numpy uint32. Every call goes through the C ABI in
+``_native``; nothing here computes on ciphertexts.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import _native as nv
+
+
+def to_device(arr, device) -> torch.Tensor:
+    a = np.ascontiguousarray(arr)
+    if a.dtype == np.uint32:
+        a = a.view(np.int32)
+    return torch.from_numpy(a).to(device)
+
+
+def to_host(t: torch.Tensor) -> np.ndarray:
+    a = t.detach().cpu().numpy()
+    return a.view(np.uint32) if a.dtype == np.int32 else a
+
+
+def _ptr(t: torch.Tensor) -> int:
+    assert t.is_contiguous(), "tensors passed to libvsp must be contiguous"
+    return t.data_ptr()
+
+
+class Context:
+    """A libvsp context on one GPU: keys resident in device memory (Bob's evaluation keys)."""
+
+    N_LWE, N_RING, L = 630, 1024, 3
+
+    def __init__(self, bk: np.ndarray, ksk: np.ndarray, device: int = 0):
+        self.device = torch.device("cuda", device)
+        torch.cuda.set_device(self.device)
+        self.handle = nv.vsp_context_create(np.ascontiguousarray(bk, dtype=np.uint32),
+                                            np.ascontiguousarray(ksk, dtype=np.uint32), device)
+
+    # -------------------------------------------------------------- lifecycle
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            nv.vsp_context_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def stream(self):
+        return torch.cuda.current_stream(self.device).cuda_stream
+
+    def sync(self) -> None:
+        nv.vsp_context_sync(self.handle)
+
+    def tensor(self, arr) -> torch.Tensor:
+        return to_device(arr, self.device)
+
+    def empty(self, *shape) -> torch.Tensor:
+        return torch.empty(shape, dtype=torch.int32, device=self.device)
+
+    # -------------------------------------------------------------- gates
+    def gates(self, ops: torch.Tensor, in0: torch.Tensor, in1: torch.Tensor, mode: int = nv.VSP_BATCHED,
+              out: torch.Tensor | None = None) -> torch.Tensor:
+        B = ops.numel()
+        if out is None:
+            out = self.empty(B, self.N_LWE + 1)
+        nv.vsp_gates(self.handle, _ptr(ops), _ptr(in0), _ptr(in1), _ptr(out), B, mode, self.stream())
+        return out
+
+    def bootstrap_trlwe(self, ops, in0, in1, out=None) -> torch.Tensor:
+        B = ops.numel()
+        if out is None:
+            out = self.empty(B, 2, self.N_RING)
+        nv.vsp_bootstrap_trlwe(self.handle, _ptr(ops), _ptr(in0), _ptr(in1), _ptr(out), B, self.stream())
+        return out
+
+    # -------------------------------------------------------------- CMUX memory
+    def rom_read(self, rom: torch.Tensor, addr: torch.Tensor, v: int, w: int, out=None) -> torch.Tensor:
+        R = addr.shape[0]
+        if out is None:
+            out = self.empty(R, w, self.N_LWE + 1)
+        nv.vsp_rom_read(self.handle, _ptr(rom), rom.shape[0], _ptr(addr), v, w, _ptr(out), R, self.stream())
+        return out
+
+    def ram_read(self, ram: torch.Tensor, addr: torch.Tensor, out=None) -> torch.Tensor:
+        w, cells = ram.shape[0], ram.shape[1]
+        v = int(cells).bit_length() - 1
+        R = addr.shape[0]
+        if out is None:
+            out = self.empty(R, w, self.N_LWE + 1)
+        nv.vsp_ram_read(self.handle, _ptr(ram), v, w, _ptr(addr), _ptr(out), R, self.stream())
+        return out
+
+    def ram_write(self, ram: torch.Tensor, addr: torch.Tensor, flag: torch.Tensor, data: torch.Tensor) -> None:
+        w, cells = ram.shape[0], ram.shape[1]
+        v = int(cells).bit_length() - 1
+        nv.vsp_ram_write(self.handle, _ptr(ram), v, w, _ptr(addr), _ptr(flag), _ptr(data), self.stream())
+
+    # -------------------------------------------------------------- circuits / serving
+    def circuit(self, gates, ninputs: int) -> "Circuit":
+        return Circuit(self, gates, ninputs)
+
+    def server(self, mem_budget_bytes: int, max_batch: int = 4096) -> "Server":
+        return Server(self, mem_budget_bytes, max_batch)
+
+    # -------------------------------------------------------------- test entries
+    def debug_external_product(self, C: torch.Tensor, x: torch.Tensor, out=None) -> torch.Tensor:
+        J = C.shape[0]
+        if out is None:
+            out = self.empty(J, 2, self.N_RING)
+        nv.vsp_debug_external_product(self.handle, _ptr(C), _ptr(x), _ptr(out), J, self.stream())
+        return out
+
+    def debug_polymul(self, a: torch.Tensor, b: torch.Tensor, out=None) -> torch.Tensor:
+        J = a.shape[0]
+        if out is None:
+            out = self.empty(J, self.N_RING)
+        nv.vsp_debug_polymul(self.handle, _ptr(a), _ptr(b), _ptr(out), J, self.stream())
+        return out
+
+
+class Circuit:
+    """A levelled circuit captured for replay (HIP graph of one batched launch per level)."""
+
+    def __init__(self, ctx: Context, gates, ninputs: int):
+        self.ctx = ctx
+        self.gates = np.asarray(gates, dtype=np.int64)
+        self.ninputs = int(ninputs)
+        self.handle = nv.vsp_circuit_create(ctx.handle, self.gates, self.ninputs)
+        self.nlevels, self.max_width = nv.vsp_circuit_info(self.handle)
+
+    @property
+    def nwires(self) -> int:
+        return self.ninputs + len(self.gates)
+
+    def run(self, inputs: torch.Tensor, wires: torch.Tensor | None = None) -> torch.Tensor:
+        if wires is None:
+            wires = self.ctx.empty(self.nwires, self.ctx.N_LWE + 1)
+        nv.vsp_circuit_run(self.handle, _ptr(inputs), _ptr(wires), self.ctx.stream())
+        return wires
+
+    def run_timed(self, inputs: torch.Tensor, wires: torch.Tensor | None = None):
+        if wires is None:
+            wires = self.ctx.empty(self.nwires, self.ctx.N_LWE + 1)
+        ms = nv.vsp_circuit_run_timed(self.handle, _ptr(inputs), _ptr(wires), self.ctx.stream(), self.nlevels)
+        return wires, ms
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            nv.vsp_circuit_destroy(self.handle)
+            self.handle = None
+
+
+class Server:
+    """Continuous-batching evaluation of many clients' circuits on one context."""
+
+    def __init__(self, ctx: Context, mem_budget_bytes: int, max_batch: int):
+        self.ctx = ctx
+        self.handle = nv.vsp_server_create(ctx.handle, int(mem_budget_bytes), int(max_batch))
+
+    def submit(self, gates, ninputs: int, inputs: np.ndarray) -> int:
+        return nv.vsp_server_submit(self.handle, np.asarray(gates, dtype=np.int64), int(ninputs),
+                                    np.ascontiguousarray(inputs, dtype=np.uint32))
+
+    def poll(self, ticket: int, nwires: int | None = None):
+        """Returns (done, wires or None, latency_ms)."""
+        buf = None if nwires is None else np.zeros((nwires, self.ctx.N_LWE + 1), dtype=np.uint32)
+        done, lat = nv.vsp_server_poll(self.handle, ticket, buf)
+        return done, (buf if done else None), lat
+
+    def stats(self):
+        return nv.vsp_server_stats(self.handle)
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            nv.vsp_server_destroy(self.handle)
+            self.handle = None

@@ -25,5 +25,20 @@ def keys():
     return dict(s0=s0, s1=s1, bk=bk, ksk=ksk, bkd=bkd, kskd=kskd)
 
 
+@pytest.fixture(scope="session")
+def gpu(keys):
+    """A libvsp context on cuda:0 built from the library client's keys (which equal the
+    oracle's, see test_client.py). Skips only where no GPU exists."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU on this machine")
+    from paper_2010_09410_amd import client
+    from paper_2010_09410_amd.device import Context
+    bk, ksk = client.keyset(keys["s0"], keys["s1"], keys["bkd"], keys["kskd"])
+    ctx = Context(bk, ksk, device=0)
+    yield ctx
+    ctx.close()
+
+
 def signed(x):
     return np.asarray(x, dtype=np.uint32).view(np.int32).astype(np.int64)
