@@ -1,0 +1,170 @@
+"""Benchmark: gate bootstraps per second on one MI355X, batched vs per-gate, with the
+per-level latency of a layered circuit.
+
+A step is one batched homomorphic-gate pass (gate linear combination, modulus switch,
+blind rotation by 630 CMUX external products, SampleExtract, identity key switch) over a
+batch of 4096 independent random gates (NAND/AND/OR/XOR/XNOR, uniform) on fresh TLWE
+ciphertexts with the 80-bit parameter set (n = 630, N = 1024, l = 3, Bg = 64, t = 8, base 4).
+Keys and inputs are synthetic (seeded) and resident in HBM before the timed region.
+
+Prints one JSON line (rank 0). Extra fields: the per-gate rate (one launch sequence per
+gate), the batched / per-gate ratio, per-level p50/p99 latency of the 64-level circuit,
+the roofline of the blind-rotation kernel and the CPU oracle baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+B_GATES = 4096
+N_LWE, N_RING, GL, STEPS_BR = 630, 1024, 3, 630
+
+# ---------------------------------------------------------------- work model
+# 32-bit VALU lane-operations of the modular arithmetic per blind-rotation step, from the
+# operation counts of the transform and the instruction counts of the compiled routines
+# (gfx950 ISA): add mod p 7, sub mod p 10, general multiply mod p 23, power-of-two multiply
+# 11 on average (7..15), gadget digit 6, exact lift 7.
+C_ADD, C_SUB, C_MUL, C_POW2, C_DIGIT, C_LIFT = 7, 10, 23, 11, 6, 7
+
+
+def br_step_lane_ops() -> int:
+    lanes = 32                                   # lanes per transform
+    bfly_nontriv = 80 + 49                       # pass 1 + cyclic DFT32, per lane
+    bfly_triv = 31                               # DFT32 butterflies with twiddle 1
+    per_ntt = lanes * (bfly_nontriv * (C_POW2 + C_ADD + C_SUB) + bfly_triv * (C_ADD + C_SUB) + 31 * C_MUL)
+    ntts = 2 * GL + 2                            # 6 forward (digits) + 2 inverse per step
+    mac = 2 * GL * N_RING * 2 * C_MUL + GL * 64 * 32 * 2 * C_ADD
+    digits = GL * 2 * N_RING * C_DIGIT
+    rot_lift = 2 * N_RING * (5 + C_LIFT + 1)
+    return ntts * per_ntt + mac + digits + rot_lift
+
+
+LANE_OPS_PER_GATE = STEPS_BR * br_step_lane_ops()
+PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9            # CUs x SIMDs x lanes/clk x clock: 39.3 T/s
+BK_NTT_BYTES = N_LWE * 2 * GL * 2 * N_RING * 8  # key stream read by every gate (61.93 MB)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--per-gate", type=int, default=8, help="gates timed in per-gate mode")
+    ap.add_argument("--no-circuit", action="store_true", help="skip the per-level circuit latency")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-gates", type=int, default=0, help="oracle sample size (default 4 x cores)")
+    return ap.parse_args()
+
+
+def cpu_baseline(s0, s1, bkd, kskd, cfg, in0, in1, ngates):
+    """The CPU oracle (test infrastructure) on this host's cores, on a bounded sample."""
+    import oracle
+    threads = max(1, len(os.sched_getaffinity(0)))
+    ngates = ngates or 4 * threads
+    bk, ksk = oracle.keyset(s0, s1, bkd, kskd)
+    t0 = time.perf_counter()
+    oracle.gates(bk, ksk, cfg["ops"][:ngates], in0[:ngates], in1[:ngates], threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": ngates / dt, "unit": "gate bootstraps/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {ngates} gates of the 4096-gate batch, {threads} threads, {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is a "
+              "design note, not a measured path.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import workloads as W
+    from paper_2010_09410_amd import VSP_PER_GATE, client
+    from paper_2010_09410_amd import _native as nv
+    from paper_2010_09410_amd.device import Context
+
+    s0, s1 = W.secret_keys()
+    bkd, kskd = W.bk_draws(), W.ksk_draws()
+    bk, ksk = client.keyset(s0, s1, bkd, kskd)
+    cfg = W.config2(B_GATES)
+    in0 = client.tlwe_encrypt_bits(s0, cfg["bits0"], *cfg["enc0"])
+    in1 = client.tlwe_encrypt_bits(s0, cfg["bits1"], *cfg["enc1"])
+    ctx = Context(bk, ksk, device=0)
+    ops_d, a_d, b_d = ctx.tensor(cfg["ops"]), ctx.tensor(in0), ctx.tensor(in1)
+    out = ctx.empty(B_GATES, N_LWE + 1)
+
+    for _ in range(args.warmup):
+        ctx.gates(ops_d, a_d, b_d, out=out)
+    ctx.sync()
+    nv.vsp_profile_enable(ctx.handle, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.gates(ops_d, a_d, b_d, out=out)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    br_ms, br_n = nv.vsp_profile_read(ctx.handle, 0)
+    ks_ms, ks_n = nv.vsp_profile_read(ctx.handle, 1)
+    nv.vsp_profile_enable(ctx.handle, False)
+    ctx.sync()
+    ms_per_step = dt * 1e3 / args.steps
+    value = B_GATES * args.steps / dt
+
+    # per-gate mode: one launch sequence per gate
+    pg = max(1, args.per_gate)
+    ctx.gates(ops_d[:1], a_d[:1], b_d[:1], mode=VSP_PER_GATE)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.gates(ops_d[:pg], a_d[:pg], b_d[:pg], mode=VSP_PER_GATE)
+    torch.cuda.synchronize()
+    per_gate = pg / (time.perf_counter() - t0)
+
+    # per-level latency of the 64-level circuit (eager levels timed with events)
+    levels = None
+    if not args.no_circuit and hasattr(nv.lib(), "vsp_circuit_create"):
+        c3 = W.config3()
+        cin = client.tlwe_encrypt_bits(s0, c3["bits"], *c3["enc"])
+        circ = ctx.circuit(c3["gates"], c3["ninputs"])
+        _, lv_ms = circ.run_timed(ctx.tensor(cin))
+        lv = np.array(lv_ms)
+        levels = {"levels": int(lv.size), "gates": int(len(c3["gates"])),
+                  "p50_ms": float(np.percentile(lv, 50)), "p99_ms": float(np.percentile(lv, 99)),
+                  "circuit_ms": float(lv.sum()), "gates_per_s": float(len(c3["gates"]) / (lv.sum() / 1e3))}
+        circ.close()
+
+    br_avg_ms = br_ms / max(br_n, 1)
+    achieved = B_GATES * LANE_OPS_PER_GATE / (br_avg_ms * 1e-3) / 1e12
+    roof = {"bound": "alu", "kernel": "k_blind_rotate", "achieved": round(achieved, 3),
+            "peak": round(PEAK_LANE_OPS / 1e12, 3), "unit": "T int32 lane-ops/s",
+            "frac": round(achieved * 1e12 / PEAK_LANE_OPS, 4), "traffic": None,
+            "avg_launch_ms": round(br_avg_ms, 3), "lane_ops_per_gate": LANE_OPS_PER_GATE,
+            "key_stream_GBps_requested": round(B_GATES * BK_NTT_BYTES / (br_avg_ms * 1e-3) / 1e9, 1),
+            "keyswitch_avg_ms": round(ks_ms / max(ks_n, 1), 3)}
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(s0, s1, bkd, kskd, cfg, in0, in1, args.cpu_gates)
+    ctx.close()
+
+    line = {
+        "metric": "gate bootstraps/sec on 1 MI355X, batched vs per-gate; p50/p99 per-level latency",
+        "value": round(value, 1), "unit": "gate bootstraps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "4096 independent random gates (NAND/AND/OR/XOR/XNOR) on fresh TLWE, "
+                               "n=630 N=1024 l=3 Bg=64 ks t=8 base=4, one batched launch",
+                   "batch": B_GATES, "parallelism": "single GPU"},
+        "per_gate_value": round(per_gate, 2), "batched_over_per_gate": round(value / per_gate, 1),
+        "per_level": levels, "roofline": roof, "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -182,6 +182,15 @@ vsp_status vsp_server_stats(vsp_server* s, uint64_t* gates, uint64_t* batches, u
 /* Stop the server thread (finishing admitted work) and free it. NULL is accepted. */
 vsp_status vsp_server_destroy(vsp_server* s);
 
+/* Kernel-time instrumentation (for benchmarks): while enabled, every eager launch of the
+ * blind-rotation, key-switch and gate-prologue kernels made by this context is bracketed by
+ * HIP events on the stream it runs on. Enabling resets the totals. */
+vsp_status vsp_profile_enable(vsp_context* ctx, int on);
+
+/* Device time (ms, summed) and number of launches of kernel `which` since enabling:
+ * 0 = blind rotation, 1 = key switch, 2 = gate prologue. Synchronises the device. */
+vsp_status vsp_profile_read(vsp_context* ctx, int which, double* total_ms, uint64_t* launches);
+
 /* Test entry: d_out[j] = C_j (ext) x_j for J (TRGSW, TRLWE) pairs, the external product
  * at the heart of CMUX (Sec. 2.1.2 "CMUX"). d_trgsw [J][2l][2][N], d_x and d_out [J][2][N]. */
 vsp_status vsp_debug_external_product(vsp_context* ctx, const uint32_t* d_trgsw, const uint32_t* d_x,

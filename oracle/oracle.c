@@ -476,22 +476,28 @@ void or_ram_read(const or_params *P, const uint32_t *ksk, const uint32_t *ram, i
 
 /* RAM control unit (Sec. 8.2): multiplex write data x_i and read data r_i by the write flag f
  * with a HomMUX without SE and IKS: u_i = BR(AND(f, x_i)) + BR(ANDNOT(r_i, f)) + (0, mu X^0).
- * u is [w][2][N]. */
-void or_ram_control(const or_params *P, const uint32_t *bk, const uint32_t *flag, const uint32_t *data,
-                    const uint32_t *rd, int w, uint32_t *u) {
-  const int n = P->n, N = P->N;
+ * u is [w][2][N]. The w bits are independent and run on `threads` threads. */
+typedef struct { const or_params *P; const uint32_t *bk, *flag, *data, *rd; uint32_t *u; } ctl_ctx;
+
+static void ctl_one(void *p, int64_t i) {
+  ctl_ctx *c = p;
+  const int n = c->P->n, N = c->P->N;
   uint32_t *lin = xmalloc(sizeof(uint32_t) * (n + 1));
   uint32_t *acc = xmalloc(sizeof(uint32_t) * 2 * N);
-  for (int i = 0; i < w; i++) {
-    uint32_t *ui = u + (size_t)i * 2 * N;
-    or_gate_linear(n, OR_AND, flag, data + (size_t)i * (n + 1), lin);
-    or_bootstrap_to_trlwe(P, bk, lin, ui);
-    or_gate_linear(n, OR_ANDNOT, rd + (size_t)i * (n + 1), flag, lin);
-    or_bootstrap_to_trlwe(P, bk, lin, acc);
-    for (int j = 0; j < 2 * N; j++) ui[j] += acc[j];
-    ui[N] += MU;
-  }
+  uint32_t *ui = c->u + (size_t)i * 2 * N;
+  or_gate_linear(n, OR_AND, c->flag, c->data + (size_t)i * (n + 1), lin);
+  or_bootstrap_to_trlwe(c->P, c->bk, lin, ui);
+  or_gate_linear(n, OR_ANDNOT, c->rd + (size_t)i * (n + 1), c->flag, lin);
+  or_bootstrap_to_trlwe(c->P, c->bk, lin, acc);
+  for (int j = 0; j < 2 * N; j++) ui[j] += acc[j];
+  ui[N] += MU;
   free(lin); free(acc);
+}
+
+void or_ram_control(const or_params *P, const uint32_t *bk, const uint32_t *flag, const uint32_t *data,
+                    const uint32_t *rd, int w, uint32_t *u) {
+  ctl_ctx c = {P, bk, flag, data, rd, u};
+  parallel_for(w, w, ctl_one, &c);
 }
 
 /* Selector of write-bar bit d for constant address bit c: C_d if c = 1, G - C_d if c = 0

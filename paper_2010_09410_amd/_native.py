@@ -62,6 +62,8 @@ SIGNATURES = {
     "vsp_server_poll": (_st, [_vp, _u64, _vp, ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_double)]),
     "vsp_server_stats": (_st, [_vp, ctypes.POINTER(_u64), ctypes.POINTER(_u64), ctypes.POINTER(_u64)]),
     "vsp_server_destroy": (_st, [_vp]),
+    "vsp_profile_enable": (_st, [_vp, _i32]),
+    "vsp_profile_read": (_st, [_vp, _i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_u64)]),
     "vsp_debug_external_product": (_st, [_vp, _vp, _vp, _vp, _u64, _vp]),
     "vsp_debug_polymul": (_st, [_vp, _vp, _vp, _vp, _u64, _vp]),
 }
@@ -195,6 +197,18 @@ def vsp_server_stats(srv):
 
 def vsp_server_destroy(srv) -> None:
     _call("vsp_server_destroy", srv)
+
+
+def vsp_profile_enable(ctx, on: bool) -> None:
+    _call("vsp_profile_enable", ctx, 1 if on else 0)
+
+
+def vsp_profile_read(ctx, which: int):
+    """(total_ms, launches) of kernel class which: 0 blind rotation, 1 key switch, 2 prologue."""
+    ms = ctypes.c_double()
+    cnt = _u64()
+    _call("vsp_profile_read", ctx, which, ctypes.byref(ms), ctypes.byref(cnt))
+    return ms.value, cnt.value
 
 
 def vsp_debug_external_product(ctx, d_trgsw, d_x, d_out, J, stream=None) -> None:

@@ -168,14 +168,14 @@ __global__ __launch_bounds__(WAVES * 64) void k_blind_rotate(const u64* __restri
   }
 }
 
-template <int WAVES>
-static void set_br_lds() {
-  static bool done = false;
-  if (!done) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_blind_rotate<WAVES>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (2048 + WAVES * WAVE_LDS_U64) * 8);
-    done = true;
-  }
+// Raises the dynamic-LDS limit of the kernels that use more than 64 KiB (once, at context
+// creation, outside any stream capture).
+hipError_t init_kernel_attributes() {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_blind_rotate<4>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (2048 + 4 * WAVE_LDS_U64) * 8);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_blind_rotate<8>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (2048 + 8 * WAVE_LDS_U64) * 8);
 }
 
 hipError_t launch_blind_rotate(const vsp_context* ctx, const uint8_t* ops, const uint32_t* abar, uint32_t* tlwe1,
@@ -183,14 +183,12 @@ hipError_t launch_blind_rotate(const vsp_context* ctx, const uint8_t* ops, const
   if (B == 0) return hipSuccess;
   switch (waves) {
     case 4: {
-      set_br_lds<4>();
       const size_t lds = (2048 + 4 * WAVE_LDS_U64) * 8;
       hipLaunchKernelGGL(k_blind_rotate<4>, dim3((unsigned)((B + 3) / 4)), dim3(256), lds, st, ctx->bkn, ctx->tw,
                          ops, abar, tlwe1, trlwe, B);
       break;
     }
     default: {
-      set_br_lds<8>();
       const size_t lds = (2048 + 8 * WAVE_LDS_U64) * 8;
       hipLaunchKernelGGL(k_blind_rotate<8>, dim3((unsigned)((B + 7) / 8)), dim3(512), lds, st, ctx->bkn, ctx->tw,
                          ops, abar, tlwe1, trlwe, B);

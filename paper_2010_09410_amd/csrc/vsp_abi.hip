@@ -67,6 +67,32 @@ vsp_status scratch_reserve(vsp_context* ctx, Scratch& s, size_t bytes) {
   return VSP_OK;
 }
 
+ProfScope::ProfScope(vsp_context* c, int w, hipStream_t s) : ctx(c), which(w), st(s) {
+  if (!ctx->prof.on) return;
+  hipEvent_t e0;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    (void)hipGetLastError();
+    e1 = nullptr;
+    return;
+  }
+  (void)hipEventRecord(e0, st);
+  ctx->prof.ev[which].push_back({e0, e1});
+}
+
+ProfScope::~ProfScope() {
+  if (e1) (void)hipEventRecord(e1, st);
+}
+
+static void profile_clear(vsp_context* ctx) {
+  for (auto& v : ctx->prof.ev) {
+    for (auto& p : v) {
+      (void)hipEventDestroy(p.first);
+      (void)hipEventDestroy(p.second);
+    }
+    v.clear();
+  }
+}
+
 // ------------------------------------------------------------------ host twiddle tables
 static u64 h_mulmod(u64 a, u64 b) { return (u64)(((unsigned __int128)a * b) % GL_P); }
 static u64 h_powmod(u64 b, u64 e) {
@@ -141,6 +167,7 @@ vsp_status vsp_context_create(const vsp_params* params, const uint32_t* bk_host,
   VSP_HIP(hipGetDeviceCount(&ndev));
   if (device < 0 || device >= ndev) return fail(VSP_E_ARG, "no such device");
   VSP_HIP(hipSetDevice(device));
+  VSP_HIP(init_kernel_attributes());
   std::vector<u64> tw;
   if (!make_tables(tw)) return fail(VSP_E_HIP, "twiddle table construction failed");
 
@@ -185,6 +212,7 @@ vsp_status vsp_context_destroy(vsp_context* ctx) {
   if (ctx == nullptr) return VSP_OK;
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
+  profile_clear(ctx);
   for (void* p : {(void*)ctx->bkn, (void*)ctx->ksk, (void*)ctx->tw, (void*)ctx->dev_err, ctx->abar.ptr, ctx->tlwe1.ptr,
                   ctx->ntt_sel.ptr, ctx->mem_a.ptr, ctx->mem_b.ptr, ctx->mem_c.ptr, ctx->mem_d.ptr})
     if (p) (void)hipFree(p);
@@ -238,18 +266,33 @@ static vsp_status gates_impl(vsp_context* ctx, const uint8_t* d_ops, const uint3
     if (trlwe_out) {
       uint32_t* o = d_out + g0 * 2 * RING_N;
       // NOT / invalid opcodes are reported through the device flag; their TRLWE stays untouched.
-      if ((e = launch_gate_prologue(ctx, ops, i0, i1, nullptr, nullptr, nullptr, abar, nullptr, nb, st, false)) !=
-          hipSuccess)
-        return hip_fail(e, "gate prologue");
-      if ((e = launch_blind_rotate(ctx, ops, abar, nullptr, o, nb, ctx->tune.br_waves, st)) != hipSuccess)
-        return hip_fail(e, "blind rotation");
+      {
+        ProfScope ps(ctx, 2, st);
+        e = launch_gate_prologue(ctx, ops, i0, i1, nullptr, nullptr, nullptr, abar, nullptr, nb, st, false);
+      }
+      if (e != hipSuccess) return hip_fail(e, "gate prologue");
+      {
+        ProfScope ps(ctx, 0, st);
+        e = launch_blind_rotate(ctx, ops, abar, nullptr, o, nb, ctx->tune.br_waves, st);
+      }
+      if (e != hipSuccess) return hip_fail(e, "blind rotation");
     } else {
       uint32_t* o = d_out + g0 * (LWE_N + 1);
-      if ((e = launch_gate_prologue(ctx, ops, i0, i1, nullptr, nullptr, nullptr, abar, o, nb, st)) != hipSuccess)
-        return hip_fail(e, "gate prologue");
-      if ((e = launch_blind_rotate(ctx, ops, abar, t1, nullptr, nb, ctx->tune.br_waves, st)) != hipSuccess)
-        return hip_fail(e, "blind rotation");
-      if ((e = launch_keyswitch(ctx, ops, t1, nullptr, o, nb, st)) != hipSuccess) return hip_fail(e, "key switch");
+      {
+        ProfScope ps(ctx, 2, st);
+        e = launch_gate_prologue(ctx, ops, i0, i1, nullptr, nullptr, nullptr, abar, o, nb, st);
+      }
+      if (e != hipSuccess) return hip_fail(e, "gate prologue");
+      {
+        ProfScope ps(ctx, 0, st);
+        e = launch_blind_rotate(ctx, ops, abar, t1, nullptr, nb, ctx->tune.br_waves, st);
+      }
+      if (e != hipSuccess) return hip_fail(e, "blind rotation");
+      {
+        ProfScope ps(ctx, 1, st);
+        e = launch_keyswitch(ctx, ops, t1, nullptr, o, nb, st);
+      }
+      if (e != hipSuccess) return hip_fail(e, "key switch");
     }
   }
   return VSP_OK;
@@ -263,6 +306,34 @@ vsp_status vsp_gates(vsp_context* ctx, const uint8_t* d_ops, const uint32_t* d_i
 vsp_status vsp_bootstrap_trlwe(vsp_context* ctx, const uint8_t* d_ops, const uint32_t* d_in0, const uint32_t* d_in1,
                                uint32_t* d_out, uint64_t B, void* stream) {
   return gates_impl(ctx, d_ops, d_in0, d_in1, d_out, B, VSP_BATCHED, stream, true);
+}
+
+vsp_status vsp_profile_enable(vsp_context* ctx, int on) {
+  vsp_status s = check_ctx(ctx);
+  if (s) return s;
+  VSP_HIP(hipSetDevice(ctx->device));
+  VSP_HIP(hipDeviceSynchronize());
+  profile_clear(ctx);
+  ctx->prof.on = on != 0;
+  return VSP_OK;
+}
+
+vsp_status vsp_profile_read(vsp_context* ctx, int which, double* total_ms, uint64_t* launches) {
+  vsp_status s = check_ctx(ctx);
+  if (s) return s;
+  if (which < 0 || which > 2 || total_ms == nullptr || launches == nullptr)
+    return fail(VSP_E_ARG, "which must be 0, 1 or 2 and the outputs non-NULL");
+  VSP_HIP(hipSetDevice(ctx->device));
+  VSP_HIP(hipDeviceSynchronize());
+  double t = 0;
+  for (auto& p : ctx->prof.ev[which]) {
+    float ms = 0;
+    VSP_HIP(hipEventElapsedTime(&ms, p.first, p.second));
+    t += ms;
+  }
+  *total_ms = t;
+  *launches = ctx->prof.ev[which].size();
+  return VSP_OK;
 }
 
 vsp_status vsp_debug_external_product(vsp_context* ctx, const uint32_t* d_trgsw, const uint32_t* d_x,

@@ -6,6 +6,8 @@
 #include <cstdint>
 #include <mutex>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "../../include/vsp.h"
 #include "ntt.h"
@@ -31,7 +33,12 @@ struct Scratch {
   size_t bytes = 0;
 };
 
-struct vsp_context_impl;
+// Event pairs bracketing instrumented launches (kernel classes: blind rotation, key switch,
+// prologue).
+struct Profile {
+  bool on = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[3];
+};
 
 }  // namespace vsp
 
@@ -43,6 +50,7 @@ struct vsp_context {
   int* dev_err = nullptr;         // device error flags
   vsp::Scratch abar, tlwe1, ntt_sel, mem_a, mem_b, mem_c, mem_d;
   vsp::Tuning tune;
+  vsp::Profile prof;
   std::mutex mu;                  // serialises scratch growth
 };
 
@@ -64,7 +72,18 @@ vsp_status check_no_overlap(const void* a, size_t abytes, const void* b, size_t 
 // Grows a scratch buffer to at least `bytes` (synchronising the device before freeing).
 vsp_status scratch_reserve(vsp_context* ctx, Scratch& s, size_t bytes);
 
+// Records an event pair around one launch of kernel class `which` when profiling is on.
+struct ProfScope {
+  vsp_context* ctx;
+  int which;
+  hipStream_t st;
+  hipEvent_t e1 = nullptr;
+  ProfScope(vsp_context* c, int w, hipStream_t s);
+  ~ProfScope();
+};
+
 // ---------------------------------------------------------------- launchers (kernels.hip)
+hipError_t init_kernel_attributes();
 // Torus TRGSW [count][2l][2][N] -> key layout [count][TRGSW_NTT_U64], scaled by 1/N.
 hipError_t launch_trgsw_to_ntt(const vsp_context* ctx, const uint32_t* src, uint64_t* dst, uint64_t count,
                                hipStream_t st);

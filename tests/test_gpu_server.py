@@ -1,0 +1,91 @@
+"""The continuous-batching server: results are bit-identical alone and in the mix (and equal
+to the circuit executor's), admission respects the memory budget, oversize requests are
+refused, and malformed circuits are rejected at submission."""
+import time
+
+import numpy as np
+import pytest
+
+import workloads as W
+from paper_2010_09410_amd import VspError, client
+from paper_2010_09410_amd import _native as nv
+from paper_2010_09410_amd.device import to_host
+
+pytestmark = pytest.mark.gpu
+ROWB = 631 * 4
+
+
+def wait(srv, ticket, nwires, timeout=120.0):
+    t0 = time.time()
+    while time.time() - t0 < timeout:
+        done, wires, lat = srv.poll(ticket, nwires)
+        if done:
+            return wires, lat
+        time.sleep(0.005)
+    raise TimeoutError(f"ticket {ticket} not done after {timeout} s")
+
+
+def requests(keys, count, seed):
+    out = []
+    for k in range(count):
+        c = W.small_circuit(seed=seed + k, levels=2 + k % 4, wmin=2, wmax=12 + 6 * k, ninputs=8 + k)
+        inputs = client.tlwe_encrypt_bits(keys["s0"], c["bits"], *c["enc"])
+        out.append((c, inputs))
+    return out
+
+
+def test_alone_equals_mixed_equals_circuit(gpu, keys):
+    reqs = requests(keys, 6, 800)
+    # alone: one request at a time on a fresh server
+    alone = []
+    srv = gpu.server(mem_budget_bytes=64 << 20, max_batch=256)
+    for c, inputs in reqs:
+        t = srv.submit(c["gates"], c["ninputs"], inputs)
+        alone.append(wait(srv, t, c["ninputs"] + len(c["gates"]))[0])
+    srv.close()
+    # mixed: all at once, small batches so that requests share batches and levels interleave
+    srv = gpu.server(mem_budget_bytes=64 << 20, max_batch=40)
+    tickets = [srv.submit(c["gates"], c["ninputs"], inputs) for c, inputs in reqs]
+    mixed = [wait(srv, t, c["ninputs"] + len(c["gates"]))[0] for t, (c, _) in zip(tickets, reqs)]
+    gates, batches, peak = srv.stats()
+    srv.close()
+    assert gates == sum(len(c["gates"]) for c, _ in reqs)
+    assert batches < sum(int(c["level"].max()) + 1 for c, _ in reqs)   # batches were shared
+    for (c, inputs), a, m in zip(reqs, alone, mixed):
+        np.testing.assert_array_equal(a, m)
+        circ = gpu.circuit(c["gates"], c["ninputs"])
+        ref = to_host(circ.run(gpu.tensor(inputs)))
+        gpu.sync()
+        circ.close()
+        np.testing.assert_array_equal(m, ref)
+
+
+def test_admission_by_memory_budget(gpu, keys):
+    reqs = requests(keys, 4, 900)
+    biggest = max(c["ninputs"] + len(c["gates"]) for c, _ in reqs)
+    budget = int(1.5 * biggest) * ROWB            # at most one or two requests resident at once
+    srv = gpu.server(mem_budget_bytes=budget, max_batch=512)
+    tickets = [srv.submit(c["gates"], c["ninputs"], inputs) for c, inputs in reqs]
+    outs = [wait(srv, t, c["ninputs"] + len(c["gates"]))[0] for t, (c, _) in zip(tickets, reqs)]
+    _, _, peak = srv.stats()
+    assert peak <= budget
+    for (c, _), o in zip(reqs, outs):
+        dec = client.tlwe_decrypt(keys["s0"], o)
+        assert dec.shape[0] == c["ninputs"] + len(c["gates"])
+    srv.close()
+
+
+def test_capacity_and_malformed_rejected(gpu, keys):
+    c = W.small_circuit(seed=950, levels=3, wmin=4, wmax=8, ninputs=8)
+    inputs = client.tlwe_encrypt_bits(keys["s0"], c["bits"], *c["enc"])
+    srv = gpu.server(mem_budget_bytes=4 * ROWB, max_batch=16)
+    with pytest.raises(VspError) as ei:
+        srv.submit(c["gates"], c["ninputs"], inputs)
+    assert ei.value.status == nv.VSP_E_CAPACITY
+    with pytest.raises(VspError) as ei:
+        srv.submit(np.array([[0, 0, 3]]), 2, inputs[:2])
+    assert ei.value.status == nv.VSP_E_ARG
+    with pytest.raises(VspError) as ei:
+        srv.poll(12345)
+    assert ei.value.status == nv.VSP_E_STATE
+    srv.close()
