@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--no-circuit", action="store_true", help="skip the per-level circuit latency")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-gates", type=int, default=0, help="oracle sample size (default 4 x cores)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="also run one plain device copy of MIB MiB (reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -118,13 +120,23 @@ def main():
     value = B_GATES * args.steps / dt
 
     # per-gate mode: one launch sequence per gate
-    pg = max(1, args.per_gate)
-    ctx.gates(ops_d[:1], a_d[:1], b_d[:1], mode=VSP_PER_GATE)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ctx.gates(ops_d[:pg], a_d[:pg], b_d[:pg], mode=VSP_PER_GATE)
-    torch.cuda.synchronize()
-    per_gate = pg / (time.perf_counter() - t0)
+    per_gate = None
+    pg = args.per_gate
+    if pg > 0:
+        ctx.gates(ops_d[:1], a_d[:1], b_d[:1], mode=VSP_PER_GATE)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.gates(ops_d[:pg], a_d[:pg], b_d[:pg], mode=VSP_PER_GATE)
+        torch.cuda.synchronize()
+        per_gate = pg / (time.perf_counter() - t0)
+
+    if args.calibrate_copy > 0:
+        src = torch.empty(args.calibrate_copy << 18, dtype=torch.int32, device=ctx.device).fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # per-level latency of the 64-level circuit (eager levels timed with events)
     levels = None
@@ -160,7 +172,8 @@ def main():
         "config": {"workload": "4096 independent random gates (NAND/AND/OR/XOR/XNOR) on fresh TLWE, "
                                "n=630 N=1024 l=3 Bg=64 ks t=8 base=4, one batched launch",
                    "batch": B_GATES, "parallelism": "single GPU"},
-        "per_gate_value": round(per_gate, 2), "batched_over_per_gate": round(value / per_gate, 1),
+        "per_gate_value": None if per_gate is None else round(per_gate, 2),
+        "batched_over_per_gate": None if per_gate is None else round(value / per_gate, 1),
         "per_level": levels, "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
