@@ -60,6 +60,7 @@ def parse():
     ap.add_argument("--per-gate", type=int, default=8, help="gates timed in per-gate mode")
     ap.add_argument("--no-circuit", action="store_true", help="skip the per-level circuit latency")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--cpu-gates", type=int, default=0, help="oracle sample size (default 4 x cores)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run one plain device copy of MIB MiB (reference for HBM byte counters)")
@@ -101,6 +102,9 @@ def main():
     ctx = Context(bk, ksk, device=0)
     ops_d, a_d, b_d = ctx.tensor(cfg["ops"]), ctx.tensor(in0), ctx.tensor(in1)
     out = ctx.empty(B_GATES, N_LWE + 1)
+    if not args.no_autotune:
+        ctx.autotune(max_batch=B_GATES)
+    br_waves, ks_tiled = ctx.tuning(B_GATES)
 
     for _ in range(args.warmup):
         ctx.gates(ops_d, a_d, b_d, out=out)
@@ -158,7 +162,8 @@ def main():
             "frac": round(achieved * 1e12 / PEAK_LANE_OPS, 4), "traffic": None,
             "avg_launch_ms": round(br_avg_ms, 3), "lane_ops_per_gate": LANE_OPS_PER_GATE,
             "key_stream_GBps_requested": round(B_GATES * BK_NTT_BYTES / (br_avg_ms * 1e-3) / 1e9, 1),
-            "keyswitch_avg_ms": round(ks_ms / max(ks_n, 1), 3)}
+            "keyswitch_avg_ms": round(ks_ms / max(ks_n, 1), 3),
+            "launch": {"br_waves_per_workgroup": br_waves, "keyswitch": "tiled" if ks_tiled else "gather"}}
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(s0, s1, bkd, kskd, cfg, in0, in1, args.cpu_gates)

@@ -182,6 +182,21 @@ vsp_status vsp_server_stats(vsp_server* s, uint64_t* gates, uint64_t* batches, u
 /* Stop the server thread (finishing admitted work) and free it. NULL is accepted. */
 vsp_status vsp_server_destroy(vsp_server* s);
 
+/* Autotuner for the batched launches (the level executor's tile and batch shapes): for each
+ * batch-size bucket up to max_batch (buckets start at 1, 16, 64, 256, 1024, 2048, 4096 gates)
+ * times the blind-rotation workgroup shape (4 or 8 gates per workgroup) and the key-switch form
+ * (one workgroup per gate, or row-stationary tiles of 16 gates) on random ciphertexts, requires
+ * every candidate to produce bit-identical outputs (else VSP_E_HIP), and keeps the fastest in
+ * the context. With cache_path non-NULL the choices are read from that JSON file when it holds
+ * an entry for this GPU, and otherwise measured and written there. Synchronous. */
+vsp_status vsp_autotune(vsp_context* ctx, uint64_t max_batch, const char* cache_path);
+
+/* The launch choice used for a batch of B gates: *br_waves (4 or 8), *ks_tiled (0 or 1). */
+vsp_status vsp_tuning_get(const vsp_context* ctx, uint64_t B, int* br_waves, int* ks_tiled);
+
+/* Override the launch choice for the bucket containing B (results are unchanged). */
+vsp_status vsp_tuning_set(vsp_context* ctx, uint64_t B, int br_waves, int ks_tiled);
+
 /* Kernel-time instrumentation (for benchmarks): while enabled, every eager launch of the
  * blind-rotation, key-switch and gate-prologue kernels made by this context is bracketed by
  * HIP events on the stream it runs on. Enabling resets the totals. */

@@ -62,6 +62,9 @@ SIGNATURES = {
     "vsp_server_poll": (_st, [_vp, _u64, _vp, ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_double)]),
     "vsp_server_stats": (_st, [_vp, ctypes.POINTER(_u64), ctypes.POINTER(_u64), ctypes.POINTER(_u64)]),
     "vsp_server_destroy": (_st, [_vp]),
+    "vsp_autotune": (_st, [_vp, _u64, ctypes.c_char_p]),
+    "vsp_tuning_get": (_st, [_vp, _u64, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+    "vsp_tuning_set": (_st, [_vp, _u64, _i32, _i32]),
     "vsp_profile_enable": (_st, [_vp, _i32]),
     "vsp_profile_read": (_st, [_vp, _i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_u64)]),
     "vsp_debug_external_product": (_st, [_vp, _vp, _vp, _vp, _u64, _vp]),
@@ -197,6 +200,22 @@ def vsp_server_stats(srv):
 
 def vsp_server_destroy(srv) -> None:
     _call("vsp_server_destroy", srv)
+
+
+def vsp_autotune(ctx, max_batch: int, cache_path: str | None = None) -> None:
+    _call("vsp_autotune", ctx, max_batch, cache_path.encode() if cache_path else None)
+
+
+def vsp_tuning_get(ctx, B: int):
+    """(blind-rotation waves per workgroup, key-switch tiled flag) used for a batch of B gates."""
+    w = _i32()
+    t = _i32()
+    _call("vsp_tuning_get", ctx, B, ctypes.byref(w), ctypes.byref(t))
+    return w.value, t.value
+
+
+def vsp_tuning_set(ctx, B: int, br_waves: int, ks_tiled: int) -> None:
+    _call("vsp_tuning_set", ctx, B, br_waves, ks_tiled)
 
 
 def vsp_profile_enable(ctx, on: bool) -> None:

@@ -1,0 +1,219 @@
+// Autotuner for the batched launches: per batch-size bucket, times the blind-rotation
+// workgroup shape (4 or 8 gates per workgroup) and the key-switch form (one workgroup per
+// gate, or row-stationary tiles of gates) on random ciphertexts, requires every candidate to
+// produce bit-identical outputs, and keeps the fastest in the context. Choices can be cached
+// in a small JSON file keyed by the GPU.
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "vsp_internal.h"
+
+using namespace vsp;
+
+namespace {
+
+__global__ void k_fill_random(uint32_t* p, uint64_t n, uint64_t seed, uint32_t mod) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint64_t z = seed + i * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  p[i] = mod ? (uint32_t)(z % mod) : (uint32_t)z;
+}
+
+__global__ void k_u32_to_u8(const uint32_t* src, uint8_t* dst, uint64_t n) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = (uint8_t)src[i];
+}
+
+hipError_t fill(uint32_t* p, uint64_t n, uint64_t seed, uint32_t mod, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_random, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, seed, mod);
+  return hipGetLastError();
+}
+
+std::string device_key(int dev) {
+  hipDeviceProp_t p;
+  if (hipGetDeviceProperties(&p, dev) != hipSuccess) return "unknown";
+  std::string arch = p.gcnArchName;
+  const size_t colon = arch.find(':');
+  if (colon != std::string::npos) arch = arch.substr(0, colon);
+  return arch + "-" + std::to_string(p.multiProcessorCount) + "cu";
+}
+
+// JSON: {"<device>": {"br_waves": [..], "ks_tiled": [..]}, ...}
+bool read_cache(const std::string& path, const std::string& key, Tuning& t) {
+  std::ifstream f(path);
+  if (!f) return false;
+  std::stringstream ss;
+  ss << f.rdbuf();
+  const std::string s = ss.str();
+  const size_t at = s.find("\"" + key + "\"");
+  if (at == std::string::npos) return false;
+  auto read_array = [&](const char* name, int* out) {
+    const size_t p = s.find(std::string("\"") + name + "\"", at);
+    if (p == std::string::npos) return false;
+    const size_t lb = s.find('[', p);
+    if (lb == std::string::npos) return false;
+    const char* c = s.c_str() + lb + 1;
+    for (int b = 0; b < kTuneBuckets; b++) {
+      char* end = nullptr;
+      const long v = std::strtol(c, &end, 10);
+      if (end == c) return false;
+      out[b] = (int)v;
+      c = end;
+      while (*c == ',' || *c == ' ') c++;
+    }
+    return true;
+  };
+  Tuning n;
+  if (!read_array("br_waves", n.br_waves) || !read_array("ks_tiled", n.ks_tiled)) return false;
+  for (int b = 0; b < kTuneBuckets; b++)
+    if ((n.br_waves[b] != 4 && n.br_waves[b] != 8) || (n.ks_tiled[b] != 0 && n.ks_tiled[b] != 1)) return false;
+  n.tuned = true;
+  t = n;
+  return true;
+}
+
+bool write_cache(const std::string& path, const std::string& key, const Tuning& t) {
+  std::ofstream f(path, std::ios::trunc);
+  if (!f) return false;
+  f << "{\"" << key << "\": {\"buckets\": [";
+  for (int b = 0; b < kTuneBuckets; b++) f << (b ? ", " : "") << kBucket[b];
+  f << "], \"br_waves\": [";
+  for (int b = 0; b < kTuneBuckets; b++) f << (b ? ", " : "") << t.br_waves[b];
+  f << "], \"ks_tiled\": [";
+  for (int b = 0; b < kTuneBuckets; b++) f << (b ? ", " : "") << t.ks_tiled[b];
+  f << "]}}\n";
+  return (bool)f;
+}
+
+struct Buf {
+  void* p = nullptr;
+  ~Buf() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+vsp_status vsp_autotune(vsp_context* ctx, uint64_t max_batch, const char* cache_path) {
+  if (ctx == nullptr) return fail(VSP_E_ARG, "context is NULL");
+  if (max_batch == 0 || max_batch > (1ull << 20)) return fail(VSP_E_ARG, "max_batch must be in [1, 2^20]");
+  VSP_HIP(hipSetDevice(ctx->device));
+  const std::string key = device_key(ctx->device);
+  if (cache_path && read_cache(cache_path, key, ctx->tune)) return VSP_OK;
+
+  const uint64_t S = std::min<uint64_t>(max_batch, kBucket[kTuneBuckets - 1]);
+  Buf in, ops32, ops, abar, t1, t1ref, out, outref;
+  const size_t T0 = (LWE_N + 1) * 4, T1 = (RING_N + 1) * 4;
+  VSP_HIP(hipMalloc(&in.p, 2 * S * T0));
+  VSP_HIP(hipMalloc(&ops32.p, S * 4));
+  VSP_HIP(hipMalloc(&ops.p, S));
+  VSP_HIP(hipMalloc(&abar.p, S * T0));
+  VSP_HIP(hipMalloc(&t1.p, S * T1));
+  VSP_HIP(hipMalloc(&t1ref.p, S * T1));
+  VSP_HIP(hipMalloc(&out.p, S * T0));
+  VSP_HIP(hipMalloc(&outref.p, S * T0));
+  hipStream_t st = nullptr;
+  uint32_t* i0 = static_cast<uint32_t*>(in.p);
+  uint32_t* i1 = i0 + S * (LWE_N + 1);
+  hipError_t e;
+  if ((e = fill(i0, 2 * S * (LWE_N + 1), 0x5eed, 0, st)) != hipSuccess) return hip_fail(e, "fill");
+  if ((e = fill(static_cast<uint32_t*>(ops32.p), S, 0x0b5, 8, st)) != hipSuccess) return hip_fail(e, "fill");
+  hipLaunchKernelGGL(k_u32_to_u8, dim3((unsigned)((S + 255) / 256)), dim3(256), 0, st,
+                     static_cast<const uint32_t*>(ops32.p), static_cast<uint8_t*>(ops.p), S);
+  if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "ops");
+  const uint8_t* dops = static_cast<const uint8_t*>(ops.p);
+  uint32_t* dab = static_cast<uint32_t*>(abar.p);
+  if ((e = launch_gate_prologue(ctx, dops, i0, i1, nullptr, nullptr, nullptr, dab, static_cast<uint32_t*>(out.p), S,
+                                st)) != hipSuccess)
+    return hip_fail(e, "prologue");
+  hipEvent_t ev0, ev1;
+  VSP_HIP(hipEventCreate(&ev0));
+  VSP_HIP(hipEventCreate(&ev1));
+  auto timed = [&](auto&& launch) -> float {
+    launch();  // warm
+    (void)hipEventRecord(ev0, st);
+    launch();
+    (void)hipEventRecord(ev1, st);
+    (void)hipEventSynchronize(ev1);
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, ev0, ev1);
+    return ms;
+  };
+  std::vector<uint32_t> ha, hb;
+  auto same = [&](const void* a, const void* b, size_t bytes) {
+    ha.resize(bytes / 4);
+    hb.resize(bytes / 4);
+    (void)hipMemcpy(ha.data(), a, bytes, hipMemcpyDeviceToHost);
+    (void)hipMemcpy(hb.data(), b, bytes, hipMemcpyDeviceToHost);
+    return std::memcmp(ha.data(), hb.data(), bytes) == 0;
+  };
+  Tuning t;
+  vsp_status result = VSP_OK;
+  for (int b = 0; b < kTuneBuckets && result == VSP_OK; b++) {
+    const uint64_t B = std::min<uint64_t>(kBucket[b], S);
+    if (kBucket[b] > max_batch && b > 0) {  // beyond the range asked for: keep the previous choice
+      t.br_waves[b] = t.br_waves[b - 1];
+      t.ks_tiled[b] = t.ks_tiled[b - 1];
+      continue;
+    }
+    float best = 1e30f;
+    for (int c = 0; c < 2; c++) {
+      const int w = kBrWaveChoices[c];
+      uint32_t* dst = static_cast<uint32_t*>(c == 0 ? t1ref.p : t1.p);
+      const float ms = timed([&] { (void)launch_blind_rotate(ctx, dops, dab, dst, nullptr, B, w, st); });
+      if (c > 0 && !same(t1ref.p, t1.p, B * T1)) result = fail(VSP_E_HIP, "autotune: blind-rotation shapes disagree");
+      if (ms < best) {
+        best = ms;
+        t.br_waves[b] = w;
+      }
+    }
+    best = 1e30f;
+    for (int c = 0; c < 2 && result == VSP_OK; c++) {
+      uint32_t* dst = static_cast<uint32_t*>(c == 0 ? outref.p : out.p);
+      const float ms = timed([&] { (void)launch_keyswitch(ctx, dops, static_cast<const uint32_t*>(t1ref.p), nullptr,
+                                                          dst, B, st, c); });
+      if (c > 0 && !same(outref.p, out.p, B * T0)) result = fail(VSP_E_HIP, "autotune: key-switch forms disagree");
+      if (ms < best) {
+        best = ms;
+        t.ks_tiled[b] = c;
+      }
+    }
+  }
+  (void)hipEventDestroy(ev0);
+  (void)hipEventDestroy(ev1);
+  if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "autotune");
+  if (result != VSP_OK) return result;
+  t.tuned = true;
+  ctx->tune = t;
+  if (cache_path && !write_cache(cache_path, key, t)) return fail(VSP_E_ARG, "cannot write the autotune cache file");
+  return VSP_OK;
+}
+
+vsp_status vsp_tuning_get(const vsp_context* ctx, uint64_t B, int* br_waves, int* ks_tiled) {
+  if (ctx == nullptr || br_waves == nullptr || ks_tiled == nullptr) return fail(VSP_E_ARG, "NULL argument");
+  const int b = Tuning::bucket(B == 0 ? 1 : B);
+  *br_waves = ctx->tune.br_waves[b];
+  *ks_tiled = ctx->tune.ks_tiled[b];
+  return VSP_OK;
+}
+
+vsp_status vsp_tuning_set(vsp_context* ctx, uint64_t B, int br_waves, int ks_tiled) {
+  if (ctx == nullptr) return fail(VSP_E_ARG, "context is NULL");
+  if ((br_waves != 4 && br_waves != 8) || (ks_tiled != 0 && ks_tiled != 1))
+    return fail(VSP_E_ARG, "br_waves must be 4 or 8 and ks_tiled 0 or 1");
+  const int b = Tuning::bucket(B == 0 ? 1 : B);
+  ctx->tune.br_waves[b] = br_waves;
+  ctx->tune.ks_tiled[b] = ks_tiled;
+  return VSP_OK;
+}
+
+}  // extern "C"

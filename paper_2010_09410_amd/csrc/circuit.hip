@@ -37,7 +37,7 @@ hipError_t launch_level(vsp_circuit* c, uint64_t L, hipStream_t st) {
   const uint8_t* ops = c->d_ops + o;
   hipError_t e = launch_gate_prologue(c->ctx, ops, c->d_wires, c->d_wires, i0, i1, io, c->d_abar, c->d_wires, w, st);
   if (e != hipSuccess) return e;
-  e = launch_blind_rotate(c->ctx, ops, c->d_abar, c->d_tlwe1, nullptr, w, c->ctx->tune.br_waves, st);
+  e = launch_blind_rotate(c->ctx, ops, c->d_abar, c->d_tlwe1, nullptr, w, 0, st);
   if (e != hipSuccess) return e;
   return launch_keyswitch(c->ctx, ops, c->d_tlwe1, io, c->d_wires, w, st);
 }

@@ -9,28 +9,27 @@ constexpr int TLWE0 = LWE_N + 1;
 constexpr int TLWE1 = RING_N + 1;
 
 // ------------------------------------------------------------------ key conversion
-// One wave per (item, round k, c'): lanes 0-31 transform row k, lanes 32-63 row k + 3; c' = 0
-// takes the output polynomial the half owns (a for rows 0..2, b for rows 3..5), c' = 1 the other.
+// One wave per (item, round k, output polynomial c): lanes 0-31 transform TRGSW row k,
+// lanes 32-63 row k + 3, both taking column c; results land in the key layout of ntt.h.
 __global__ __launch_bounds__(256) void k_trgsw_to_ntt(const u32* __restrict__ src, u64* __restrict__ dst,
                                                       const u64* __restrict__ tw, u64 ninv, uint64_t jobs) {
-  __shared__ u64 lds[4 * WAVE_LDS_U64];
+  __shared__ u32 lds[4 * WAVE_T_U32];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint64_t job = (uint64_t)blockIdx.x * 4 + wave;
   if (job >= jobs) return;
   const int lane = threadIdx.x & 63, l = lane & 31, h = lane >> 5;
   const uint64_t item = job / 6;
-  const int rem = (int)(job % 6), k = rem >> 1, cp = rem & 1;
+  const int rem = (int)(job % 6), k = rem >> 1, c = rem & 1;
   const int row = k + GADGET_L * h;
-  const int col = (cp == 0) ? h : 1 - h;
-  const u32* poly = src + ((item * 2 * GADGET_L + row) * 2 + col) * RING_N;
+  const u32* poly = src + ((item * 2 * GADGET_L + row) * 2 + c) * RING_N;
   u64 v[32];
 #pragma unroll
   for (int t = 0; t < 32; t++) v[t] = poly[l + 32 * t];
-  u64* reg = lds + wave * WAVE_LDS_U64 + h * TREGION;
+  u32* reg = lds + wave * WAVE_T_U32 + h * TREGION;
   ntt_forward(v, tw, reg, l);
-  u64* out = dst + item * TRGSW_NTT_U64 + ((size_t)k * 2 + cp) * 32 * 64;
+  u64* out = dst + item * TRGSW_NTT_U64 + (size_t)k * 32 * 64 * 2;
 #pragma unroll
-  for (int s = 0; s < 32; s++) out[s * 64 + lane] = gl_canon(gl_mul(v[s], ninv));
+  for (int s = 0; s < 32; s++) out[((size_t)s * 64 + lane) * 2 + c] = gl_canon(gl_mul(v[s], ninv));
 }
 
 hipError_t launch_trgsw_to_ntt(const vsp_context* ctx, const uint32_t* src, uint64_t* dst, uint64_t count,
@@ -114,17 +113,22 @@ hipError_t launch_gate_prologue_uniform(const vsp_context* ctx, uint32_t op, con
 }
 
 // ------------------------------------------------------------------ blind rotation
-// One wave per gate. Lanes 0-31 own the accumulator's a polynomial, lanes 32-63 its b
-// polynomial (coefficient l + 32 t in register t). ACC starts as (0, X^{-bbar} tv) with tv = mu
-// everywhere; step i applies ACC <- ACC + BK_i (ext) (X^{abar_i} ACC - ACC) (a CMUX between
-// ACC and its rotation selected by the key bit s0_i), skipped when abar_i = 0 (then the
-// difference is zero and so is the product).
+// One wave per gate. The accumulator lives in LDS (its a polynomial for lanes 0-31, b for
+// lanes 32-63; coefficient l + 32 t belongs to lane l). ACC starts as (0, X^{-bbar} tv) with
+// tv = mu everywhere; step i adds BK_i (ext) (X^{abar_i} ACC - ACC) (a CMUX between ACC and
+// its rotation selected by the key bit s0_i); a step with abar_i = 0 has a zero difference,
+// hence a zero product, and is skipped. LDS per workgroup: the twiddle tables, then per wave
+// the accumulator (2 x 1024 u32) and the two transpose regions.
+constexpr int BR_WAVE_U32 = 2 * RING_N + WAVE_T_U32;
+
+constexpr size_t br_lds_bytes(int waves) { return 2048 * 8 + (size_t)waves * BR_WAVE_U32 * 4; }
+
 template <int WAVES>
 __global__ __launch_bounds__(WAVES * 64) void k_blind_rotate(const u64* __restrict__ bkn, const u64* __restrict__ tw,
                                                              const uint8_t* __restrict__ ops,
                                                              const u32* __restrict__ abar, u32* __restrict__ tlwe1,
                                                              u32* __restrict__ trlwe, uint64_t B) {
-  extern __shared__ u64 lds[];  // [2048] twiddles, then WAVES transform regions
+  extern __shared__ u64 lds[];
   u64* tws = lds;
   for (int i = threadIdx.x; i < 2048; i += WAVES * 64) tws[i] = tw[i];
   __syncthreads();
@@ -133,25 +137,45 @@ __global__ __launch_bounds__(WAVES * 64) void k_blind_rotate(const u64* __restri
   if (g >= B) return;
   if (ops && !op_bootstraps(ops[g])) return;
   const int lane = threadIdx.x & 63, l = lane & 31, h = lane >> 5;
+  u32* wbase = reinterpret_cast<u32*>(lds + 2048) + wave * BR_WAVE_U32;
   const u32* ab = abar + g * TLWE0;
   const int bbar = (int)ab[LWE_N];
   const int k0 = (2 * RING_N - bbar) & (2 * RING_N - 1);
-  u32 acc[32];
+  {
+    u32* accs = wbase + h * RING_N;
 #pragma unroll
-  for (int t = 0; t < 32; t++) acc[t] = h ? rotated_testvector(l + 32 * t, k0) : 0u;
+    for (int t = 0; t < 32; t++) accs[l + 32 * t] = h ? rotated_testvector(l + 32 * t, k0) : 0u;
+  }
+  wave_lds_sync();
   for (int i = 0; i < LWE_N; i++) {
     const int a = (int)__builtin_amdgcn_readfirstlane(ab[i]);
     if (a == 0) continue;
     const int ln = opaque_lane(lane);
-    u64* rg = lds + 2048 + wave * WAVE_LDS_U64 + (ln >> 5) * TREGION;
-    u32 D[32];
-    rotate_minus(acc, a, rg, ln & 31, D);
-    external_product_acc(D, bkn + (size_t)i * TRGSW_NTT_U64, tws, tws + 1024, rg, ln, acc);
+    const int li = ln & 31, hi = ln >> 5;
+    u32* accs = wbase + hi * RING_N;
+    u32* treg = wbase + 2 * RING_N + hi * TREGION;
+    // digits of X^a ACC - ACC, recomputed from the LDS accumulator in every round
+    auto digits = [&](int sh, u64 (&x)[32]) {
+#pragma unroll
+      for (int t = 0; t < 32; t++) {
+        const int idx = (li + 32 * t - a) & (2 * RING_N - 1);
+        u32 r = accs[idx & (RING_N - 1)];
+        if (idx & RING_N) r = 0u - r;
+        x[t] = gadget_digit(r - accs[li + 32 * t], sh);
+      }
+    };
+    u32 z[32];
+    external_product(digits, bkn + (size_t)i * TRGSW_NTT_U64, tws, tws + 1024, treg, ln, z);
+#pragma unroll
+    for (int t = 0; t < 32; t++)
+      __hip_atomic_fetch_add(&accs[li + 32 * t], z[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    wave_lds_sync();
   }
+  const u32* accs = wbase + h * RING_N;
   if (trlwe) {
     u32* o = trlwe + g * 2 * RING_N + h * RING_N;
 #pragma unroll
-    for (int t = 0; t < 32; t++) o[l + 32 * t] = acc[t];
+    for (int t = 0; t < 32; t++) o[l + 32 * t] = accs[l + 32 * t];
   }
   if (tlwe1) {
     // SampleExtract at 0: a'_0 = A_0, a'_j = -A_{N-j}; b' = B_0.
@@ -160,10 +184,11 @@ __global__ __launch_bounds__(WAVES * 64) void k_blind_rotate(const u64* __restri
 #pragma unroll
       for (int t = 0; t < 32; t++) {
         const int j = l + 32 * t;
-        o[(RING_N - j) & (RING_N - 1)] = (j == 0) ? acc[t] : 0u - acc[t];
+        const u32 v = accs[j];
+        o[(RING_N - j) & (RING_N - 1)] = (j == 0) ? v : 0u - v;
       }
     } else if (l == 0) {
-      o[RING_N] = acc[0];
+      o[RING_N] = accs[0];
     }
   }
 }
@@ -172,28 +197,22 @@ __global__ __launch_bounds__(WAVES * 64) void k_blind_rotate(const u64* __restri
 // creation, outside any stream capture).
 hipError_t init_kernel_attributes() {
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_blind_rotate<4>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (2048 + 4 * WAVE_LDS_U64) * 8);
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)br_lds_bytes(4));
   if (e != hipSuccess) return e;
   return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_blind_rotate<8>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (2048 + 8 * WAVE_LDS_U64) * 8);
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)br_lds_bytes(8));
 }
 
 hipError_t launch_blind_rotate(const vsp_context* ctx, const uint8_t* ops, const uint32_t* abar, uint32_t* tlwe1,
                                uint32_t* trlwe, uint64_t B, int waves, hipStream_t st) {
   if (B == 0) return hipSuccess;
-  switch (waves) {
-    case 4: {
-      const size_t lds = (2048 + 4 * WAVE_LDS_U64) * 8;
-      hipLaunchKernelGGL(k_blind_rotate<4>, dim3((unsigned)((B + 3) / 4)), dim3(256), lds, st, ctx->bkn, ctx->tw,
-                         ops, abar, tlwe1, trlwe, B);
-      break;
-    }
-    default: {
-      const size_t lds = (2048 + 8 * WAVE_LDS_U64) * 8;
-      hipLaunchKernelGGL(k_blind_rotate<8>, dim3((unsigned)((B + 7) / 8)), dim3(512), lds, st, ctx->bkn, ctx->tw,
-                         ops, abar, tlwe1, trlwe, B);
-      break;
-    }
+  if (waves <= 0) waves = ctx->tune.br_waves[Tuning::bucket(B)];
+  if (waves == 4) {
+    hipLaunchKernelGGL(k_blind_rotate<4>, dim3((unsigned)((B + 3) / 4)), dim3(256), br_lds_bytes(4), st, ctx->bkn,
+                       ctx->tw, ops, abar, tlwe1, trlwe, B);
+  } else {
+    hipLaunchKernelGGL(k_blind_rotate<8>, dim3((unsigned)((B + 7) / 8)), dim3(512), br_lds_bytes(8), st, ctx->bkn,
+                       ctx->tw, ops, abar, tlwe1, trlwe, B);
   }
   return hipGetLastError();
 }
@@ -233,30 +252,84 @@ __global__ __launch_bounds__(256) void k_keyswitch(const u32* __restrict__ ksk, 
   if (has2) o[c2] = (c2 == LWE_N ? b : 0u) - acc2;
 }
 
+// Row-stationary form: a workgroup takes a tile of G gates; for every (j, p) it loads the
+// three key rows once (3 coefficients per thread) and applies them to all G gates, whose
+// digits are wave-uniform values. The key is then read once per tile instead of once per
+// gate.
+template <int G>
+__global__ __launch_bounds__(256) void k_keyswitch_tiled(const u32* __restrict__ ksk, const uint8_t* __restrict__ ops,
+                                                         const u32* __restrict__ tlwe1, const u32* __restrict__ idxo,
+                                                         u32* __restrict__ out, uint64_t B) {
+  const uint64_t g0 = (uint64_t)blockIdx.x * G;
+  const int tid = threadIdx.x;
+  const int c0 = tid, c1 = tid + 256, c2 = tid + 512;
+  const bool has2 = c2 < TLWE0;
+  const int ng = (int)((B - g0) < (uint64_t)G ? (B - g0) : (uint64_t)G);
+  u32 acc[G][3];
+#pragma unroll
+  for (int g = 0; g < G; g++) acc[g][0] = acc[g][1] = acc[g][2] = 0;
+  for (int j = 0; j < RING_N; j++) {
+    u32 ahat[G];
+#pragma unroll
+    for (int g = 0; g < G; g++)
+      ahat[g] = (g < ng ? __builtin_amdgcn_readfirstlane(tlwe1[(g0 + g) * TLWE1 + j]) : 0u) + (1u << 15);
+    const u32* base = ksk + (size_t)j * KS_T * 4 * TLWE0;
+#pragma unroll 2
+    for (int p = 0; p < KS_T; p++) {
+      const u32* r = base + (size_t)p * 4 * TLWE0;
+      const u32 r10 = r[TLWE0 + c0], r11 = r[TLWE0 + c1], r12 = has2 ? r[TLWE0 + c2] : 0u;
+      const u32 r20 = r[2 * TLWE0 + c0], r21 = r[2 * TLWE0 + c1], r22 = has2 ? r[2 * TLWE0 + c2] : 0u;
+      const u32 r30 = r[3 * TLWE0 + c0], r31 = r[3 * TLWE0 + c1], r32 = has2 ? r[3 * TLWE0 + c2] : 0u;
+#pragma unroll
+      for (int g = 0; g < G; g++) {
+        const u32 v = (ahat[g] >> (30 - 2 * p)) & 3u;
+        acc[g][0] += v == 1 ? r10 : v == 2 ? r20 : v == 3 ? r30 : 0u;
+        acc[g][1] += v == 1 ? r11 : v == 2 ? r21 : v == 3 ? r31 : 0u;
+        acc[g][2] += v == 1 ? r12 : v == 2 ? r22 : v == 3 ? r32 : 0u;
+      }
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < G; g++) {
+    const uint64_t gg = g0 + g;
+    if (g < ng && (!ops || op_bootstraps(ops[gg]))) {
+      const uint64_t ro = idxo ? idxo[gg] : gg;
+      u32* o = out + ro * TLWE0;
+      o[c0] = 0u - acc[g][0];
+      o[c1] = 0u - acc[g][1];
+      if (has2) o[c2] = (c2 == LWE_N ? tlwe1[gg * TLWE1 + RING_N] : 0u) - acc[g][2];
+    }
+  }
+}
+
 hipError_t launch_keyswitch(const vsp_context* ctx, const uint8_t* ops, const uint32_t* tlwe1, const uint32_t* idxo,
-                            uint32_t* out, uint64_t B, hipStream_t st) {
+                            uint32_t* out, uint64_t B, hipStream_t st, int tiled) {
   if (B == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_keyswitch, dim3((unsigned)B), dim3(256), 0, st, ctx->ksk, ops, tlwe1, idxo, out, B);
+  if (tiled < 0) tiled = ctx->tune.ks_tiled[Tuning::bucket(B)];
+  if (tiled) {
+    constexpr int G = 16;
+    hipLaunchKernelGGL(k_keyswitch_tiled<G>, dim3((unsigned)((B + G - 1) / G)), dim3(256), 0, st, ctx->ksk, ops, tlwe1,
+                       idxo, out, B);
+  } else {
+    hipLaunchKernelGGL(k_keyswitch, dim3((unsigned)B), dim3(256), 0, st, ctx->ksk, ops, tlwe1, idxo, out, B);
+  }
   return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ test kernels
 __global__ __launch_bounds__(256) void k_ext_product(const u64* __restrict__ Cn, const u32* __restrict__ x,
                                                      u32* __restrict__ out, const u64* __restrict__ tw, uint64_t J) {
-  __shared__ u64 lds[4 * WAVE_LDS_U64];
+  __shared__ u32 lds[4 * WAVE_T_U32];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint64_t j = (uint64_t)blockIdx.x * 4 + wave;
   if (j >= J) return;
   const int lane = threadIdx.x & 63, l = lane & 31, h = lane >> 5;
-  u64* reg = lds + wave * WAVE_LDS_U64 + h * TREGION;
+  u32* reg = lds + wave * WAVE_T_U32 + h * TREGION;
   const u32* xp = x + j * 2 * RING_N + h * RING_N;
   u32 D[32], acc[32];
 #pragma unroll
-  for (int t = 0; t < 32; t++) {
-    D[t] = xp[l + 32 * t];
-    acc[t] = 0;
-  }
-  external_product_acc(D, Cn + j * TRGSW_NTT_U64, tw, tw + 1024, reg, lane, acc);
+  for (int t = 0; t < 32; t++) D[t] = xp[l + 32 * t];
+  external_product(OperandDigits{D}, Cn + j * TRGSW_NTT_U64, tw, tw + 1024, reg, lane, acc);
   u32* o = out + j * 2 * RING_N + h * RING_N;
 #pragma unroll
   for (int t = 0; t < 32; t++) o[l + 32 * t] = acc[t];
@@ -274,12 +347,12 @@ hipError_t launch_ext_product(const vsp_context* ctx, const uint64_t* Cn, const 
 __global__ __launch_bounds__(256) void k_polymul(const int32_t* __restrict__ a, const u32* __restrict__ b,
                                                  u32* __restrict__ out, const u64* __restrict__ tw, u64 ninv,
                                                  uint64_t J) {
-  __shared__ u64 lds[4 * WAVE_LDS_U64];
+  __shared__ u32 lds[4 * WAVE_T_U32];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint64_t j = (uint64_t)blockIdx.x * 4 + wave;
   if (j >= J) return;
   const int lane = threadIdx.x & 63, l = lane & 31, h = lane >> 5;
-  u64* reg = lds + wave * WAVE_LDS_U64 + h * TREGION;
+  u32* reg = lds + wave * WAVE_T_U32 + h * TREGION;
   u64 v[32];
 #pragma unroll
   for (int t = 0; t < 32; t++)

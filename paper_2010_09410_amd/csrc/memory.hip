@@ -15,7 +15,7 @@ __global__ __launch_bounds__(256) void k_cmux_tree_level(const u64* __restrict__
                                                          const u32* __restrict__ in, uint64_t s_r, uint64_t s_b,
                                                          u32* __restrict__ out, uint64_t R, uint64_t nb, uint64_t half,
                                                          const u64* __restrict__ tw) {
-  __shared__ u64 lds[4 * WAVE_LDS_U64];
+  __shared__ u32 lds[4 * WAVE_T_U32];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint64_t job = (uint64_t)blockIdx.x * 4 + wave;
   if (job >= R * nb * half) return;
@@ -24,15 +24,17 @@ __global__ __launch_bounds__(256) void k_cmux_tree_level(const u64* __restrict__
   const u32* x0 = in + r * s_r + blk * s_b + (2 * m) * TRLWE_WORDS + h * RING_N;
   const u32* x1 = x0 + TRLWE_WORDS;
   const u64* C = sel + (r * sel_r_stride + (uint64_t)selbit) * TRGSW_NTT_U64;
-  u64* reg = lds + wave * WAVE_LDS_U64 + h * TREGION;
-  u32 D[32], acc[32];
+  u32* reg = lds + wave * WAVE_T_U32 + h * TREGION;
+  u32 D[32], acc[32], z[32];
 #pragma unroll
   for (int t = 0; t < 32; t++) {
     const u32 a = x0[l + 32 * t], b = x1[l + 32 * t];
     acc[t] = a;
     D[t] = b - a;
   }
-  external_product_acc(D, C, tw, tw + 1024, reg, lane, acc);
+  external_product(OperandDigits{D}, C, tw, tw + 1024, reg, lane, z);
+#pragma unroll
+  for (int t = 0; t < 32; t++) acc[t] += z[t];
   u32* o = out + job * TRLWE_WORDS + h * RING_N;
 #pragma unroll
   for (int t = 0; t < 32; t++) o[l + 32 * t] = acc[t];
@@ -42,20 +44,22 @@ __global__ __launch_bounds__(256) void k_cmux_tree_level(const u64* __restrict__
 __global__ __launch_bounds__(256) void k_rom_rotate(const u64* __restrict__ sel, uint64_t sel_r_stride,
                                                     u32* __restrict__ accbuf, uint64_t R, int rotbits, int w,
                                                     const u64* __restrict__ tw) {
-  __shared__ u64 lds[4 * WAVE_LDS_U64];
+  __shared__ u32 lds[4 * WAVE_T_U32];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint64_t r = (uint64_t)blockIdx.x * 4 + wave;
   if (r >= R) return;
   const int lane = threadIdx.x & 63, l = lane & 31, h = lane >> 5;
-  u64* reg = lds + wave * WAVE_LDS_U64 + h * TREGION;
+  u32* reg = lds + wave * WAVE_T_U32 + h * TREGION;
   u32* p = accbuf + r * TRLWE_WORDS + h * RING_N;
-  u32 acc[32], D[32];
+  u32 acc[32], D[32], z[32];
 #pragma unroll
   for (int t = 0; t < 32; t++) acc[t] = p[l + 32 * t];
   for (int j = 0; j < rotbits; j++) {
     const int k = (2 * RING_N - (w << j)) & (2 * RING_N - 1);
     rotate_minus(acc, k, reg, l, D);
-    external_product_acc(D, sel + (r * sel_r_stride + (uint64_t)j) * TRGSW_NTT_U64, tw, tw + 1024, reg, lane, acc);
+    external_product(OperandDigits{D}, sel + (r * sel_r_stride + (uint64_t)j) * TRGSW_NTT_U64, tw, tw + 1024, reg, lane, z);
+#pragma unroll
+    for (int t = 0; t < 32; t++) acc[t] += z[t];
   }
 #pragma unroll
   for (int t = 0; t < 32; t++) p[l + 32 * t] = acc[t];
@@ -91,16 +95,16 @@ __global__ __launch_bounds__(256) void k_ram_control(const u32* __restrict__ acc
 __global__ __launch_bounds__(256) void k_ram_bars(const u64* __restrict__ sel, const u64* __restrict__ selneg,
                                                   const u32* __restrict__ ram, const u32* __restrict__ u,
                                                   u32* __restrict__ tlwe1, int v, int w, const u64* __restrict__ tw) {
-  __shared__ u64 lds[4 * WAVE_LDS_U64];
+  __shared__ u32 lds[4 * WAVE_T_U32];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint64_t bar = (uint64_t)blockIdx.x * 4 + wave;
   if (bar >= ((uint64_t)w << v)) return;
   const int lane = threadIdx.x & 63, l = lane & 31, h = lane >> 5;
   const uint64_t i = bar >> v, A = bar & ((1ull << v) - 1);
-  u64* reg = lds + wave * WAVE_LDS_U64 + h * TREGION;
+  u32* reg = lds + wave * WAVE_T_U32 + h * TREGION;
   const u32* old = ram + bar * TRLWE_WORDS + h * RING_N;
   const u32* ui = u + i * TRLWE_WORDS + h * RING_N;
-  u32 o[32], y[32], D[32];
+  u32 o[32], y[32], D[32], z[32];
 #pragma unroll
   for (int t = 0; t < 32; t++) {
     o[t] = old[l + 32 * t];
@@ -109,11 +113,10 @@ __global__ __launch_bounds__(256) void k_ram_bars(const u64* __restrict__ sel, c
   for (int d = 0; d < v; d++) {
     const u64* C = (((A >> d) & 1) ? sel : selneg) + (size_t)d * TRGSW_NTT_U64;
 #pragma unroll
-    for (int t = 0; t < 32; t++) {
-      D[t] = y[t] - o[t];
-      y[t] = o[t];
-    }
-    external_product_acc(D, C, tw, tw + 1024, reg, lane, y);
+    for (int t = 0; t < 32; t++) D[t] = y[t] - o[t];
+    external_product(OperandDigits{D}, C, tw, tw + 1024, reg, lane, z);
+#pragma unroll
+    for (int t = 0; t < 32; t++) y[t] = o[t] + z[t];
   }
   u32* out = tlwe1 + bar * (RING_N + 1);
   if (h == 0) {
@@ -397,14 +400,14 @@ vsp_status vsp_ram_write(vsp_context* ctx, uint32_t* d_ram, uint32_t v, uint32_t
   if ((e = launch_gate_prologue(ctx, ops, src, src, idx, idx + 2 * w, nullptr, abar, nullptr, 2 * (uint64_t)w, st,
                                 false)) != hipSuccess)
     return hip_fail(e, "control prologue");
-  if ((e = launch_blind_rotate(ctx, ops, abar, nullptr, acc2, 2 * (uint64_t)w, ctx->tune.br_waves, st)) != hipSuccess)
+  if ((e = launch_blind_rotate(ctx, ops, abar, nullptr, acc2, 2 * (uint64_t)w, 0, st)) != hipSuccess)
     return hip_fail(e, "control bootstraps");
   if ((e = launch_ram_control(acc2, u, (int)w, st)) != hipSuccess) return hip_fail(e, "control combine");
   // write unit: bars, then refresh every cell with a bootstrap back to TRLWE, in place
   if ((e = launch_ram_bars(ctx, sel, selneg, d_ram, u, t1, (int)v, (int)w, st)) != hipSuccess) return hip_fail(e, "write bars");
   if ((e = launch_keyswitch(ctx, nullptr, t1, nullptr, t0, cells, st)) != hipSuccess) return hip_fail(e, "refresh key switch");
   if ((e = launch_gate_prologue_uniform(ctx, OP_IDENT, t0, abar, cells, st)) != hipSuccess) return hip_fail(e, "refresh prologue");
-  if ((e = launch_blind_rotate(ctx, nullptr, abar, nullptr, d_ram, cells, ctx->tune.br_waves, st)) != hipSuccess)
+  if ((e = launch_blind_rotate(ctx, nullptr, abar, nullptr, d_ram, cells, 0, st)) != hipSuccess)
     return hip_fail(e, "refresh bootstraps");
   return VSP_OK;
 }

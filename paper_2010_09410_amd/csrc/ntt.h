@@ -27,15 +27,17 @@ constexpr int KS_BASEBIT = 2;
 constexpr u32 MU = 1u << 29;                // 1/8
 constexpr u32 DECOMP_OFFSET = 0x82082000u;  // sum_r (Bg/2) 2^(32-6r) + 2^(32-18-1)
 
-// One transform region: 32 rows of 33 u64 (the pad column keeps LDS accesses conflict-free).
+// One transpose region per half-wave: 32 rows of 33 u32 (the pad column keeps the row and
+// column accesses of a half-wave on distinct LDS banks); 64-bit values cross it in two
+// 32-bit passes. The regions of the two halves start 32 words apart modulo the bank count.
 constexpr int TROW = 33;
-constexpr int TREGION = 32 * TROW + 16;     // + pad so the two halves start 16 u64 apart
-constexpr int WAVE_LDS_U64 = 2 * TREGION;   // per wave
+constexpr int TREGION = 32 * TROW + 64;     // u32 per half
+constexpr int WAVE_T_U32 = 2 * TREGION;     // u32 per wave
 
-// External-product key layout in u64: [round k][c'][slot s][lane] per TRGSW, where
-// lanes 0-31 carry row k and lanes 32-63 row k+3; c' = 0 is the output polynomial the
-// half owns (a for lanes 0-31, b for lanes 32-63) and c' = 1 the other one.
-constexpr int TRGSW_NTT_U64 = GADGET_L * 2 * 32 * 64;
+// External-product key layout in u64, per TRGSW: [round k][slot s][lane][c], where lanes
+// 0-31 carry TRGSW row k and lanes 32-63 row k+3, and c selects the output polynomial
+// (0: a, 1: b). One 16-byte load gives a lane both entries of a slot.
+constexpr int TRGSW_NTT_U64 = GADGET_L * 32 * 64 * 2;
 
 constexpr int brv5(int k) {
   return ((k & 1) << 4) | ((k & 2) << 2) | (k & 4) | ((k & 8) >> 2) | ((k & 16) >> 4);
@@ -157,41 +159,69 @@ __device__ __forceinline__ void dft32_inverse(u64 (&v)[32]) {
   }
 }
 
-// Lane l, register k (residue brv5(k), coefficient l) -> lane u = brv5(k), register l.
-__device__ __forceinline__ void transpose_forward(u64 (&v)[32], u64* reg, int l) {
+// Lane l, register k (residue brv5(k), coefficient l) -> lane u = brv5(k), register l,
+// through the half-wave's u32 region (low words, then high words).
+__device__ __forceinline__ void transpose_forward(u64 (&v)[32], u32* reg, int l) {
+  u32 lo[32];
 #pragma unroll
-  for (int k = 0; k < 32; k++) reg[brv5(k) * TROW + l] = v[k];
+  for (int k = 0; k < 32; k++) reg[brv5(k) * TROW + l] = (u32)v[k];
   wave_lds_sync();
 #pragma unroll
-  for (int j = 0; j < 32; j++) v[j] = reg[l * TROW + j];
+  for (int j = 0; j < 32; j++) lo[j] = reg[l * TROW + j];
+  wave_lds_sync();
+#pragma unroll
+  for (int k = 0; k < 32; k++) reg[brv5(k) * TROW + l] = (u32)(v[k] >> 32);
+  wave_lds_sync();
+#pragma unroll
+  for (int j = 0; j < 32; j++) v[j] = ((u64)reg[l * TROW + j] << 32) | lo[j];
   wave_lds_sync();
 }
 
 // Inverse of transpose_forward.
-__device__ __forceinline__ void transpose_inverse(u64 (&v)[32], u64* reg, int l) {
+__device__ __forceinline__ void transpose_inverse(u64 (&v)[32], u32* reg, int l) {
+  u32 lo[32];
 #pragma unroll
-  for (int j = 0; j < 32; j++) reg[j * TROW + l] = v[j];
+  for (int j = 0; j < 32; j++) reg[j * TROW + l] = (u32)v[j];
   wave_lds_sync();
 #pragma unroll
-  for (int k = 0; k < 32; k++) v[k] = reg[l * TROW + brv5(k)];
+  for (int k = 0; k < 32; k++) lo[k] = reg[l * TROW + brv5(k)];
   wave_lds_sync();
+#pragma unroll
+  for (int j = 0; j < 32; j++) reg[j * TROW + l] = (u32)(v[j] >> 32);
+  wave_lds_sync();
+#pragma unroll
+  for (int k = 0; k < 32; k++) v[k] = ((u64)reg[l * TROW + brv5(k)] << 32) | lo[k];
+  wave_lds_sync();
+}
+
+// v[j] *= T[j][l] for j >= 1 (T[0][*] = 1), loading the table entries eight at a time so that
+// at most sixteen of them are in flight.
+__device__ __forceinline__ void table_multiply(u64 (&v)[32], const u64* T, int l) {
+#pragma unroll
+  for (int c = 0; c < 4; c++) {
+    u64 w[8];
+#pragma unroll
+    for (int q = 0; q < 8; q++) w[q] = (8 * c + q == 0) ? 1 : T[(8 * c + q) * 32 + l];
+#pragma unroll
+    for (int q = 0; q < 8; q++)
+      if (8 * c + q != 0) v[8 * c + q] = gl_mul(v[8 * c + q], w[q]);
+    __builtin_amdgcn_sched_barrier(0);
+  }
 }
 
 // Forward transform of this half's polynomial (values already residues mod p).
 // tf is the [j][u] table psi_u^j (in LDS or global memory).
-__device__ __forceinline__ void ntt_forward(u64 (&v)[32], const u64* tf, u64* reg, int l) {
+__device__ __forceinline__ void ntt_forward(u64 (&v)[32], const u64* tf, u32* reg, int l) {
   pass1_forward(v);
   transpose_forward(v, reg, l);
-#pragma unroll
-  for (int j = 1; j < 32; j++) v[j] = gl_mul(v[j], tf[j * 32 + l]);
+  table_multiply(v, tf, l);
   dft32_forward(v);
 }
 
 // Inverse transform (unscaled: returns N times the polynomial); ti is psi_u^-j.
-__device__ __forceinline__ void ntt_inverse(u64 (&v)[32], const u64* ti, u64* reg, int l) {
+__device__ __forceinline__ void ntt_inverse(u64 (&v)[32], const u64* ti, u32* reg, int l) {
   dft32_inverse(v);
-#pragma unroll
-  for (int j = 1; j < 32; j++) v[j] = gl_mul(v[j], ti[j * 32 + l]);
+  table_multiply(v, ti, l);
   transpose_inverse(v, reg, l);
   pass1_inverse(v);
 }
@@ -205,67 +235,79 @@ __device__ __forceinline__ u64 gadget_digit(u32 x, int sh) {
   return gl_from_i32(d);
 }
 
-// Wave-cooperative external product: this half's polynomial of C (ext) D, added to acc.
-// D holds this half's polynomial of the TRLWE operand (lanes 0-31: a, lanes 32-63: b);
-// Cn is the TRGSW in the key layout above (already scaled by 1/N). Round k transforms
-// digit k+1 of both halves (rows k and k+3 of C); each lane multiplies its transformed
-// digits by the key entries of both output polynomials, keeps its own and passes the other
-// to the partner lane 32 away. Key entries stream from memory in chunks of KCH slots, the
-// next chunk in flight while the current one is used.
+// Sum over the two halves of a wave: lanes 0-31 receive P0[l] + P0[l + 32], lanes 32-63
+// receive P1[l - 32] + P1[l]. v_permlane32_swap exchanges the upper half-wave of its first
+// operand with the lower half-wave of its second, so after one swap per 32-bit word each
+// lane holds exactly the two terms it needs.
+__device__ __forceinline__ u64 sum_halves(u64 p0, u64 p1) {
+  const auto lo = __builtin_amdgcn_permlane32_swap((u32)p0, (u32)p1, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((u32)(p0 >> 32), (u32)(p1 >> 32), false, false);
+  const u64 a = ((u64)hi[0] << 32) | lo[0];
+  const u64 b = ((u64)hi[1] << 32) | lo[1];
+  return gl_add(a, b);
+}
+
+// Wave-cooperative external product: out = this half's polynomial of C (ext) D (lifted to
+// the torus). D holds this half's polynomial of the TRLWE operand (lanes 0-31: a, lanes
+// 32-63: b); Cn is the TRGSW in the key layout above (already scaled by 1/N). Round k
+// transforms gadget digit k+1 of both halves (TRGSW rows k and k+3); each lane multiplies
+// its transformed digits by the row's entries for both output polynomials, and the halves'
+// contributions are summed with one swap, lanes 0-31 accumulating output a and lanes 32-63
+// output b. Key entries stream in chunks of KCH slots, the next chunk in flight while the
+// current one is used.
 constexpr int KCH = 4;
 
-__device__ __forceinline__ void external_product_acc(const u32 (&D)[32], const u64* __restrict__ Cn,
-                                                     const u64* tf, const u64* ti, u64* reg, int lane,
-                                                     u32 (&acc)[32]) {
+// DigitSource: callable (int sh, u64 (&x)[32]) filling x with the gadget digit at bit offset
+// sh of this half's operand polynomial (as residues), e.g. OperandDigits below.
+template <class DigitSource>
+__device__ __forceinline__ void external_product(DigitSource digits, const u64* __restrict__ Cn, const u64* tf,
+                                                 const u64* ti, u32* reg, int lane, u32 (&out)[32]) {
   const int l = lane & 31;
   u64 x[32], sum[32];
 #pragma unroll
   for (int s = 0; s < 32; s++) sum[s] = 0;
 #pragma unroll 1
   for (int k = 0; k < GADGET_L; k++) {
-    const u64* key = Cn + (size_t)k * (2 * 32 * 64) + lane;
-    u64 ka[KCH], kb[KCH];
+    const ulonglong2* key = reinterpret_cast<const ulonglong2*>(Cn) + (size_t)k * 32 * 64 + lane;
+    ulonglong2 kc[KCH];
 #pragma unroll
-    for (int q = 0; q < KCH; q++) {
-      ka[q] = __builtin_nontemporal_load(key + q * 64);
-      kb[q] = __builtin_nontemporal_load(key + (32 + q) * 64);
-    }
-    const int sh = 32 - BG_BIT * (k + 1);
-#pragma unroll
-    for (int t = 0; t < 32; t++) x[t] = gadget_digit(D[t], sh);
+    for (int q = 0; q < KCH; q++) kc[q] = key[q * 64];
+    digits(32 - BG_BIT * (k + 1), x);
     ntt_forward(x, tf, reg, l);
 #pragma unroll
     for (int c = 0; c < 32 / KCH; c++) {
-      u64 na[KCH], nb[KCH];
+      ulonglong2 kn[KCH];
       if (c + 1 < 32 / KCH) {
 #pragma unroll
-        for (int q = 0; q < KCH; q++) {
-          na[q] = __builtin_nontemporal_load(key + (KCH * (c + 1) + q) * 64);
-          nb[q] = __builtin_nontemporal_load(key + (32 + KCH * (c + 1) + q) * 64);
-        }
+        for (int q = 0; q < KCH; q++) kn[q] = key[(KCH * (c + 1) + q) * 64];
       }
 #pragma unroll
       for (int q = 0; q < KCH; q++) {
         const int s = KCH * c + q;
-        const u64 keep = gl_mul(x[s], ka[q]);
-        const u64 send = gl_mul(x[s], kb[q]);
-        const u64 recv = __shfl_xor(send, 32);
-        sum[s] = gl_add(sum[s], gl_add(keep, recv));
+        const u64 p0 = gl_mul(x[s], kc[q].x);
+        const u64 p1 = gl_mul(x[s], kc[q].y);
+        sum[s] = gl_add(sum[s], sum_halves(p0, p1));
       }
       __builtin_amdgcn_sched_barrier(0);
       if (c + 1 < 32 / KCH) {
 #pragma unroll
-        for (int q = 0; q < KCH; q++) {
-          ka[q] = na[q];
-          kb[q] = nb[q];
-        }
+        for (int q = 0; q < KCH; q++) kc[q] = kn[q];
       }
     }
   }
   ntt_inverse(sum, ti, reg, l);
 #pragma unroll
-  for (int t = 0; t < 32; t++) acc[t] += gl_lift_u32(gl_canon(sum[t]));
+  for (int t = 0; t < 32; t++) out[t] = gl_lift_u32(gl_canon(sum[t]));
 }
+
+// Digits of an operand polynomial held in registers.
+struct OperandDigits {
+  const u32 (&D)[32];
+  __device__ __forceinline__ void operator()(int sh, u64 (&x)[32]) const {
+#pragma unroll
+    for (int t = 0; t < 32; t++) x[t] = gadget_digit(D[t], sh);
+  }
+};
 
 // Coefficient j of X^k * (mu, mu, ..., mu), k in [0, 2N).
 __device__ __forceinline__ u32 rotated_testvector(int j, int k) {
@@ -275,8 +317,7 @@ __device__ __forceinline__ u32 rotated_testvector(int j, int k) {
 }
 
 // D = X^k * P - P for this half's polynomial (k in [0, 2N)), through the LDS region.
-__device__ __forceinline__ void rotate_minus(const u32 (&P)[32], int k, u64* reg, int l, u32 (&D)[32]) {
-  u32* buf = reinterpret_cast<u32*>(reg);
+__device__ __forceinline__ void rotate_minus(const u32 (&P)[32], int k, u32* buf, int l, u32 (&D)[32]) {
 #pragma unroll
   for (int t = 0; t < 32; t++) buf[l + 32 * t] = P[t];
   wave_lds_sync();

@@ -225,7 +225,7 @@ void worker_loop(vsp_server* s) {
     hipError_t e = launch_gate_prologue(s->ctx, sl.d_ops, s->arena, s->arena, sl.d_idx, sl.d_idx + M, sl.d_idx + 2 * M,
                                         sl.d_abar, s->arena, nb, st);
     if (e == hipSuccess)
-      e = launch_blind_rotate(s->ctx, sl.d_ops, sl.d_abar, sl.d_tlwe1, nullptr, nb, s->ctx->tune.br_waves, st);
+      e = launch_blind_rotate(s->ctx, sl.d_ops, sl.d_abar, sl.d_tlwe1, nullptr, nb, 0, st);
     if (e == hipSuccess) e = launch_keyswitch(s->ctx, sl.d_ops, sl.d_tlwe1, sl.d_idx + 2 * M, s->arena, nb, st);
     if (e == hipSuccess) e = hipEventRecord(sl.ev, st);
     if (e != hipSuccess) {

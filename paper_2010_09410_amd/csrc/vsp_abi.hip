@@ -273,7 +273,7 @@ static vsp_status gates_impl(vsp_context* ctx, const uint8_t* d_ops, const uint3
       if (e != hipSuccess) return hip_fail(e, "gate prologue");
       {
         ProfScope ps(ctx, 0, st);
-        e = launch_blind_rotate(ctx, ops, abar, nullptr, o, nb, ctx->tune.br_waves, st);
+        e = launch_blind_rotate(ctx, ops, abar, nullptr, o, nb, 0, st);
       }
       if (e != hipSuccess) return hip_fail(e, "blind rotation");
     } else {
@@ -285,7 +285,7 @@ static vsp_status gates_impl(vsp_context* ctx, const uint8_t* d_ops, const uint3
       if (e != hipSuccess) return hip_fail(e, "gate prologue");
       {
         ProfScope ps(ctx, 0, st);
-        e = launch_blind_rotate(ctx, ops, abar, t1, nullptr, nb, ctx->tune.br_waves, st);
+        e = launch_blind_rotate(ctx, ops, abar, t1, nullptr, nb, 0, st);
       }
       if (e != hipSuccess) return hip_fail(e, "blind rotation");
       {

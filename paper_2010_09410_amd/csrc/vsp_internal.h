@@ -22,9 +22,20 @@ __host__ __device__ inline bool op_bootstraps(uint32_t op) { return op < 8 || op
 // Device-side error flags (bits), read back by vsp_context_sync.
 constexpr int DEVERR_BAD_OP = 1;
 
+// Launch choices per batch-size bucket (bucket b covers batches in [kBucket[b], kBucket[b+1])),
+// set by vsp_autotune or left at the defaults. Every choice gives bit-identical results.
+constexpr int kTuneBuckets = 7;
+constexpr uint64_t kBucket[kTuneBuckets] = {1, 16, 64, 256, 1024, 2048, 4096};
+
 struct Tuning {
-  int br_waves = 4;      // waves (gates) per workgroup of the blind-rotation kernel (4 or 8)
-  int ks_gates = 1;      // gates per workgroup of the key-switch kernel
+  int br_waves[kTuneBuckets] = {8, 8, 8, 8, 8, 8, 8};  // blind-rotation workgroup: 4 or 8 waves (gates)
+  int ks_tiled[kTuneBuckets] = {0, 0, 0, 1, 1, 1, 1};  // key switch: 0 gather per gate, 1 tiled row-stationary
+  bool tuned = false;
+  static int bucket(uint64_t B) {
+    int b = 0;
+    while (b + 1 < kTuneBuckets && B >= kBucket[b + 1]) b++;
+    return b;
+  }
 };
 
 // Growable device scratch owned by a context.
@@ -97,12 +108,15 @@ hipError_t launch_gate_prologue(const vsp_context* ctx, const uint8_t* ops, cons
 hipError_t launch_gate_prologue_uniform(const vsp_context* ctx, uint32_t op, const uint32_t* in0, uint32_t* abar,
                                         uint64_t B, hipStream_t st);
 // Blind rotation of B gates (abar from the prologue). Writes SE_0 (TLWE1 [B][N+1]) and/or
-// the accumulator (TRLWE [B][2][N], optionally scattered by trlwe_idx).
+// the accumulator (TRLWE [B][2][N]). waves: 4 or 8 gates per workgroup, <= 0 the tuned choice.
 hipError_t launch_blind_rotate(const vsp_context* ctx, const uint8_t* ops, const uint32_t* abar, uint32_t* tlwe1,
                                uint32_t* trlwe, uint64_t B, int waves, hipStream_t st);
 // Identity key switch TLWE1 [B][N+1] -> TLWE0 [B][n+1] (outputs scattered by idxo if given).
+// tiled: 1 row-stationary tiles of gates, 0 one workgroup per gate, -1 the tuned choice.
 hipError_t launch_keyswitch(const vsp_context* ctx, const uint8_t* ops, const uint32_t* tlwe1, const uint32_t* idxo,
-                            uint32_t* out, uint64_t B, hipStream_t st);
+                            uint32_t* out, uint64_t B, hipStream_t st, int tiled = -1);
+// Blind-rotation workgroup sizes the kernels are instantiated for (waves = gates per group).
+constexpr int kBrWaveChoices[2] = {4, 8};
 // out[j] = C_j (ext) x_j, or with `x0` given: out[j] = x0_j + C_j (ext) (x_j - x0_j).
 hipError_t launch_ext_product(const vsp_context* ctx, const uint64_t* Cn, const uint32_t* x, uint32_t* out,
                               uint64_t J, hipStream_t st);

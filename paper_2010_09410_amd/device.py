@@ -102,6 +102,16 @@ class Context:
         v = int(cells).bit_length() - 1
         nv.vsp_ram_write(self.handle, _ptr(ram), v, w, _ptr(addr), _ptr(flag), _ptr(data), self.stream())
 
+    # -------------------------------------------------------------- launch tuning
+    def autotune(self, max_batch: int = 4096, cache_path: str | None = None) -> None:
+        nv.vsp_autotune(self.handle, max_batch, cache_path)
+
+    def tuning(self, B: int):
+        return nv.vsp_tuning_get(self.handle, B)
+
+    def set_tuning(self, B: int, br_waves: int, ks_tiled: int) -> None:
+        nv.vsp_tuning_set(self.handle, B, br_waves, ks_tiled)
+
     # -------------------------------------------------------------- circuits / serving
     def circuit(self, gates, ninputs: int) -> "Circuit":
         return Circuit(self, gates, ninputs)

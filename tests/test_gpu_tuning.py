@@ -1,0 +1,76 @@
+"""Launch-shape invariance: every blind-rotation workgroup shape and key-switch form gives the
+same ciphertexts bit for bit (integer arithmetic), equal to the oracle's; the autotuner keeps
+valid choices and round-trips them through its cache file."""
+import json
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from paper_2010_09410_amd import VspError, client
+from paper_2010_09410_amd.device import to_host
+
+pytestmark = pytest.mark.gpu
+SHAPES = [(4, 0), (4, 1), (8, 0), (8, 1)]
+
+
+def batch(keys, B, seed):
+    cfg = W.gate_batch(seed, B)
+    g = W.rng(900 + seed)
+    cfg["ops"] = g.integers(0, 9, B).astype(np.uint8)  # all nine opcodes, NOT included
+    in0 = client.tlwe_encrypt_bits(keys["s0"], cfg["bits0"], *cfg["enc0"])
+    in1 = client.tlwe_encrypt_bits(keys["s0"], cfg["bits1"], *cfg["enc1"])
+    return cfg, in0, in1
+
+
+@pytest.mark.parametrize("B,sample", [(37, None), (300, 12)])
+def test_every_launch_shape_bit_identical(gpu, keys, B, sample):
+    """B=37 and B=300 are ragged for 4- and 8-gate workgroups and for 16-gate key-switch tiles."""
+    saved = gpu.tuning(B)
+    cfg, in0, in1 = batch(keys, B, 31 + B)
+    d0, d1, dops = gpu.tensor(in0), gpu.tensor(in1), gpu.tensor(cfg["ops"])
+    outs = []
+    try:
+        for w, t in SHAPES:
+            gpu.set_tuning(B, w, t)
+            assert gpu.tuning(B) == (w, t)
+            outs.append(to_host(gpu.gates(dops, d0, d1)))
+    finally:
+        gpu.set_tuning(B, *saved)
+    for o, shape in zip(outs[1:], SHAPES[1:]):
+        np.testing.assert_array_equal(o, outs[0], err_msg=f"shape {shape}")
+    idx = np.arange(B) if sample is None else np.unique(np.r_[0, B - 1, W.rng(7).choice(B, sample, replace=False)])
+    ref = oracle.gates(keys["bk"], keys["ksk"], cfg["ops"][idx], in0[idx], in1[idx])
+    np.testing.assert_array_equal(outs[0][idx], ref)
+
+
+def test_tuning_set_rejects_unknown_shapes(gpu):
+    with pytest.raises(VspError):
+        gpu.set_tuning(64, 6, 0)
+    with pytest.raises(VspError):
+        gpu.set_tuning(64, 8, 2)
+
+
+def test_autotune_and_cache_round_trip(gpu, tmp_path):
+    saved = {b: gpu.tuning(b) for b in (1, 16, 64, 256, 1024, 2048, 4096)}
+    path = tmp_path / "tune.json"
+    try:
+        gpu.autotune(max_batch=64, cache_path=str(path))
+        doc = json.loads(path.read_text())
+        (key, entry), = doc.items()
+        assert key.startswith("gfx950")
+        assert len(entry["br_waves"]) == 7 and len(entry["ks_tiled"]) == 7
+        assert all(w in (4, 8) for w in entry["br_waves"]) and all(t in (0, 1) for t in entry["ks_tiled"])
+        for b, w, t in zip(entry["buckets"], entry["br_waves"], entry["ks_tiled"]):
+            assert gpu.tuning(b) == (w, t)
+        # a cache entry for this GPU is read back instead of measuring again
+        entry["br_waves"] = [4, 8, 4, 8, 4, 8, 4]
+        entry["ks_tiled"] = [1, 0, 1, 0, 1, 0, 1]
+        path.write_text(json.dumps({key: entry}))
+        gpu.autotune(max_batch=64, cache_path=str(path))
+        for b, w, t in zip(entry["buckets"], entry["br_waves"], entry["ks_tiled"]):
+            assert gpu.tuning(b) == (w, t)
+    finally:
+        for b, (w, t) in saved.items():
+            gpu.set_tuning(b, w, t)
