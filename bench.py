@@ -8,12 +8,16 @@ ciphertexts with the 80-bit parameter set (n = 630, N = 1024, l = 3, Bg = 64, t 
 Keys and inputs are synthetic (seeded) and resident in HBM before the timed region.
 
 Prints one JSON line (rank 0). Extra fields: the per-gate rate (one launch sequence per
-gate), the batched / per-gate ratio, per-level p50/p99 latency of the 64-level circuit,
-the roofline of the blind-rotation kernel and the CPU oracle baseline.
+gate), the batched / per-gate ratio, per-level p50/p99 latency of the 64-level circuit, a
+serving run (Poisson arrivals of layered circuits from 64 clients: throughput and p50/p99
+circuit latency), the integer-ALU and HBM rooflines of the blind-rotation kernel and the
+CPU oracle baseline.
 """
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -50,6 +54,37 @@ def br_step_lane_ops() -> int:
 LANE_OPS_PER_GATE = STEPS_BR * br_step_lane_ops()
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9            # CUs x SIMDs x lanes/clk x clock: 39.3 T/s
 BK_NTT_BYTES = N_LWE * 2 * GL * 2 * N_RING * 8  # key stream read by every gate (61.93 MB)
+HBM_PEAK = 8.0e12                               # bytes/s
+
+
+def br_hbm_bytes(B: int) -> int:
+    """Algorithmic HBM bytes of one blind-rotation launch over B gates: the key once, the
+    opcodes and modulus-switched inputs read, the extracted TLWE rows written."""
+    return BK_NTT_BYTES + B * (1 + (N_LWE + 1) * 4 + (N_RING + 1) * 4)
+
+
+def br_fingerprint() -> str:
+    h = hashlib.sha256()
+    for f in ("gl64.h", "ntt.h", "blind_rotate.h"):
+        with open(os.path.join(ROOT, "paper_2010_09410_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per blind-rotation launch from a committed rocprofv3 summary of this exact
+    kernel source (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), else None."""
+    fp = br_fingerprint()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.txt"))):
+        fields = {}
+        with open(path) as fh:
+            for line in fh:
+                if line.startswith("traffic_"):
+                    k, _, v = line.partition(":")
+                    fields[k.strip()] = v.strip()
+        if fields.get("traffic_fingerprint") == fp and "traffic_bytes_per_launch" in fields:
+            return int(fields["traffic_bytes_per_launch"]), os.path.basename(path)
+    return None, None
 
 
 def parse():
@@ -61,23 +96,69 @@ def parse():
     ap.add_argument("--no-circuit", action="store_true", help="skip the per-level circuit latency")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
-    ap.add_argument("--cpu-gates", type=int, default=0, help="oracle sample size (default 4 x cores)")
+    ap.add_argument("--cpu-gates", type=int, default=0, help="oracle sample size (default: about 12 s of work)")
+    ap.add_argument("--serving", type=float, default=2.0, metavar="SECONDS",
+                    help="arrival window of the serving run (0 skips it)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run one plain device copy of MIB MiB (reference for HBM byte counters)")
     return ap.parse_args()
 
 
 def cpu_baseline(s0, s1, bkd, kskd, cfg, in0, in1, ngates):
-    """The CPU oracle (test infrastructure) on this host's cores, on a bounded sample."""
+    """The CPU oracle (test infrastructure) on this host's cores, on a bounded sample sized
+    to about 12 s of work from a short first pass."""
     import oracle
     threads = max(1, len(os.sched_getaffinity(0)))
-    ngates = ngates or 4 * threads
     bk, ksk = oracle.keyset(s0, s1, bkd, kskd)
+    if not ngates:
+        n0 = 2 * threads
+        t0 = time.perf_counter()
+        oracle.gates(bk, ksk, cfg["ops"][:n0], in0[:n0], in1[:n0], threads=threads)
+        rate0 = n0 / (time.perf_counter() - t0)
+        ngates = int(min(len(cfg["ops"]), max(n0, round(rate0 * 12.0 / threads) * threads)))
     t0 = time.perf_counter()
     oracle.gates(bk, ksk, cfg["ops"][:ngates], in0[:ngates], in1[:ngates], threads=threads)
     dt = time.perf_counter() - t0
-    return {"value": ngates / dt, "unit": "gate bootstraps/s", "cores": threads, "kind": "oracle",
+    return {"value": round(ngates / dt, 2), "unit": "gate bootstraps/s", "cores": threads, "kind": "oracle",
             "sample": f"first {ngates} gates of the 4096-gate batch, {threads} threads, {dt:.1f} s"}
+
+
+def serving_run(ctx, s0, duration: float, mem_budget: int = 2 << 30):
+    """Replays Poisson arrivals of layered circuits from 64 clients in real time against the
+    continuous-batching server; inputs are encrypted before the clock starts."""
+    import workloads as W
+    from paper_2010_09410_amd import client
+    trace = W.serving_trace(duration=duration)
+    enc = [client.tlwe_encrypt_bits(s0, r["bits"], *W.tlwe_draws(W.rng(r["enc_seed"]), r["ninputs"]))
+           for r in trace]
+    srv = ctx.server(mem_budget, max_batch=4096)
+    pending, lat, done_t = {}, [], []
+    i = 0
+    t0 = time.perf_counter()
+    while i < len(trace) or pending:
+        now = time.perf_counter() - t0
+        while i < len(trace) and trace[i]["t"] <= now:
+            r = trace[i]
+            pending[srv.submit(r["gates"], r["ninputs"], enc[i])] = i
+            i += 1
+        for tk, j in list(pending.items()):
+            done, _, ms = srv.poll(tk, trace[j]["ninputs"] + len(trace[j]["gates"]))
+            if done:
+                lat.append(ms)
+                done_t.append(time.perf_counter() - t0)
+                del pending[tk]
+        time.sleep(0.002)
+    gates, batches, peak = srv.stats()
+    srv.close()
+    total = sum(len(r["gates"]) for r in trace)
+    span = max(done_t) - trace[0]["t"]
+    lat = np.array(lat)
+    return {"circuits": len(trace), "clients": 64, "gates": total, "arrival_window_s": duration,
+            "offered_gates_per_s": round(total / duration, 1), "served_gates_per_s": round(total / span, 1),
+            "makespan_s": round(span, 3), "p50_latency_ms": round(float(np.percentile(lat, 50)), 1),
+            "p99_latency_ms": round(float(np.percentile(lat, 99)), 1), "batches": int(batches),
+            "mean_batch": round(gates / max(batches, 1), 1), "peak_resident_MB": round(peak / 1e6, 1),
+            "memory_budget_MB": round(mem_budget / 1e6, 1)}
 
 
 def main():
@@ -155,12 +236,21 @@ def main():
                   "circuit_ms": float(lv.sum()), "gates_per_s": float(len(c3["gates"]) / (lv.sum() / 1e3))}
         circ.close()
 
+    serving = None
+    if args.serving > 0:
+        serving = serving_run(ctx, s0, args.serving)
+
     br_avg_ms = br_ms / max(br_n, 1)
     achieved = B_GATES * LANE_OPS_PER_GATE / (br_avg_ms * 1e-3) / 1e12
-    roof = {"bound": "alu", "kernel": "k_blind_rotate", "achieved": round(achieved, 3),
+    traffic, traffic_src = measured_traffic()
+    hbm = br_hbm_bytes(B_GATES) / (br_avg_ms * 1e-3)
+    roof = {"bound": "alu", "kernel": f"k_blind_rotate<{br_waves}>", "achieved": round(achieved, 3),
             "peak": round(PEAK_LANE_OPS / 1e12, 3), "unit": "T int32 lane-ops/s",
-            "frac": round(achieved * 1e12 / PEAK_LANE_OPS, 4), "traffic": None,
+            "frac": round(achieved * 1e12 / PEAK_LANE_OPS, 4), "traffic": traffic, "traffic_source": traffic_src,
             "avg_launch_ms": round(br_avg_ms, 3), "lane_ops_per_gate": LANE_OPS_PER_GATE,
+            "hbm": {"achieved": round(hbm / 1e9, 1), "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                    "frac": round(hbm / HBM_PEAK, 4), "algorithmic_bytes_per_launch": br_hbm_bytes(B_GATES),
+                    "measured_GBps": None if traffic is None else round(traffic / (br_avg_ms * 1e-3) / 1e9, 1)},
             "key_stream_GBps_requested": round(B_GATES * BK_NTT_BYTES / (br_avg_ms * 1e-3) / 1e9, 1),
             "keyswitch_avg_ms": round(ks_ms / max(ks_n, 1), 3),
             "launch": {"br_waves_per_workgroup": br_waves, "keyswitch": "tiled" if ks_tiled else "gather"}}
@@ -179,7 +269,7 @@ def main():
                    "batch": B_GATES, "parallelism": "single GPU"},
         "per_gate_value": None if per_gate is None else round(per_gate, 2),
         "batched_over_per_gate": None if per_gate is None else round(value / per_gate, 1),
-        "per_level": levels, "roofline": roof, "cpu_baseline": cpu,
+        "per_level": levels, "serving": serving, "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
 

@@ -182,19 +182,24 @@ vsp_status vsp_server_stats(vsp_server* s, uint64_t* gates, uint64_t* batches, u
 /* Stop the server thread (finishing admitted work) and free it. NULL is accepted. */
 vsp_status vsp_server_destroy(vsp_server* s);
 
-/* Autotuner for the batched launches (the level executor's tile and batch shapes): for each
- * batch-size bucket up to max_batch (buckets start at 1, 16, 64, 256, 1024, 2048, 4096 gates)
- * times the blind-rotation workgroup shape (4 or 8 gates per workgroup) and the key-switch form
- * (one workgroup per gate, or row-stationary tiles of 16 gates) on random ciphertexts, requires
- * every candidate to produce bit-identical outputs (else VSP_E_HIP), and keeps the fastest in
- * the context. With cache_path non-NULL the choices are read from that JSON file when it holds
- * an entry for this GPU, and otherwise measured and written there. Synchronous. */
+/* Autotuner for the batched launches (the level executor's tile and batch shapes). A gate's
+ * blind rotation is one wave, so a batch of B gates runs in ceil(B / cap) rounds, cap being
+ * the gates the GPU holds at once for a workgroup shape (4 or 8 gates per workgroup). This
+ * call times one full round of each shape on random ciphertexts, and times both key-switch
+ * forms (one workgroup per gate, or row-stationary tiles of 16 gates) for each batch-size
+ * bucket up to max_batch (buckets end at 1, 16, 64, 256, 1024, 2048, 4096 gates; larger
+ * batches share the last). Every candidate must give bit-identical outputs (else VSP_E_HIP).
+ * Later launches pick the shape with the fewest rounds x round time, and the faster key
+ * switch for their bucket. With cache_path non-NULL the measurements are read from that JSON
+ * file when it holds an entry for this GPU, and otherwise measured and written there.
+ * Synchronous; allocates and frees its own buffers. */
 vsp_status vsp_autotune(vsp_context* ctx, uint64_t max_batch, const char* cache_path);
 
-/* The launch choice used for a batch of B gates: *br_waves (4 or 8), *ks_tiled (0 or 1). */
+/* The launch choice for a batch of B gates: *br_waves (4 or 8), *ks_tiled (0 or 1). */
 vsp_status vsp_tuning_get(const vsp_context* ctx, uint64_t B, int* br_waves, int* ks_tiled);
 
-/* Override the launch choice for the bucket containing B (results are unchanged). */
+/* Pin the launch choice for the bucket containing B: br_waves 4 or 8 (0 returns that bucket
+ * to the round-time model), ks_tiled 0 or 1. Results are the same for every choice. */
 vsp_status vsp_tuning_set(vsp_context* ctx, uint64_t B, int br_waves, int ks_tiled);
 
 /* Kernel-time instrumentation (for benchmarks): while enabled, every eager launch of the

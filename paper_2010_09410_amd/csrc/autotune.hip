@@ -1,8 +1,9 @@
-// Autotuner for the batched launches: per batch-size bucket, times the blind-rotation
-// workgroup shape (4 or 8 gates per workgroup) and the key-switch form (one workgroup per
-// gate, or row-stationary tiles of gates) on random ciphertexts, requires every candidate to
-// produce bit-identical outputs, and keeps the fastest in the context. Choices can be cached
-// in a small JSON file keyed by the GPU.
+// Autotuner for the batched launches. On random ciphertexts it times one full round of gates
+// for each blind-rotation workgroup shape (4 or 8 gates per workgroup; the launch then picks
+// the shape with the fewest rounds x round time for its batch) and both key-switch forms (one
+// workgroup per gate, or row-stationary tiles of gates) per batch-size bucket. Every
+// candidate must produce bit-identical outputs. The result can be cached in a small JSON file
+// keyed by the GPU.
 #include <cstdio>
 #include <cstring>
 #include <fstream>
@@ -45,7 +46,25 @@ std::string device_key(int dev) {
   return arch + "-" + std::to_string(p.multiProcessorCount) + "cu";
 }
 
-// JSON: {"<device>": {"br_waves": [..], "ks_tiled": [..]}, ...}
+// Cache file: {"<device>": {"br_waves": [4, 8], "br_cap": [..], "br_round_ms": [..],
+//                          "buckets": [..], "ks_tiled": [..]}}
+bool read_numbers(const std::string& s, size_t from, const char* name, double* out, int count) {
+  const size_t p = s.find(std::string("\"") + name + "\"", from);
+  if (p == std::string::npos) return false;
+  const size_t lb = s.find('[', p);
+  if (lb == std::string::npos) return false;
+  const char* c = s.c_str() + lb + 1;
+  for (int i = 0; i < count; i++) {
+    char* end = nullptr;
+    const double v = std::strtod(c, &end);
+    if (end == c) return false;
+    out[i] = v;
+    c = end;
+    while (*c == ',' || *c == ' ') c++;
+  }
+  return *c == ']';
+}
+
 bool read_cache(const std::string& path, const std::string& key, Tuning& t) {
   std::ifstream f(path);
   if (!f) return false;
@@ -54,26 +73,20 @@ bool read_cache(const std::string& path, const std::string& key, Tuning& t) {
   const std::string s = ss.str();
   const size_t at = s.find("\"" + key + "\"");
   if (at == std::string::npos) return false;
-  auto read_array = [&](const char* name, int* out) {
-    const size_t p = s.find(std::string("\"") + name + "\"", at);
-    if (p == std::string::npos) return false;
-    const size_t lb = s.find('[', p);
-    if (lb == std::string::npos) return false;
-    const char* c = s.c_str() + lb + 1;
-    for (int b = 0; b < kTuneBuckets; b++) {
-      char* end = nullptr;
-      const long v = std::strtol(c, &end, 10);
-      if (end == c) return false;
-      out[b] = (int)v;
-      c = end;
-      while (*c == ',' || *c == ' ') c++;
-    }
-    return true;
-  };
-  Tuning n;
-  if (!read_array("br_waves", n.br_waves) || !read_array("ks_tiled", n.ks_tiled)) return false;
-  for (int b = 0; b < kTuneBuckets; b++)
-    if ((n.br_waves[b] != 4 && n.br_waves[b] != 8) || (n.ks_tiled[b] != 0 && n.ks_tiled[b] != 1)) return false;
+  double cap[kBrShapes], ms[kBrShapes], ks[kTuneBuckets];
+  if (!read_numbers(s, at, "br_cap", cap, kBrShapes) || !read_numbers(s, at, "br_round_ms", ms, kBrShapes) ||
+      !read_numbers(s, at, "ks_tiled", ks, kTuneBuckets))
+    return false;
+  Tuning n = t;  // keeps forced shapes
+  for (int i = 0; i < kBrShapes; i++) {
+    if (!(cap[i] >= 1 && cap[i] < 1e9 && ms[i] > 0 && ms[i] < 1e9)) return false;
+    n.br_cap[i] = (uint64_t)cap[i];
+    n.br_round_ms[i] = (float)ms[i];
+  }
+  for (int b = 0; b < kTuneBuckets; b++) {
+    if (ks[b] != 0 && ks[b] != 1) return false;
+    n.ks_tiled[b] = (int)ks[b];
+  }
   n.tuned = true;
   t = n;
   return true;
@@ -82,13 +95,22 @@ bool read_cache(const std::string& path, const std::string& key, Tuning& t) {
 bool write_cache(const std::string& path, const std::string& key, const Tuning& t) {
   std::ofstream f(path, std::ios::trunc);
   if (!f) return false;
-  f << "{\"" << key << "\": {\"buckets\": [";
-  for (int b = 0; b < kTuneBuckets; b++) f << (b ? ", " : "") << kBucket[b];
-  f << "], \"br_waves\": [";
-  for (int b = 0; b < kTuneBuckets; b++) f << (b ? ", " : "") << t.br_waves[b];
-  f << "], \"ks_tiled\": [";
-  for (int b = 0; b < kTuneBuckets; b++) f << (b ? ", " : "") << t.ks_tiled[b];
-  f << "]}}\n";
+  auto list = [&](auto get, int count) {
+    f << "[";
+    for (int i = 0; i < count; i++) f << (i ? ", " : "") << get(i);
+    f << "]";
+  };
+  f << "{\"" << key << "\": {\"br_waves\": ";
+  list([](int i) { return kBrWaveChoices[i]; }, kBrShapes);
+  f << ", \"br_cap\": ";
+  list([&](int i) { return t.br_cap[i]; }, kBrShapes);
+  f << ", \"br_round_ms\": ";
+  list([&](int i) { return t.br_round_ms[i]; }, kBrShapes);
+  f << ", \"buckets\": ";
+  list([](int i) { return kBucket[i]; }, kTuneBuckets);
+  f << ", \"ks_tiled\": ";
+  list([&](int i) { return t.ks_tiled[i]; }, kTuneBuckets);
+  f << "}}\n";
   return (bool)f;
 }
 
@@ -110,7 +132,9 @@ vsp_status vsp_autotune(vsp_context* ctx, uint64_t max_batch, const char* cache_
   const std::string key = device_key(ctx->device);
   if (cache_path && read_cache(cache_path, key, ctx->tune)) return VSP_OK;
 
-  const uint64_t S = std::min<uint64_t>(max_batch, kBucket[kTuneBuckets - 1]);
+  const uint64_t Sks = std::min<uint64_t>(max_batch, kBucket[kTuneBuckets - 1]);
+  const uint64_t Sbr = std::max(ctx->tune.br_cap[0], ctx->tune.br_cap[1]);
+  const uint64_t S = std::max(Sks, Sbr);
   Buf in, ops32, ops, abar, t1, t1ref, out, outref;
   const size_t T0 = (LWE_N + 1) * 4, T1 = (RING_N + 1) * 4;
   VSP_HIP(hipMalloc(&in.p, 2 * S * T0));
@@ -156,27 +180,26 @@ vsp_status vsp_autotune(vsp_context* ctx, uint64_t max_batch, const char* cache_
     (void)hipMemcpy(hb.data(), b, bytes, hipMemcpyDeviceToHost);
     return std::memcmp(ha.data(), hb.data(), bytes) == 0;
   };
-  Tuning t;
+  Tuning t = ctx->tune;
   vsp_status result = VSP_OK;
+  // Blind rotation: one full round of gates per shape.
+  for (int s = 0; s < kBrShapes && result == VSP_OK; s++) {
+    uint32_t* dst = static_cast<uint32_t*>(s == 0 ? t1ref.p : t1.p);
+    const uint64_t B = t.br_cap[s];
+    t.br_round_ms[s] = timed([&] { (void)launch_blind_rotate(ctx, dops, dab, dst, nullptr, B, kBrWaveChoices[s], st); });
+    if (s > 0 && !same(t1ref.p, t1.p, std::min(t.br_cap[0], B) * T1))
+      result = fail(VSP_E_HIP, "autotune: blind-rotation shapes disagree");
+  }
+  // Key switch on random TLWE1 rows, per bucket, at the bucket's largest batch.
+  if (result == VSP_OK && (e = fill(static_cast<uint32_t*>(t1ref.p), S * (RING_N + 1), 0x7a11, 0, st)) != hipSuccess)
+    result = hip_fail(e, "fill");
   for (int b = 0; b < kTuneBuckets && result == VSP_OK; b++) {
-    const uint64_t B = std::min<uint64_t>(kBucket[b], S);
-    if (kBucket[b] > max_batch && b > 0) {  // beyond the range asked for: keep the previous choice
-      t.br_waves[b] = t.br_waves[b - 1];
+    if (b > 0 && kBucket[b - 1] >= Sks) {  // beyond the batches asked for: keep the previous choice
       t.ks_tiled[b] = t.ks_tiled[b - 1];
       continue;
     }
+    const uint64_t B = std::min<uint64_t>(kBucket[b], Sks);
     float best = 1e30f;
-    for (int c = 0; c < 2; c++) {
-      const int w = kBrWaveChoices[c];
-      uint32_t* dst = static_cast<uint32_t*>(c == 0 ? t1ref.p : t1.p);
-      const float ms = timed([&] { (void)launch_blind_rotate(ctx, dops, dab, dst, nullptr, B, w, st); });
-      if (c > 0 && !same(t1ref.p, t1.p, B * T1)) result = fail(VSP_E_HIP, "autotune: blind-rotation shapes disagree");
-      if (ms < best) {
-        best = ms;
-        t.br_waves[b] = w;
-      }
-    }
-    best = 1e30f;
     for (int c = 0; c < 2 && result == VSP_OK; c++) {
       uint32_t* dst = static_cast<uint32_t*>(c == 0 ? outref.p : out.p);
       const float ms = timed([&] { (void)launch_keyswitch(ctx, dops, static_cast<const uint32_t*>(t1ref.p), nullptr,
@@ -200,18 +223,17 @@ vsp_status vsp_autotune(vsp_context* ctx, uint64_t max_batch, const char* cache_
 
 vsp_status vsp_tuning_get(const vsp_context* ctx, uint64_t B, int* br_waves, int* ks_tiled) {
   if (ctx == nullptr || br_waves == nullptr || ks_tiled == nullptr) return fail(VSP_E_ARG, "NULL argument");
-  const int b = Tuning::bucket(B == 0 ? 1 : B);
-  *br_waves = ctx->tune.br_waves[b];
-  *ks_tiled = ctx->tune.ks_tiled[b];
+  *br_waves = ctx->tune.br_waves(B == 0 ? 1 : B);
+  *ks_tiled = ctx->tune.ks_tiled_for(B == 0 ? 1 : B) ? 1 : 0;
   return VSP_OK;
 }
 
 vsp_status vsp_tuning_set(vsp_context* ctx, uint64_t B, int br_waves, int ks_tiled) {
   if (ctx == nullptr) return fail(VSP_E_ARG, "context is NULL");
-  if ((br_waves != 4 && br_waves != 8) || (ks_tiled != 0 && ks_tiled != 1))
-    return fail(VSP_E_ARG, "br_waves must be 4 or 8 and ks_tiled 0 or 1");
+  if ((br_waves != 0 && br_waves != 4 && br_waves != 8) || (ks_tiled != 0 && ks_tiled != 1))
+    return fail(VSP_E_ARG, "br_waves must be 0 (model), 4 or 8 and ks_tiled 0 or 1");
   const int b = Tuning::bucket(B == 0 ? 1 : B);
-  ctx->tune.br_waves[b] = br_waves;
+  ctx->tune.br_force[b] = br_waves;
   ctx->tune.ks_tiled[b] = ks_tiled;
   return VSP_OK;
 }

@@ -177,6 +177,10 @@ vsp_status vsp_context_create(const vsp_params* params, const uint32_t* bk_host,
     vsp_context_destroy(ctx);
     return s;
   };
+  {
+    const hipError_t e = blind_rotate_capacity(device, ctx->tune.br_cap);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "occupancy query"));
+  }
   const size_t bk_words = (size_t)LWE_N * 2 * GADGET_L * 2 * RING_N;
   const size_t ksk_rows = (size_t)RING_N * KS_T * 4;
   hipError_t e;

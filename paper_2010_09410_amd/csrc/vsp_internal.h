@@ -14,6 +14,10 @@
 
 namespace vsp {
 
+// Row lengths of TLWE ciphertexts under the LWE key (n + 1) and the extracted ring key (N + 1).
+constexpr int TLWE0 = LWE_N + 1;
+constexpr int TLWE1 = RING_N + 1;
+
 // Internal opcode: bootstrap the first input unchanged (refresh of a noisy TLWE).
 constexpr uint8_t OP_IDENT = 16;
 
@@ -22,20 +26,50 @@ __host__ __device__ inline bool op_bootstraps(uint32_t op) { return op < 8 || op
 // Device-side error flags (bits), read back by vsp_context_sync.
 constexpr int DEVERR_BAD_OP = 1;
 
-// Launch choices per batch-size bucket (bucket b covers batches in [kBucket[b], kBucket[b+1])),
-// set by vsp_autotune or left at the defaults. Every choice gives bit-identical results.
+// Blind-rotation workgroup sizes the kernels are instantiated for (waves = gates per group).
+constexpr int kBrShapes = 2;
+constexpr int kBrWaveChoices[kBrShapes] = {4, 8};
+
+// Batch-size buckets: bucket b holds batches with kBucket[b-1] < B <= kBucket[b]; the last
+// one also holds every larger batch.
 constexpr int kTuneBuckets = 7;
 constexpr uint64_t kBucket[kTuneBuckets] = {1, 16, 64, 256, 1024, 2048, 4096};
 
+// Launch choices, set by vsp_autotune or left at the defaults. Every choice gives
+// bit-identical results.
+//  * Blind rotation: a gate is one wave from start to end, so a batch of B gates takes
+//    ceil(B / br_cap[s]) rounds of br_round_ms[s] with shape s, where br_cap[s] is the number
+//    of gates the whole GPU holds at once (occupancy x compute units x gates per group) and
+//    br_round_ms[s] the time of one full round. The shape with the fewer milliseconds wins
+//    (ties: the larger workgroup). br_force[b] != 0 pins the shape for bucket b.
+//  * Key switch: per bucket, 0 gathers key rows per gate, 1 reads them once per tile of gates.
 struct Tuning {
-  int br_waves[kTuneBuckets] = {8, 8, 8, 8, 8, 8, 8};  // blind-rotation workgroup: 4 or 8 waves (gates)
-  int ks_tiled[kTuneBuckets] = {0, 0, 0, 1, 1, 1, 1};  // key switch: 0 gather per gate, 1 tiled row-stationary
+  uint64_t br_cap[kBrShapes] = {1024, 2048};
+  float br_round_ms[kBrShapes] = {1.0f, 1.5f};
+  int br_force[kTuneBuckets] = {0, 0, 0, 0, 0, 0, 0};
+  int ks_tiled[kTuneBuckets] = {0, 0, 0, 0, 0, 1, 1};
   bool tuned = false;
   static int bucket(uint64_t B) {
     int b = 0;
-    while (b + 1 < kTuneBuckets && B >= kBucket[b + 1]) b++;
+    while (b + 1 < kTuneBuckets && B > kBucket[b]) b++;
     return b;
   }
+  int br_waves(uint64_t B) const {
+    const int f = br_force[bucket(B)];
+    if (f) return f;
+    int best = kBrShapes - 1;
+    double best_ms = 0;
+    for (int s = kBrShapes - 1; s >= 0; s--) {
+      const uint64_t cap = br_cap[s] ? br_cap[s] : 1;
+      const double ms = (double)((B + cap - 1) / cap) * br_round_ms[s];
+      if (s == kBrShapes - 1 || ms < best_ms) {
+        best = s;
+        best_ms = ms;
+      }
+    }
+    return kBrWaveChoices[best];
+  }
+  bool ks_tiled_for(uint64_t B) const { return ks_tiled[bucket(B)] != 0; }
 };
 
 // Growable device scratch owned by a context.
@@ -95,6 +129,8 @@ struct ProfScope {
 
 // ---------------------------------------------------------------- launchers (kernels.hip)
 hipError_t init_kernel_attributes();
+// Gates the device runs at once with each blind-rotation shape (resident groups x CUs x waves).
+hipError_t blind_rotate_capacity(int device, uint64_t (&cap)[kBrShapes]);
 // Torus TRGSW [count][2l][2][N] -> key layout [count][TRGSW_NTT_U64], scaled by 1/N.
 hipError_t launch_trgsw_to_ntt(const vsp_context* ctx, const uint32_t* src, uint64_t* dst, uint64_t count,
                                hipStream_t st);
@@ -115,8 +151,6 @@ hipError_t launch_blind_rotate(const vsp_context* ctx, const uint8_t* ops, const
 // tiled: 1 row-stationary tiles of gates, 0 one workgroup per gate, -1 the tuned choice.
 hipError_t launch_keyswitch(const vsp_context* ctx, const uint8_t* ops, const uint32_t* tlwe1, const uint32_t* idxo,
                             uint32_t* out, uint64_t B, hipStream_t st, int tiled = -1);
-// Blind-rotation workgroup sizes the kernels are instantiated for (waves = gates per group).
-constexpr int kBrWaveChoices[2] = {4, 8};
 // out[j] = C_j (ext) x_j, or with `x0` given: out[j] = x0_j + C_j (ext) (x_j - x0_j).
 hipError_t launch_ext_product(const vsp_context* ctx, const uint64_t* Cn, const uint32_t* x, uint32_t* out,
                               uint64_t J, hipStream_t st);

@@ -27,7 +27,7 @@ def batch(keys, B, seed):
 @pytest.mark.parametrize("B,sample", [(37, None), (300, 12)])
 def test_every_launch_shape_bit_identical(gpu, keys, B, sample):
     """B=37 and B=300 are ragged for 4- and 8-gate workgroups and for 16-gate key-switch tiles."""
-    saved = gpu.tuning(B)
+    _, saved_t = gpu.tuning(B)
     cfg, in0, in1 = batch(keys, B, 31 + B)
     d0, d1, dops = gpu.tensor(in0), gpu.tensor(in1), gpu.tensor(cfg["ops"])
     outs = []
@@ -37,7 +37,7 @@ def test_every_launch_shape_bit_identical(gpu, keys, B, sample):
             assert gpu.tuning(B) == (w, t)
             outs.append(to_host(gpu.gates(dops, d0, d1)))
     finally:
-        gpu.set_tuning(B, *saved)
+        gpu.set_tuning(B, 0, saved_t)
     for o, shape in zip(outs[1:], SHAPES[1:]):
         np.testing.assert_array_equal(o, outs[0], err_msg=f"shape {shape}")
     idx = np.arange(B) if sample is None else np.unique(np.r_[0, B - 1, W.rng(7).choice(B, sample, replace=False)])
@@ -52,25 +52,29 @@ def test_tuning_set_rejects_unknown_shapes(gpu):
         gpu.set_tuning(64, 8, 2)
 
 
-def test_autotune_and_cache_round_trip(gpu, tmp_path):
-    saved = {b: gpu.tuning(b) for b in (1, 16, 64, 256, 1024, 2048, 4096)}
+BUCKETS = (1, 16, 64, 256, 1024, 2048, 4096)
+
+
+def test_autotune_model_and_cache_round_trip(gpu, tmp_path):
+    saved = {b: gpu.tuning(b)[1] for b in BUCKETS}
     path = tmp_path / "tune.json"
     try:
         gpu.autotune(max_batch=64, cache_path=str(path))
-        doc = json.loads(path.read_text())
-        (key, entry), = doc.items()
+        (key, entry), = json.loads(path.read_text()).items()
         assert key.startswith("gfx950")
-        assert len(entry["br_waves"]) == 7 and len(entry["ks_tiled"]) == 7
-        assert all(w in (4, 8) for w in entry["br_waves"]) and all(t in (0, 1) for t in entry["ks_tiled"])
-        for b, w, t in zip(entry["buckets"], entry["br_waves"], entry["ks_tiled"]):
-            assert gpu.tuning(b) == (w, t)
-        # a cache entry for this GPU is read back instead of measuring again
-        entry["br_waves"] = [4, 8, 4, 8, 4, 8, 4]
-        entry["ks_tiled"] = [1, 0, 1, 0, 1, 0, 1]
-        path.write_text(json.dumps({key: entry}))
-        gpu.autotune(max_batch=64, cache_path=str(path))
-        for b, w, t in zip(entry["buckets"], entry["br_waves"], entry["ks_tiled"]):
-            assert gpu.tuning(b) == (w, t)
+        assert entry["br_waves"] == [4, 8] and list(entry["buckets"]) == list(BUCKETS)
+        cap4, cap8 = entry["br_cap"]
+        assert 256 <= cap4 < cap8 and all(ms > 0 for ms in entry["br_round_ms"])
+        assert all(t in (0, 1) for t in entry["ks_tiled"])
+        for b, t in zip(BUCKETS, entry["ks_tiled"]):
+            assert gpu.tuning(b)[1] == t
+        # the launch follows rounds x round time; a cache entry for this GPU is read back
+        for ms, small, large in (([1.0, 100.0], 4, 4), ([100.0, 1.0], 8, 8), ([1.0, 1.5], 4, 8)):
+            entry["br_round_ms"] = ms
+            path.write_text(json.dumps({key: entry}))
+            gpu.autotune(max_batch=64, cache_path=str(path))
+            assert gpu.tuning(cap4)[0] == small
+            assert gpu.tuning(cap4 + 1)[0] == large
     finally:
-        for b, (w, t) in saved.items():
-            gpu.set_tuning(b, w, t)
+        for b, t in saved.items():
+            gpu.set_tuning(b, 0, t)
