@@ -32,23 +32,42 @@ B_GATES = 4096
 N_LWE, N_RING, GL, STEPS_BR = 630, 1024, 3, 630
 
 # ---------------------------------------------------------------- work model
-# 32-bit VALU lane-operations of the modular arithmetic per blind-rotation step, from the
-# operation counts of the transform and the instruction counts of the compiled routines
-# (gfx950 ISA): add mod p 7, sub mod p 10, general multiply mod p 23, power-of-two multiply
-# 11 on average (7..15), gadget digit 6, exact lift 7.
-C_ADD, C_SUB, C_MUL, C_POW2, C_DIGIT, C_LIFT = 7, 10, 23, 11, 6, 7
+# 32-bit VALU lane-operations of one blind-rotation step: the modular operations of the
+# algorithm (per lane of a wave; lanes 0-31 and 32-63 each carry one polynomial) priced at
+# the instruction counts of the compiled gfx950 routines they use. Butterflies multiply
+# their second input by 2^E (canonical result) and then add and subtract with one carry fix:
+# 17.5 instructions for E mod 96 below 32, 25 in [32, 64), 20 in [64, 96), 14 for E = 0,
+# 8 for the first stage on small digits. A general product mod p is 22, a canonical 2^E
+# product 9 / 15 / 10 by the same classes, an add mod p 7, a gadget digit with its rotation
+# 8, an exact lift 4.
+C_MUL, C_ADD, C_DIGIT, C_LIFT = 22, 7, 8, 4
+BF_LO, BF_MID, BF_HI, BF_TRIV, BF_SMALL = 17.5, 25, 20, 14, 8
+P2_LO, P2_MID, P2_HI = 9, 15, 10
+
+
+def _exp_class(E: int) -> int:
+    e = E % 96
+    return 3 if e == 0 else (0 if e < 32 else (1 if e < 64 else 2))
+
+
+def _brv5(k: int) -> int:
+    return int(f"{k:05b}"[::-1], 2)
 
 
 def br_step_lane_ops() -> int:
-    lanes = 32                                   # lanes per transform
-    bfly_nontriv = 80 + 49                       # pass 1 + cyclic DFT32, per lane
-    bfly_triv = 31                               # DFT32 butterflies with twiddle 1
-    per_ntt = lanes * (bfly_nontriv * (C_POW2 + C_ADD + C_SUB) + bfly_triv * (C_ADD + C_SUB) + 31 * C_MUL)
-    ntts = 2 * GL + 2                            # 6 forward (digits) + 2 inverse per step
-    mac = 2 * GL * N_RING * 2 * C_MUL + GL * 64 * 32 * 2 * C_ADD
-    digits = GL * 2 * N_RING * C_DIGIT
-    rot_lift = 2 * N_RING * (5 + C_LIFT + 1)
-    return ntts * per_ntt + mac + digits + rot_lift
+    cost = {0: BF_LO, 1: BF_MID, 2: BF_HI, 3: BF_TRIV}
+    # pass 1 (negacyclic, twiddle 2^(3 brv5(m)) at stage s for blocks m in [2^s, 2^(s+1)))
+    pass1 = 16 * BF_SMALL + sum((16 >> s) * cost[_exp_class(3 * _brv5(m))]
+                                for s in range(1, 5) for m in range(1 << s, 2 << s))
+    # cyclic DFT32 with w = 2^6 (decimation in time: span H uses w^(j 16 / H))
+    dft = sum(cost[_exp_class(6 * j * (16 // H))] * (32 // (2 * H)) for H in (1, 2, 4, 8, 16) for j in range(H))
+    table = 31 * C_MUL
+    twist = sum({0: P2_LO, 1: P2_MID, 2: P2_HI}[_exp_class(96 - 3 * t)] for t in range(1, 32))
+    forward = pass1 + table + dft
+    inverse = dft + table + dft + twist + 32 * C_LIFT
+    mac = GL * 32 * (2 * C_MUL + 2 * C_ADD)      # per lane: 32 slots, 3 rounds
+    digits = GL * 32 * C_DIGIT
+    return int(round(64 * (GL * forward + inverse + mac + digits)))
 
 
 LANE_OPS_PER_GATE = STEPS_BR * br_step_lane_ops()
@@ -185,7 +204,7 @@ def main():
     out = ctx.empty(B_GATES, N_LWE + 1)
     if not args.no_autotune:
         ctx.autotune(max_batch=B_GATES)
-    br_waves, ks_tiled = ctx.tuning(B_GATES)
+    br_waves, ks_form = ctx.tuning(B_GATES)
 
     for _ in range(args.warmup):
         ctx.gates(ops_d, a_d, b_d, out=out)
@@ -253,7 +272,7 @@ def main():
                     "measured_GBps": None if traffic is None else round(traffic / (br_avg_ms * 1e-3) / 1e9, 1)},
             "key_stream_GBps_requested": round(B_GATES * BK_NTT_BYTES / (br_avg_ms * 1e-3) / 1e9, 1),
             "keyswitch_avg_ms": round(ks_ms / max(ks_n, 1), 3),
-            "launch": {"br_waves_per_workgroup": br_waves, "keyswitch": "tiled" if ks_tiled else "gather"}}
+            "launch": {"br_waves_per_workgroup": br_waves, "keyswitch": ["gather", "tiled", "split"][ks_form]}}
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(s0, s1, bkd, kskd, cfg, in0, in1, args.cpu_gates)

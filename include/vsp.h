@@ -185,8 +185,10 @@ vsp_status vsp_server_destroy(vsp_server* s);
 /* Autotuner for the batched launches (the level executor's tile and batch shapes). A gate's
  * blind rotation is one wave, so a batch of B gates runs in ceil(B / cap) rounds, cap being
  * the gates the GPU holds at once for a workgroup shape (4 or 8 gates per workgroup). This
- * call times one full round of each shape on random ciphertexts, and times both key-switch
- * forms (one workgroup per gate, or row-stationary tiles of 16 gates) for each batch-size
+ * call times one full round of each shape on random ciphertexts, and times the three
+ * key-switch forms (0: one workgroup per gate gathering its key rows; 1: tiles of 16 gates
+ * reading each key row once and selecting in registers; 2: tiles of 16 gates staging key rows
+ * through LDS, with the j range split over workgroups and atomic accumulation) for each batch-size
  * bucket up to max_batch (buckets end at 1, 16, 64, 256, 1024, 2048, 4096 gates; larger
  * batches share the last). Every candidate must give bit-identical outputs (else VSP_E_HIP).
  * Later launches pick the shape with the fewest rounds x round time, and the faster key
@@ -195,12 +197,12 @@ vsp_status vsp_server_destroy(vsp_server* s);
  * Synchronous; allocates and frees its own buffers. */
 vsp_status vsp_autotune(vsp_context* ctx, uint64_t max_batch, const char* cache_path);
 
-/* The launch choice for a batch of B gates: *br_waves (4 or 8), *ks_tiled (0 or 1). */
-vsp_status vsp_tuning_get(const vsp_context* ctx, uint64_t B, int* br_waves, int* ks_tiled);
+/* The launch choice for a batch of B gates: *br_waves (4 or 8), *ks_form (0, 1 or 2). */
+vsp_status vsp_tuning_get(const vsp_context* ctx, uint64_t B, int* br_waves, int* ks_form);
 
 /* Pin the launch choice for the bucket containing B: br_waves 4 or 8 (0 returns that bucket
- * to the round-time model), ks_tiled 0 or 1. Results are the same for every choice. */
-vsp_status vsp_tuning_set(vsp_context* ctx, uint64_t B, int br_waves, int ks_tiled);
+ * to the round-time model), ks_form 0, 1 or 2. Results are the same for every choice. */
+vsp_status vsp_tuning_set(vsp_context* ctx, uint64_t B, int br_waves, int ks_form);
 
 /* Kernel-time instrumentation (for benchmarks): while enabled, every eager launch of the
  * blind-rotation, key-switch and gate-prologue kernels made by this context is bracketed by

@@ -214,8 +214,8 @@ def vsp_tuning_get(ctx, B: int):
     return w.value, t.value
 
 
-def vsp_tuning_set(ctx, B: int, br_waves: int, ks_tiled: int) -> None:
-    _call("vsp_tuning_set", ctx, B, br_waves, ks_tiled)
+def vsp_tuning_set(ctx, B: int, br_waves: int, ks_form: int) -> None:
+    _call("vsp_tuning_set", ctx, B, br_waves, ks_form)
 
 
 def vsp_profile_enable(ctx, on: bool) -> None:

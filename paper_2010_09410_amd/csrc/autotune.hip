@@ -1,7 +1,7 @@
 // Autotuner for the batched launches. On random ciphertexts it times one full round of gates
 // for each blind-rotation workgroup shape (4 or 8 gates per workgroup; the launch then picks
-// the shape with the fewest rounds x round time for its batch) and both key-switch forms (one
-// workgroup per gate, or row-stationary tiles of gates) per batch-size bucket. Every
+// the shape with the fewest rounds x round time for its batch) and the three key-switch forms
+// (one workgroup per gate, row-stationary tiles, LDS-staged split) per batch-size bucket. Every
 // candidate must produce bit-identical outputs. The result can be cached in a small JSON file
 // keyed by the GPU.
 #include <cstdio>
@@ -47,7 +47,7 @@ std::string device_key(int dev) {
 }
 
 // Cache file: {"<device>": {"br_waves": [4, 8], "br_cap": [..], "br_round_ms": [..],
-//                          "buckets": [..], "ks_tiled": [..]}}
+//                          "buckets": [..], "ks_form": [..]}}
 bool read_numbers(const std::string& s, size_t from, const char* name, double* out, int count) {
   const size_t p = s.find(std::string("\"") + name + "\"", from);
   if (p == std::string::npos) return false;
@@ -75,7 +75,7 @@ bool read_cache(const std::string& path, const std::string& key, Tuning& t) {
   if (at == std::string::npos) return false;
   double cap[kBrShapes], ms[kBrShapes], ks[kTuneBuckets];
   if (!read_numbers(s, at, "br_cap", cap, kBrShapes) || !read_numbers(s, at, "br_round_ms", ms, kBrShapes) ||
-      !read_numbers(s, at, "ks_tiled", ks, kTuneBuckets))
+      !read_numbers(s, at, "ks_form", ks, kTuneBuckets))
     return false;
   Tuning n = t;  // keeps forced shapes
   for (int i = 0; i < kBrShapes; i++) {
@@ -84,8 +84,8 @@ bool read_cache(const std::string& path, const std::string& key, Tuning& t) {
     n.br_round_ms[i] = (float)ms[i];
   }
   for (int b = 0; b < kTuneBuckets; b++) {
-    if (ks[b] != 0 && ks[b] != 1) return false;
-    n.ks_tiled[b] = (int)ks[b];
+    if (!(ks[b] == 0 || ks[b] == 1 || ks[b] == 2)) return false;
+    n.ks_form[b] = (int)ks[b];
   }
   n.tuned = true;
   t = n;
@@ -108,8 +108,8 @@ bool write_cache(const std::string& path, const std::string& key, const Tuning& 
   list([&](int i) { return t.br_round_ms[i]; }, kBrShapes);
   f << ", \"buckets\": ";
   list([](int i) { return kBucket[i]; }, kTuneBuckets);
-  f << ", \"ks_tiled\": ";
-  list([&](int i) { return t.ks_tiled[i]; }, kTuneBuckets);
+  f << ", \"ks_form\": ";
+  list([&](int i) { return t.ks_form[i]; }, kTuneBuckets);
   f << "}}\n";
   return (bool)f;
 }
@@ -195,19 +195,19 @@ vsp_status vsp_autotune(vsp_context* ctx, uint64_t max_batch, const char* cache_
     result = hip_fail(e, "fill");
   for (int b = 0; b < kTuneBuckets && result == VSP_OK; b++) {
     if (b > 0 && kBucket[b - 1] >= Sks) {  // beyond the batches asked for: keep the previous choice
-      t.ks_tiled[b] = t.ks_tiled[b - 1];
+      t.ks_form[b] = t.ks_form[b - 1];
       continue;
     }
     const uint64_t B = std::min<uint64_t>(kBucket[b], Sks);
     float best = 1e30f;
-    for (int c = 0; c < 2 && result == VSP_OK; c++) {
+    for (int c = 0; c < kKsForms && result == VSP_OK; c++) {
       uint32_t* dst = static_cast<uint32_t*>(c == 0 ? outref.p : out.p);
       const float ms = timed([&] { (void)launch_keyswitch(ctx, dops, static_cast<const uint32_t*>(t1ref.p), nullptr,
                                                           dst, B, st, c); });
       if (c > 0 && !same(outref.p, out.p, B * T0)) result = fail(VSP_E_HIP, "autotune: key-switch forms disagree");
       if (ms < best) {
         best = ms;
-        t.ks_tiled[b] = c;
+        t.ks_form[b] = c;
       }
     }
   }
@@ -221,20 +221,20 @@ vsp_status vsp_autotune(vsp_context* ctx, uint64_t max_batch, const char* cache_
   return VSP_OK;
 }
 
-vsp_status vsp_tuning_get(const vsp_context* ctx, uint64_t B, int* br_waves, int* ks_tiled) {
-  if (ctx == nullptr || br_waves == nullptr || ks_tiled == nullptr) return fail(VSP_E_ARG, "NULL argument");
+vsp_status vsp_tuning_get(const vsp_context* ctx, uint64_t B, int* br_waves, int* ks_form) {
+  if (ctx == nullptr || br_waves == nullptr || ks_form == nullptr) return fail(VSP_E_ARG, "NULL argument");
   *br_waves = ctx->tune.br_waves(B == 0 ? 1 : B);
-  *ks_tiled = ctx->tune.ks_tiled_for(B == 0 ? 1 : B) ? 1 : 0;
+  *ks_form = ctx->tune.ks_form_for(B == 0 ? 1 : B);
   return VSP_OK;
 }
 
-vsp_status vsp_tuning_set(vsp_context* ctx, uint64_t B, int br_waves, int ks_tiled) {
+vsp_status vsp_tuning_set(vsp_context* ctx, uint64_t B, int br_waves, int ks_form) {
   if (ctx == nullptr) return fail(VSP_E_ARG, "context is NULL");
-  if ((br_waves != 0 && br_waves != 4 && br_waves != 8) || (ks_tiled != 0 && ks_tiled != 1))
-    return fail(VSP_E_ARG, "br_waves must be 0 (model), 4 or 8 and ks_tiled 0 or 1");
+  if ((br_waves != 0 && br_waves != 4 && br_waves != 8) || ks_form < 0 || ks_form >= kKsForms)
+    return fail(VSP_E_ARG, "br_waves must be 0 (model), 4 or 8 and ks_form 0, 1 or 2");
   const int b = Tuning::bucket(B == 0 ? 1 : B);
   ctx->tune.br_force[b] = br_waves;
-  ctx->tune.ks_tiled[b] = ks_tiled;
+  ctx->tune.ks_form[b] = ks_form;
   return VSP_OK;
 }
 

@@ -56,58 +56,73 @@ __device__ __forceinline__ u64 gl_sub(u64 a, u64 b) {
   return d2 - c2;
 }
 
-// (hi:lo) mod p using 2^64 = 2^32 - 1 and 2^96 = -1: lo - hi_hi + hi_lo (2^32 - 1).
-__device__ __forceinline__ u64 gl_reduce128(u64 lo, u64 hi) {
-  const u32 hh = (u32)(hi >> 32), hl = (u32)hi;
-  u64 t0 = lo - hh;
-  if (lo < hh) t0 -= GL_EPS;  // cannot borrow twice: lo - hh + 2^64 > 2^32
-  const u64 t1 = ((u64)hl << 32) - hl;
-  u64 r = t0 + t1;
-  if (r < t1) r += GL_EPS;    // cannot carry twice: t1 <= (2^32-1)^2
-  return r;
+// a + t mod p for lazy a and t <= p: a carry can then happen only once, because the wrapped
+// sum is below t.
+__device__ __forceinline__ u64 gl_add_c(u64 a, u64 t) {
+  const u64 s = a + t;
+  return s + ((s < t) ? GL_EPS : 0);
 }
 
-// 64 x 64 -> 128-bit product from four 32 x 32 -> 64 multiply-adds.
-__device__ __forceinline__ void mul128(u64 a, u64 b, u64& lo, u64& hi) {
+// a - t mod p for lazy a and t <= p: after a borrow the difference is at least 2^64 - p.
+__device__ __forceinline__ u64 gl_sub_c(u64 a, u64 t) {
+  const u64 d = a - t;
+  return d - ((a < t) ? GL_EPS : 0);
+}
+
+// Product modulo p (lazy result). The 128-bit product is (hi:lo); with hi = hh 2^32 + hl,
+// 2^64 = 2^32 - 1 and 2^96 = -1 give lo + hl (2^32 - 1) - hh. hl (2^32 - 1) <= 2^64 - 2^33 + 1,
+// so the sum carries at most once and the difference borrows at most once.
+__device__ __forceinline__ u64 gl_mul(u64 a, u64 b) {
   const u32 a0 = (u32)a, a1 = (u32)(a >> 32), b0 = (u32)b, b1 = (u32)(b >> 32);
   const u64 p00 = (u64)a0 * b0;
   const u64 t = (u64)a0 * b1 + (p00 >> 32);
   const u64 u = (u64)a1 * b0 + (u32)t;
-  hi = (u64)a1 * b1 + (t >> 32) + (u >> 32);
-  lo = (u << 32) | (u32)p00;
+  const u64 hi = (u64)a1 * b1 + (t >> 32) + (u >> 32);
+  const u64 lo = (u << 32) | (u32)p00;
+  const u32 hh = (u32)(hi >> 32), hl = (u32)hi;
+  const u64 tl = (u64)hl * GL_EPS;
+  u64 r = lo + tl;
+  r += (r < tl) ? GL_EPS : 0;
+  const u64 r2 = r - hh;
+  return r2 - ((r < hh) ? GL_EPS : 0);
 }
 
-__device__ __forceinline__ u64 gl_mul(u64 a, u64 b) {
-  u64 lo, hi;
-  mul128(a, b, lo, hi);
-  return gl_reduce128(lo, hi);
-}
-
-// x * 2^E mod p for a compile-time E in [0, 96), without a general multiply.
-// Write x 2^E as 32-bit words w0..w4 of a 160-bit integer; then 2^64 = 2^32 - 1,
-// 2^96 = -1 and 2^128 = -2^32 (mod p) fold it back to 64 bits.
+// x * 2^E mod p for a compile-time E in [0, 96), returned canonical (in [0, p)). Write
+// x 2^E as 32-bit words of a 160-bit integer and fold it back with 2^64 = 2^32 - 1 and
+// 2^96 = -1:
+//  E < 32:  x 2^E = L + w 2^64 (L the low 64 bits, w the top E bits) = L + w (2^32 - 1).
+//           w (2^32 - 1) < 2^63, so after a carry the sum is below 2^63; without one it may
+//           lie in [p, 2^64). Both cases are fixed by adding 2^32 - 1 once.
+//  E >= 64: with F = E - 64 and (w4:w3:w2) = x 2^F, x 2^E = w2 (2^32 - 1) - (w4:w3), where
+//           w2 (2^32 - 1) < p; one conditional subtraction of 2^32 - 1 after a borrow lands
+//           in [0, p).
+//  else:    with F = E - 32 and (w2:w1:w0) = x 2^F, x 2^E = [w0 2^32 + w1 (2^32 - 1)] - w2,
+//           the bracket made canonical as in the first case, then w2 subtracted as in the
+//           second.
 __device__ __forceinline__ u64 gl_mul_pow2(u64 x, int E) {
-  if (E == 0) return x;
-  if (E <= 32) {
-    // (hi:lo) = x << E with hi < 2^32: value = lo + hi (2^32 - 1).
-    const u64 lo = (E == 32) ? (x << 32) : (x << E);
-    const u64 hi = x >> (64 - E);
-    const u64 t1 = (hi << 32) - hi;
-    u64 r = lo + t1;
-    if (r < t1) r += GL_EPS;
-    return r;
+  if (E == 0) return (x >= GL_P) ? x + GL_EPS : x;
+  if (E < 32) {
+    const u64 t = (u64)(u32)(x >> (64 - E)) * GL_EPS;
+    const u64 r = (x << E) + t;
+    return r + (((r < t) | (r >= GL_P)) ? GL_EPS : 0);
   }
-  if (E < 64) return gl_reduce128(x << E, x >> (64 - E));
-  // E in [64, 96): F = E - 64, (w4:w3:w2) = x << F; value = w2 (2^32 - 1) - w3 - w4 2^32.
-  const int F = E - 64;
-  const u32 x0 = (u32)x, x1 = (u32)(x >> 32);
-  const u32 w2 = (F == 0) ? x0 : (x0 << F);
-  const u32 w3 = (F == 0) ? x1 : ((x1 << F) | (x0 >> (32 - F)));
-  const u32 w4 = (F == 0) ? 0u : (x1 >> (32 - F));
-  const u64 A = (u64)w2 << 32;
-  const u64 B = ((u64)w4 << 32) + (u64)w2 + (u64)w3;  // < 2^63 + 2^33 < p
-  const u64 d = A - B;
-  return (A < B) ? d - GL_EPS : d;                    // one borrow at most (B < p)
+  if (E >= 64) {
+    const int F = E - 64;
+    const u64 sh = x << F;
+    const u32 w4 = F ? (u32)(x >> (64 - F)) : 0u;
+    const u64 A = (u64)(u32)sh * GL_EPS;
+    const u64 Bv = ((u64)w4 << 32) | (sh >> 32);
+    const u64 r = A - Bv;
+    return r - ((A < Bv) ? GL_EPS : 0);
+  }
+  const int F = E - 32;
+  const u64 sh = x << F;
+  const u32 w2 = F ? (u32)(x >> (64 - F)) : 0u;
+  const u64 t = (u64)(u32)(sh >> 32) * GL_EPS;
+  u64 a = (sh << 32) + t;
+  a += ((a < t) | (a >= GL_P)) ? GL_EPS : 0;
+  const u64 r = a - w2;
+  return r - ((a < (u64)w2) ? GL_EPS : 0);
 }
 
 // Canonical representative in [0, p).

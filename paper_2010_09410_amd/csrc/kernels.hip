@@ -236,11 +236,117 @@ __global__ __launch_bounds__(256) void k_keyswitch_tiled(const u32* __restrict__
   }
 }
 
+// Split form: the output rows are first set to (0, ..., 0, b'), then workgroups of G gates
+// each take a chunk of the j range, stage the three non-zero key rows of every (j, p)
+// through LDS (double-buffered, one barrier per (j, p)), add the row selected by each gate's
+// digit from LDS, and subtract their partial sums from the output with atomic adds. Integer
+// addition mod 2^32 is associative, so the result does not depend on the order.
+__global__ __launch_bounds__(256) void k_keyswitch_init(const uint8_t* __restrict__ ops, const u32* __restrict__ tlwe1,
+                                                        const u32* __restrict__ idxo, u32* __restrict__ out,
+                                                        uint64_t B) {
+  const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= B * TLWE0) return;
+  const uint64_t g = i / TLWE0;
+  const int c = (int)(i - g * TLWE0);
+  if (ops && !op_bootstraps(ops[g])) return;
+  const uint64_t ro = idxo ? idxo[g] : g;
+  out[ro * TLWE0 + c] = (c == LWE_N) ? tlwe1[g * TLWE1 + RING_N] : 0u;
+}
+
+constexpr int KS_ROW = 640;  // LDS row pitch (u32) of a staged key row
+
+template <int G>
+__global__ __launch_bounds__(256) void k_keyswitch_split(const u32* __restrict__ ksk, const uint8_t* __restrict__ ops,
+                                                         const u32* __restrict__ tlwe1, const u32* __restrict__ idxo,
+                                                         u32* __restrict__ out, uint64_t B, int jchunk) {
+  __shared__ u32 rows[2][4 * KS_ROW];  // per buffer: row 0 zero, rows 1..3 the key rows of one (j, p)
+  const uint64_t g0 = (uint64_t)blockIdx.x * G;
+  const int ng = (int)((B - g0) < (uint64_t)G ? (B - g0) : (uint64_t)G);
+  const int j0 = blockIdx.y * jchunk;
+  const int j1 = (j0 + jchunk < RING_N) ? j0 + jchunk : RING_N;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < KS_ROW; i += 256) rows[0][i] = rows[1][i] = 0u;
+  constexpr int STAGE = 3 * TLWE0;              // words staged per (j, p)
+  constexpr int PER_T = (STAGE + 255) / 256;    // loads per thread
+  auto fetch = [&](int j, int p, u32 (&r)[PER_T]) {
+    const u32* src = ksk + ((size_t)j * KS_T + p) * 4 * TLWE0 + TLWE0;  // rows v = 1..3 are contiguous
+#pragma unroll
+    for (int q = 0; q < PER_T; q++) {
+      const int i = tid + 256 * q;
+      r[q] = (i < STAGE) ? src[i] : 0u;
+    }
+  };
+  auto store = [&](int buf, const u32 (&r)[PER_T]) {
+#pragma unroll
+    for (int q = 0; q < PER_T; q++) {
+      const int i = tid + 256 * q;
+      if (i < STAGE) {
+        const int v = i / TLWE0;
+        rows[buf][(v + 1) * KS_ROW + (i - v * TLWE0)] = r[q];
+      }
+    }
+  };
+  u32 acc[G][3];
+#pragma unroll
+  for (int g = 0; g < G; g++) acc[g][0] = acc[g][1] = acc[g][2] = 0u;
+  const int c0 = tid, c1 = tid + 256, c2 = tid + 512;  // c2 valid below TLWE0
+  u32 pre[PER_T];
+  fetch(j0, 0, pre);
+  store(0, pre);
+  __syncthreads();
+  int buf = 0;
+  for (int j = j0; j < j1; j++) {
+    u32 ahat[G];
+#pragma unroll
+    for (int g = 0; g < G; g++) ahat[g] = (g < ng ? tlwe1[(g0 + g) * TLWE1 + j] : 0u) + (1u << 15);
+#pragma unroll 1
+    for (int p = 0; p < KS_T; p++) {
+      const bool more = (p + 1 < KS_T) || (j + 1 < j1);
+      if (more) fetch(p + 1 < KS_T ? j : j + 1, (p + 1) & (KS_T - 1), pre);
+      const u32* rb = rows[buf];
+#pragma unroll
+      for (int g = 0; g < G; g++) {
+        const u32 v = (ahat[g] >> (30 - 2 * p)) & 3u;
+        const u32* row = rb + v * KS_ROW;
+        acc[g][0] += row[c0];
+        acc[g][1] += row[c1];
+        if (c2 < TLWE0) acc[g][2] += row[c2];
+      }
+      if (more) store(buf ^ 1, pre);
+      __syncthreads();
+      buf ^= 1;
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < G; g++) {
+    const uint64_t gg = g0 + g;
+    if (g < ng && (!ops || op_bootstraps(ops[gg]))) {
+      const uint64_t ro = idxo ? idxo[gg] : gg;
+      u32* o = out + ro * TLWE0;
+      __hip_atomic_fetch_add(&o[c0], 0u - acc[g][0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&o[c1], 0u - acc[g][1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (c2 < TLWE0) __hip_atomic_fetch_add(&o[c2], 0u - acc[g][2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
 hipError_t launch_keyswitch(const vsp_context* ctx, const uint8_t* ops, const uint32_t* tlwe1, const uint32_t* idxo,
-                            uint32_t* out, uint64_t B, hipStream_t st, int tiled) {
+                            uint32_t* out, uint64_t B, hipStream_t st, int form) {
   if (B == 0) return hipSuccess;
-  if (tiled < 0) tiled = ctx->tune.ks_tiled_for(B) ? 1 : 0;
-  if (tiled) {
+  if (form < 0) form = ctx->tune.ks_form_for(B);
+  if (form == 2) {
+    constexpr int G = 16;
+    const uint64_t tiles = (B + G - 1) / G;
+    // split the j range so that the launch has about 2048 workgroups (chunks of >= 16 j)
+    uint64_t split = 2048 / tiles;
+    split = split < 1 ? 1 : (split > RING_N / 16 ? RING_N / 16 : split);
+    const int jchunk = (int)((RING_N + split - 1) / split);
+    const unsigned ychunks = (unsigned)((RING_N + jchunk - 1) / jchunk);
+    hipLaunchKernelGGL(k_keyswitch_init, dim3((unsigned)((B * TLWE0 + 255) / 256)), dim3(256), 0, st, ops, tlwe1, idxo,
+                       out, B);
+    hipLaunchKernelGGL(k_keyswitch_split<G>, dim3((unsigned)tiles, ychunks), dim3(256), 0, st, ctx->ksk, ops, tlwe1,
+                       idxo, out, B, jchunk);
+  } else if (form == 1) {
     constexpr int G = 16;
     hipLaunchKernelGGL(k_keyswitch_tiled<G>, dim3((unsigned)((B + G - 1) / G)), dim3(256), 0, st, ctx->ksk, ops, tlwe1,
                        idxo, out, B);
@@ -297,10 +403,11 @@ __global__ __launch_bounds__(256) void k_polymul(const int32_t* __restrict__ a, 
     const u64 other = __shfl_xor(v[s], 32);
     v[s] = gl_mul(gl_mul(v[s], other), ninv);
   }
-  ntt_inverse(v, tw + 1024, reg, l);
+  u32 z[32];
+  ntt_inverse_lift(v, tw + 1024, reg, l, z);
   if (h == 0) {
 #pragma unroll
-    for (int t = 0; t < 32; t++) out[j * RING_N + l + 32 * t] = gl_lift_u32(gl_canon(v[t]));
+    for (int t = 0; t < 32; t++) out[j * RING_N + l + 32 * t] = z[t];
   }
 }
 

@@ -12,7 +12,11 @@
 //  pass 2 (in registers): a mod (X^32 - zeta_u) is evaluated at psi_u w^k (w = 2^6, a
 //    primitive 32nd root; psi_u = psi^{2u+1} with psi^32 = 8): multiply coefficient j by
 //    psi_u^j (table) then a cyclic 32-point DFT with power-of-two twiddles.
-// The inverse runs the same steps backwards; the factor 1/N is folded into the key.
+// The inverse undoes pass 2 (inverse DFT, psi_u^-j), transposes back, and undoes pass 1 as
+// a cyclic inverse DFT over the residues followed by the twist zeta^-t of coefficient t.
+// The factor 1/N is folded into the key. Every butterfly multiplies its second input by the
+// twiddle (Cooley-Tukey form), so the product is canonical and the sum and difference
+// need a single carry fix each.
 #pragma once
 #include "gl64.h"
 
@@ -68,22 +72,14 @@ __device__ constexpr TwiddleExps kTwE = make_twiddle_exps();
 // the upper half of the exponents into a swap of the sum and the difference.
 __device__ __forceinline__ void bfly_ct(u64& x, u64& y, int E) {
   const u64 a = x;
+  const u64 t = gl_mul_pow2(y, E % 96);  // canonical
   if (E >= 96) {
-    const u64 t = gl_mul_pow2(y, E - 96);
-    x = gl_sub(a, t);
-    y = gl_add(a, t);
+    x = gl_sub_c(a, t);
+    y = gl_add_c(a, t);
   } else {
-    const u64 t = gl_mul_pow2(y, E);
-    x = gl_add(a, t);
-    y = gl_sub(a, t);
+    x = gl_add_c(a, t);
+    y = gl_sub_c(a, t);
   }
-}
-
-// Gentleman-Sande butterfly (x, y) -> (x + y, (x - y) 2^E), E in [0, 192).
-__device__ __forceinline__ void bfly_gs(u64& x, u64& y, int E) {
-  const u64 a = x, b = y;
-  x = gl_add(a, b);
-  y = (E >= 96) ? gl_mul_pow2(gl_sub(b, a), E - 96) : gl_mul_pow2(gl_sub(a, b), E);
 }
 
 // Hides x from the optimiser so that per-lane address arithmetic derived from it is
@@ -101,8 +97,12 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 // Pass 1, forward: negacyclic Cooley-Tukey over the register index (natural order in,
-// bit-reversed out: register k holds residue u = brv5(k)).
+// bit-reversed out: register k holds residue u = brv5(k)). With SMALL the inputs are signed
+// integers of at most 2^6 in magnitude (two's complement in the 64-bit word), and the first
+// stage, x +- 2^48 y, is computed exactly in 64-bit integers before entering the field.
+template <bool SMALL>
 __device__ __forceinline__ void pass1_forward(u64 (&v)[32]) {
+  static_assert(3 * 16 == 48, "first-stage twiddle zeta^16 = 2^48");
 #pragma unroll
   for (int s = 0; s < 5; s++) {
     const int M = 1 << s, H = 16 >> s;
@@ -111,42 +111,36 @@ __device__ __forceinline__ void pass1_forward(u64 (&v)[32]) {
 #pragma unroll
       for (int j = 0; j < H; j++) {
         const int i = b * 2 * H + j;
-        bfly_ct(v[i], v[i + H], kTwE.p1f[M + b]);
+        if (SMALL && s == 0) {
+          const int64_t x = (int64_t)v[i], y = (int64_t)v[i + H] * ((int64_t)1 << 48);
+          const int64_t sp = x + y, sm = x - y;  // |.| < 2^54
+          v[i] = (u64)sp - ((sp < 0) ? GL_EPS : 0);
+          v[i + H] = (u64)sm - ((sm < 0) ? GL_EPS : 0);
+        } else {
+          bfly_ct(v[i], v[i + H], kTwE.p1f[M + b]);
+        }
       }
     }
   }
 }
 
-// Pass 1, inverse (Gentleman-Sande; bit-reversed in, natural out; unscaled).
-__device__ __forceinline__ void pass1_inverse(u64 (&v)[32]) {
-#pragma unroll
-  for (int s = 4; s >= 0; s--) {
-    const int M = 1 << s, H = 16 >> s;
-#pragma unroll
-    for (int b = 0; b < M; b++) {
-#pragma unroll
-      for (int j = 0; j < H; j++) {
-        const int i = b * 2 * H + j;
-        bfly_gs(v[i], v[i + H], kTwE.p1i[M + b]);
-      }
-    }
-  }
-}
-
-// Cyclic 32-point DFT with w = 2^6, decimation in frequency (natural in, bit-reversed out).
+// Cyclic 32-point DFT with w = 2^6 (natural order in, bit-reversed out: register brv5(k)
+// receives X_k), as decimation in time over the bit-reversed register names.
 __device__ __forceinline__ void dft32_forward(u64 (&v)[32]) {
 #pragma unroll
-  for (int s = 0; s < 5; s++) {
+  for (int s = 4; s >= 0; s--) {
     const int H = 16 >> s;
 #pragma unroll
     for (int blk = 0; blk < 32; blk += 2 * H) {
 #pragma unroll
-      for (int j = 0; j < H; j++) bfly_gs(v[blk + j], v[blk + j + H], kTwE.dft[(j << s) & 31]);
+      for (int j = 0; j < H; j++) bfly_ct(v[brv5(blk + j)], v[brv5(blk + j + H)], kTwE.dft[(j << s) & 31]);
     }
   }
 }
 
-// Inverse of dft32_forward (decimation in time; bit-reversed in, natural out; unscaled).
+// Cyclic inverse DFT with w^-1 (decimation in time; bit-reversed in, natural out; unscaled).
+// Inverts dft32_forward, and also pass 1: register k of a lane holding the residues at
+// zeta w^brv5(k) yields sum_u A_u w^-ut in register t.
 __device__ __forceinline__ void dft32_inverse(u64 (&v)[32]) {
 #pragma unroll
   for (int s = 4; s >= 0; s--) {
@@ -209,30 +203,37 @@ __device__ __forceinline__ void table_multiply(u64 (&v)[32], const u64* T, int l
   }
 }
 
-// Forward transform of this half's polynomial (values already residues mod p).
-// tf is the [j][u] table psi_u^j (in LDS or global memory).
+// Forward transform of this half's polynomial (values already residues mod p; with SMALL,
+// signed integers of magnitude at most 2^6). tf is the [j][u] table psi_u^j (in LDS or
+// global memory).
+template <bool SMALL = false>
 __device__ __forceinline__ void ntt_forward(u64 (&v)[32], const u64* tf, u32* reg, int l) {
-  pass1_forward(v);
+  pass1_forward<SMALL>(v);
   transpose_forward(v, reg, l);
   table_multiply(v, tf, l);
   dft32_forward(v);
 }
 
-// Inverse transform (unscaled: returns N times the polynomial); ti is psi_u^-j.
-__device__ __forceinline__ void ntt_inverse(u64 (&v)[32], const u64* ti, u32* reg, int l) {
+// Inverse transform, lifted: out[t] receives coefficient l + 32 t of N times the polynomial,
+// as the exact integer in (-p/2, p/2) reduced mod 2^32 (ti is psi_u^-j). After the inverse
+// DFT over the residues, coefficient t still carries zeta^t; zeta^-t = 2^(192 - 3t) =
+// -2^(96 - 3t) removes it, the sign going into the final negation.
+__device__ __forceinline__ void ntt_inverse_lift(u64 (&v)[32], const u64* ti, u32* reg, int l, u32 (&out)[32]) {
   dft32_inverse(v);
   table_multiply(v, ti, l);
   transpose_inverse(v, reg, l);
-  pass1_inverse(v);
+  dft32_inverse(v);
+  out[0] = gl_lift_u32(gl_canon(v[0]));
+#pragma unroll
+  for (int t = 1; t < 32; t++) out[t] = 0u - gl_lift_u32(gl_mul_pow2(v[t], 96 - 3 * t));
 }
 
 // Gadget digit of a torus value at bit offset sh = 32 - 6r (r = 1..3): signed in [-32, 31],
-// returned as a residue mod p. The rounding offset makes the l digits a round-to-nearest
-// decomposition.
+// returned sign-extended to 64 bits (the small-input form of ntt_forward). The rounding
+// offset makes the l digits a round-to-nearest decomposition.
 __device__ __forceinline__ u64 gadget_digit(u32 x, int sh) {
   const u32 t = x + DECOMP_OFFSET;
-  const int32_t d = (int32_t)((t >> sh) & 63u) - 32;
-  return gl_from_i32(d);
+  return (u64)(int64_t)((int32_t)((t >> sh) & 63u) - 32);
 }
 
 // Sum over the two halves of a wave: lanes 0-31 receive P0[l] + P0[l + 32], lanes 32-63
@@ -273,7 +274,7 @@ __device__ __forceinline__ void external_product(DigitSource digits, const u64* 
 #pragma unroll
     for (int q = 0; q < KCH; q++) kc[q] = key[q * 64];
     digits(32 - BG_BIT * (k + 1), x);
-    ntt_forward(x, tf, reg, l);
+    ntt_forward<true>(x, tf, reg, l);
 #pragma unroll
     for (int c = 0; c < 32 / KCH; c++) {
       ulonglong2 kn[KCH];
@@ -295,9 +296,7 @@ __device__ __forceinline__ void external_product(DigitSource digits, const u64* 
       }
     }
   }
-  ntt_inverse(sum, ti, reg, l);
-#pragma unroll
-  for (int t = 0; t < 32; t++) out[t] = gl_lift_u32(gl_canon(sum[t]));
+  ntt_inverse_lift(sum, ti, reg, l, out);
 }
 
 // Digits of an operand polynomial held in registers.

@@ -42,12 +42,14 @@ constexpr uint64_t kBucket[kTuneBuckets] = {1, 16, 64, 256, 1024, 2048, 4096};
 //    of gates the whole GPU holds at once (occupancy x compute units x gates per group) and
 //    br_round_ms[s] the time of one full round. The shape with the fewer milliseconds wins
 //    (ties: the larger workgroup). br_force[b] != 0 pins the shape for bucket b.
-//  * Key switch: per bucket, 0 gathers key rows per gate, 1 reads them once per tile of gates.
+//  * Key switch: per bucket, form 0 gathers key rows per gate, 1 reads them once per tile of
+//    gates and selects in registers, 2 stages them through LDS for a tile of gates and splits
+//    the j range over workgroups.
 struct Tuning {
   uint64_t br_cap[kBrShapes] = {1024, 2048};
-  float br_round_ms[kBrShapes] = {1.0f, 1.5f};
+  float br_round_ms[kBrShapes] = {1.0f, 1.48f};
   int br_force[kTuneBuckets] = {0, 0, 0, 0, 0, 0, 0};
-  int ks_tiled[kTuneBuckets] = {0, 0, 0, 0, 0, 1, 1};
+  int ks_form[kTuneBuckets] = {2, 2, 2, 2, 2, 2, 2};
   bool tuned = false;
   static int bucket(uint64_t B) {
     int b = 0;
@@ -69,7 +71,7 @@ struct Tuning {
     }
     return kBrWaveChoices[best];
   }
-  bool ks_tiled_for(uint64_t B) const { return ks_tiled[bucket(B)] != 0; }
+  int ks_form_for(uint64_t B) const { return ks_form[bucket(B)]; }
 };
 
 // Growable device scratch owned by a context.
@@ -148,9 +150,10 @@ hipError_t launch_gate_prologue_uniform(const vsp_context* ctx, uint32_t op, con
 hipError_t launch_blind_rotate(const vsp_context* ctx, const uint8_t* ops, const uint32_t* abar, uint32_t* tlwe1,
                                uint32_t* trlwe, uint64_t B, int waves, hipStream_t st);
 // Identity key switch TLWE1 [B][N+1] -> TLWE0 [B][n+1] (outputs scattered by idxo if given).
-// tiled: 1 row-stationary tiles of gates, 0 one workgroup per gate, -1 the tuned choice.
+// form: 0 one workgroup per gate, 1 row-stationary tiles, 2 LDS-staged split, -1 the tuned one.
+constexpr int kKsForms = 3;
 hipError_t launch_keyswitch(const vsp_context* ctx, const uint8_t* ops, const uint32_t* tlwe1, const uint32_t* idxo,
-                            uint32_t* out, uint64_t B, hipStream_t st, int tiled = -1);
+                            uint32_t* out, uint64_t B, hipStream_t st, int form = -1);
 // out[j] = C_j (ext) x_j, or with `x0` given: out[j] = x0_j + C_j (ext) (x_j - x0_j).
 hipError_t launch_ext_product(const vsp_context* ctx, const uint64_t* Cn, const uint32_t* x, uint32_t* out,
                               uint64_t J, hipStream_t st);

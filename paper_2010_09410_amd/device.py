@@ -109,8 +109,8 @@ class Context:
     def tuning(self, B: int):
         return nv.vsp_tuning_get(self.handle, B)
 
-    def set_tuning(self, B: int, br_waves: int, ks_tiled: int) -> None:
-        nv.vsp_tuning_set(self.handle, B, br_waves, ks_tiled)
+    def set_tuning(self, B: int, br_waves: int, ks_form: int) -> None:
+        nv.vsp_tuning_set(self.handle, B, br_waves, ks_form)
 
     # -------------------------------------------------------------- circuits / serving
     def circuit(self, gates, ninputs: int) -> "Circuit":
