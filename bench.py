@@ -116,6 +116,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--cpu-gates", type=int, default=0, help="oracle sample size (default: about 12 s of work)")
+    ap.add_argument("--no-memory", action="store_true", help="skip the CMUX-memory timings")
     ap.add_argument("--serving", type=float, default=2.0, metavar="SECONDS",
                     help="arrival window of the serving run (0 skips it)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -140,6 +141,56 @@ def cpu_baseline(s0, s1, bkd, kskd, cfg, in0, in1, ngates):
     dt = time.perf_counter() - t0
     return {"value": round(ngates / dt, 2), "unit": "gate bootstraps/s", "cores": threads, "kind": "oracle",
             "sample": f"first {ngates} gates of the 4096-gate batch, {threads} threads, {dt:.1f} s"}
+
+
+def memory_run(ctx, s0, s1, reps: int = 3):
+    """CMUX memory (Sec. 8): 256 ROM reads of 32 bits from a 512-word ROM, 256 RAM reads and
+    one RAM write of an 8-bit word over 256 addresses, timed with events on the library's
+    stream (median of `reps` after one warm-up). Encrypted inputs from the seeded workloads."""
+    import torch
+
+    import workloads as W
+    from paper_2010_09410_amd import client
+    wl = W.rom_workload(reads=256)
+    rom = client.trlwe_encrypt_torus(s1, client.pack_rom(wl["words"]), *wl["cells"])
+    sel = client.trgsw_encrypt(s1, (wl["addr"][:, None] >> np.arange(9)[None, :]) & 1, *wl["sel"])
+    rw = W.ram_workload(v=8, w=8, reads=1, flag=1)
+    ram = client.trlwe_encrypt_torus(s1, client.ram_cell_messages(rw["contents"]), *rw["cells"])
+    wsel = client.trgsw_encrypt(s1, (rw["waddr"] >> np.arange(8)) & 1, *rw["wsel"])
+    flag = client.tlwe_encrypt_bits(s0, [rw["flag"]], *rw["fenc"])[0]
+    data = client.tlwe_encrypt_bits(s0, rw["wdata"], *rw["denc"])
+    rsel = client.trgsw_encrypt(s1, (wl["addr"][:, None] % 256 >> np.arange(8)[None, :]) & 1,
+                                wl["sel"][0][:, :8], wl["sel"][1][:, :8])
+    d_rom, d_sel, d_ram0 = ctx.tensor(rom), ctx.tensor(sel), ctx.tensor(ram)
+    d_wsel, d_flag, d_data, d_rsel = ctx.tensor(wsel), ctx.tensor(flag), ctx.tensor(data), ctx.tensor(rsel)
+    d_ram = d_ram0.clone()
+    st = torch.cuda.current_stream(ctx.device)
+
+    def timed(fn):
+        fn()
+        ms = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            fn()
+            e1.record(st)
+            e1.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        return float(np.median(ms))
+
+    rom_ms = timed(lambda: ctx.rom_read(d_rom, d_sel, 9, 32))
+    rd_ms = timed(lambda: ctx.ram_read(d_ram0, d_rsel))
+
+    def write():
+        d_ram.copy_(d_ram0)
+        ctx.ram_write(d_ram, d_wsel, d_flag, d_data)
+    wr_ms = timed(write)
+    ctx.sync()
+    return {"rom_256_reads_ms": round(rom_ms, 2), "rom_reads_per_s": round(256 / (rom_ms / 1e3), 1),
+            "ram_256_reads_ms": round(rd_ms, 2), "ram_write_ms": round(wr_ms, 2),
+            "workload": "ROM 512 x 32-bit words (16 packed TRLWE), 9-bit encrypted addresses; RAM v = 8, "
+                        "w = 8 (2,048 TRLWE cells); write = read + control unit + 2,048 write bars + "
+                        "2,048 refresh bootstraps"}
 
 
 def serving_run(ctx, s0, duration: float, mem_budget: int = 2 << 30):
@@ -255,6 +306,10 @@ def main():
                   "circuit_ms": float(lv.sum()), "gates_per_s": float(len(c3["gates"]) / (lv.sum() / 1e3))}
         circ.close()
 
+    memory = None
+    if not args.no_memory:
+        memory = memory_run(ctx, s0, s1)
+
     serving = None
     if args.serving > 0:
         serving = serving_run(ctx, s0, args.serving)
@@ -288,7 +343,7 @@ def main():
                    "batch": B_GATES, "parallelism": "single GPU"},
         "per_gate_value": None if per_gate is None else round(per_gate, 2),
         "batched_over_per_gate": None if per_gate is None else round(value / per_gate, 1),
-        "per_level": levels, "serving": serving, "roofline": roof, "cpu_baseline": cpu,
+        "per_level": levels, "cmux_memory": memory, "serving": serving, "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
 

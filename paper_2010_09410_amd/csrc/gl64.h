@@ -87,6 +87,41 @@ __device__ __forceinline__ u64 gl_mul(u64 a, u64 b) {
   return r2 - ((r < hh) ? GL_EPS : 0);
 }
 
+// x0 k0 + x1 k1 mod p (lazy result) with one reduction: the two 128-bit products are added
+// as a 129-bit integer (top:hi:lo); with hi = hh 2^32 + hl, 2^64 = 2^32 - 1, 2^96 = -1 and
+// 2^128 = -2^32 it is lo + hl (2^32 - 1) - (hh + top 2^32), and the same single carry and
+// single borrow fixes as in gl_mul apply (hh + top 2^32 < 2^33).
+__device__ __forceinline__ u64 gl_dot2(u64 x0, u64 k0, u64 x1, u64 k1) {
+  u64 l0, h0, l1, h1;
+  {
+    const u32 a0 = (u32)x0, a1 = (u32)(x0 >> 32), b0 = (u32)k0, b1 = (u32)(k0 >> 32);
+    const u64 p00 = (u64)a0 * b0;
+    const u64 t = (u64)a0 * b1 + (p00 >> 32);
+    const u64 u = (u64)a1 * b0 + (u32)t;
+    h0 = (u64)a1 * b1 + (t >> 32) + (u >> 32);
+    l0 = (u << 32) | (u32)p00;
+  }
+  {
+    const u32 a0 = (u32)x1, a1 = (u32)(x1 >> 32), b0 = (u32)k1, b1 = (u32)(k1 >> 32);
+    const u64 p00 = (u64)a0 * b0;
+    const u64 t = (u64)a0 * b1 + (p00 >> 32);
+    const u64 u = (u64)a1 * b0 + (u32)t;
+    h1 = (u64)a1 * b1 + (t >> 32) + (u >> 32);
+    l1 = (u << 32) | (u32)p00;
+  }
+  const u64 lo = l0 + l1;
+  const u64 hs = h0 + h1;
+  const u64 hi = hs + (lo < l0 ? 1u : 0u);
+  const bool top = (hs < h0) | (hi < hs);  // at most one of the two carries happens
+  const u32 hh = (u32)(hi >> 32), hl = (u32)hi;
+  const u64 tl = (u64)hl * GL_EPS;
+  u64 r = lo + tl;
+  r += (r < tl) ? GL_EPS : 0;
+  const u64 sub = (u64)hh + (top ? (1ull << 32) : 0);
+  const u64 r2 = r - sub;
+  return r2 - ((r < sub) ? GL_EPS : 0);
+}
+
 // x * 2^E mod p for a compile-time E in [0, 96), returned canonical (in [0, p)). Write
 // x 2^E as 32-bit words of a 160-bit integer and fold it back with 2^64 = 2^32 - 1 and
 // 2^96 = -1:

@@ -25,9 +25,11 @@ __global__ __launch_bounds__(256) void k_trgsw_to_ntt(const u32* __restrict__ sr
   for (int t = 0; t < 32; t++) v[t] = poly[l + 32 * t];
   u32* reg = lds + wave * WAVE_T_U32 + h * TREGION;
   ntt_forward(v, tw, reg, l);
+  // lanes 0-31 hold row k, lanes 32-63 row k + 3, both for output polynomial c: they become
+  // entries 0 and 1 of lane l + 32 c
   u64* out = dst + item * TRGSW_NTT_U64 + (size_t)k * 32 * 64 * 2;
 #pragma unroll
-  for (int s = 0; s < 32; s++) out[((size_t)s * 64 + lane) * 2 + c] = gl_canon(gl_mul(v[s], ninv));
+  for (int s = 0; s < 32; s++) out[((size_t)s * 64 + l + 32 * c) * 2 + h] = gl_canon(gl_mul(v[s], ninv));
 }
 
 hipError_t launch_trgsw_to_ntt(const vsp_context* ctx, const uint32_t* src, uint64_t* dst, uint64_t count,

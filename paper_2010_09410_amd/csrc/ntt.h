@@ -38,9 +38,10 @@ constexpr int TROW = 33;
 constexpr int TREGION = 32 * TROW + 64;     // u32 per half
 constexpr int WAVE_T_U32 = 2 * TREGION;     // u32 per wave
 
-// External-product key layout in u64, per TRGSW: [round k][slot s][lane][c], where lanes
-// 0-31 carry TRGSW row k and lanes 32-63 row k+3, and c selects the output polynomial
-// (0: a, 1: b). One 16-byte load gives a lane both entries of a slot.
+// External-product key layout in u64, per TRGSW: [round k][slot s][lane][e]: lane l + 32 h
+// holds, for output polynomial h (0: a, 1: b), entry e = 0 from TRGSW row k (the row that
+// multiplies the digits of ACC.a) and e = 1 from row k + 3 (digits of ACC.b). One 16-byte
+// load gives a lane both entries of a slot.
 constexpr int TRGSW_NTT_U64 = GADGET_L * 32 * 64 * 2;
 
 constexpr int brv5(int k) {
@@ -236,26 +237,24 @@ __device__ __forceinline__ u64 gadget_digit(u32 x, int sh) {
   return (u64)(int64_t)((int32_t)((t >> sh) & 63u) - 32);
 }
 
-// Sum over the two halves of a wave: lanes 0-31 receive P0[l] + P0[l + 32], lanes 32-63
-// receive P1[l - 32] + P1[l]. v_permlane32_swap exchanges the upper half-wave of its first
-// operand with the lower half-wave of its second, so after one swap per 32-bit word each
-// lane holds exactly the two terms it needs.
-__device__ __forceinline__ u64 sum_halves(u64 p0, u64 p1) {
-  const auto lo = __builtin_amdgcn_permlane32_swap((u32)p0, (u32)p1, false, false);
-  const auto hi = __builtin_amdgcn_permlane32_swap((u32)(p0 >> 32), (u32)(p1 >> 32), false, false);
-  const u64 a = ((u64)hi[0] << 32) | lo[0];
-  const u64 b = ((u64)hi[1] << 32) | lo[1];
-  return gl_add(a, b);
+// Both halves' values of one slot: v_permlane32_swap(x, x) exchanges the upper half-wave of
+// its first operand with the lower half-wave of its second, so afterwards the first result
+// holds the lanes 0-31 value (the digit transform of ACC.a) and the second the lanes 32-63
+// value (ACC.b) in every lane.
+__device__ __forceinline__ void both_halves(u64 x, u64& xa, u64& xb) {
+  const auto lo = __builtin_amdgcn_permlane32_swap((u32)x, (u32)x, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((u32)(x >> 32), (u32)(x >> 32), false, false);
+  xa = ((u64)hi[0] << 32) | lo[0];
+  xb = ((u64)hi[1] << 32) | lo[1];
 }
 
 // Wave-cooperative external product: out = this half's polynomial of C (ext) D (lifted to
 // the torus). D holds this half's polynomial of the TRLWE operand (lanes 0-31: a, lanes
 // 32-63: b); Cn is the TRGSW in the key layout above (already scaled by 1/N). Round k
-// transforms gadget digit k+1 of both halves (TRGSW rows k and k+3); each lane multiplies
-// its transformed digits by the row's entries for both output polynomials, and the halves'
-// contributions are summed with one swap, lanes 0-31 accumulating output a and lanes 32-63
-// output b. Key entries stream in chunks of KCH slots, the next chunk in flight while the
-// current one is used.
+// transforms gadget digit k+1 of both halves (TRGSW rows k and k+3); each lane takes both
+// halves' transformed digits of a slot and adds their products with its output polynomial's
+// two key entries to its accumulator, reducing the 129-bit sum once. Key entries stream in
+// chunks of KCH slots, the next chunk in flight while the current one is used.
 constexpr int KCH = 4;
 
 // DigitSource: callable (int sh, u64 (&x)[32]) filling x with the gadget digit at bit offset
@@ -285,9 +284,9 @@ __device__ __forceinline__ void external_product(DigitSource digits, const u64* 
 #pragma unroll
       for (int q = 0; q < KCH; q++) {
         const int s = KCH * c + q;
-        const u64 p0 = gl_mul(x[s], kc[q].x);
-        const u64 p1 = gl_mul(x[s], kc[q].y);
-        sum[s] = gl_add(sum[s], sum_halves(p0, p1));
+        u64 xa, xb;
+        both_halves(x[s], xa, xb);
+        sum[s] = gl_add(sum[s], gl_dot2(xa, kc[q].x, xb, kc[q].y));
       }
       __builtin_amdgcn_sched_barrier(0);
       if (c + 1 < 32 / KCH) {

@@ -89,3 +89,26 @@ def test_config3_full_decrypt_and_sampled_parity(gpu, keys):
     ref = oracle.gates(keys["bk"], keys["ksk"], ops, wires[c["gates"][sample, 1]], wires[c["gates"][sample, 2]])
     np.testing.assert_array_equal(wires[c["ninputs"] + sample], ref)
     circ.close()
+
+
+def test_graph_replays_with_eager_work_between(gpu, keys):
+    """The captured level sequence is replayed several times, with unrelated eager launches and
+    synchronisations in between; every replay equals the eager result."""
+    c = W.small_circuit(seed=702, levels=5, wmin=4, wmax=40, ninputs=16)
+    inputs = gpu.tensor(client.tlwe_encrypt_bits(keys["s0"], c["bits"], *c["enc"]))
+    circ = gpu.circuit(c["gates"], c["ninputs"])
+    eager, _ = circ.run_timed(inputs)
+    eager = to_host(eager)
+    g = W.rng(703)
+    other = W.gate_batch(7, 50)
+    o0 = gpu.tensor(client.tlwe_encrypt_bits(keys["s0"], other["bits0"], *other["enc0"]))
+    o1 = gpu.tensor(client.tlwe_encrypt_bits(keys["s0"], other["bits1"], *other["enc1"]))
+    ops = gpu.tensor(other["ops"])
+    for rep in range(3):
+        gpu.gates(ops, o0, o1)                     # eager work on the same stream
+        gpu.sync()
+        replay = to_host(circ.run(inputs))
+        np.testing.assert_array_equal(replay, eager, err_msg=f"replay {rep}")
+        o0 = gpu.tensor(W.uniform_u32(g, (50, n + 1)))
+    circ.close()
+    np.testing.assert_array_equal(client.tlwe_decrypt(keys["s0"], eager), plaintext_eval(c["gates"], c["bits"]))
