@@ -39,8 +39,9 @@ N_LWE, N_RING, GL, STEPS_BR = 630, 1024, 3, 630
 # 17.5 instructions for E mod 96 below 32, 25 in [32, 64), 20 in [64, 96), 14 for E = 0,
 # 8 for the first stage on small digits. A general product mod p is 22, a canonical 2^E
 # product 9 / 15 / 10 by the same classes, an add mod p 7, a gadget digit with its rotation
-# 8, an exact lift 4.
-C_MUL, C_ADD, C_DIGIT, C_LIFT = 22, 7, 8, 4
+# 8, an exact lift 4; the key MAC adds two products with one reduction (40) and the two
+# half-wave swaps (2) to the accumulator (7).
+C_MUL, C_ADD, C_DIGIT, C_LIFT, C_DOT2, C_SWAP = 22, 7, 8, 4, 40, 2
 BF_LO, BF_MID, BF_HI, BF_TRIV, BF_SMALL = 17.5, 25, 20, 14, 8
 P2_LO, P2_MID, P2_HI = 9, 15, 10
 
@@ -65,7 +66,7 @@ def br_step_lane_ops() -> int:
     twist = sum({0: P2_LO, 1: P2_MID, 2: P2_HI}[_exp_class(96 - 3 * t)] for t in range(1, 32))
     forward = pass1 + table + dft
     inverse = dft + table + dft + twist + 32 * C_LIFT
-    mac = GL * 32 * (2 * C_MUL + 2 * C_ADD)      # per lane: 32 slots, 3 rounds
+    mac = GL * 32 * (C_DOT2 + C_SWAP + C_ADD)    # per lane: 32 slots, 3 rounds
     digits = GL * 32 * C_DIGIT
     return int(round(64 * (GL * forward + inverse + mac + digits)))
 
@@ -118,7 +119,10 @@ def parse():
     ap.add_argument("--cpu-gates", type=int, default=0, help="oracle sample size (default: about 12 s of work)")
     ap.add_argument("--no-memory", action="store_true", help="skip the CMUX-memory timings")
     ap.add_argument("--serving", type=float, default=2.0, metavar="SECONDS",
-                    help="arrival window of the serving run (0 skips it)")
+                    help="arrival window of the serving run at 50 circuits/s (0 skips it)")
+    ap.add_argument("--serving-light", type=float, default=0.7, metavar="FRACTION",
+                    help="also serve about 30 circuits offered at this fraction of the measured batched "
+                         "throughput (0 skips it)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run one plain device copy of MIB MiB (reference for HBM byte counters)")
     return ap.parse_args()
@@ -126,8 +130,11 @@ def parse():
 
 def cpu_baseline(s0, s1, bkd, kskd, cfg, in0, in1, ngates):
     """The CPU oracle (test infrastructure) on this host's cores, on a bounded sample sized
-    to about 12 s of work from a short first pass."""
+    to about 12 s of work from a short first pass; also one gate on one thread and 16 ROM
+    reads (512-word ROM, 9-bit addresses) on all threads."""
     import oracle
+    import workloads as W
+    from paper_2010_09410_amd import client
     threads = max(1, len(os.sched_getaffinity(0)))
     bk, ksk = oracle.keyset(s0, s1, bkd, kskd)
     if not ngates:
@@ -139,8 +146,18 @@ def cpu_baseline(s0, s1, bkd, kskd, cfg, in0, in1, ngates):
     t0 = time.perf_counter()
     oracle.gates(bk, ksk, cfg["ops"][:ngates], in0[:ngates], in1[:ngates], threads=threads)
     dt = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    oracle.gates(bk, ksk, cfg["ops"][:1], in0[:1], in1[:1], threads=1)
+    single = time.perf_counter() - t1
+    wl = W.rom_workload(reads=16)
+    rom = client.trlwe_encrypt_torus(s1, client.pack_rom(wl["words"]), *wl["cells"])
+    sel = client.trgsw_encrypt(s1, (wl["addr"][:, None] >> np.arange(9)[None, :]) & 1, *wl["sel"])
+    t2 = time.perf_counter()
+    oracle.rom_reads(ksk, rom, sel, threads=threads)
+    rom_dt = time.perf_counter() - t2
     return {"value": round(ngates / dt, 2), "unit": "gate bootstraps/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {ngates} gates of the 4096-gate batch, {threads} threads, {dt:.1f} s"}
+            "sample": f"first {ngates} gates of the 4096-gate batch, {threads} threads, {dt:.1f} s",
+            "single_thread_s_per_gate": round(single, 3), "rom_reads_per_s": round(16 / rom_dt, 1)}
 
 
 def memory_run(ctx, s0, s1, reps: int = 3):
@@ -193,12 +210,15 @@ def memory_run(ctx, s0, s1, reps: int = 3):
                         "2,048 refresh bootstraps"}
 
 
-def serving_run(ctx, s0, duration: float, mem_budget: int = 2 << 30):
+MEAN_CIRCUIT_GATES = (20000 - 100) / np.log(20000 / 100)   # log-uniform sizes in [100, 20000]
+
+
+def serving_run(ctx, s0, duration: float, rate: float = 50.0, mem_budget: int = 2 << 30):
     """Replays Poisson arrivals of layered circuits from 64 clients in real time against the
     continuous-batching server; inputs are encrypted before the clock starts."""
     import workloads as W
     from paper_2010_09410_amd import client
-    trace = W.serving_trace(duration=duration)
+    trace = W.serving_trace(rate=rate, duration=duration)
     enc = [client.tlwe_encrypt_bits(s0, r["bits"], *W.tlwe_draws(W.rng(r["enc_seed"]), r["ninputs"]))
            for r in trace]
     srv = ctx.server(mem_budget, max_batch=4096)
@@ -223,7 +243,8 @@ def serving_run(ctx, s0, duration: float, mem_budget: int = 2 << 30):
     total = sum(len(r["gates"]) for r in trace)
     span = max(done_t) - trace[0]["t"]
     lat = np.array(lat)
-    return {"circuits": len(trace), "clients": 64, "gates": total, "arrival_window_s": duration,
+    return {"circuits": len(trace), "clients": 64, "gates": total, "rate_circuits_per_s": round(rate, 2),
+            "arrival_window_s": round(duration, 2),
             "offered_gates_per_s": round(total / duration, 1), "served_gates_per_s": round(total / span, 1),
             "makespan_s": round(span, 3), "p50_latency_ms": round(float(np.percentile(lat, 50)), 1),
             "p99_latency_ms": round(float(np.percentile(lat, 99)), 1), "batches": int(batches),
@@ -285,6 +306,19 @@ def main():
         torch.cuda.synchronize()
         per_gate = pg / (time.perf_counter() - t0)
 
+    # homomorphic MUX (two bootstraps and one key switch per MUX), 2048 rows of the same inputs
+    mux_rate = None
+    if pg > 0:
+        M = B_GATES // 2
+        mo = ctx.empty(M, N_LWE + 1)
+        ctx.mux(a_d[:M], b_d[:M], a_d[M:2 * M], out=mo)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.mux(a_d[:M], b_d[:M], a_d[M:2 * M], out=mo)
+        torch.cuda.synchronize()
+        mux_rate = M / (time.perf_counter() - t0)
+        del mo
+
     if args.calibrate_copy > 0:
         src = torch.empty(args.calibrate_copy << 18, dtype=torch.int32, device=ctx.device).fill_(1)
         dst = torch.empty_like(src)
@@ -313,6 +347,11 @@ def main():
     serving = None
     if args.serving > 0:
         serving = serving_run(ctx, s0, args.serving)
+    if args.serving_light > 0:
+        rate = args.serving_light * value / MEAN_CIRCUIT_GATES
+        light = serving_run(ctx, s0, 30.0 / rate, rate=rate)
+        light["offered_fraction_of_batched_throughput"] = args.serving_light
+        serving = {"config": serving, "light": light} if serving else {"light": light}
 
     br_avg_ms = br_ms / max(br_n, 1)
     achieved = B_GATES * LANE_OPS_PER_GATE / (br_avg_ms * 1e-3) / 1e12
@@ -343,6 +382,7 @@ def main():
                    "batch": B_GATES, "parallelism": "single GPU"},
         "per_gate_value": None if per_gate is None else round(per_gate, 2),
         "batched_over_per_gate": None if per_gate is None else round(value / per_gate, 1),
+        "mux_per_s": None if mux_rate is None else round(mux_rate, 1),
         "per_level": levels, "cmux_memory": memory, "serving": serving, "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

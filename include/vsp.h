@@ -182,26 +182,37 @@ vsp_status vsp_server_stats(vsp_server* s, uint64_t* gates, uint64_t* batches, u
 /* Stop the server thread (finishing admitted work) and free it. NULL is accepted. */
 vsp_status vsp_server_destroy(vsp_server* s);
 
+/* Homomorphic MUX of B rows (the three-operand gate of Sec. 2.1.2): d_out[g] = d_sel[g] ? d_in1[g]
+ * : d_in0[g] on encrypted bits, all [B][n+1] TLWE rows under the LWE key. Each MUX bootstraps
+ * AND(s, c1) and ANDNOT(c0, s) to TRLWE, adds them and (0, mu) (the HomMUX without SE and IKS
+ * of Sec. 2.1.2, as in the RAM control unit of Sec. 8.2), then SampleExtracts and key-switches
+ * once: twice a gate's blind rotations, one key switch. d_out must not overlap the inputs
+ * (VSP_E_ARG). Asynchronous on `stream`. */
+vsp_status vsp_mux(vsp_context* ctx, const uint32_t* d_sel, const uint32_t* d_in1, const uint32_t* d_in0,
+                   uint32_t* d_out, uint64_t B, void* stream);
+
 /* Autotuner for the batched launches (the level executor's tile and batch shapes). A gate's
- * blind rotation is one wave, so a batch of B gates runs in ceil(B / cap) rounds, cap being
- * the gates the GPU holds at once for a workgroup shape (4 or 8 gates per workgroup). This
- * call times one full round of each shape on random ciphertexts, and times the three
- * key-switch forms (0: one workgroup per gate gathering its key rows; 1: tiles of 16 gates
- * reading each key row once and selecting in registers; 2: tiles of 16 gates staging key rows
- * through LDS, with the j range split over workgroups and atomic accumulation) for each batch-size
- * bucket up to max_batch (buckets end at 1, 16, 64, 256, 1024, 2048, 4096 gates; larger
- * batches share the last). Every candidate must give bit-identical outputs (else VSP_E_HIP).
- * Later launches pick the shape with the fewest rounds x round time, and the faster key
- * switch for their bucket. With cache_path non-NULL the measurements are read from that JSON
- * file when it holds an entry for this GPU, and otherwise measured and written there.
- * Synchronous; allocates and frees its own buffers. */
+ * blind rotation runs on one wave (or, in the latency shape, on three waves that split each
+ * external product by gadget level), so a batch of B gates runs in ceil(B / cap) rounds, cap
+ * being the gates the GPU holds at once for a workgroup shape (4 or 8 gates per workgroup, or
+ * one gate per three-wave workgroup). This call times one full round of each shape on random
+ * ciphertexts, and times the three key-switch forms (0: one workgroup per gate gathering its
+ * key rows; 1: tiles of 16 gates reading each key row once and selecting in registers;
+ * 2: tiles of 16 gates staging key rows through LDS, with the j range split over workgroups
+ * and atomic accumulation) for each batch-size bucket up to max_batch (buckets end at 1, 16,
+ * 64, 256, 1024, 2048, 4096 gates; larger batches share the last). Every candidate must give
+ * bit-identical outputs (else VSP_E_HIP). Later launches pick the shape with the fewest
+ * rounds x round time, and the faster key switch for their bucket. With cache_path non-NULL
+ * the measurements are read from that JSON file when it holds an entry for this GPU, and
+ * otherwise measured and written there. Synchronous; allocates and frees its own buffers. */
 vsp_status vsp_autotune(vsp_context* ctx, uint64_t max_batch, const char* cache_path);
 
-/* The launch choice for a batch of B gates: *br_waves (4 or 8), *ks_form (0, 1 or 2). */
+/* The launch choice for a batch of B gates: *br_waves (4 or 8 gates per workgroup at one wave
+ * per gate, or 3 for one gate per workgroup on three waves), *ks_form (0, 1 or 2). */
 vsp_status vsp_tuning_get(const vsp_context* ctx, uint64_t B, int* br_waves, int* ks_form);
 
-/* Pin the launch choice for the bucket containing B: br_waves 4 or 8 (0 returns that bucket
- * to the round-time model), ks_form 0, 1 or 2. Results are the same for every choice. */
+/* Pin the launch choice for the bucket containing B: br_waves 3, 4 or 8 (0 returns that
+ * bucket to the round-time model), ks_form 0, 1 or 2. Results are the same for every choice. */
 vsp_status vsp_tuning_set(vsp_context* ctx, uint64_t B, int br_waves, int ks_form);
 
 /* Kernel-time instrumentation (for benchmarks): while enabled, every eager launch of the

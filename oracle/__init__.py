@@ -49,7 +49,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_SO):
+        if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
             build()
         _lib = ctypes.CDLL(_SO)
         _declare(_lib)
@@ -91,6 +91,8 @@ def _declare(L):
         "or_bootstrap_to_trlwe": (None, [_P, _u32p, _u32p, _u32p]),
         "or_gate": (None, [_P, _u32p, _u32p, _c.c_int, _u32p, _u32p, _u32p]),
         "or_gates": (None, [_P, _u32p, _u32p, _u8p, _u32p, _u32p, _u32p, _c.c_int64, _c.c_int]),
+        "or_mux": (None, [_P, _u32p, _u32p, _u32p, _u32p, _u32p, _u32p]),
+        "or_muxes": (None, [_P, _u32p, _u32p, _u32p, _u32p, _u32p, _u32p, _c.c_int64, _c.c_int]),
         "or_rom_read": (None, [_P, _u32p, _u32p, _c.c_int, _u32p, _c.c_int, _c.c_int, _u32p]),
         "or_ram_read": (None, [_P, _u32p, _u32p, _c.c_int, _c.c_int, _u32p, _u32p]),
         "or_ram_control": (None, [_P, _u32p, _u32p, _u32p, _u32p, _c.c_int, _u32p]),
@@ -295,6 +297,16 @@ def gates(bk, ksk, ops, in0, in1, P=DEFAULT, threads=None):
     lib().or_gates(ctypes.byref(P), _u32(bk).reshape(-1), _u32(ksk).reshape(-1), ops,
                    _u32(in0).reshape(-1), _u32(in1).reshape(-1), out.reshape(-1), B,
                    threads or default_threads())
+    return out
+
+
+def muxes(bk, ksk, s, c1, c0, P=DEFAULT, threads=None):
+    """Homomorphic MUX s ? c1 : c0 over B rows of TLWE inputs."""
+    s = _u32(s)
+    B = s.shape[0]
+    out = np.zeros((B, P.n + 1), dtype=np.uint32)
+    lib().or_muxes(ctypes.byref(P), _u32(bk).reshape(-1), _u32(ksk).reshape(-1), s.reshape(-1),
+                   _u32(c1).reshape(-1), _u32(c0).reshape(-1), out.reshape(-1), B, threads or default_threads())
     return out
 
 

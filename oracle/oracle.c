@@ -396,6 +396,43 @@ void or_gates(const or_params *P, const uint32_t *bk, const uint32_t *ksk, const
   parallel_for(B, threads, gate_one, &c);
 }
 
+/* Homomorphic MUX, s ? c1 : c0 (the three-operand gate of Sec. 2.1.2, TFHE section): the two
+ * bootstrapped halves AND(s, c1) and ANDNOT(c0, s) are added as TRLWE together with (0, mu),
+ * which is the HomMUX without SE and IKS of Sec. 2.1.2; SampleExtract at 0 and the identity
+ * key switch then return a TLWE under the LWE key. */
+void or_mux(const or_params *P, const uint32_t *bk, const uint32_t *ksk, const uint32_t *s,
+            const uint32_t *c1, const uint32_t *c0, uint32_t *out) {
+  const int n = P->n, N = P->N;
+  uint32_t *lin = xmalloc(sizeof(uint32_t) * (n + 1));
+  uint32_t *acc = xmalloc(sizeof(uint32_t) * 2 * N);
+  uint32_t *acc2 = xmalloc(sizeof(uint32_t) * 2 * N);
+  uint32_t *ext = xmalloc(sizeof(uint32_t) * (N + 1));
+  or_gate_linear(n, OR_AND, s, c1, lin);
+  or_bootstrap_to_trlwe(P, bk, lin, acc);
+  or_gate_linear(n, OR_ANDNOT, c0, s, lin);
+  or_bootstrap_to_trlwe(P, bk, lin, acc2);
+  for (int j = 0; j < 2 * N; j++) acc[j] += acc2[j];
+  acc[N] += MU;
+  or_sample_extract(N, acc, 0, ext);
+  or_keyswitch(P, ksk, ext, out);
+  free(lin); free(acc); free(acc2); free(ext);
+}
+
+typedef struct { const or_params *P; const uint32_t *bk, *ksk, *s, *c1, *c0; uint32_t *out; } mux_ctx;
+
+static void mux_one(void *p, int64_t g) {
+  mux_ctx *c = p;
+  const size_t w = (size_t)c->P->n + 1;
+  or_mux(c->P, c->bk, c->ksk, c->s + g * w, c->c1 + g * w, c->c0 + g * w, c->out + g * w);
+}
+
+/* B independent MUXes, spread over `threads` threads. */
+void or_muxes(const or_params *P, const uint32_t *bk, const uint32_t *ksk, const uint32_t *s,
+              const uint32_t *c1, const uint32_t *c0, uint32_t *out, int64_t B, int threads) {
+  mux_ctx c = {P, bk, ksk, s, c1, c0, out};
+  parallel_for(B, threads, mux_one, &c);
+}
+
 /* ------------------------------------------------------------------ CMUX memory (Sec. 8) */
 
 /* ROM read by a CMUX tree over packed TRLWE cells (LUT with vertical and horizontal

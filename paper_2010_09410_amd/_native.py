@@ -62,6 +62,7 @@ SIGNATURES = {
     "vsp_server_poll": (_st, [_vp, _u64, _vp, ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_double)]),
     "vsp_server_stats": (_st, [_vp, ctypes.POINTER(_u64), ctypes.POINTER(_u64), ctypes.POINTER(_u64)]),
     "vsp_server_destroy": (_st, [_vp]),
+    "vsp_mux": (_st, [_vp, _vp, _vp, _vp, _vp, _u64, _vp]),
     "vsp_autotune": (_st, [_vp, _u64, ctypes.c_char_p]),
     "vsp_tuning_get": (_st, [_vp, _u64, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "vsp_tuning_set": (_st, [_vp, _u64, _i32, _i32]),
@@ -200,6 +201,10 @@ def vsp_server_stats(srv):
 
 def vsp_server_destroy(srv) -> None:
     _call("vsp_server_destroy", srv)
+
+
+def vsp_mux(ctx, d_sel, d_in1, d_in0, d_out, B, stream=None) -> None:
+    _call("vsp_mux", ctx, d_sel, d_in1, d_in0, d_out, B, stream)
 
 
 def vsp_autotune(ctx, max_batch: int, cache_path: str | None = None) -> None:

@@ -1,6 +1,7 @@
 // Autotuner for the batched launches. On random ciphertexts it times one full round of gates
-// for each blind-rotation workgroup shape (4 or 8 gates per workgroup; the launch then picks
-// the shape with the fewest rounds x round time for its batch) and the three key-switch forms
+// for each blind-rotation workgroup shape (4 or 8 gates per workgroup at one wave per gate, or
+// one gate on three waves; the launch then picks the shape with the fewest rounds x round
+// time for its batch) and the three key-switch forms
 // (one workgroup per gate, row-stationary tiles, LDS-staged split) per batch-size bucket. Every
 // candidate must produce bit-identical outputs. The result can be cached in a small JSON file
 // keyed by the GPU.
@@ -133,7 +134,8 @@ vsp_status vsp_autotune(vsp_context* ctx, uint64_t max_batch, const char* cache_
   if (cache_path && read_cache(cache_path, key, ctx->tune)) return VSP_OK;
 
   const uint64_t Sks = std::min<uint64_t>(max_batch, kBucket[kTuneBuckets - 1]);
-  const uint64_t Sbr = std::max(ctx->tune.br_cap[0], ctx->tune.br_cap[1]);
+  uint64_t Sbr = 0;
+  for (int s = 0; s < kBrShapes; s++) Sbr = std::max(Sbr, ctx->tune.br_cap[s]);
   const uint64_t S = std::max(Sks, Sbr);
   Buf in, ops32, ops, abar, t1, t1ref, out, outref;
   const size_t T0 = (LWE_N + 1) * 4, T1 = (RING_N + 1) * 4;
@@ -230,8 +232,8 @@ vsp_status vsp_tuning_get(const vsp_context* ctx, uint64_t B, int* br_waves, int
 
 vsp_status vsp_tuning_set(vsp_context* ctx, uint64_t B, int br_waves, int ks_form) {
   if (ctx == nullptr) return fail(VSP_E_ARG, "context is NULL");
-  if ((br_waves != 0 && br_waves != 4 && br_waves != 8) || ks_form < 0 || ks_form >= kKsForms)
-    return fail(VSP_E_ARG, "br_waves must be 0 (model), 4 or 8 and ks_form 0, 1 or 2");
+  if ((br_waves != 0 && br_waves != 3 && br_waves != 4 && br_waves != 8) || ks_form < 0 || ks_form >= kKsForms)
+    return fail(VSP_E_ARG, "br_waves must be 0 (model), 3, 4 or 8 and ks_form 0, 1 or 2");
   const int b = Tuning::bucket(B == 0 ? 1 : B);
   ctx->tune.br_force[b] = br_waves;
   ctx->tune.ks_form[b] = ks_form;

@@ -3,6 +3,7 @@
 // identity key switching, and test kernels for the external product and polynomial product.
 #include "vsp_internal.h"
 #include "blind_rotate.h"
+#include "blind_rotate_wide.h"
 
 namespace vsp {
 
@@ -112,19 +113,65 @@ hipError_t launch_gate_prologue_uniform(const vsp_context* ctx, uint32_t op, con
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ homomorphic MUX
+// Prologue of s ? c1 : c0 over 2B bootstraps: row g < B takes AND(s, c1), row B + g takes
+// ANDNOT(c0, s) (then the modulus switch).
+__global__ __launch_bounds__(256) void k_mux_prologue(const u32* __restrict__ sel, const u32* __restrict__ in1,
+                                                      const u32* __restrict__ in0, u32* __restrict__ abar,
+                                                      uint64_t B) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 2 * B * TLWE0) return;
+  const uint64_t r = i / TLWE0;
+  const int c = (int)(i - r * TLWE0);
+  const bool second = r >= B;
+  const uint64_t g = second ? r - B : r;
+  const u32 s = sel[g * TLWE0 + c];
+  u32 v;
+  if (second)
+    gate_linear(VSP_ANDNOT, in0[g * TLWE0 + c], s, c == LWE_N, v);
+  else
+    gate_linear(VSP_AND, s, in1[g * TLWE0 + c], c == LWE_N, v);
+  abar[r * TLWE0 + c] = modswitch_2n(v);
+}
+
+// t[g] += t[B + g] + (0, ..., 0, mu): the sum of the two extracted halves plus the constant
+// term of the HomMUX without SE and IKS (SampleExtract is linear).
+__global__ __launch_bounds__(256) void k_mux_combine(u32* __restrict__ t, uint64_t B) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= B * TLWE1) return;
+  const uint64_t g = i / TLWE1;
+  const int c = (int)(i - g * TLWE1);
+  t[i] += t[(B + g) * TLWE1 + c] + (c == RING_N ? MU : 0u);
+}
+
+hipError_t launch_mux_prologue(const uint32_t* sel, const uint32_t* in1, const uint32_t* in0, uint32_t* abar,
+                               uint64_t B, hipStream_t st) {
+  if (B == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mux_prologue, dim3((unsigned)((2 * B * TLWE0 + 255) / 256)), dim3(256), 0, st, sel, in1, in0,
+                     abar, B);
+  return hipGetLastError();
+}
+
+hipError_t launch_mux_combine(uint32_t* t, uint64_t B, hipStream_t st) {
+  if (B == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mux_combine, dim3((unsigned)((B * TLWE1 + 255) / 256)), dim3(256), 0, st, t, B);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ blind rotation
 // Raises the dynamic-LDS limit of the kernels that use more than 64 KiB (once, at context
 // creation, outside any stream capture).
 hipError_t init_kernel_attributes() {
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_blind_rotate<4>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)br_lds_bytes(4));
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_blind_rotate<8>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)br_lds_bytes(8));
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_blind_rotate<8>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)br_lds_bytes(8));
+  return e;
 }
 
 hipError_t blind_rotate_capacity(int device, uint64_t (&cap)[kBrShapes]) {
-  int cus = 0, n4 = 0, n8 = 0;
+  int cus = 0, n4 = 0, n8 = 0, nw = 0;
   hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
   if (e == hipSuccess)
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n4, reinterpret_cast<const void*>(&k_blind_rotate<4>), 256,
@@ -132,10 +179,14 @@ hipError_t blind_rotate_capacity(int device, uint64_t (&cap)[kBrShapes]) {
   if (e == hipSuccess)
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n8, reinterpret_cast<const void*>(&k_blind_rotate<8>), 512,
                                                      br_lds_bytes(8));
+  if (e == hipSuccess)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nw, reinterpret_cast<const void*>(&k_blind_rotate_wide),
+                                                     BRW_WAVES * 64, brw_lds_bytes());
   if (e != hipSuccess) return e;
-  static_assert(kBrWaveChoices[0] == 4 && kBrWaveChoices[1] == 8, "shape order");
+  static_assert(kBrWaveChoices[0] == 4 && kBrWaveChoices[1] == 8 && kBrWaveChoices[2] == 3, "shape order");
   cap[0] = (uint64_t)(n4 > 0 ? n4 : 1) * (uint64_t)cus * 4;
   cap[1] = (uint64_t)(n8 > 0 ? n8 : 1) * (uint64_t)cus * 8;
+  cap[2] = (uint64_t)(nw > 0 ? nw : 1) * (uint64_t)cus;
   return hipSuccess;
 }
 
@@ -143,7 +194,10 @@ hipError_t launch_blind_rotate(const vsp_context* ctx, const uint8_t* ops, const
                                uint32_t* trlwe, uint64_t B, int waves, hipStream_t st) {
   if (B == 0) return hipSuccess;
   if (waves <= 0) waves = ctx->tune.br_waves(B);
-  if (waves == 4) {
+  if (waves == 3) {
+    hipLaunchKernelGGL(k_blind_rotate_wide, dim3((unsigned)B), dim3(BRW_WAVES * 64), brw_lds_bytes(), st, ctx->bkn,
+                       ctx->tw, ops, abar, tlwe1, trlwe, B);
+  } else if (waves == 4) {
     hipLaunchKernelGGL(k_blind_rotate<4>, dim3((unsigned)((B + 3) / 4)), dim3(256), br_lds_bytes(4), st, ctx->bkn,
                        ctx->tw, ops, abar, tlwe1, trlwe, B);
   } else {

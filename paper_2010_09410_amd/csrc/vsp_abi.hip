@@ -312,6 +312,46 @@ vsp_status vsp_bootstrap_trlwe(vsp_context* ctx, const uint8_t* d_ops, const uin
   return gates_impl(ctx, d_ops, d_in0, d_in1, d_out, B, VSP_BATCHED, stream, true);
 }
 
+vsp_status vsp_mux(vsp_context* ctx, const uint32_t* d_sel, const uint32_t* d_in1, const uint32_t* d_in0,
+                   uint32_t* d_out, uint64_t B, void* stream) {
+  vsp_status s = check_ctx(ctx);
+  if (s) return s;
+  if (B == 0) return VSP_OK;
+  if (B > (1ull << 30)) return fail(VSP_E_ARG, "B too large");
+  VSP_HIP(hipSetDevice(ctx->device));
+  const size_t tl = (size_t)B * (LWE_N + 1) * 4;
+  if ((s = check_device_range(ctx, d_sel, tl, "d_sel"))) return s;
+  if ((s = check_device_range(ctx, d_in1, tl, "d_in1"))) return s;
+  if ((s = check_device_range(ctx, d_in0, tl, "d_in0"))) return s;
+  if ((s = check_device_range(ctx, d_out, tl, "d_out"))) return s;
+  if ((s = check_no_overlap(d_out, tl, d_sel, tl, "d_out and d_sel"))) return s;
+  if ((s = check_no_overlap(d_out, tl, d_in1, tl, "d_out and d_in1"))) return s;
+  if ((s = check_no_overlap(d_out, tl, d_in0, tl, "d_out and d_in0"))) return s;
+  if ((s = scratch_reserve(ctx, ctx->abar, 2 * B * (LWE_N + 1) * 4))) return s;
+  if ((s = scratch_reserve(ctx, ctx->tlwe1, 2 * B * (RING_N + 1) * 4))) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  uint32_t* abar = static_cast<uint32_t*>(ctx->abar.ptr);
+  uint32_t* t1 = static_cast<uint32_t*>(ctx->tlwe1.ptr);
+  hipError_t e;
+  {
+    ProfScope ps(ctx, 2, st);
+    e = launch_mux_prologue(d_sel, d_in1, d_in0, abar, B, st);
+  }
+  if (e != hipSuccess) return hip_fail(e, "mux prologue");
+  {
+    ProfScope ps(ctx, 0, st);
+    e = launch_blind_rotate(ctx, nullptr, abar, t1, nullptr, 2 * B, 0, st);
+  }
+  if (e != hipSuccess) return hip_fail(e, "blind rotation");
+  if ((e = launch_mux_combine(t1, B, st)) != hipSuccess) return hip_fail(e, "mux combine");
+  {
+    ProfScope ps(ctx, 1, st);
+    e = launch_keyswitch(ctx, nullptr, t1, nullptr, d_out, B, st);
+  }
+  if (e != hipSuccess) return hip_fail(e, "key switch");
+  return VSP_OK;
+}
+
 vsp_status vsp_profile_enable(vsp_context* ctx, int on) {
   vsp_status s = check_ctx(ctx);
   if (s) return s;

@@ -26,9 +26,10 @@ __host__ __device__ inline bool op_bootstraps(uint32_t op) { return op < 8 || op
 // Device-side error flags (bits), read back by vsp_context_sync.
 constexpr int DEVERR_BAD_OP = 1;
 
-// Blind-rotation workgroup sizes the kernels are instantiated for (waves = gates per group).
-constexpr int kBrShapes = 2;
-constexpr int kBrWaveChoices[kBrShapes] = {4, 8};
+// Blind-rotation workgroup shapes: 4 or 8 gates per workgroup at one wave per gate, or 3 for
+// one gate per workgroup on three waves (the latency form).
+constexpr int kBrShapes = 3;
+constexpr int kBrWaveChoices[kBrShapes] = {4, 8, 3};
 
 // Batch-size buckets: bucket b holds batches with kBucket[b-1] < B <= kBucket[b]; the last
 // one also holds every larger batch.
@@ -41,13 +42,13 @@ constexpr uint64_t kBucket[kTuneBuckets] = {1, 16, 64, 256, 1024, 2048, 4096};
 //    ceil(B / br_cap[s]) rounds of br_round_ms[s] with shape s, where br_cap[s] is the number
 //    of gates the whole GPU holds at once (occupancy x compute units x gates per group) and
 //    br_round_ms[s] the time of one full round. The shape with the fewer milliseconds wins
-//    (ties: the larger workgroup). br_force[b] != 0 pins the shape for bucket b.
+//    (ties: the 8-gate workgroup). br_force[b] != 0 pins the shape for bucket b.
 //  * Key switch: per bucket, form 0 gathers key rows per gate, 1 reads them once per tile of
 //    gates and selects in registers, 2 stages them through LDS for a tile of gates and splits
 //    the j range over workgroups.
 struct Tuning {
-  uint64_t br_cap[kBrShapes] = {1024, 2048};
-  float br_round_ms[kBrShapes] = {1.0f, 1.48f};
+  uint64_t br_cap[kBrShapes] = {1024, 2048, 512};
+  float br_round_ms[kBrShapes] = {1.0f, 1.48f, 0.8f};
   int br_force[kTuneBuckets] = {0, 0, 0, 0, 0, 0, 0};
   int ks_form[kTuneBuckets] = {2, 2, 2, 2, 2, 2, 2};
   bool tuned = false;
@@ -59,12 +60,12 @@ struct Tuning {
   int br_waves(uint64_t B) const {
     const int f = br_force[bucket(B)];
     if (f) return f;
-    int best = kBrShapes - 1;
+    int best = 1;
     double best_ms = 0;
-    for (int s = kBrShapes - 1; s >= 0; s--) {
+    for (int s : {1, 0, 2}) {
       const uint64_t cap = br_cap[s] ? br_cap[s] : 1;
       const double ms = (double)((B + cap - 1) / cap) * br_round_ms[s];
-      if (s == kBrShapes - 1 || ms < best_ms) {
+      if (s == 1 || ms < best_ms) {
         best = s;
         best_ms = ms;
       }
@@ -145,8 +146,13 @@ hipError_t launch_gate_prologue(const vsp_context* ctx, const uint8_t* ops, cons
 // The same opcode for every gate, one input (e.g. OP_IDENT for a refresh bootstrap).
 hipError_t launch_gate_prologue_uniform(const vsp_context* ctx, uint32_t op, const uint32_t* in0, uint32_t* abar,
                                         uint64_t B, hipStream_t st);
+// Homomorphic MUX pieces: the 2B prologue rows (AND(s, c1), then ANDNOT(c0, s)) and the sum of
+// the two extracted halves plus (0, mu) into the first B rows of t [2B][N+1].
+hipError_t launch_mux_prologue(const uint32_t* sel, const uint32_t* in1, const uint32_t* in0, uint32_t* abar,
+                               uint64_t B, hipStream_t st);
+hipError_t launch_mux_combine(uint32_t* t, uint64_t B, hipStream_t st);
 // Blind rotation of B gates (abar from the prologue). Writes SE_0 (TLWE1 [B][N+1]) and/or
-// the accumulator (TRLWE [B][2][N]). waves: 4 or 8 gates per workgroup, <= 0 the tuned choice.
+// the accumulator (TRLWE [B][2][N]). waves: a shape of kBrWaveChoices, <= 0 the tuned choice.
 hipError_t launch_blind_rotate(const vsp_context* ctx, const uint8_t* ops, const uint32_t* abar, uint32_t* tlwe1,
                                uint32_t* trlwe, uint64_t B, int waves, hipStream_t st);
 // Identity key switch TLWE1 [B][N+1] -> TLWE0 [B][n+1] (outputs scattered by idxo if given).

@@ -73,6 +73,14 @@ class Context:
         nv.vsp_gates(self.handle, _ptr(ops), _ptr(in0), _ptr(in1), _ptr(out), B, mode, self.stream())
         return out
 
+    def mux(self, sel: torch.Tensor, in1: torch.Tensor, in0: torch.Tensor, out=None) -> torch.Tensor:
+        """Encrypted sel ? in1 : in0, row by row."""
+        B = sel.shape[0]
+        if out is None:
+            out = self.empty(B, self.N_LWE + 1)
+        nv.vsp_mux(self.handle, _ptr(sel), _ptr(in1), _ptr(in0), _ptr(out), B, self.stream())
+        return out
+
     def bootstrap_trlwe(self, ops, in0, in1, out=None) -> torch.Tensor:
         B = ops.numel()
         if out is None:

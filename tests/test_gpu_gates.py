@@ -185,3 +185,34 @@ def test_config2_sampled_parity_and_full_decryption(gpu, keys):
     idx = np.array([0, 1, 2, 1023, 2048, 3071, 4094, 4095] + list(W.rng(505).integers(0, 4096, 8)))
     ref = oracle.gates(keys["bk"], keys["ksk"], cfg["ops"][idx], in0[idx], in1[idx])
     np.testing.assert_array_equal(out[idx], ref)
+
+
+MUX_ROWS = [(s, a, b) for s in (0, 1) for a in (0, 1) for b in (0, 1)]
+
+
+def test_mux_matches_oracle_and_truth_table(gpu, keys):
+    """HomMUX s ? c1 : c0 over the full truth table twice plus a ragged random batch: bit-exact
+    against the oracle, and every row decrypts to the selected bit."""
+    s0 = keys["s0"]
+    g = W.rng(510)
+    rows = MUX_ROWS * 2 + [tuple(g.integers(0, 2, 3)) for _ in range(21)]   # 37 rows
+    enc = lambda bits: client.tlwe_encrypt_bits(s0, np.array(bits), *W.tlwe_draws(g, len(bits)))
+    S, A, Bb = enc([r[0] for r in rows]), enc([r[1] for r in rows]), enc([r[2] for r in rows])
+    out = to_host(gpu.mux(dev(gpu, S), dev(gpu, A), dev(gpu, Bb)))
+    gpu.sync()
+    want = np.array([a if s else b for s, a, b in rows])
+    np.testing.assert_array_equal(client.tlwe_decrypt(s0, out), want)
+    np.testing.assert_array_equal(out, oracle.muxes(keys["bk"], keys["ksk"], S, A, Bb))
+    # trivial inputs give exactly (0, +-1/8)
+    T = lambda bits: client.trivial_tlwe_bits(np.array(bits))
+    tout = to_host(gpu.mux(dev(gpu, T([r[0] for r in MUX_ROWS])), dev(gpu, T([r[1] for r in MUX_ROWS])),
+                           dev(gpu, T([r[2] for r in MUX_ROWS]))))
+    np.testing.assert_array_equal(tout, T([a if s else b for s, a, b in MUX_ROWS]))
+
+
+def test_mux_rejects_overlap_and_accepts_empty(gpu):
+    x = gpu.empty(4, n + 1)
+    y = gpu.empty(4, n + 1)
+    with pytest.raises(VspError):
+        gpu.mux(x, y, y, out=x)
+    gpu.mux(x[:0], y[:0], y[:0], out=gpu.empty(0, n + 1))

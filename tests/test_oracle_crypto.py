@@ -238,3 +238,42 @@ def test_half_adder_from_paper(keys):
     for case in spec["printed_cases"]:
         k = rows.index((case["A"], case["B"]))
         assert (S[k], C[k]) == (case["S"], case["C"])
+
+
+MUX_ROWS = [(s, a, b) for s in (0, 1) for a in (0, 1) for b in (0, 1)]
+
+
+def trivial_bit(bit):
+    t = np.zeros(n + 1, dtype=np.uint32)
+    t[n] = MU if bit else (-MU) & 0xFFFFFFFF
+    return t
+
+
+def test_mux_trivial_inputs_exact(keys):
+    """MUX(s, a, b) = s ? a : b: with trivial inputs every abar is 0, both halves bootstrap to
+    exactly (0, +-1/8), and the result is exactly (0, +-1/8) for the selected bit."""
+    S = np.array([trivial_bit(r[0]) for r in MUX_ROWS])
+    A = np.array([trivial_bit(r[1]) for r in MUX_ROWS])
+    Bb = np.array([trivial_bit(r[2]) for r in MUX_ROWS])
+    out = oracle.muxes(keys["bk"], keys["ksk"], S, A, Bb)
+    want = np.array([a if s else b for s, a, b in MUX_ROWS])
+    np.testing.assert_array_equal(out, np.array([trivial_bit(w) for w in want]))
+
+
+def test_mux_truth_table_and_control_unit(keys):
+    """Encrypted inputs decrypt to s ? a : b over the full truth table (two draws), and the
+    result is the SampleExtract + key switch of the RAM control unit's HomMUX without SE and
+    IKS (Sec. 2.1.2) on the same inputs."""
+    s0 = keys["s0"]
+    g = W.rng(111)
+    rows = MUX_ROWS * 2
+    enc = lambda bits: oracle.tlwe_encrypt_bits(s0, np.array(bits), *W.tlwe_draws(g, len(bits)))
+    S, A, Bb = enc([r[0] for r in rows]), enc([r[1] for r in rows]), enc([r[2] for r in rows])
+    out = oracle.muxes(keys["bk"], keys["ksk"], S, A, Bb)
+    want = np.array([a if s else b for s, a, b in rows])
+    np.testing.assert_array_equal(oracle.tlwe_decrypt(s0, out), want)
+    err = signed(oracle.tlwe_phase(s0, out)) - np.where(want == 1, MU, -MU)
+    assert np.abs(err).max() < (1 << 26)
+    for k in (0, 5, 11):
+        u = oracle.ram_control(keys["bk"], S[k], A[k:k + 1], Bb[k:k + 1])[0]
+        np.testing.assert_array_equal(out[k], oracle.keyswitch(keys["ksk"], oracle.sample_extract(u, 0)))
