@@ -213,14 +213,22 @@ def memory_run(ctx, s0, s1, reps: int = 3):
 MEAN_CIRCUIT_GATES = (20000 - 100) / np.log(20000 / 100)   # log-uniform sizes in [100, 20000]
 
 
-def serving_run(ctx, s0, duration: float, rate: float = 50.0, mem_budget: int = 2 << 30):
+def serving_run(ctx, s0, duration: float, rate: float = 50.0, mem_budget: int = 2 << 30, nkeys: int = 1):
     """Replays Poisson arrivals of layered circuits from 64 clients in real time against the
-    continuous-batching server; inputs are encrypted before the clock starts."""
+    continuous-batching server; inputs are encrypted before the clock starts. With nkeys > 1,
+    client c encrypts under key set c mod nkeys (set 0 is the context's keys, the others are
+    drawn from seeds 30 + 3k) and the server batches per key set."""
     import workloads as W
     from paper_2010_09410_amd import client
     trace = W.serving_trace(rate=rate, duration=duration)
-    enc = [client.tlwe_encrypt_bits(s0, r["bits"], *W.tlwe_draws(W.rng(r["enc_seed"]), r["ninputs"]))
-           for r in trace]
+    sks, keysets = [s0], [None]
+    for k in range(1, nkeys):
+        a0, a1 = W.secret_keys(30 + 3 * k)
+        sks.append(a0)
+        keysets.append(ctx.keyset(*client.keyset(a0, a1, W.bk_draws(31 + 3 * k), W.ksk_draws(32 + 3 * k))))
+    which = [r["client"] % nkeys for r in trace]
+    enc = [client.tlwe_encrypt_bits(sks[w], r["bits"], *W.tlwe_draws(W.rng(r["enc_seed"]), r["ninputs"]))
+           for r, w in zip(trace, which)]
     srv = ctx.server(mem_budget, max_batch=4096)
     pending, lat, done_t = {}, [], []
     i = 0
@@ -229,7 +237,7 @@ def serving_run(ctx, s0, duration: float, rate: float = 50.0, mem_budget: int = 
         now = time.perf_counter() - t0
         while i < len(trace) and trace[i]["t"] <= now:
             r = trace[i]
-            pending[srv.submit(r["gates"], r["ninputs"], enc[i])] = i
+            pending[srv.submit(r["gates"], r["ninputs"], enc[i], keyset=keysets[which[i]])] = i
             i += 1
         for tk, j in list(pending.items()):
             done, _, ms = srv.poll(tk, trace[j]["ninputs"] + len(trace[j]["gates"]))
@@ -240,10 +248,13 @@ def serving_run(ctx, s0, duration: float, rate: float = 50.0, mem_budget: int = 
         time.sleep(0.002)
     gates, batches, peak = srv.stats()
     srv.close()
+    for k in keysets[1:]:
+        k.close()
     total = sum(len(r["gates"]) for r in trace)
     span = max(done_t) - trace[0]["t"]
     lat = np.array(lat)
-    return {"circuits": len(trace), "clients": 64, "gates": total, "rate_circuits_per_s": round(rate, 2),
+    return {"circuits": len(trace), "clients": 64, "key_sets": nkeys, "gates": total,
+            "rate_circuits_per_s": round(rate, 2),
             "arrival_window_s": round(duration, 2),
             "offered_gates_per_s": round(total / duration, 1), "served_gates_per_s": round(total / span, 1),
             "makespan_s": round(span, 3), "p50_latency_ms": round(float(np.percentile(lat, 50)), 1),
@@ -274,8 +285,14 @@ def main():
     ctx = Context(bk, ksk, device=0)
     ops_d, a_d, b_d = ctx.tensor(cfg["ops"]), ctx.tensor(in0), ctx.tensor(in1)
     out = ctx.empty(B_GATES, N_LWE + 1)
+    tune = None
     if not args.no_autotune:
-        ctx.autotune(max_batch=B_GATES)
+        import tempfile
+        with tempfile.TemporaryDirectory() as td:
+            path = os.path.join(td, "tune.json")
+            ctx.autotune(max_batch=B_GATES, cache_path=path)
+            with open(path) as fh:
+                (_, tune), = json.load(fh).items()
     br_waves, ks_form = ctx.tuning(B_GATES)
 
     for _ in range(args.warmup):
@@ -351,7 +368,9 @@ def main():
         rate = args.serving_light * value / MEAN_CIRCUIT_GATES
         light = serving_run(ctx, s0, 30.0 / rate, rate=rate)
         light["offered_fraction_of_batched_throughput"] = args.serving_light
-        serving = {"config": serving, "light": light} if serving else {"light": light}
+        keyed = serving_run(ctx, s0, 30.0 / rate, rate=rate, nkeys=4)
+        keyed["offered_fraction_of_batched_throughput"] = args.serving_light
+        serving = dict(config=serving, light=light, light_4_key_sets=keyed)
 
     br_avg_ms = br_ms / max(br_n, 1)
     achieved = B_GATES * LANE_OPS_PER_GATE / (br_avg_ms * 1e-3) / 1e12
@@ -366,7 +385,7 @@ def main():
                     "measured_GBps": None if traffic is None else round(traffic / (br_avg_ms * 1e-3) / 1e9, 1)},
             "key_stream_GBps_requested": round(B_GATES * BK_NTT_BYTES / (br_avg_ms * 1e-3) / 1e9, 1),
             "keyswitch_avg_ms": round(ks_ms / max(ks_n, 1), 3),
-            "launch": {"br_waves_per_workgroup": br_waves, "keyswitch": ["gather", "tiled", "split"][ks_form]}}
+            "launch": {"br_shape": br_waves, "keyswitch": ["gather", "tiled", "split"][ks_form], "autotune": tune}}
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(s0, s1, bkd, kskd, cfg, in0, in1, args.cpu_gates)

@@ -68,6 +68,7 @@ typedef enum vsp_gate {
 typedef struct vsp_context vsp_context;
 typedef struct vsp_circuit vsp_circuit;
 typedef struct vsp_server vsp_server;
+typedef struct vsp_keyset vsp_keyset;
 
 /* A gate of a circuit: opcode and the wire ids of its inputs (in1 ignored by NOT). Wires
  * 0..ninputs-1 are the circuit inputs; gate g writes wire ninputs + g. */
@@ -175,6 +176,19 @@ vsp_status vsp_server_submit(vsp_server* s, const vsp_gate_desc* gates, uint64_t
  * wires [ninputs + ngates][n+1] to h_wires and releases the ticket; latency_ms (if not
  * NULL) receives submit-to-completion time. *done = 0 while queued or running. */
 vsp_status vsp_server_poll(vsp_server* s, uint64_t ticket, uint32_t* h_wires, int* done, double* latency_ms);
+
+/* A further client's key set on the context's GPU (the protocol gives every client its own
+ * keys, Sec. 4.1): bk_host [n][2l][2][N] and ksk_host [N][t][base-1][n+1] as for
+ * vsp_context_create, converted and copied to the device (about 145 MB); the caller keeps its
+ * arrays. Synchronous. A key set must outlive every request submitted with it. */
+vsp_status vsp_keyset_create(vsp_context* ctx, const uint32_t* bk_host, const uint32_t* ksk_host, vsp_keyset** out);
+vsp_status vsp_keyset_destroy(vsp_keyset* k);
+
+/* vsp_server_submit for a circuit encrypted under `keys` (a key set of the server's context;
+ * NULL means the context's own keys). Batches are grouped by key set: the ready gates of the
+ * circuits that share one key set go into one launch sequence. */
+vsp_status vsp_server_submit_keyset(vsp_server* s, const vsp_keyset* keys, const vsp_gate_desc* gates,
+                                    uint64_t ngates, uint64_t ninputs, const uint32_t* h_inputs, uint64_t* ticket);
 
 /* Counters: gates launched, batches launched, peak resident bytes. */
 vsp_status vsp_server_stats(vsp_server* s, uint64_t* gates, uint64_t* batches, uint64_t* peak_bytes);

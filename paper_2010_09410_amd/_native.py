@@ -62,6 +62,9 @@ SIGNATURES = {
     "vsp_server_poll": (_st, [_vp, _u64, _vp, ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_double)]),
     "vsp_server_stats": (_st, [_vp, ctypes.POINTER(_u64), ctypes.POINTER(_u64), ctypes.POINTER(_u64)]),
     "vsp_server_destroy": (_st, [_vp]),
+    "vsp_keyset_create": (_st, [_vp, _vp, _vp, ctypes.POINTER(_vp)]),
+    "vsp_keyset_destroy": (_st, [_vp]),
+    "vsp_server_submit_keyset": (_st, [_vp, _vp, ctypes.POINTER(vsp_gate_desc), _u64, _u64, _vp, ctypes.POINTER(_u64)]),
     "vsp_mux": (_st, [_vp, _vp, _vp, _vp, _vp, _u64, _vp]),
     "vsp_autotune": (_st, [_vp, _u64, ctypes.c_char_p]),
     "vsp_tuning_get": (_st, [_vp, _u64, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
@@ -182,6 +185,24 @@ def vsp_server_submit(srv, gates, ninputs: int, h_inputs) -> int:
     descs = gate_descs(gates)
     t = _u64()
     _call("vsp_server_submit", srv, descs, len(gates), ninputs, h_inputs.ctypes.data, ctypes.byref(t))
+    return t.value
+
+
+def vsp_keyset_create(ctx, bk_host, ksk_host) -> int:
+    """bk_host / ksk_host: C-contiguous uint32 numpy arrays (another client's keys)."""
+    out = _vp()
+    _call("vsp_keyset_create", ctx, bk_host.ctypes.data, ksk_host.ctypes.data, ctypes.byref(out))
+    return out.value
+
+
+def vsp_keyset_destroy(k) -> None:
+    _call("vsp_keyset_destroy", k)
+
+
+def vsp_server_submit_keyset(srv, keys, gates, ninputs: int, h_inputs) -> int:
+    descs = gate_descs(gates)
+    t = _u64()
+    _call("vsp_server_submit_keyset", srv, keys, descs, len(gates), ninputs, h_inputs.ctypes.data, ctypes.byref(t))
     return t.value
 
 

@@ -191,17 +191,18 @@ hipError_t blind_rotate_capacity(int device, uint64_t (&cap)[kBrShapes]) {
 }
 
 hipError_t launch_blind_rotate(const vsp_context* ctx, const uint8_t* ops, const uint32_t* abar, uint32_t* tlwe1,
-                               uint32_t* trlwe, uint64_t B, int waves, hipStream_t st) {
+                               uint32_t* trlwe, uint64_t B, int waves, hipStream_t st, const uint64_t* bkn) {
   if (B == 0) return hipSuccess;
+  if (bkn == nullptr) bkn = ctx->bkn;
   if (waves <= 0) waves = ctx->tune.br_waves(B);
   if (waves == 3) {
-    hipLaunchKernelGGL(k_blind_rotate_wide, dim3((unsigned)B), dim3(BRW_WAVES * 64), brw_lds_bytes(), st, ctx->bkn,
+    hipLaunchKernelGGL(k_blind_rotate_wide, dim3((unsigned)B), dim3(BRW_WAVES * 64), brw_lds_bytes(), st, bkn,
                        ctx->tw, ops, abar, tlwe1, trlwe, B);
   } else if (waves == 4) {
-    hipLaunchKernelGGL(k_blind_rotate<4>, dim3((unsigned)((B + 3) / 4)), dim3(256), br_lds_bytes(4), st, ctx->bkn,
+    hipLaunchKernelGGL(k_blind_rotate<4>, dim3((unsigned)((B + 3) / 4)), dim3(256), br_lds_bytes(4), st, bkn,
                        ctx->tw, ops, abar, tlwe1, trlwe, B);
   } else {
-    hipLaunchKernelGGL(k_blind_rotate<8>, dim3((unsigned)((B + 7) / 8)), dim3(512), br_lds_bytes(8), st, ctx->bkn,
+    hipLaunchKernelGGL(k_blind_rotate<8>, dim3((unsigned)((B + 7) / 8)), dim3(512), br_lds_bytes(8), st, bkn,
                        ctx->tw, ops, abar, tlwe1, trlwe, B);
   }
   return hipGetLastError();
@@ -387,8 +388,9 @@ __global__ __launch_bounds__(256) void k_keyswitch_split(const u32* __restrict__
 }
 
 hipError_t launch_keyswitch(const vsp_context* ctx, const uint8_t* ops, const uint32_t* tlwe1, const uint32_t* idxo,
-                            uint32_t* out, uint64_t B, hipStream_t st, int form) {
+                            uint32_t* out, uint64_t B, hipStream_t st, int form, const uint32_t* ksk) {
   if (B == 0) return hipSuccess;
+  if (ksk == nullptr) ksk = ctx->ksk;
   if (form < 0) form = ctx->tune.ks_form_for(B);
   if (form == 2) {
     constexpr int G = 16;
@@ -400,14 +402,14 @@ hipError_t launch_keyswitch(const vsp_context* ctx, const uint8_t* ops, const ui
     const unsigned ychunks = (unsigned)((RING_N + jchunk - 1) / jchunk);
     hipLaunchKernelGGL(k_keyswitch_init, dim3((unsigned)((B * TLWE0 + 255) / 256)), dim3(256), 0, st, ops, tlwe1, idxo,
                        out, B);
-    hipLaunchKernelGGL(k_keyswitch_split<G>, dim3((unsigned)tiles, ychunks), dim3(256), 0, st, ctx->ksk, ops, tlwe1,
+    hipLaunchKernelGGL(k_keyswitch_split<G>, dim3((unsigned)tiles, ychunks), dim3(256), 0, st, ksk, ops, tlwe1,
                        idxo, out, B, jchunk);
   } else if (form == 1) {
     constexpr int G = 16;
-    hipLaunchKernelGGL(k_keyswitch_tiled<G>, dim3((unsigned)((B + G - 1) / G)), dim3(256), 0, st, ctx->ksk, ops, tlwe1,
+    hipLaunchKernelGGL(k_keyswitch_tiled<G>, dim3((unsigned)((B + G - 1) / G)), dim3(256), 0, st, ksk, ops, tlwe1,
                        idxo, out, B);
   } else {
-    hipLaunchKernelGGL(k_keyswitch, dim3((unsigned)B), dim3(256), 0, st, ctx->ksk, ops, tlwe1, idxo, out, B);
+    hipLaunchKernelGGL(k_keyswitch, dim3((unsigned)B), dim3(256), 0, st, ksk, ops, tlwe1, idxo, out, B);
   }
   return hipGetLastError();
 }

@@ -2,8 +2,9 @@
 // GPU (Sec. 4.1, the server evaluates for each client; Sec. 6.2(d), gates of a level are
 // independent). Admitted circuits keep their wires resident in a device arena whose size is
 // the memory budget; each iteration gathers the ready gates (the next level of every
-// admitted circuit, round-robin, up to max_batch) into one batched launch sequence on the
-// server's stream. At most two batches are in flight, so host-side assembly and admission
+// admitted circuit that uses the same key set, round-robin, up to max_batch) into one batched
+// launch sequence on the server's stream. Circuits may come with their own key set (each
+// client's bootstrapping and key-switching keys); a batch never mixes key sets. At most two batches are in flight, so host-side assembly and admission
 // overlap device execution, and requests that arrive meanwhile join the next batch.
 #include <algorithm>
 #include <chrono>
@@ -32,6 +33,7 @@ struct Request {
   uint64_t base = 0, rows = 0;                 // arena rows [base, base + rows)
   int64_t last_batch = -1;                     // batch that launched the final gate
   bool admitted = false, done = false;
+  const vsp_keyset* keys = nullptr;            // NULL: the context's keys
   std::vector<uint32_t> result;
   Clock::time_point t_submit, t_done;
 };
@@ -179,11 +181,20 @@ void worker_loop(vsp_server* s) {
     // gather ready gates: the next level of every active request, round-robin
     uint64_t nb = 0;
     const size_t na = s->active.size();
+    bool keyed = false;
+    const vsp_keyset* bkeys = nullptr;
     for (size_t k = 0; k < na && nb < s->max_batch; k++) {
       Request* r = s->active[(s->rr + k) % na];
       if (r->level >= r->levels.size()) continue;
       // a request's next level may only follow its previous one in a later batch
       if (r->last_batch == s->batch_no) continue;
+      // the first request with work fixes the batch's key set
+      if (!keyed) {
+        bkeys = r->keys;
+        keyed = true;
+      } else if (r->keys != bkeys) {
+        continue;
+      }
       const auto& lv = r->levels[r->level];
       while (r->pos < lv.size() && nb < s->max_batch) {
         const vsp_gate_desc& d = r->gates[lv[r->pos]];
@@ -225,8 +236,11 @@ void worker_loop(vsp_server* s) {
     hipError_t e = launch_gate_prologue(s->ctx, sl.d_ops, s->arena, s->arena, sl.d_idx, sl.d_idx + M, sl.d_idx + 2 * M,
                                         sl.d_abar, s->arena, nb, st);
     if (e == hipSuccess)
-      e = launch_blind_rotate(s->ctx, sl.d_ops, sl.d_abar, sl.d_tlwe1, nullptr, nb, 0, st);
-    if (e == hipSuccess) e = launch_keyswitch(s->ctx, sl.d_ops, sl.d_tlwe1, sl.d_idx + 2 * M, s->arena, nb, st);
+      e = launch_blind_rotate(s->ctx, sl.d_ops, sl.d_abar, sl.d_tlwe1, nullptr, nb, 0, st,
+                              bkeys ? bkeys->bkn : nullptr);
+    if (e == hipSuccess)
+      e = launch_keyswitch(s->ctx, sl.d_ops, sl.d_tlwe1, sl.d_idx + 2 * M, s->arena, nb, st, -1,
+                           bkeys ? bkeys->ksk : nullptr);
     if (e == hipSuccess) e = hipEventRecord(sl.ev, st);
     if (e != hipSuccess) {
       std::lock_guard<std::mutex> g(s->mu);
@@ -296,7 +310,13 @@ vsp_status vsp_server_create(vsp_context* ctx, uint64_t mem_budget_bytes, uint64
 
 vsp_status vsp_server_submit(vsp_server* s, const vsp_gate_desc* gates, uint64_t ngates, uint64_t ninputs,
                              const uint32_t* h_inputs, uint64_t* ticket) {
+  return vsp_server_submit_keyset(s, nullptr, gates, ngates, ninputs, h_inputs, ticket);
+}
+
+vsp_status vsp_server_submit_keyset(vsp_server* s, const vsp_keyset* keys, const vsp_gate_desc* gates,
+                                    uint64_t ngates, uint64_t ninputs, const uint32_t* h_inputs, uint64_t* ticket) {
   if (s == nullptr || ticket == nullptr) return fail(VSP_E_ARG, "server or ticket is NULL");
+  if (keys != nullptr && keys->ctx != s->ctx) return fail(VSP_E_ARG, "the key set belongs to another context");
   if (ngates > 0 && gates == nullptr) return fail(VSP_E_ARG, "gates is NULL");
   if (ninputs > 0 && h_inputs == nullptr) return fail(VSP_E_ARG, "h_inputs is NULL");
   auto* r = new Request();
@@ -314,6 +334,7 @@ vsp_status vsp_server_submit(vsp_server* s, const vsp_gate_desc* gates, uint64_t
   }
   r->gates.assign(gates, gates + ngates);
   r->inputs.assign(h_inputs, h_inputs + ninputs * (LWE_N + 1));
+  r->keys = keys;
   r->t_submit = Clock::now();
   std::lock_guard<std::mutex> lk(s->mu);
   if (s->stop) {

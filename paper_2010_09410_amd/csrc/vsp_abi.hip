@@ -128,6 +128,43 @@ static bool make_tables(std::vector<u64>& tw) {
   return true;
 }
 
+vsp_status upload_keys(const vsp_context* ctx, const uint32_t* bk_host, const uint32_t* ksk_host, uint64_t** bkn,
+                       uint32_t** ksk) {
+  *bkn = nullptr;
+  *ksk = nullptr;
+  const size_t bk_words = (size_t)LWE_N * 2 * GADGET_L * 2 * RING_N;
+  const size_t ksk_rows = (size_t)RING_N * KS_T * 4;
+  uint64_t* b = nullptr;
+  uint32_t* k = nullptr;
+  uint32_t* tmp = nullptr;
+  auto undo = [&](vsp_status st) {
+    for (void* p : {(void*)b, (void*)k, (void*)tmp})
+      if (p) (void)hipFree(p);
+    return st;
+  };
+  hipError_t e;
+  if ((e = hipMalloc(&b, (size_t)LWE_N * TRGSW_NTT_U64 * 8)) != hipSuccess) return undo(hip_fail(e, "hipMalloc(bk)"));
+  if ((e = hipMalloc(&k, ksk_rows * (LWE_N + 1) * 4)) != hipSuccess) return undo(hip_fail(e, "hipMalloc(ksk)"));
+  // Bootstrapping key: torus -> NTT domain on the device.
+  if ((e = hipMalloc(&tmp, bk_words * 4)) != hipSuccess) return undo(hip_fail(e, "hipMalloc(bk staging)"));
+  e = hipMemcpy(tmp, bk_host, bk_words * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = launch_trgsw_to_ntt(ctx, tmp, b, LWE_N, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) return undo(hip_fail(e, "bootstrapping-key conversion"));
+  (void)hipFree(tmp);
+  tmp = nullptr;
+  // Key-switching key, with a zero row in front of the three digit rows of every (j, p).
+  std::vector<uint32_t> k4(ksk_rows * (LWE_N + 1), 0u);
+  for (size_t jp = 0; jp < (size_t)RING_N * KS_T; jp++)
+    for (int v = 1; v < 4; v++)
+      std::memcpy(&k4[(jp * 4 + v) * (LWE_N + 1)], &ksk_host[(jp * 3 + (v - 1)) * (LWE_N + 1)], (LWE_N + 1) * 4);
+  if ((e = hipMemcpy(k, k4.data(), k4.size() * 4, hipMemcpyHostToDevice)) != hipSuccess)
+    return undo(hip_fail(e, "upload ksk"));
+  *bkn = b;
+  *ksk = k;
+  return VSP_OK;
+}
+
 static vsp_status check_ctx(const vsp_context* ctx) {
   if (ctx == nullptr) return fail(VSP_E_ARG, "context is NULL");
   return VSP_OK;
@@ -181,33 +218,13 @@ vsp_status vsp_context_create(const vsp_params* params, const uint32_t* bk_host,
     const hipError_t e = blind_rotate_capacity(device, ctx->tune.br_cap);
     if (e != hipSuccess) return cleanup(hip_fail(e, "occupancy query"));
   }
-  const size_t bk_words = (size_t)LWE_N * 2 * GADGET_L * 2 * RING_N;
-  const size_t ksk_rows = (size_t)RING_N * KS_T * 4;
   hipError_t e;
-  if ((e = hipMalloc(&ctx->bkn, (size_t)LWE_N * TRGSW_NTT_U64 * 8)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc(bk)"));
-  if ((e = hipMalloc(&ctx->ksk, ksk_rows * (LWE_N + 1) * 4)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc(ksk)"));
   if ((e = hipMalloc(&ctx->tw, tw.size() * 8)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc(tw)"));
   if ((e = hipMalloc(&ctx->dev_err, 256)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc(err)"));
   if ((e = hipMemcpy(ctx->tw, tw.data(), tw.size() * 8, hipMemcpyHostToDevice)) != hipSuccess)
     return cleanup(hip_fail(e, "upload twiddles"));
   if ((e = hipMemset(ctx->dev_err, 0, 256)) != hipSuccess) return cleanup(hip_fail(e, "clear flags"));
-
-  // Bootstrapping key: torus -> NTT domain on the device.
-  uint32_t* tmp = nullptr;
-  if ((e = hipMalloc(&tmp, bk_words * 4)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc(bk staging)"));
-  e = hipMemcpy(tmp, bk_host, bk_words * 4, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = launch_trgsw_to_ntt(ctx, tmp, ctx->bkn, LWE_N, nullptr);
-  if (e == hipSuccess) e = hipDeviceSynchronize();
-  (void)hipFree(tmp);
-  if (e != hipSuccess) return cleanup(hip_fail(e, "bootstrapping-key conversion"));
-
-  // Key-switching key, with a zero row in front of the three digit rows of every (j, p).
-  std::vector<uint32_t> k4(ksk_rows * (LWE_N + 1), 0u);
-  for (size_t jp = 0; jp < (size_t)RING_N * KS_T; jp++)
-    for (int v = 1; v < 4; v++)
-      std::memcpy(&k4[(jp * 4 + v) * (LWE_N + 1)], &ksk_host[(jp * 3 + (v - 1)) * (LWE_N + 1)], (LWE_N + 1) * 4);
-  if ((e = hipMemcpy(ctx->ksk, k4.data(), k4.size() * 4, hipMemcpyHostToDevice)) != hipSuccess)
-    return cleanup(hip_fail(e, "upload ksk"));
+  if (vsp_status st = upload_keys(ctx, bk_host, ksk_host, &ctx->bkn, &ctx->ksk)) return cleanup(st);
   *out = ctx;
   return VSP_OK;
 }
@@ -310,6 +327,33 @@ vsp_status vsp_gates(vsp_context* ctx, const uint8_t* d_ops, const uint32_t* d_i
 vsp_status vsp_bootstrap_trlwe(vsp_context* ctx, const uint8_t* d_ops, const uint32_t* d_in0, const uint32_t* d_in1,
                                uint32_t* d_out, uint64_t B, void* stream) {
   return gates_impl(ctx, d_ops, d_in0, d_in1, d_out, B, VSP_BATCHED, stream, true);
+}
+
+vsp_status vsp_keyset_create(vsp_context* ctx, const uint32_t* bk_host, const uint32_t* ksk_host, vsp_keyset** out) {
+  if (out == nullptr) return fail(VSP_E_ARG, "out is NULL");
+  *out = nullptr;
+  vsp_status s = check_ctx(ctx);
+  if (s) return s;
+  if (bk_host == nullptr || ksk_host == nullptr) return fail(VSP_E_ARG, "bk_host and ksk_host must not be NULL");
+  VSP_HIP(hipSetDevice(ctx->device));
+  auto* k = new vsp_keyset();
+  k->ctx = ctx;
+  if ((s = upload_keys(ctx, bk_host, ksk_host, &k->bkn, &k->ksk))) {
+    delete k;
+    return s;
+  }
+  *out = k;
+  return VSP_OK;
+}
+
+vsp_status vsp_keyset_destroy(vsp_keyset* k) {
+  if (k == nullptr) return VSP_OK;
+  (void)hipSetDevice(k->ctx->device);
+  (void)hipDeviceSynchronize();
+  if (k->bkn) (void)hipFree(k->bkn);
+  if (k->ksk) (void)hipFree(k->ksk);
+  delete k;
+  return VSP_OK;
 }
 
 vsp_status vsp_mux(vsp_context* ctx, const uint32_t* d_sel, const uint32_t* d_in1, const uint32_t* d_in0,

@@ -90,6 +90,14 @@ struct Profile {
 
 }  // namespace vsp
 
+// A client's key set converted for the device: bootstrapping key in the NTT domain and the
+// key-switching key with zero rows (layouts as in vsp_context).
+struct vsp_keyset {
+  vsp_context* ctx = nullptr;
+  uint64_t* bkn = nullptr;
+  uint32_t* ksk = nullptr;
+};
+
 struct vsp_context {
   int device = 0;
   uint64_t* bkn = nullptr;        // bootstrapping key, NTT domain: [n][TRGSW_NTT_U64]
@@ -116,6 +124,11 @@ vsp_status hip_fail(hipError_t e, const char* what);
 // Returns VSP_OK if [p, p + bytes) lies inside one device allocation on ctx's device.
 vsp_status check_device_range(const vsp_context* ctx, const void* p, size_t bytes, const char* name);
 vsp_status check_no_overlap(const void* a, size_t abytes, const void* b, size_t bbytes, const char* what);
+
+// Converts host keys (BK torus [n][2l][2][N], KSK [N][t][3][n+1]) into freshly allocated device
+// buffers in the kernels' layouts; on failure nothing stays allocated.
+vsp_status upload_keys(const vsp_context* ctx, const uint32_t* bk_host, const uint32_t* ksk_host, uint64_t** bkn,
+                       uint32_t** ksk);
 
 // Grows a scratch buffer to at least `bytes` (synchronising the device before freeing).
 vsp_status scratch_reserve(vsp_context* ctx, Scratch& s, size_t bytes);
@@ -153,13 +166,15 @@ hipError_t launch_mux_prologue(const uint32_t* sel, const uint32_t* in1, const u
 hipError_t launch_mux_combine(uint32_t* t, uint64_t B, hipStream_t st);
 // Blind rotation of B gates (abar from the prologue). Writes SE_0 (TLWE1 [B][N+1]) and/or
 // the accumulator (TRLWE [B][2][N]). waves: a shape of kBrWaveChoices, <= 0 the tuned choice.
+// bkn: the bootstrapping key to use (NULL: the context's).
 hipError_t launch_blind_rotate(const vsp_context* ctx, const uint8_t* ops, const uint32_t* abar, uint32_t* tlwe1,
-                               uint32_t* trlwe, uint64_t B, int waves, hipStream_t st);
+                               uint32_t* trlwe, uint64_t B, int waves, hipStream_t st, const uint64_t* bkn = nullptr);
 // Identity key switch TLWE1 [B][N+1] -> TLWE0 [B][n+1] (outputs scattered by idxo if given).
 // form: 0 one workgroup per gate, 1 row-stationary tiles, 2 LDS-staged split, -1 the tuned one.
 constexpr int kKsForms = 3;
+// ksk: the key-switching key to use (NULL: the context's).
 hipError_t launch_keyswitch(const vsp_context* ctx, const uint8_t* ops, const uint32_t* tlwe1, const uint32_t* idxo,
-                            uint32_t* out, uint64_t B, hipStream_t st, int form = -1);
+                            uint32_t* out, uint64_t B, hipStream_t st, int form = -1, const uint32_t* ksk = nullptr);
 // out[j] = C_j (ext) x_j, or with `x0` given: out[j] = x0_j + C_j (ext) (x_j - x0_j).
 hipError_t launch_ext_product(const vsp_context* ctx, const uint64_t* Cn, const uint32_t* x, uint32_t* out,
                               uint64_t J, hipStream_t st);

@@ -124,6 +124,9 @@ class Context:
     def circuit(self, gates, ninputs: int) -> "Circuit":
         return Circuit(self, gates, ninputs)
 
+    def keyset(self, bk: np.ndarray, ksk: np.ndarray) -> "Keyset":
+        return Keyset(self, bk, ksk)
+
     def server(self, mem_budget_bytes: int, max_batch: int = 4096) -> "Server":
         return Server(self, mem_budget_bytes, max_batch)
 
@@ -175,6 +178,20 @@ class Circuit:
             self.handle = None
 
 
+class Keyset:
+    """Another client's bootstrapping and key-switching keys on the context's GPU."""
+
+    def __init__(self, ctx: Context, bk: np.ndarray, ksk: np.ndarray):
+        self.ctx = ctx
+        self.handle = nv.vsp_keyset_create(ctx.handle, np.ascontiguousarray(bk, dtype=np.uint32),
+                                           np.ascontiguousarray(ksk, dtype=np.uint32))
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            nv.vsp_keyset_destroy(self.handle)
+            self.handle = None
+
+
 class Server:
     """Continuous-batching evaluation of many clients' circuits on one context."""
 
@@ -182,9 +199,12 @@ class Server:
         self.ctx = ctx
         self.handle = nv.vsp_server_create(ctx.handle, int(mem_budget_bytes), int(max_batch))
 
-    def submit(self, gates, ninputs: int, inputs: np.ndarray) -> int:
-        return nv.vsp_server_submit(self.handle, np.asarray(gates, dtype=np.int64), int(ninputs),
-                                    np.ascontiguousarray(inputs, dtype=np.uint32))
+    def submit(self, gates, ninputs: int, inputs: np.ndarray, keyset: "Keyset | None" = None) -> int:
+        gates = np.asarray(gates, dtype=np.int64)
+        inputs = np.ascontiguousarray(inputs, dtype=np.uint32)
+        if keyset is None:
+            return nv.vsp_server_submit(self.handle, gates, int(ninputs), inputs)
+        return nv.vsp_server_submit_keyset(self.handle, keyset.handle, gates, int(ninputs), inputs)
 
     def poll(self, ticket: int, nwires: int | None = None):
         """Returns (done, wires or None, latency_ms)."""

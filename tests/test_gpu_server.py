@@ -89,3 +89,37 @@ def test_capacity_and_malformed_rejected(gpu, keys):
         srv.poll(12345)
     assert ei.value.status == nv.VSP_E_STATE
     srv.close()
+
+
+def test_per_client_key_sets(gpu, keys):
+    """Two clients with their own key sets (each client generates and ships its own keys,
+    Sec. 4.1): a batch never mixes key sets; client B's results equal the oracle evaluated with
+    B's keys and decrypt under B's secret key, and client A's equal the circuit executor."""
+    import oracle
+    from test_gpu_circuit import oracle_eval, plaintext_eval
+    s0b, s1b = W.secret_keys(5)
+    bkd, kskd = W.bk_draws(6), W.ksk_draws(7)
+    kb = gpu.keyset(*client.keyset(s0b, s1b, bkd, kskd))
+    reqs_a = requests(keys, 3, 1000)
+    reqs_b = []
+    for k in range(3):
+        c = W.small_circuit(seed=1100 + k, levels=2 + k, wmin=2, wmax=10, ninputs=6 + k)
+        reqs_b.append((c, client.tlwe_encrypt_bits(s0b, c["bits"], *c["enc"])))
+    srv = gpu.server(mem_budget_bytes=64 << 20, max_batch=64)
+    ta = [srv.submit(c["gates"], c["ninputs"], x) for c, x in reqs_a]
+    tb = [srv.submit(c["gates"], c["ninputs"], x, keyset=kb) for c, x in reqs_b]
+    outs_a = [wait(srv, t, c["ninputs"] + len(c["gates"]))[0] for t, (c, _) in zip(ta, reqs_a)]
+    outs_b = [wait(srv, t, c["ninputs"] + len(c["gates"]))[0] for t, (c, _) in zip(tb, reqs_b)]
+    srv.close()
+    for (c, x), o in zip(reqs_b, outs_b):
+        np.testing.assert_array_equal(client.tlwe_decrypt(s0b, o), plaintext_eval(c["gates"], c["bits"]))
+    bk_b, ksk_b = oracle.keyset(s0b, s1b, bkd, kskd)
+    c, x = reqs_b[0]
+    ref = oracle_eval({"bk": bk_b, "ksk": ksk_b}, c["gates"], c["level"], x)
+    np.testing.assert_array_equal(outs_b[0], ref)
+    for (c, x), o in zip(reqs_a, outs_a):
+        circ = gpu.circuit(c["gates"], c["ninputs"])
+        np.testing.assert_array_equal(o, to_host(circ.run(gpu.tensor(x))))
+        gpu.sync()
+        circ.close()
+    kb.close()
