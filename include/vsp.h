@@ -185,8 +185,9 @@ vsp_status vsp_keyset_create(vsp_context* ctx, const uint32_t* bk_host, const ui
 vsp_status vsp_keyset_destroy(vsp_keyset* k);
 
 /* vsp_server_submit for a circuit encrypted under `keys` (a key set of the server's context;
- * NULL means the context's own keys). Batches are grouped by key set: the ready gates of the
- * circuits that share one key set go into one launch sequence. */
+ * NULL means the context's own keys). A batch may hold the ready gates of up to 64 key sets:
+ * it is ordered by key set, each gate's blind rotation reads its own key, and the key switch
+ * runs once per key set. */
 vsp_status vsp_server_submit_keyset(vsp_server* s, const vsp_keyset* keys, const vsp_gate_desc* gates,
                                     uint64_t ngates, uint64_t ninputs, const uint32_t* h_inputs, uint64_t* ticket);
 

@@ -16,11 +16,15 @@ constexpr int BR_WAVE_U32 = 2 * RING_N + WAVE_T_U32;
 
 constexpr size_t br_lds_bytes(int waves) { return 2048 * 8 + (size_t)waves * BR_WAVE_U32 * 4; }
 
+// With keytab non-NULL gate g uses the bootstrapping key keytab[kid[g]] (clients with their
+// own keys in one launch), else bkn.
 template <int WAVES>
 __global__ __launch_bounds__(WAVES * 64) void k_blind_rotate(const u64* __restrict__ bkn, const u64* __restrict__ tw,
                                                              const uint8_t* __restrict__ ops,
                                                              const u32* __restrict__ abar, u32* __restrict__ tlwe1,
-                                                             u32* __restrict__ trlwe, uint64_t B) {
+                                                             u32* __restrict__ trlwe, uint64_t B,
+                                                             const u64* const* __restrict__ keytab,
+                                                             const uint8_t* __restrict__ kid) {
   extern __shared__ u64 lds[];
   u64* tws = lds;
   for (int i = threadIdx.x; i < 2048; i += WAVES * 64) tws[i] = tw[i];
@@ -29,6 +33,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_blind_rotate(const u64* __restri
   const uint64_t g = (uint64_t)blockIdx.x * WAVES + wave;
   if (g >= B) return;
   if (ops && !op_bootstraps(ops[g])) return;
+  if (keytab) bkn = keytab[__builtin_amdgcn_readfirstlane(kid[g])];
   const int lane = threadIdx.x & 63, l = lane & 31, h = lane >> 5;
   u32* wbase = reinterpret_cast<u32*>(lds + 2048) + wave * BR_WAVE_U32;
   const u32* ab = abar + g * TLWE0;

@@ -59,12 +59,14 @@ __global__ __launch_bounds__(BRW_WAVES * 64) void k_blind_rotate_wide(const u64*
                                                                       const uint8_t* __restrict__ ops,
                                                                       const u32* __restrict__ abar,
                                                                       u32* __restrict__ tlwe1, u32* __restrict__ trlwe,
-                                                                      uint64_t B) {
+                                                                      uint64_t B, const u64* const* __restrict__ keytab,
+                                                                      const uint8_t* __restrict__ kid) {
   extern __shared__ u64 lds[];
   u64* tws = lds;
   for (int i = threadIdx.x; i < 2048; i += BRW_WAVES * 64) tws[i] = tw[i];
   const uint64_t g = blockIdx.x;  // the grid has exactly B workgroups
   if (ops && !op_bootstraps(ops[g])) return;  // uniform over the workgroup: no barrier is skipped by half
+  if (keytab) bkn = keytab[kid[g]];           // per-gate key (same value in every wave)
   const int k = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // this wave's digit level
   const int lane = threadIdx.x & 63, l = lane & 31, h = lane >> 5;
   u32* gbase = reinterpret_cast<u32*>(lds + 2048);

@@ -191,19 +191,20 @@ hipError_t blind_rotate_capacity(int device, uint64_t (&cap)[kBrShapes]) {
 }
 
 hipError_t launch_blind_rotate(const vsp_context* ctx, const uint8_t* ops, const uint32_t* abar, uint32_t* tlwe1,
-                               uint32_t* trlwe, uint64_t B, int waves, hipStream_t st, const uint64_t* bkn) {
+                               uint32_t* trlwe, uint64_t B, int waves, hipStream_t st, const uint64_t* bkn,
+                               const uint64_t* const* keytab, const uint8_t* kid) {
   if (B == 0) return hipSuccess;
   if (bkn == nullptr) bkn = ctx->bkn;
   if (waves <= 0) waves = ctx->tune.br_waves(B);
   if (waves == 3) {
     hipLaunchKernelGGL(k_blind_rotate_wide, dim3((unsigned)B), dim3(BRW_WAVES * 64), brw_lds_bytes(), st, bkn,
-                       ctx->tw, ops, abar, tlwe1, trlwe, B);
+                       ctx->tw, ops, abar, tlwe1, trlwe, B, keytab, kid);
   } else if (waves == 4) {
     hipLaunchKernelGGL(k_blind_rotate<4>, dim3((unsigned)((B + 3) / 4)), dim3(256), br_lds_bytes(4), st, bkn,
-                       ctx->tw, ops, abar, tlwe1, trlwe, B);
+                       ctx->tw, ops, abar, tlwe1, trlwe, B, keytab, kid);
   } else {
     hipLaunchKernelGGL(k_blind_rotate<8>, dim3((unsigned)((B + 7) / 8)), dim3(512), br_lds_bytes(8), st, bkn,
-                       ctx->tw, ops, abar, tlwe1, trlwe, B);
+                       ctx->tw, ops, abar, tlwe1, trlwe, B, keytab, kid);
   }
   return hipGetLastError();
 }

@@ -2,9 +2,11 @@
 // GPU (Sec. 4.1, the server evaluates for each client; Sec. 6.2(d), gates of a level are
 // independent). Admitted circuits keep their wires resident in a device arena whose size is
 // the memory budget; each iteration gathers the ready gates (the next level of every
-// admitted circuit that uses the same key set, round-robin, up to max_batch) into one batched
-// launch sequence on the server's stream. Circuits may come with their own key set (each
-// client's bootstrapping and key-switching keys); a batch never mixes key sets. At most two batches are in flight, so host-side assembly and admission
+// admitted circuit, round-robin, up to max_batch) into one batched launch sequence on the
+// server's stream. Circuits may come with their own key set (each client's bootstrapping and
+// key-switching keys): the batch is ordered by key set, the blind rotation reads each gate's
+// key through a per-gate key index, and the key switch runs once per key set over its
+// contiguous range. At most two batches are in flight, so host-side assembly and admission
 // overlap device execution, and requests that arrive meanwhile join the next batch.
 #include <algorithm>
 #include <chrono>
@@ -38,11 +40,17 @@ struct Request {
   Clock::time_point t_submit, t_done;
 };
 
+constexpr int kMaxBatchKeys = 64;  // distinct key sets in one batch
+
 struct Slot {  // one in-flight batch
   uint8_t* h_ops = nullptr;
   uint32_t* h_idx = nullptr;
+  uint8_t* h_kid = nullptr;
+  const uint64_t** h_keytab = nullptr;
   uint8_t* d_ops = nullptr;
   uint32_t* d_idx = nullptr;
+  uint8_t* d_kid = nullptr;
+  const uint64_t** d_keytab = nullptr;
   uint32_t* d_abar = nullptr;
   uint32_t* d_tlwe1 = nullptr;
   hipEvent_t ev = nullptr;
@@ -64,6 +72,11 @@ struct vsp_server {
   std::map<uint64_t, Request*> all;
   size_t rr = 0;
   Slot slots[2];
+  struct Cand {
+    uint8_t key, op;
+    uint32_t i0, i1, io;
+  };
+  std::vector<Cand> cand;  // gates of the batch being assembled
   hipStream_t st = nullptr;
   std::mutex mu;
   std::condition_variable cv;
@@ -181,27 +194,24 @@ void worker_loop(vsp_server* s) {
     // gather ready gates: the next level of every active request, round-robin
     uint64_t nb = 0;
     const size_t na = s->active.size();
-    bool keyed = false;
-    const vsp_keyset* bkeys = nullptr;
+    std::vector<const vsp_keyset*> kset;
+    s->cand.clear();
     for (size_t k = 0; k < na && nb < s->max_batch; k++) {
       Request* r = s->active[(s->rr + k) % na];
       if (r->level >= r->levels.size()) continue;
       // a request's next level may only follow its previous one in a later batch
       if (r->last_batch == s->batch_no) continue;
-      // the first request with work fixes the batch's key set
-      if (!keyed) {
-        bkeys = r->keys;
-        keyed = true;
-      } else if (r->keys != bkeys) {
-        continue;
+      size_t key = std::find(kset.begin(), kset.end(), r->keys) - kset.begin();
+      if (key == kset.size()) {
+        if (kset.size() == (size_t)kMaxBatchKeys) continue;  // this key set waits for the next batch
+        kset.push_back(r->keys);
       }
       const auto& lv = r->levels[r->level];
       while (r->pos < lv.size() && nb < s->max_batch) {
         const vsp_gate_desc& d = r->gates[lv[r->pos]];
-        sl.h_ops[nb] = (uint8_t)d.op;
-        sl.h_idx[nb] = (uint32_t)(r->base + d.in0);
-        sl.h_idx[s->max_batch + nb] = (uint32_t)(r->base + (d.op == VSP_NOT ? d.in0 : d.in1));
-        sl.h_idx[2 * s->max_batch + nb] = (uint32_t)(r->base + r->ninputs + lv[r->pos]);
+        s->cand.push_back({(uint8_t)key, (uint8_t)d.op, (uint32_t)(r->base + d.in0),
+                           (uint32_t)(r->base + (d.op == VSP_NOT ? d.in0 : d.in1)),
+                           (uint32_t)(r->base + r->ninputs + lv[r->pos])});
         nb++;
         r->pos++;
       }
@@ -212,6 +222,24 @@ void worker_loop(vsp_server* s) {
       }
     }
     if (na) s->rr = (s->rr + 1) % na;
+    // lay the batch out grouped by key set (counting sort on the key index)
+    const size_t nk = kset.size();
+    std::vector<uint64_t> start(nk + 1, 0);
+    for (const auto& c : s->cand) start[c.key + 1]++;
+    for (size_t k = 0; k < nk; k++) start[k + 1] += start[k];
+    {
+      std::vector<uint64_t> fill(start.begin(), start.end() - 1);
+      const uint64_t M = s->max_batch;
+      for (const auto& c : s->cand) {
+        const uint64_t i = fill[c.key]++;
+        sl.h_ops[i] = c.op;
+        sl.h_kid[i] = c.key;
+        sl.h_idx[i] = c.i0;
+        sl.h_idx[M + i] = c.i1;
+        sl.h_idx[2 * M + i] = c.io;
+      }
+      for (size_t k = 0; k < nk; k++) sl.h_keytab[k] = kset[k] ? kset[k]->bkn : s->ctx->bkn;
+    }
     if (nb == 0) {
       const bool inflight = s->slots[0].busy || s->slots[1].busy;
       if (inflight) {
@@ -233,14 +261,20 @@ void worker_loop(vsp_server* s) {
     (void)hipMemcpyAsync(sl.d_idx, sl.h_idx, nb * 4, hipMemcpyHostToDevice, st);
     (void)hipMemcpyAsync(sl.d_idx + M, sl.h_idx + M, nb * 4, hipMemcpyHostToDevice, st);
     (void)hipMemcpyAsync(sl.d_idx + 2 * M, sl.h_idx + 2 * M, nb * 4, hipMemcpyHostToDevice, st);
+    if (nk > 1) {
+      (void)hipMemcpyAsync(sl.d_kid, sl.h_kid, nb, hipMemcpyHostToDevice, st);
+      (void)hipMemcpyAsync(sl.d_keytab, sl.h_keytab, nk * sizeof(void*), hipMemcpyHostToDevice, st);
+    }
     hipError_t e = launch_gate_prologue(s->ctx, sl.d_ops, s->arena, s->arena, sl.d_idx, sl.d_idx + M, sl.d_idx + 2 * M,
                                         sl.d_abar, s->arena, nb, st);
     if (e == hipSuccess)
-      e = launch_blind_rotate(s->ctx, sl.d_ops, sl.d_abar, sl.d_tlwe1, nullptr, nb, 0, st,
-                              bkeys ? bkeys->bkn : nullptr);
-    if (e == hipSuccess)
-      e = launch_keyswitch(s->ctx, sl.d_ops, sl.d_tlwe1, sl.d_idx + 2 * M, s->arena, nb, st, -1,
-                           bkeys ? bkeys->ksk : nullptr);
+      e = launch_blind_rotate(s->ctx, sl.d_ops, sl.d_abar, sl.d_tlwe1, nullptr, nb, 0, st, sl.h_keytab[0],
+                              nk > 1 ? sl.d_keytab : nullptr, nk > 1 ? sl.d_kid : nullptr);
+    for (size_t k = 0; k < nk && e == hipSuccess; k++) {
+      const uint64_t a = start[k], n = start[k + 1] - start[k];
+      e = launch_keyswitch(s->ctx, sl.d_ops + a, sl.d_tlwe1 + a * (RING_N + 1), sl.d_idx + 2 * M + a, s->arena, n, st,
+                           -1, kset[k] ? kset[k]->ksk : nullptr);
+    }
     if (e == hipSuccess) e = hipEventRecord(sl.ev, st);
     if (e != hipSuccess) {
       std::lock_guard<std::mutex> g(s->mu);
@@ -257,9 +291,10 @@ void free_server(vsp_server* s) {
   (void)hipSetDevice(s->ctx->device);
   (void)hipDeviceSynchronize();
   for (auto& sl : s->slots) {
-    if (sl.h_ops) (void)hipHostFree(sl.h_ops);
-    if (sl.h_idx) (void)hipHostFree(sl.h_idx);
-    for (void* p : {(void*)sl.d_ops, (void*)sl.d_idx, (void*)sl.d_abar, (void*)sl.d_tlwe1})
+    for (void* p : {(void*)sl.h_ops, (void*)sl.h_idx, (void*)sl.h_kid, (void*)sl.h_keytab})
+      if (p) (void)hipHostFree(p);
+    for (void* p : {(void*)sl.d_ops, (void*)sl.d_idx, (void*)sl.d_kid, (void*)sl.d_keytab, (void*)sl.d_abar,
+                    (void*)sl.d_tlwe1})
       if (p) (void)hipFree(p);
     if (sl.ev) (void)hipEventDestroy(sl.ev);
   }
@@ -297,6 +332,11 @@ vsp_status vsp_server_create(vsp_context* ctx, uint64_t mem_budget_bytes, uint64
   for (auto& sl : s->slots) {
     if ((e = hipHostMalloc(&sl.h_ops, max_batch)) != hipSuccess) return bail(hip_fail(e, "hipHostMalloc"));
     if ((e = hipHostMalloc(&sl.h_idx, 3 * max_batch * 4)) != hipSuccess) return bail(hip_fail(e, "hipHostMalloc"));
+    if ((e = hipHostMalloc(&sl.h_kid, max_batch)) != hipSuccess) return bail(hip_fail(e, "hipHostMalloc"));
+    if ((e = hipHostMalloc(&sl.h_keytab, kMaxBatchKeys * sizeof(void*))) != hipSuccess)
+      return bail(hip_fail(e, "hipHostMalloc"));
+    if ((e = hipMalloc(&sl.d_kid, max_batch)) != hipSuccess) return bail(hip_fail(e, "hipMalloc"));
+    if ((e = hipMalloc(&sl.d_keytab, kMaxBatchKeys * sizeof(void*))) != hipSuccess) return bail(hip_fail(e, "hipMalloc"));
     if ((e = hipMalloc(&sl.d_ops, max_batch)) != hipSuccess) return bail(hip_fail(e, "hipMalloc"));
     if ((e = hipMalloc(&sl.d_idx, 3 * max_batch * 4)) != hipSuccess) return bail(hip_fail(e, "hipMalloc"));
     if ((e = hipMalloc(&sl.d_abar, max_batch * ROWB)) != hipSuccess) return bail(hip_fail(e, "hipMalloc"));

@@ -166,9 +166,11 @@ hipError_t launch_mux_prologue(const uint32_t* sel, const uint32_t* in1, const u
 hipError_t launch_mux_combine(uint32_t* t, uint64_t B, hipStream_t st);
 // Blind rotation of B gates (abar from the prologue). Writes SE_0 (TLWE1 [B][N+1]) and/or
 // the accumulator (TRLWE [B][2][N]). waves: a shape of kBrWaveChoices, <= 0 the tuned choice.
-// bkn: the bootstrapping key to use (NULL: the context's).
+// bkn: the bootstrapping key to use (NULL: the context's); with keytab non-NULL gate g uses
+// keytab[kid[g]] instead (device arrays).
 hipError_t launch_blind_rotate(const vsp_context* ctx, const uint8_t* ops, const uint32_t* abar, uint32_t* tlwe1,
-                               uint32_t* trlwe, uint64_t B, int waves, hipStream_t st, const uint64_t* bkn = nullptr);
+                               uint32_t* trlwe, uint64_t B, int waves, hipStream_t st, const uint64_t* bkn = nullptr,
+                               const uint64_t* const* keytab = nullptr, const uint8_t* kid = nullptr);
 // Identity key switch TLWE1 [B][N+1] -> TLWE0 [B][n+1] (outputs scattered by idxo if given).
 // form: 0 one workgroup per gate, 1 row-stationary tiles, 2 LDS-staged split, -1 the tuned one.
 constexpr int kKsForms = 3;

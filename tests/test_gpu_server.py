@@ -93,8 +93,9 @@ def test_capacity_and_malformed_rejected(gpu, keys):
 
 def test_per_client_key_sets(gpu, keys):
     """Two clients with their own key sets (each client generates and ships its own keys,
-    Sec. 4.1): a batch never mixes key sets; client B's results equal the oracle evaluated with
-    B's keys and decrypt under B's secret key, and client A's equal the circuit executor."""
+    Sec. 4.1) served together, so that batches hold gates of both key sets: client B's results
+    equal the oracle evaluated with B's keys and decrypt under B's secret key, and client A's
+    equal the circuit executor."""
     import oracle
     from test_gpu_circuit import oracle_eval, plaintext_eval
     s0b, s1b = W.secret_keys(5)
@@ -110,7 +111,9 @@ def test_per_client_key_sets(gpu, keys):
     tb = [srv.submit(c["gates"], c["ninputs"], x, keyset=kb) for c, x in reqs_b]
     outs_a = [wait(srv, t, c["ninputs"] + len(c["gates"]))[0] for t, (c, _) in zip(ta, reqs_a)]
     outs_b = [wait(srv, t, c["ninputs"] + len(c["gates"]))[0] for t, (c, _) in zip(tb, reqs_b)]
+    _, batches, _ = srv.stats()
     srv.close()
+    assert batches < sum(int(c["level"].max()) + 1 for c, _ in reqs_a + reqs_b)   # batches mixed clients
     for (c, x), o in zip(reqs_b, outs_b):
         np.testing.assert_array_equal(client.tlwe_decrypt(s0b, o), plaintext_eval(c["gates"], c["bits"]))
     bk_b, ksk_b = oracle.keyset(s0b, s1b, bkd, kskd)
