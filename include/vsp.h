@@ -25,7 +25,8 @@
  *    as VSP_E_HIP from a later call or from vsp_context_sync.
  *  - A context is not re-entrant: calls on one context must be ordered by the caller
  *    (one host thread, one stream, or explicit synchronisation). The server serialises
- *    its own work.
+ *    its own work. Circuits, servers and key sets hold a pointer to their context: destroy
+ *    them before the context.
  *  - Every call returns a vsp_status; nothing unwinds across this interface. The detail
  *    of the last failure on the calling thread is available from vsp_last_error().
  */
