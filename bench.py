@@ -118,6 +118,7 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--cpu-gates", type=int, default=0, help="oracle sample size (default: about 12 s of work)")
     ap.add_argument("--no-memory", action="store_true", help="skip the CMUX-memory timings")
+    ap.add_argument("--no-machine", action="store_true", help="skip the clocked-netlist cycle timing")
     ap.add_argument("--serving", type=float, default=2.0, metavar="SECONDS",
                     help="arrival window of the serving run at 50 circuits/s (0 skips it)")
     ap.add_argument("--serving-light", type=float, default=0.7, metavar="FRACTION",
@@ -208,6 +209,31 @@ def memory_run(ctx, s0, s1, reps: int = 3):
             "workload": "ROM 512 x 32-bit words (16 packed TRLWE), 9-bit encrypted addresses; RAM v = 8, "
                         "w = 8 (2,048 TRLWE cells); write = read + control unit + 2,048 write bars + "
                         "2,048 refresh bootstraps"}
+
+
+def machine_run(ctx, s0, cycles: int = 3):
+    """Clock cycles of a synthetic clocked netlist of a small processor's size (2,422 gates in
+    32 levels, 256 flip-flops), one HIP graph replay per cycle, timed with events."""
+    import torch
+
+    import workloads as W
+    from paper_2010_09410_amd import client
+    net = W.clocked_netlist()
+    m = ctx.machine(net["gates"], 0, net["next_state"])
+    state = ctx.tensor(client.tlwe_encrypt_bits(s0, net["bits"], *net["enc"]))
+    m.run(state, 1)
+    st = torch.cuda.current_stream(ctx.device)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    m.run(state, cycles)
+    e1.record(st)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / cycles
+    m.close()
+    return {"gates": len(net["gates"]), "levels": int(net["level"].max()) + 1, "flip_flops": net["nstate"],
+            "s_per_cycle": round(ms / 1e3, 4), "gates_per_s": round(len(net["gates"]) / (ms / 1e3), 1),
+            "workload": "synthetic layered netlist of the paper's pipelined-processor gate count (2,422 two-input "
+                        "gates), 32 levels, 256 flip-flops; no CMUX memory"}
 
 
 MEAN_CIRCUIT_GATES = (20000 - 100) / np.log(20000 / 100)   # log-uniform sizes in [100, 20000]
@@ -360,6 +386,9 @@ def main():
     memory = None
     if not args.no_memory:
         memory = memory_run(ctx, s0, s1)
+    machine = None
+    if not args.no_machine:
+        machine = machine_run(ctx, s0)
 
     serving = None
     if args.serving > 0:
@@ -402,7 +431,7 @@ def main():
         "per_gate_value": None if per_gate is None else round(per_gate, 2),
         "batched_over_per_gate": None if per_gate is None else round(value / per_gate, 1),
         "mux_per_s": None if mux_rate is None else round(mux_rate, 1),
-        "per_level": levels, "cmux_memory": memory, "serving": serving, "roofline": roof, "cpu_baseline": cpu,
+        "per_level": levels, "clocked_netlist": machine, "cmux_memory": memory, "serving": serving, "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
 

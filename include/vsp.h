@@ -70,6 +70,7 @@ typedef struct vsp_context vsp_context;
 typedef struct vsp_circuit vsp_circuit;
 typedef struct vsp_server vsp_server;
 typedef struct vsp_keyset vsp_keyset;
+typedef struct vsp_machine vsp_machine;
 
 /* A gate of a circuit: opcode and the wire ids of its inputs (in1 ignored by NOT). Wires
  * 0..ninputs-1 are the circuit inputs; gate g writes wire ninputs + g. */
@@ -159,6 +160,24 @@ vsp_status vsp_ram_read(vsp_context* ctx, const uint32_t* d_ram, uint32_t v, uin
  * d_ram is updated in place; d_addr [v][2l][2][N]; d_flag [n+1]; d_data [w][n+1]. */
 vsp_status vsp_ram_write(vsp_context* ctx, uint32_t* d_ram, uint32_t v, uint32_t w, const uint32_t* d_addr,
                          const uint32_t* d_flag, const uint32_t* d_data, void* stream);
+
+/* A clocked circuit (the cycle loop of the paper's evaluation engine, Sec. 6.2(d)): wires
+ * 0..ninputs-1 are the external inputs of a cycle, ninputs..ninputs+nstate-1 the flip-flop
+ * outputs, and gate g writes wire ninputs + nstate + g (gates as for vsp_circuit_create,
+ * reading any earlier wire). At the end of every cycle flip-flop k latches wire
+ * next_state[k] (any wire; all flip-flops latch at once). The level sequence and the latch
+ * are captured once in a HIP graph. */
+vsp_status vsp_machine_create(vsp_context* ctx, const vsp_gate_desc* gates, uint64_t ngates, uint64_t ninputs,
+                              uint64_t nstate, const uint32_t* next_state, vsp_machine** out);
+
+/* Runs ncycles clock cycles on `stream`: d_state [nstate][n+1] holds the flip-flops' state
+ * before (in) and after (out) the run; d_inputs [ncycles][ninputs][n+1] the external inputs
+ * of every cycle (NULL when ninputs = 0); d_wires (optional, NULL to skip) receives all
+ * [ninputs + nstate + ngates][n+1] wires of the last cycle, whose flip-flop rows already hold
+ * the latched state. A machine runs one call at a time. */
+vsp_status vsp_machine_run(vsp_machine* m, const uint32_t* d_inputs, uint32_t* d_state, uint32_t* d_wires,
+                           uint64_t ncycles, void* stream);
+vsp_status vsp_machine_destroy(vsp_machine* m);
 
 /* Continuous-batching server over one context (Bob evaluating many clients' circuits,
  * Sec. 4.1): admits submitted circuits while their resident wire buffers fit in

@@ -10,6 +10,8 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libvsp.so")
 
@@ -62,6 +64,9 @@ SIGNATURES = {
     "vsp_server_poll": (_st, [_vp, _u64, _vp, ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_double)]),
     "vsp_server_stats": (_st, [_vp, ctypes.POINTER(_u64), ctypes.POINTER(_u64), ctypes.POINTER(_u64)]),
     "vsp_server_destroy": (_st, [_vp]),
+    "vsp_machine_create": (_st, [_vp, ctypes.POINTER(vsp_gate_desc), _u64, _u64, _u64, _vp, ctypes.POINTER(_vp)]),
+    "vsp_machine_run": (_st, [_vp, _vp, _vp, _vp, _u64, _vp]),
+    "vsp_machine_destroy": (_st, [_vp]),
     "vsp_keyset_create": (_st, [_vp, _vp, _vp, ctypes.POINTER(_vp)]),
     "vsp_keyset_destroy": (_st, [_vp]),
     "vsp_server_submit_keyset": (_st, [_vp, _vp, ctypes.POINTER(vsp_gate_desc), _u64, _u64, _vp, ctypes.POINTER(_u64)]),
@@ -186,6 +191,22 @@ def vsp_server_submit(srv, gates, ninputs: int, h_inputs) -> int:
     t = _u64()
     _call("vsp_server_submit", srv, descs, len(gates), ninputs, h_inputs.ctypes.data, ctypes.byref(t))
     return t.value
+
+
+def vsp_machine_create(ctx, gates, ninputs: int, next_state) -> int:
+    descs = gate_descs(gates)
+    nxt = np.ascontiguousarray(next_state, dtype=np.uint32)
+    out = _vp()
+    _call("vsp_machine_create", ctx, descs, len(gates), ninputs, nxt.size, nxt.ctypes.data, ctypes.byref(out))
+    return out.value
+
+
+def vsp_machine_run(m, d_inputs, d_state, d_wires, ncycles: int, stream=None) -> None:
+    _call("vsp_machine_run", m, d_inputs, d_state, d_wires, ncycles, stream)
+
+
+def vsp_machine_destroy(m) -> None:
+    _call("vsp_machine_destroy", m)
 
 
 def vsp_keyset_create(ctx, bk_host, ksk_host) -> int:

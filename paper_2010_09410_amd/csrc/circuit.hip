@@ -56,6 +56,18 @@ void free_circuit(vsp_circuit* c) {
 
 }  // namespace
 
+namespace vsp {
+
+hipError_t circuit_launch_levels(vsp_circuit* c, hipStream_t st) {
+  hipError_t e = hipSuccess;
+  for (uint64_t L = 0; L < c->nlevels && e == hipSuccess; L++) e = launch_level(c, L, st);
+  return e;
+}
+
+uint32_t* circuit_wires(vsp_circuit* c) { return c->d_wires; }
+
+}  // namespace vsp
+
 extern "C" {
 
 vsp_status vsp_circuit_create(vsp_context* ctx, const vsp_gate_desc* gates, uint64_t ngates, uint64_t ninputs,
@@ -123,8 +135,7 @@ vsp_status vsp_circuit_create(vsp_context* ctx, const vsp_gate_desc* gates, uint
   if ((e = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking)) != hipSuccess) return bail(hip_fail(e, "stream"));
   if ((e = hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess)
     return bail(hip_fail(e, "begin capture"));
-  hipError_t le = hipSuccess;
-  for (uint64_t L = 0; L < nlev && le == hipSuccess; L++) le = launch_level(c, L, c->cap);
+  const hipError_t le = circuit_launch_levels(c, c->cap);
   e = hipStreamEndCapture(c->cap, &c->graph);
   if (le != hipSuccess) return bail(hip_fail(le, "level launch during capture"));
   if (e != hipSuccess) return bail(hip_fail(e, "end capture"));

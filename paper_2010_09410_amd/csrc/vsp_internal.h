@@ -183,6 +183,12 @@ hipError_t launch_ext_product(const vsp_context* ctx, const uint64_t* Cn, const 
 hipError_t launch_polymul(const vsp_context* ctx, const int32_t* a, const uint32_t* b, uint32_t* out, uint64_t J,
                           hipStream_t st);
 
+// ---------------------------------------------------------------- circuits (circuit.hip)
+// Launches every level of a circuit on `st` (eager or under capture); the circuit's own wire
+// buffer [inputs + gates][n+1].
+hipError_t circuit_launch_levels(vsp_circuit* c, hipStream_t st);
+uint32_t* circuit_wires(vsp_circuit* c);
+
 // ---------------------------------------------------------------- CMUX memory (memory.hip)
 // One level of CMUX trees: for r < R, blk < nb, m < W/2:
 //   out[(r nb + blk) W/2 + m] = CMUX(sel[r * sel_r_stride + selbit], in[r s_r + blk s_b + 2m], in[.. + 2m + 1]).

@@ -124,6 +124,9 @@ class Context:
     def circuit(self, gates, ninputs: int) -> "Circuit":
         return Circuit(self, gates, ninputs)
 
+    def machine(self, gates, ninputs: int, next_state) -> "Machine":
+        return Machine(self, gates, ninputs, next_state)
+
     def keyset(self, bk: np.ndarray, ksk: np.ndarray) -> "Keyset":
         return Keyset(self, bk, ksk)
 
@@ -175,6 +178,35 @@ class Circuit:
     def close(self) -> None:
         if getattr(self, "handle", None):
             nv.vsp_circuit_destroy(self.handle)
+            self.handle = None
+
+
+class Machine:
+    """A clocked circuit: external inputs, flip-flops latching named wires every cycle, and a
+    levelled gate DAG replayed as one HIP graph per cycle."""
+
+    def __init__(self, ctx: Context, gates, ninputs: int, next_state):
+        self.ctx = ctx
+        self.gates = np.asarray(gates, dtype=np.int64)
+        self.ninputs = int(ninputs)
+        self.nstate = int(np.asarray(next_state).size)
+        self.handle = nv.vsp_machine_create(ctx.handle, self.gates, self.ninputs, next_state)
+
+    @property
+    def nwires(self) -> int:
+        return self.ninputs + self.nstate + len(self.gates)
+
+    def run(self, state: torch.Tensor, ncycles: int, inputs: torch.Tensor | None = None,
+            wires: torch.Tensor | None = None) -> torch.Tensor:
+        """Advances `state` ([nstate][n+1], updated in place) by ncycles cycles; inputs are
+        [ncycles][ninputs][n+1]. Returns `wires` (all wires of the last cycle) if given."""
+        nv.vsp_machine_run(self.handle, None if inputs is None else _ptr(inputs), _ptr(state),
+                           None if wires is None else _ptr(wires), int(ncycles), self.ctx.stream())
+        return wires
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            nv.vsp_machine_destroy(self.handle)
             self.handle = None
 
 

@@ -112,3 +112,54 @@ def test_graph_replays_with_eager_work_between(gpu, keys):
         o0 = gpu.tensor(W.uniform_u32(g, (50, n + 1)))
     circ.close()
     np.testing.assert_array_equal(client.tlwe_decrypt(keys["s0"], eager), plaintext_eval(c["gates"], c["bits"]))
+
+
+# A 4-bit counter with an enable input: next = state + e, as XOR / AND gates.
+COUNTER_GATES = np.array([[nv.XOR, 1, 0], [nv.AND, 1, 0],        # bit 0, carry into bit 1
+                          [nv.XOR, 2, 6], [nv.AND, 2, 6],        # bit 1, carry into bit 2
+                          [nv.XOR, 3, 8], [nv.AND, 3, 8],        # bit 2, carry into bit 3
+                          [nv.XOR, 4, 10]])                      # bit 3
+COUNTER_NEXT = [5, 7, 9, 11]
+
+
+def counter_oracle(keys, state, ins):
+    """The same cycles on the oracle: gates level by level, then the latch."""
+    for e in ins:
+        wires = np.zeros((12, n + 1), dtype=np.uint32)
+        wires[0], wires[1:5] = e, state
+        for lo, hi in ((0, 2), (2, 4), (4, 6), (6, 7)):
+            g = COUNTER_GATES[lo:hi]
+            wires[5 + lo:5 + hi] = oracle.gates(keys["bk"], keys["ksk"], g[:, 0].astype(np.uint8), wires[g[:, 1]],
+                                                wires[g[:, 2]])
+        state = wires[COUNTER_NEXT].copy()
+    return state
+
+
+def test_machine_counter_cycles(gpu, keys):
+    """Six clock cycles of the counter with enable bits 1,1,0,1,1,1 from state 0: the state
+    decrypts to 5, is bit-exact against the oracle, and two runs of three cycles equal one of six."""
+    s0 = keys["s0"]
+    g = W.rng(704)
+    en = [1, 1, 0, 1, 1, 1]
+    ins = client.tlwe_encrypt_bits(s0, np.array(en), *W.tlwe_draws(g, len(en))).reshape(len(en), 1, n + 1)
+    st0 = client.tlwe_encrypt_bits(s0, np.zeros(4, dtype=np.int64), *W.tlwe_draws(g, 4))
+    m = gpu.machine(COUNTER_GATES, 1, COUNTER_NEXT)
+    state = gpu.tensor(st0)
+    wires = gpu.empty(m.nwires, n + 1)
+    m.run(state, 6, gpu.tensor(ins), wires)
+    full = to_host(state)
+    state2 = gpu.tensor(st0)
+    m.run(state2, 3, gpu.tensor(ins[:3]))
+    m.run(state2, 3, gpu.tensor(ins[3:]))
+    halves = to_host(state2)
+    gpu.sync()
+    m.close()
+    np.testing.assert_array_equal(client.tlwe_decrypt(s0, full), [1, 0, 1, 0])   # 5, least significant bit first
+    np.testing.assert_array_equal(full, halves)
+    np.testing.assert_array_equal(full, counter_oracle(keys, st0, ins[:, 0]))
+    np.testing.assert_array_equal(to_host(wires)[1:5], full)                   # flip-flop rows hold the latched state
+
+
+def test_machine_rejects_bad_latch(gpu):
+    with pytest.raises(VspError):
+        gpu.machine(COUNTER_GATES, 1, [5, 7, 9, 99])

@@ -164,6 +164,21 @@ def small_circuit(seed: int, levels: int, wmin: int, wmax: int, ninputs: int):
     return dict(ninputs=ninputs, widths=widths, gates=gates, level=level, bits=bits, enc=enc)
 
 
+def clocked_netlist(gates: int = 2422, levels: int = 32, nstate: int = 256, seed: int = 16):
+    """A synthetic clocked netlist of a small processor's size (2,422 two-input gates, the
+    gate count of the paper's pipelined processor without its MUX and NOT cells): a layered
+    DAG over 256 flip-flop outputs with equal level widths; flip-flop k latches the k-th of
+    the last 256 gate outputs. Wire ids: flip-flops 0..nstate-1, then the gates."""
+    g = rng(seed)
+    widths = np.full(levels, gates // levels, dtype=np.int64)
+    widths[: gates - int(widths.sum())] += 1
+    gl, level = layered_circuit(g, nstate, widths)
+    next_state = (nstate + gates - nstate + np.arange(nstate)).astype(np.uint32)
+    bits = g.integers(0, 2, size=nstate, dtype=np.uint8)
+    enc = tlwe_draws(rng(seed + 10), nstate)
+    return dict(gates=gl, level=level, nstate=nstate, next_state=next_state, bits=bits, enc=enc)
+
+
 # ------------------------------------------------------------- CMUX memory
 def rom_workload(reads: int = 256, words: int = 512, seed_off: int = 0):
     """ROM of 512 uniform 32-bit words and `reads` uniform 9-bit addresses.
