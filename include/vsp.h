@@ -141,14 +141,14 @@ vsp_status vsp_circuit_destroy(vsp_circuit* c);
  * encryptions of the v address bits, least significant first. The high v - log2(N/w) bits
  * walk a CMUX tree over the cells, the low log2(N/w) bits rotate the chosen cell by
  * X^(-w q) with CMUXes, then bit b is KS(SampleExtract_b). d_out [R][w][n+1]. w must divide
- * N, be a power of two and P >= 1. */
+ * N, be a power of two and P >= 1; R w <= 2^22. */
 vsp_status vsp_rom_read(vsp_context* ctx, const uint32_t* d_rom, uint32_t P, const uint32_t* d_addr, uint32_t v,
                         uint32_t w, uint32_t* d_out, uint64_t R, void* stream);
 
 /* RAM read unit (Sec. 8.2): d_ram [w][2^v][2][N], block i holds bit i of every word in its
  * constant coefficient. Per read and bit: CMUX tree over the 2^v cells (address bit d
  * selects at level d, least significant first), SampleExtract_0, key switch.
- * d_addr [R][v][2l][2][N]; d_out [R][w][n+1]. 1 <= v <= 16. */
+ * d_addr [R][v][2l][2][N]; d_out [R][w][n+1]. 1 <= v <= 16, 1 <= w <= 1024, R w <= 2^22. */
 vsp_status vsp_ram_read(vsp_context* ctx, const uint32_t* d_ram, uint32_t v, uint32_t w, const uint32_t* d_addr,
                         uint32_t* d_out, uint64_t R, void* stream);
 
@@ -157,7 +157,8 @@ vsp_status vsp_ram_read(vsp_context* ctx, const uint32_t* d_ram, uint32_t v, uin
  * (0, mu X^0) (HomMUX without SE and IKS); each of the w 2^v write bars (bit i, address A)
  * chains v CMUXes y <- CMUX(s_d, R[i][A], y) from y = u_i, with s_d = C_d when bit d of A is
  * 1 and G - C_d otherwise (Sec. 8.2 Remark), and refreshes R[i][A] <- BR(KS(SE_0(y))).
- * d_ram is updated in place; d_addr [v][2l][2][N]; d_flag [n+1]; d_data [w][n+1]. */
+ * d_ram is updated in place; d_addr [v][2l][2][N]; d_flag [n+1]; d_data [w][n+1].
+ * 1 <= v <= 16, 1 <= w <= 1024, w 2^v <= 2^22. */
 vsp_status vsp_ram_write(vsp_context* ctx, uint32_t* d_ram, uint32_t v, uint32_t w, const uint32_t* d_addr,
                          const uint32_t* d_flag, const uint32_t* d_data, void* stream);
 

@@ -28,18 +28,20 @@ namespace {
 
 constexpr size_t T0B = (LWE_N + 1) * 4;
 
+// One level, in launch sequences of at most kMaxLaunch gates.
 hipError_t launch_level(vsp_circuit* c, uint64_t L, hipStream_t st) {
-  const uint64_t o = c->off[L], w = c->off[L + 1] - o;
-  if (w == 0) return hipSuccess;
-  const uint32_t* i0 = c->d_idx + o;
-  const uint32_t* i1 = c->d_idx + c->ngates + o;
-  const uint32_t* io = c->d_idx + 2 * c->ngates + o;
-  const uint8_t* ops = c->d_ops + o;
-  hipError_t e = launch_gate_prologue(c->ctx, ops, c->d_wires, c->d_wires, i0, i1, io, c->d_abar, c->d_wires, w, st);
-  if (e != hipSuccess) return e;
-  e = launch_blind_rotate(c->ctx, ops, c->d_abar, c->d_tlwe1, nullptr, w, 0, st);
-  if (e != hipSuccess) return e;
-  return launch_keyswitch(c->ctx, ops, c->d_tlwe1, io, c->d_wires, w, st);
+  hipError_t e = hipSuccess;
+  for (uint64_t o = c->off[L]; o < c->off[L + 1] && e == hipSuccess; o += kMaxLaunch) {
+    const uint64_t w = std::min<uint64_t>(kMaxLaunch, c->off[L + 1] - o);
+    const uint32_t* i0 = c->d_idx + o;
+    const uint32_t* i1 = c->d_idx + c->ngates + o;
+    const uint32_t* io = c->d_idx + 2 * c->ngates + o;
+    const uint8_t* ops = c->d_ops + o;
+    e = launch_gate_prologue(c->ctx, ops, c->d_wires, c->d_wires, i0, i1, io, c->d_abar, c->d_wires, w, st);
+    if (e == hipSuccess) e = launch_blind_rotate(c->ctx, ops, c->d_abar, c->d_tlwe1, nullptr, w, 0, st);
+    if (e == hipSuccess) e = launch_keyswitch(c->ctx, ops, c->d_tlwe1, io, c->d_wires, w, st);
+  }
+  return e;
 }
 
 void free_circuit(vsp_circuit* c) {
@@ -119,7 +121,7 @@ vsp_status vsp_circuit_create(vsp_context* ctx, const vsp_gate_desc* gates, uint
   };
   hipError_t e;
   if ((e = hipSetDevice(ctx->device)) != hipSuccess) return bail(hip_fail(e, "hipSetDevice"));
-  const uint64_t wmax = std::max<uint64_t>(c->maxw, 1);
+  const uint64_t wmax = std::max<uint64_t>(std::min<uint64_t>(c->maxw, kMaxLaunch), 1);
   if ((e = hipMalloc(&c->d_ops, std::max<uint64_t>(ngates, 1))) != hipSuccess) return bail(hip_fail(e, "hipMalloc"));
   if ((e = hipMalloc(&c->d_idx, std::max<uint64_t>(3 * ngates, 1) * 4)) != hipSuccess) return bail(hip_fail(e, "hipMalloc"));
   if ((e = hipMalloc(&c->d_wires, std::max<uint64_t>(ninputs + ngates, 1) * T0B)) != hipSuccess)

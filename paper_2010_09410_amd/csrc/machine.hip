@@ -60,6 +60,7 @@ vsp_status vsp_machine_create(vsp_context* ctx, const vsp_gate_desc* gates, uint
   *out = nullptr;
   if (ctx == nullptr) return fail(VSP_E_ARG, "context is NULL");
   if (nstate > 0 && next_state == nullptr) return fail(VSP_E_ARG, "next_state is NULL");
+  if (nstate > kMaxLaunch) return fail(VSP_E_ARG, "too many flip-flops");
   const uint64_t nwires = ninputs + nstate + ngates;
   for (uint64_t k = 0; k < nstate; k++)
     if (next_state[k] >= nwires) return fail(VSP_E_ARG, "flip-flop " + std::to_string(k) + " latches a wire that does not exist");

@@ -256,7 +256,7 @@ vsp_status vsp_rom_read(vsp_context* ctx, const uint32_t* d_rom, uint32_t P, con
   const int rotbits = ilog2(RING_N / w);
   if (v < (uint32_t)rotbits || v > 32) return fail(VSP_E_ARG, "v must be at least log2(N / w)");
   if ((uint64_t)P != (1ull << (v - rotbits))) return fail(VSP_E_ARG, "P must equal 2^(v - log2(N / w))");
-  if (R > (1ull << 24)) return fail(VSP_E_ARG, "R too large");
+  if (R > (1ull << 24) || R * w > kMaxLaunch) return fail(VSP_E_ARG, "R too large (R * w must not exceed 2^22)");
   VSP_HIP(hipSetDevice(ctx->device));
   vsp_status s;
   const size_t rom_b = (size_t)P * TRLWE_WORDS * 4, addr_b = (size_t)R * v * TRGSW_WORDS * 4,
@@ -292,7 +292,7 @@ vsp_status vsp_ram_read(vsp_context* ctx, const uint32_t* d_ram, uint32_t v, uin
   if (R == 0) return VSP_OK;
   if (v < 1 || v > 16) return fail(VSP_E_ARG, "v must be in [1, 16]");
   if (w < 1 || w > 1024) return fail(VSP_E_ARG, "w must be in [1, 1024]");
-  if (R > (1ull << 20)) return fail(VSP_E_ARG, "R too large");
+  if (R > (1ull << 20) || R * w > kMaxLaunch) return fail(VSP_E_ARG, "R too large (R * w must not exceed 2^22)");
   VSP_HIP(hipSetDevice(ctx->device));
   vsp_status s;
   const uint64_t cells = (uint64_t)w << v;
@@ -327,6 +327,7 @@ vsp_status vsp_ram_write(vsp_context* ctx, uint32_t* d_ram, uint32_t v, uint32_t
   if (ctx == nullptr) return fail(VSP_E_ARG, "context is NULL");
   if (v < 1 || v > 16) return fail(VSP_E_ARG, "v must be in [1, 16]");
   if (w < 1 || w > 1024) return fail(VSP_E_ARG, "w must be in [1, 1024]");
+  if (((uint64_t)w << v) > kMaxLaunch) return fail(VSP_E_ARG, "w * 2^v must not exceed 2^22");
   VSP_HIP(hipSetDevice(ctx->device));
   vsp_status s;
   const uint64_t cells = (uint64_t)w << v;

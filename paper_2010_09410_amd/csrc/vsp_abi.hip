@@ -272,7 +272,7 @@ static vsp_status gates_impl(vsp_context* ctx, const uint8_t* d_ops, const uint3
   if ((s = check_no_overlap(d_out, ob, d_in0, tl, "d_out and d_in0"))) return s;
   if ((s = check_no_overlap(d_out, ob, d_in1, tl, "d_out and d_in1"))) return s;
   if ((s = check_no_overlap(d_out, ob, d_ops, B, "d_out and d_ops"))) return s;
-  const uint64_t chunk = (mode == VSP_BATCHED) ? B : 1;
+  const uint64_t chunk = (mode == VSP_BATCHED) ? std::min<uint64_t>(B, kMaxLaunch) : 1;
   if ((s = scratch_reserve(ctx, ctx->abar, chunk * (LWE_N + 1) * 4))) return s;
   if (!trlwe_out && (s = scratch_reserve(ctx, ctx->tlwe1, chunk * (RING_N + 1) * 4))) return s;
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -371,28 +371,33 @@ vsp_status vsp_mux(vsp_context* ctx, const uint32_t* d_sel, const uint32_t* d_in
   if ((s = check_no_overlap(d_out, tl, d_sel, tl, "d_out and d_sel"))) return s;
   if ((s = check_no_overlap(d_out, tl, d_in1, tl, "d_out and d_in1"))) return s;
   if ((s = check_no_overlap(d_out, tl, d_in0, tl, "d_out and d_in0"))) return s;
-  if ((s = scratch_reserve(ctx, ctx->abar, 2 * B * (LWE_N + 1) * 4))) return s;
-  if ((s = scratch_reserve(ctx, ctx->tlwe1, 2 * B * (RING_N + 1) * 4))) return s;
+  const uint64_t chunk = std::min<uint64_t>(B, kMaxLaunch / 2);
+  if ((s = scratch_reserve(ctx, ctx->abar, 2 * chunk * (LWE_N + 1) * 4))) return s;
+  if ((s = scratch_reserve(ctx, ctx->tlwe1, 2 * chunk * (RING_N + 1) * 4))) return s;
   hipStream_t st = static_cast<hipStream_t>(stream);
   uint32_t* abar = static_cast<uint32_t*>(ctx->abar.ptr);
   uint32_t* t1 = static_cast<uint32_t*>(ctx->tlwe1.ptr);
-  hipError_t e;
-  {
-    ProfScope ps(ctx, 2, st);
-    e = launch_mux_prologue(d_sel, d_in1, d_in0, abar, B, st);
+  for (uint64_t g0 = 0; g0 < B; g0 += chunk) {
+    const uint64_t nb = std::min<uint64_t>(chunk, B - g0);
+    const size_t o = g0 * (LWE_N + 1);
+    hipError_t e;
+    {
+      ProfScope ps(ctx, 2, st);
+      e = launch_mux_prologue(d_sel + o, d_in1 + o, d_in0 + o, abar, nb, st);
+    }
+    if (e != hipSuccess) return hip_fail(e, "mux prologue");
+    {
+      ProfScope ps(ctx, 0, st);
+      e = launch_blind_rotate(ctx, nullptr, abar, t1, nullptr, 2 * nb, 0, st);
+    }
+    if (e != hipSuccess) return hip_fail(e, "blind rotation");
+    if ((e = launch_mux_combine(t1, nb, st)) != hipSuccess) return hip_fail(e, "mux combine");
+    {
+      ProfScope ps(ctx, 1, st);
+      e = launch_keyswitch(ctx, nullptr, t1, nullptr, d_out + o, nb, st);
+    }
+    if (e != hipSuccess) return hip_fail(e, "key switch");
   }
-  if (e != hipSuccess) return hip_fail(e, "mux prologue");
-  {
-    ProfScope ps(ctx, 0, st);
-    e = launch_blind_rotate(ctx, nullptr, abar, t1, nullptr, 2 * B, 0, st);
-  }
-  if (e != hipSuccess) return hip_fail(e, "blind rotation");
-  if ((e = launch_mux_combine(t1, B, st)) != hipSuccess) return hip_fail(e, "mux combine");
-  {
-    ProfScope ps(ctx, 1, st);
-    e = launch_keyswitch(ctx, nullptr, t1, nullptr, d_out, B, st);
-  }
-  if (e != hipSuccess) return hip_fail(e, "key switch");
   return VSP_OK;
 }
 

@@ -18,6 +18,10 @@ namespace vsp {
 constexpr int TLWE0 = LWE_N + 1;
 constexpr int TLWE1 = RING_N + 1;
 
+// Largest number of gates (bootstraps, key switches) in one launch sequence; larger calls are
+// split so that every grid stays far below the 2^31 workgroup limit.
+constexpr uint64_t kMaxLaunch = 1ull << 22;
+
 // Internal opcode: bootstrap the first input unchanged (refresh of a noisy TLWE).
 constexpr uint8_t OP_IDENT = 16;
 

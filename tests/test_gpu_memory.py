@@ -115,3 +115,17 @@ def test_ram_write_then_read_full_workload(gpu, keys):
     idx = np.array([wl["waddr"], 256 + wl["waddr"], 7 * 256 + 3, 1000])
     bars = oracle.ram_write_bars(keys["bk"], keys["ksk"], ram, sel, u, idx)
     np.testing.assert_array_equal(new.reshape(-1, 2, N)[idx], bars)
+
+
+def test_memory_size_limits_rejected(gpu):
+    """Requests beyond the launch limit (R w or w 2^v above 2^22) are refused before any work."""
+    from paper_2010_09410_amd import VspError
+    from paper_2010_09410_amd import _native as nv
+    buf = gpu.empty(16, 2, N)
+    ptr = buf.data_ptr()
+    with pytest.raises(VspError):
+        nv.vsp_rom_read(gpu.handle, ptr, 16, ptr, 9, 32, ptr, 1 << 18, gpu.stream())
+    with pytest.raises(VspError):
+        nv.vsp_ram_read(gpu.handle, ptr, 8, 1024, ptr, ptr, 1 << 13, gpu.stream())
+    with pytest.raises(VspError):
+        nv.vsp_ram_write(gpu.handle, ptr, 16, 128, ptr, ptr, ptr, gpu.stream())
