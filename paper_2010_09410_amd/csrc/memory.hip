@@ -10,59 +10,156 @@ constexpr int TRLWE_WORDS = 2 * RING_N;
 constexpr int TRGSW_WORDS = 2 * GADGET_L * 2 * RING_N;
 
 // ------------------------------------------------------------------ kernels
+// The CMUX kernels run one CMUX chain per wave, WAVES waves per workgroup. The workgroup's
+// LDS holds the twiddle tables, then per wave a polynomial pair (2N u32: lanes 0-31 own the
+// a polynomial, lanes 32-63 the b polynomial, coefficient l + 32 t in lane l) and the wave's
+// two transpose regions. Keeping the pair in LDS instead of registers and reading the
+// gadget digits from it in every round leaves the external product within 256 VGPRs, so a
+// SIMD runs two waves.
+constexpr int MEM_WAVE_U32 = 2 * RING_N + WAVE_T_U32;
+constexpr size_t mem_lds_bytes(int waves) { return 2048 * 8 + (size_t)waves * MEM_WAVE_U32 * 4; }
+
+template <int WAVES>
+__device__ __forceinline__ void stage_twiddles(u64* tws, const u64* __restrict__ tw) {
+  for (int i = threadIdx.x; i < 2048; i += WAVES * 64) tws[i] = tw[i];
+  __syncthreads();
+}
+
+// z = C (ext) P for the pair P at the start of this wave's LDS area; the wave's transpose
+// regions follow the pair. The product of external_product, with the digits re-read from LDS
+// and every LDS and key address formed anew in each round (from an opaque copy of the lane
+// index), so that none of them stays live across the rounds. KEY_LATE issues a round's first
+// key loads after its forward transform instead of before its digits: fewer live registers
+// during the transform, less latency hidden (the choice that keeps each caller's register
+// spills smallest at 256 VGPRs).
+template <bool KEY_LATE>
+__device__ __forceinline__ void ext_product_lds(u32* wbase, const u64* __restrict__ C, const u64* tws, int lane,
+                                                u32 (&z)[32]) {
+  u64 sum[32];
+#pragma unroll
+  for (int s = 0; s < 32; s++) sum[s] = 0;
+#pragma unroll 1
+  for (int k = 0; k < GADGET_L; k++) {
+    const int ln = opaque_lane(lane);
+    const int li = ln & 31;
+    const u32* p = wbase + (ln >> 5) * RING_N + li;
+    const ulonglong2* key = reinterpret_cast<const ulonglong2*>(C) + (size_t)k * 32 * 64 + ln;
+    ulonglong2 kc[KCH];
+    if (!KEY_LATE) {
+#pragma unroll
+      for (int q = 0; q < KCH; q++) kc[q] = key[q * 64];
+    }
+    u64 x[32];
+    const int sh = 32 - BG_BIT * (k + 1);
+#pragma unroll
+    for (int t = 0; t < 32; t++) x[t] = gadget_digit(p[32 * t], sh);
+    ntt_forward<true>(x, tws, wbase + 2 * RING_N + (ln >> 5) * TREGION, li);
+    if (KEY_LATE) {
+#pragma unroll
+      for (int q = 0; q < KCH; q++) kc[q] = key[q * 64];
+    }
+#pragma unroll
+    for (int c = 0; c < 32 / KCH; c++) {
+      ulonglong2 kn[KCH];
+      if (c + 1 < 32 / KCH) {
+#pragma unroll
+        for (int q = 0; q < KCH; q++) kn[q] = key[(KCH * (c + 1) + q) * 64];
+      }
+#pragma unroll
+      for (int q = 0; q < KCH; q++) {
+        const int s = KCH * c + q;
+        u64 xa, xb;
+        both_halves(x[s], xa, xb);
+        sum[s] = gl_add(sum[s], gl_dot2(xa, kc[q].x, xb, kc[q].y));
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      if (c + 1 < 32 / KCH) {
+#pragma unroll
+        for (int q = 0; q < KCH; q++) kc[q] = kn[q];
+      }
+    }
+  }
+  const int ln = opaque_lane(lane);
+  ntt_inverse_lift(sum, tws + 1024, wbase + 2 * RING_N + (ln >> 5) * TREGION, ln & 31, z);
+}
+
 // One wave per CMUX: out = x0 + C (ext) (x1 - x0).
-__global__ __launch_bounds__(256) void k_cmux_tree_level(const u64* __restrict__ sel, uint64_t sel_r_stride, int selbit,
-                                                         const u32* __restrict__ in, uint64_t s_r, uint64_t s_b,
-                                                         u32* __restrict__ out, uint64_t R, uint64_t nb, uint64_t half,
-                                                         const u64* __restrict__ tw) {
-  __shared__ u32 lds[4 * WAVE_T_U32];
+template <int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void k_cmux_tree_level(const u64* __restrict__ sel, uint64_t sel_r_stride,
+                                                                int selbit, const u32* __restrict__ in, uint64_t s_r,
+                                                                uint64_t s_b, u32* __restrict__ out, uint64_t R,
+                                                                uint64_t nb, uint64_t half,
+                                                                const u64* __restrict__ tw) {
+  extern __shared__ u64 lds[];
+  stage_twiddles<WAVES>(lds, tw);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const uint64_t job = (uint64_t)blockIdx.x * 4 + wave;
+  const uint64_t job = (uint64_t)blockIdx.x * WAVES + wave;
   if (job >= R * nb * half) return;
   const int lane = threadIdx.x & 63, l = lane & 31, h = lane >> 5;
   const uint64_t m = job % half, rb = job / half, blk = rb % nb, r = rb / nb;
   const u32* x0 = in + r * s_r + blk * s_b + (2 * m) * TRLWE_WORDS + h * RING_N;
   const u32* x1 = x0 + TRLWE_WORDS;
-  const u64* C = sel + (r * sel_r_stride + (uint64_t)selbit) * TRGSW_NTT_U64;
-  u32* reg = lds + wave * WAVE_T_U32 + h * TREGION;
-  u32 D[32], acc[32], z[32];
+  u32* wbase = reinterpret_cast<u32*>(lds + 2048) + wave * MEM_WAVE_U32;
+  u32* buf = wbase + h * RING_N;
 #pragma unroll
-  for (int t = 0; t < 32; t++) {
-    const u32 a = x0[l + 32 * t], b = x1[l + 32 * t];
-    acc[t] = a;
-    D[t] = b - a;
-  }
-  external_product(OperandDigits{D}, C, tw, tw + 1024, reg, lane, z);
+  for (int t = 0; t < 32; t++) buf[l + 32 * t] = x1[l + 32 * t] - x0[l + 32 * t];
+  wave_lds_sync();
+  u32 z[32];
+  ext_product_lds<false>(wbase, sel + (r * sel_r_stride + (uint64_t)selbit) * TRGSW_NTT_U64, lds, lane, z);
+  // the epilogue's addresses are formed anew here rather than kept live across the product
+  const int ln = opaque_lane(lane);
+  const u32* y0 = in + r * s_r + blk * s_b + (2 * m) * TRLWE_WORDS + (ln >> 5) * RING_N + (ln & 31);
+  u32* o = out + job * TRLWE_WORDS + (ln >> 5) * RING_N + (ln & 31);
 #pragma unroll
-  for (int t = 0; t < 32; t++) acc[t] += z[t];
-  u32* o = out + job * TRLWE_WORDS + h * RING_N;
-#pragma unroll
-  for (int t = 0; t < 32; t++) o[l + 32 * t] = acc[t];
+  for (int t = 0; t < 32; t++) o[32 * t] = y0[32 * t] + z[t];
 }
 
-// One wave per read: R <- CMUX(C_j, R, X^{-w 2^j} R) = R + C_j (ext) (X^{-w 2^j} R - R), j ascending.
-__global__ __launch_bounds__(256) void k_rom_rotate(const u64* __restrict__ sel, uint64_t sel_r_stride,
-                                                    u32* __restrict__ accbuf, uint64_t R, int rotbits, int w,
-                                                    const u64* __restrict__ tw) {
-  __shared__ u32 lds[4 * WAVE_T_U32];
+// One wave per read: R <- CMUX(C_j, R, X^{-w 2^j} R) = R + C_j (ext) (X^{-w 2^j} R - R), j
+// ascending. R lives in the wave's LDS buffer; the digits of the rotation difference are
+// formed from it in every round, and the product is added to it in place.
+template <int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void k_rom_rotate(const u64* __restrict__ sel, uint64_t sel_r_stride,
+                                                           u32* __restrict__ accbuf, uint64_t R, int rotbits, int w,
+                                                           const u64* __restrict__ tw) {
+  extern __shared__ u64 lds[];
+  stage_twiddles<WAVES>(lds, tw);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const uint64_t r = (uint64_t)blockIdx.x * 4 + wave;
+  const uint64_t r = (uint64_t)blockIdx.x * WAVES + wave;
   if (r >= R) return;
   const int lane = threadIdx.x & 63, l = lane & 31, h = lane >> 5;
-  u32* reg = lds + wave * WAVE_T_U32 + h * TREGION;
+  u32* wbase = reinterpret_cast<u32*>(lds + 2048) + wave * MEM_WAVE_U32;
   u32* p = accbuf + r * TRLWE_WORDS + h * RING_N;
-  u32 acc[32], D[32], z[32];
+  {
+    u32* accs = wbase + h * RING_N;
 #pragma unroll
-  for (int t = 0; t < 32; t++) acc[t] = p[l + 32 * t];
+    for (int t = 0; t < 32; t++) accs[l + 32 * t] = p[l + 32 * t];
+  }
+  wave_lds_sync();
   for (int j = 0; j < rotbits; j++) {
     const int k = (2 * RING_N - (w << j)) & (2 * RING_N - 1);
-    rotate_minus(acc, k, reg, l, D);
-    external_product(OperandDigits{D}, sel + (r * sel_r_stride + (uint64_t)j) * TRGSW_NTT_U64, tw, tw + 1024, reg, lane, z);
+    const int ln = opaque_lane(lane);
+    const int li = ln & 31, hi = ln >> 5;
+    u32* accs = wbase + hi * RING_N;
+    auto digits = [&](int sh, u64 (&x)[32]) {
 #pragma unroll
-    for (int t = 0; t < 32; t++) acc[t] += z[t];
+      for (int t = 0; t < 32; t++) {
+        const int idx = (li + 32 * t - k) & (2 * RING_N - 1);
+        u32 v = accs[idx & (RING_N - 1)];
+        if (idx & RING_N) v = 0u - v;
+        x[t] = gadget_digit(v - accs[li + 32 * t], sh);
+      }
+    };
+    u32 z[32];
+    external_product(digits, sel + (r * sel_r_stride + (uint64_t)j) * TRGSW_NTT_U64, lds, lds + 1024,
+                     wbase + 2 * RING_N + hi * TREGION, ln, z);
+#pragma unroll
+    for (int t = 0; t < 32; t++)
+      __hip_atomic_fetch_add(&accs[li + 32 * t], z[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    wave_lds_sync();
   }
+  const u32* accs = wbase + h * RING_N;
 #pragma unroll
-  for (int t = 0; t < 32; t++) p[l + 32 * t] = acc[t];
+  for (int t = 0; t < 32; t++) p[l + 32 * t] = accs[l + 32 * t];
 }
 
 // SampleExtract_h for h < W: out[r][h] (N + 1 words) from in[r] = (A, B).
@@ -91,33 +188,44 @@ __global__ __launch_bounds__(256) void k_ram_control(const u32* __restrict__ acc
 
 // One wave per write bar (bit i, address A): y = u_i; for d < v: y = CMUX(s_d, R[i][A], y)
 // = R[i][A] + s_d (ext) (y - R[i][A]) with s_d = C_d (bit d of A is 1) or G - C_d (0);
-// then SampleExtract_0(y) into tlwe1[i 2^v + A].
-__global__ __launch_bounds__(256) void k_ram_bars(const u64* __restrict__ sel, const u64* __restrict__ selneg,
-                                                  const u32* __restrict__ ram, const u32* __restrict__ u,
-                                                  u32* __restrict__ tlwe1, int v, int w, const u64* __restrict__ tw) {
-  __shared__ u32 lds[4 * WAVE_T_U32];
+// then SampleExtract_0(y) into tlwe1[i 2^v + A]. The chain runs on the difference
+// D = y - R[i][A]: D starts as u_i - R[i][A], each step replaces it by s_d (ext) D, and the
+// result is y = R[i][A] + D. D lives in the wave's LDS buffer.
+template <int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void k_ram_bars(const u64* __restrict__ sel, const u64* __restrict__ selneg,
+                                                         const u32* __restrict__ ram, const u32* __restrict__ u,
+                                                         u32* __restrict__ tlwe1, int v, int w,
+                                                         const u64* __restrict__ tw) {
+  extern __shared__ u64 lds[];
+  stage_twiddles<WAVES>(lds, tw);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const uint64_t bar = (uint64_t)blockIdx.x * 4 + wave;
+  const uint64_t bar = (uint64_t)blockIdx.x * WAVES + wave;
   if (bar >= ((uint64_t)w << v)) return;
   const int lane = threadIdx.x & 63, l = lane & 31, h = lane >> 5;
   const uint64_t i = bar >> v, A = bar & ((1ull << v) - 1);
-  u32* reg = lds + wave * WAVE_T_U32 + h * TREGION;
+  u32* wbase = reinterpret_cast<u32*>(lds + 2048) + wave * MEM_WAVE_U32;
+  u32* buf = wbase + h * RING_N;
   const u32* old = ram + bar * TRLWE_WORDS + h * RING_N;
   const u32* ui = u + i * TRLWE_WORDS + h * RING_N;
-  u32 o[32], y[32], D[32], z[32];
 #pragma unroll
-  for (int t = 0; t < 32; t++) {
-    o[t] = old[l + 32 * t];
-    y[t] = ui[l + 32 * t];
-  }
+  for (int t = 0; t < 32; t++) buf[l + 32 * t] = ui[l + 32 * t] - old[l + 32 * t];
+  wave_lds_sync();
   for (int d = 0; d < v; d++) {
     const u64* C = (((A >> d) & 1) ? sel : selneg) + (size_t)d * TRGSW_NTT_U64;
+    u32 z[32];
+    ext_product_lds<true>(wbase, C, lds, lane, z);
+    // a lane reads and writes only its own coefficients of D
 #pragma unroll
-    for (int t = 0; t < 32; t++) D[t] = y[t] - o[t];
-    external_product(OperandDigits{D}, C, tw, tw + 1024, reg, lane, z);
-#pragma unroll
-    for (int t = 0; t < 32; t++) y[t] = o[t] + z[t];
+    for (int t = 0; t < 32; t++) buf[l + 32 * t] = z[t];
+    wave_lds_sync();
   }
+  const int ln = opaque_lane(lane);  // addresses formed anew, not kept live across the chain
+  const int li = ln & 31;
+  const u32* cell = ram + bar * TRLWE_WORDS + (ln >> 5) * RING_N;
+  const u32* dfin = wbase + (ln >> 5) * RING_N;
+  u32 y[32];
+#pragma unroll
+  for (int t = 0; t < 32; t++) y[t] = cell[li + 32 * t] + dfin[li + 32 * t];
   u32* out = tlwe1 + bar * (RING_N + 1);
   if (h == 0) {
 #pragma unroll
@@ -154,21 +262,49 @@ __global__ __launch_bounds__(256) void k_broadcast(const u32* __restrict__ src, 
 // ------------------------------------------------------------------ launchers
 static unsigned blocks_for(uint64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
+// The CMUX kernels in two shapes: eight waves per workgroup (two waves per SIMD once every CU
+// holds one workgroup) for wide launches, one wave per workgroup for narrow ones, where
+// spreading the few chains over all CUs shortens the launch.
+hipError_t init_memory_kernel_attributes() {
+  const void* fns[] = {reinterpret_cast<const void*>(&k_cmux_tree_level<8>),
+                       reinterpret_cast<const void*>(&k_rom_rotate<8>),
+                       reinterpret_cast<const void*>(&k_ram_bars<8>),
+                       reinterpret_cast<const void*>(&k_cmux_tree_level<1>),
+                       reinterpret_cast<const void*>(&k_rom_rotate<1>),
+                       reinterpret_cast<const void*>(&k_ram_bars<1>)};
+  for (int f = 0; f < 6; f++) {
+    const hipError_t e =
+        hipFuncSetAttribute(fns[f], hipFuncAttributeMaxDynamicSharedMemorySize, (int)mem_lds_bytes(f < 3 ? 8 : 1));
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+static bool wide_launch(const vsp_context* ctx, uint64_t chains) { return chains >= 8ull * (uint64_t)ctx->cus; }
+
 hipError_t launch_cmux_tree_level(const vsp_context* ctx, const uint64_t* sel, uint64_t sel_r_stride, int selbit,
                                   const uint32_t* in, uint64_t s_r, uint64_t s_b, uint32_t* out, uint64_t R,
                                   uint64_t nb, uint64_t W, hipStream_t st) {
   const uint64_t jobs = R * nb * (W / 2);
   if (jobs == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_cmux_tree_level, dim3(blocks_for(jobs, 4)), dim3(256), 0, st, sel, sel_r_stride, selbit, in,
-                     s_r, s_b, out, R, nb, W / 2, ctx->tw);
+  if (wide_launch(ctx, jobs))
+    hipLaunchKernelGGL(k_cmux_tree_level<8>, dim3(blocks_for(jobs, 8)), dim3(512), mem_lds_bytes(8), st, sel,
+                       sel_r_stride, selbit, in, s_r, s_b, out, R, nb, W / 2, ctx->tw);
+  else
+    hipLaunchKernelGGL(k_cmux_tree_level<1>, dim3(blocks_for(jobs, 1)), dim3(64), mem_lds_bytes(1), st, sel,
+                       sel_r_stride, selbit, in, s_r, s_b, out, R, nb, W / 2, ctx->tw);
   return hipGetLastError();
 }
 
 hipError_t launch_rom_rotate(const vsp_context* ctx, const uint64_t* sel, uint64_t sel_r_stride, uint32_t* acc,
                              uint64_t R, int rotbits, int w, hipStream_t st) {
   if (R == 0 || rotbits == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_rom_rotate, dim3(blocks_for(R, 4)), dim3(256), 0, st, sel, sel_r_stride, acc, R, rotbits, w,
-                     ctx->tw);
+  if (wide_launch(ctx, R))
+    hipLaunchKernelGGL(k_rom_rotate<8>, dim3(blocks_for(R, 8)), dim3(512), mem_lds_bytes(8), st, sel, sel_r_stride,
+                       acc, R, rotbits, w, ctx->tw);
+  else
+    hipLaunchKernelGGL(k_rom_rotate<1>, dim3(blocks_for(R, 1)), dim3(64), mem_lds_bytes(1), st, sel, sel_r_stride,
+                       acc, R, rotbits, w, ctx->tw);
   return hipGetLastError();
 }
 
@@ -187,8 +323,12 @@ hipError_t launch_ram_control(const uint32_t* acc2, uint32_t* u, int w, hipStrea
 hipError_t launch_ram_bars(const vsp_context* ctx, const uint64_t* sel, const uint64_t* selneg, const uint32_t* ram,
                            const uint32_t* u, uint32_t* tlwe1, int v, int w, hipStream_t st) {
   const uint64_t bars = (uint64_t)w << v;
-  hipLaunchKernelGGL(k_ram_bars, dim3(blocks_for(bars, 4)), dim3(256), 0, st, sel, selneg, ram, u, tlwe1, v, w,
-                     ctx->tw);
+  if (wide_launch(ctx, bars))
+    hipLaunchKernelGGL(k_ram_bars<8>, dim3(blocks_for(bars, 8)), dim3(512), mem_lds_bytes(8), st, sel, selneg, ram, u,
+                       tlwe1, v, w, ctx->tw);
+  else
+    hipLaunchKernelGGL(k_ram_bars<1>, dim3(blocks_for(bars, 1)), dim3(64), mem_lds_bytes(1), st, sel, selneg, ram, u,
+                       tlwe1, v, w, ctx->tw);
   return hipGetLastError();
 }
 

@@ -205,6 +205,7 @@ vsp_status vsp_context_create(const vsp_params* params, const uint32_t* bk_host,
   if (device < 0 || device >= ndev) return fail(VSP_E_ARG, "no such device");
   VSP_HIP(hipSetDevice(device));
   VSP_HIP(init_kernel_attributes());
+  VSP_HIP(init_memory_kernel_attributes());
   std::vector<u64> tw;
   if (!make_tables(tw)) return fail(VSP_E_HIP, "twiddle table construction failed");
 
@@ -215,7 +216,8 @@ vsp_status vsp_context_create(const vsp_params* params, const uint32_t* bk_host,
     return s;
   };
   {
-    const hipError_t e = blind_rotate_capacity(device, ctx->tune.br_cap);
+    hipError_t e = blind_rotate_capacity(device, ctx->tune.br_cap);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ctx->cus, hipDeviceAttributeMultiprocessorCount, device);
     if (e != hipSuccess) return cleanup(hip_fail(e, "occupancy query"));
   }
   hipError_t e;

@@ -104,6 +104,7 @@ struct vsp_keyset {
 
 struct vsp_context {
   int device = 0;
+  int cus = 1;                    // compute units of the device
   uint64_t* bkn = nullptr;        // bootstrapping key, NTT domain: [n][TRGSW_NTT_U64]
   uint32_t* ksk = nullptr;        // key-switching key [N][t][4][n+1]; digit value 0 points at a zero row
   uint64_t* tw = nullptr;         // psi_u^j [32][32] then psi_u^-j [32][32]
@@ -194,6 +195,8 @@ hipError_t circuit_launch_levels(vsp_circuit* c, hipStream_t st);
 uint32_t* circuit_wires(vsp_circuit* c);
 
 // ---------------------------------------------------------------- CMUX memory (memory.hip)
+// Sets the LDS limits of the CMUX kernels (once per process and device, before any launch).
+hipError_t init_memory_kernel_attributes();
 // One level of CMUX trees: for r < R, blk < nb, m < W/2:
 //   out[(r nb + blk) W/2 + m] = CMUX(sel[r * sel_r_stride + selbit], in[r s_r + blk s_b + 2m], in[.. + 2m + 1]).
 hipError_t launch_cmux_tree_level(const vsp_context* ctx, const uint64_t* sel, uint64_t sel_r_stride, int selbit,
