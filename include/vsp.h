@@ -231,7 +231,11 @@ vsp_status vsp_mux(vsp_context* ctx, const uint32_t* d_sel, const uint32_t* d_in
  * blind rotation runs on one wave (or, in the latency shape, on three waves that split each
  * external product by gadget level), so a batch of B gates runs in ceil(B / cap) rounds, cap
  * being the gates the GPU holds at once for a workgroup shape (4 or 8 gates per workgroup, or
- * one gate per three-wave workgroup). This call times one full round of each shape on random
+ * one gate per three-wave workgroup). The matrix-core form (32) instead runs each step as int8
+ * MFMA products of the batch's digit rows with the key's Toeplitz blocks (tiles of 32 gates;
+ * one round holds 16 gates per compute unit; used by vsp_gates and vsp_bootstrap_trlwe with the
+ * context's own key, the other callers run the 8-gate form in its place; it needs a workspace
+ * of 14 KiB per gate, grown on demand). This call times one full round of each shape on random
  * ciphertexts, and times the three key-switch forms (0: one workgroup per gate gathering its
  * key rows; 1: tiles of 16 gates reading each key row once and selecting in registers;
  * 2: tiles of 16 gates staging key rows through LDS, with the j range split over workgroups
@@ -244,10 +248,11 @@ vsp_status vsp_mux(vsp_context* ctx, const uint32_t* d_sel, const uint32_t* d_in
 vsp_status vsp_autotune(vsp_context* ctx, uint64_t max_batch, const char* cache_path);
 
 /* The launch choice for a batch of B gates: *br_waves (4 or 8 gates per workgroup at one wave
- * per gate, or 3 for one gate per workgroup on three waves), *ks_form (0, 1 or 2). */
+ * per gate, 3 for one gate per workgroup on three waves, 32 for the matrix-core form),
+ * *ks_form (0, 1 or 2). */
 vsp_status vsp_tuning_get(const vsp_context* ctx, uint64_t B, int* br_waves, int* ks_form);
 
-/* Pin the launch choice for the bucket containing B: br_waves 3, 4 or 8 (0 returns that
+/* Pin the launch choice for the bucket containing B: br_waves 3, 4, 8 or 32 (0 returns that
  * bucket to the round-time model), ks_form 0, 1 or 2. Results are the same for every choice. */
 vsp_status vsp_tuning_set(vsp_context* ctx, uint64_t B, int br_waves, int ks_form);
 

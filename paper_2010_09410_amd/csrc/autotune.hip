@@ -185,10 +185,15 @@ vsp_status vsp_autotune(vsp_context* ctx, uint64_t max_batch, const char* cache_
   Tuning t = ctx->tune;
   vsp_status result = VSP_OK;
   // Blind rotation: one full round of gates per shape.
+  if (ctx->mf_key && (result = scratch_reserve(ctx, ctx->mf_work, mf_work_bytes(t.br_cap[3], true))) != VSP_OK)
+    return result;
   for (int s = 0; s < kBrShapes && result == VSP_OK; s++) {
     uint32_t* dst = static_cast<uint32_t*>(s == 0 ? t1ref.p : t1.p);
     const uint64_t B = t.br_cap[s];
-    t.br_round_ms[s] = timed([&] { (void)launch_blind_rotate(ctx, dops, dab, dst, nullptr, B, kBrWaveChoices[s], st); });
+    t.br_round_ms[s] = timed([&] {
+      (void)launch_blind_rotate(ctx, dops, dab, dst, nullptr, B, kBrWaveChoices[s], st, nullptr, nullptr, nullptr,
+                                ctx->mf_work.ptr);
+    });
     if (s > 0 && !same(t1ref.p, t1.p, std::min(t.br_cap[0], B) * T1))
       result = fail(VSP_E_HIP, "autotune: blind-rotation shapes disagree");
   }
@@ -232,8 +237,9 @@ vsp_status vsp_tuning_get(const vsp_context* ctx, uint64_t B, int* br_waves, int
 
 vsp_status vsp_tuning_set(vsp_context* ctx, uint64_t B, int br_waves, int ks_form) {
   if (ctx == nullptr) return fail(VSP_E_ARG, "context is NULL");
-  if ((br_waves != 0 && br_waves != 3 && br_waves != 4 && br_waves != 8) || ks_form < 0 || ks_form >= kKsForms)
-    return fail(VSP_E_ARG, "br_waves must be 0 (model), 3, 4 or 8 and ks_form 0, 1 or 2");
+  if ((br_waves != 0 && br_waves != 3 && br_waves != 4 && br_waves != 8 && br_waves != 32) || ks_form < 0 ||
+      ks_form >= kKsForms)
+    return fail(VSP_E_ARG, "br_waves must be 0 (model), 3, 4, 8 or 32 and ks_form 0, 1 or 2");
   const int b = Tuning::bucket(B == 0 ? 1 : B);
   ctx->tune.br_force[b] = br_waves;
   ctx->tune.ks_form[b] = ks_form;

@@ -129,16 +129,18 @@ static bool make_tables(std::vector<u64>& tw) {
 }
 
 vsp_status upload_keys(const vsp_context* ctx, const uint32_t* bk_host, const uint32_t* ksk_host, uint64_t** bkn,
-                       uint32_t** ksk) {
+                       uint32_t** ksk, int8_t** mf_key) {
   *bkn = nullptr;
   *ksk = nullptr;
+  if (mf_key) *mf_key = nullptr;
   const size_t bk_words = (size_t)LWE_N * 2 * GADGET_L * 2 * RING_N;
   const size_t ksk_rows = (size_t)RING_N * KS_T * 4;
   uint64_t* b = nullptr;
   uint32_t* k = nullptr;
   uint32_t* tmp = nullptr;
+  int8_t* E = nullptr;
   auto undo = [&](vsp_status st) {
-    for (void* p : {(void*)b, (void*)k, (void*)tmp})
+    for (void* p : {(void*)b, (void*)k, (void*)tmp, (void*)E})
       if (p) (void)hipFree(p);
     return st;
   };
@@ -149,6 +151,10 @@ vsp_status upload_keys(const vsp_context* ctx, const uint32_t* bk_host, const ui
   if ((e = hipMalloc(&tmp, bk_words * 4)) != hipSuccess) return undo(hip_fail(e, "hipMalloc(bk staging)"));
   e = hipMemcpy(tmp, bk_host, bk_words * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = launch_trgsw_to_ntt(ctx, tmp, b, LWE_N, nullptr);
+  if (e == hipSuccess && mf_key) {
+    e = hipMalloc(&E, mf_key_bytes());
+    if (e == hipSuccess) e = launch_mf_key(tmp, E, nullptr);
+  }
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) return undo(hip_fail(e, "bootstrapping-key conversion"));
   (void)hipFree(tmp);
@@ -162,6 +168,7 @@ vsp_status upload_keys(const vsp_context* ctx, const uint32_t* bk_host, const ui
     return undo(hip_fail(e, "upload ksk"));
   *bkn = b;
   *ksk = k;
+  if (mf_key) *mf_key = E;
   return VSP_OK;
 }
 
@@ -206,6 +213,7 @@ vsp_status vsp_context_create(const vsp_params* params, const uint32_t* bk_host,
   VSP_HIP(hipSetDevice(device));
   VSP_HIP(init_kernel_attributes());
   VSP_HIP(init_memory_kernel_attributes());
+  VSP_HIP(init_mf_kernel_attributes());
   std::vector<u64> tw;
   if (!make_tables(tw)) return fail(VSP_E_HIP, "twiddle table construction failed");
 
@@ -226,7 +234,7 @@ vsp_status vsp_context_create(const vsp_params* params, const uint32_t* bk_host,
   if ((e = hipMemcpy(ctx->tw, tw.data(), tw.size() * 8, hipMemcpyHostToDevice)) != hipSuccess)
     return cleanup(hip_fail(e, "upload twiddles"));
   if ((e = hipMemset(ctx->dev_err, 0, 256)) != hipSuccess) return cleanup(hip_fail(e, "clear flags"));
-  if (vsp_status st = upload_keys(ctx, bk_host, ksk_host, &ctx->bkn, &ctx->ksk)) return cleanup(st);
+  if (vsp_status st = upload_keys(ctx, bk_host, ksk_host, &ctx->bkn, &ctx->ksk, &ctx->mf_key)) return cleanup(st);
   *out = ctx;
   return VSP_OK;
 }
@@ -236,8 +244,9 @@ vsp_status vsp_context_destroy(vsp_context* ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
   profile_clear(ctx);
-  for (void* p : {(void*)ctx->bkn, (void*)ctx->ksk, (void*)ctx->tw, (void*)ctx->dev_err, ctx->abar.ptr, ctx->tlwe1.ptr,
-                  ctx->ntt_sel.ptr, ctx->mem_a.ptr, ctx->mem_b.ptr, ctx->mem_c.ptr, ctx->mem_d.ptr})
+  for (void* p : {(void*)ctx->bkn, (void*)ctx->ksk, (void*)ctx->mf_key, (void*)ctx->tw, (void*)ctx->dev_err,
+                  ctx->abar.ptr, ctx->tlwe1.ptr, ctx->ntt_sel.ptr, ctx->mem_a.ptr, ctx->mem_b.ptr, ctx->mem_c.ptr,
+                  ctx->mem_d.ptr, ctx->mf_work.ptr})
     if (p) (void)hipFree(p);
   delete ctx;
   return VSP_OK;
@@ -277,6 +286,9 @@ static vsp_status gates_impl(vsp_context* ctx, const uint8_t* d_ops, const uint3
   const uint64_t chunk = (mode == VSP_BATCHED) ? std::min<uint64_t>(B, kMaxLaunch) : 1;
   if ((s = scratch_reserve(ctx, ctx->abar, chunk * (LWE_N + 1) * 4))) return s;
   if (!trlwe_out && (s = scratch_reserve(ctx, ctx->tlwe1, chunk * (RING_N + 1) * 4))) return s;
+  const bool matrix = ctx->tune.br_waves(chunk) == 32 || (B > chunk && ctx->tune.br_waves(B % chunk) == 32);
+  if (matrix && (s = scratch_reserve(ctx, ctx->mf_work, mf_work_bytes(chunk, !trlwe_out)))) return s;
+  void* mfw = matrix ? ctx->mf_work.ptr : nullptr;
   hipStream_t st = static_cast<hipStream_t>(stream);
   uint32_t* abar = static_cast<uint32_t*>(ctx->abar.ptr);
   uint32_t* t1 = static_cast<uint32_t*>(ctx->tlwe1.ptr);
@@ -296,7 +308,7 @@ static vsp_status gates_impl(vsp_context* ctx, const uint8_t* d_ops, const uint3
       if (e != hipSuccess) return hip_fail(e, "gate prologue");
       {
         ProfScope ps(ctx, 0, st);
-        e = launch_blind_rotate(ctx, ops, abar, nullptr, o, nb, 0, st);
+        e = launch_blind_rotate(ctx, ops, abar, nullptr, o, nb, 0, st, nullptr, nullptr, nullptr, mfw);
       }
       if (e != hipSuccess) return hip_fail(e, "blind rotation");
     } else {
@@ -308,7 +320,7 @@ static vsp_status gates_impl(vsp_context* ctx, const uint8_t* d_ops, const uint3
       if (e != hipSuccess) return hip_fail(e, "gate prologue");
       {
         ProfScope ps(ctx, 0, st);
-        e = launch_blind_rotate(ctx, ops, abar, t1, nullptr, nb, 0, st);
+        e = launch_blind_rotate(ctx, ops, abar, t1, nullptr, nb, 0, st, nullptr, nullptr, nullptr, mfw);
       }
       if (e != hipSuccess) return hip_fail(e, "blind rotation");
       {

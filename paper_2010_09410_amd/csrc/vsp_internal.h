@@ -30,10 +30,12 @@ __host__ __device__ inline bool op_bootstraps(uint32_t op) { return op < 8 || op
 // Device-side error flags (bits), read back by vsp_context_sync.
 constexpr int DEVERR_BAD_OP = 1;
 
-// Blind-rotation workgroup shapes: 4 or 8 gates per workgroup at one wave per gate, or 3 for
-// one gate per workgroup on three waves (the latency form).
-constexpr int kBrShapes = 3;
-constexpr int kBrWaveChoices[kBrShapes] = {4, 8, 3};
+// Blind-rotation forms: 4 or 8 gates per workgroup at one wave per gate, 3 for one gate per
+// workgroup on three waves (the latency form), and 32 for the matrix-core form (int8 MFMA
+// products over tiles of MF_TILE gates, two launches per step).
+constexpr int kBrShapes = 4;
+constexpr int kBrWaveChoices[kBrShapes] = {4, 8, 3, 32};
+constexpr int MF_TILE = 32;
 
 // Batch-size buckets: bucket b holds batches with kBucket[b-1] < B <= kBucket[b]; the last
 // one also holds every larger batch.
@@ -51,8 +53,8 @@ constexpr uint64_t kBucket[kTuneBuckets] = {1, 16, 64, 256, 1024, 2048, 4096};
 //    gates and selects in registers, 2 stages them through LDS for a tile of gates and splits
 //    the j range over workgroups.
 struct Tuning {
-  uint64_t br_cap[kBrShapes] = {1024, 2048, 512};
-  float br_round_ms[kBrShapes] = {1.0f, 1.48f, 0.8f};
+  uint64_t br_cap[kBrShapes] = {1024, 2048, 512, 4096};
+  float br_round_ms[kBrShapes] = {1.0f, 1.48f, 0.8f, 1e9f};  // the matrix-core form only once measured
   int br_force[kTuneBuckets] = {0, 0, 0, 0, 0, 0, 0};
   int ks_form[kTuneBuckets] = {2, 2, 2, 2, 2, 2, 2};
   bool tuned = false;
@@ -66,7 +68,7 @@ struct Tuning {
     if (f) return f;
     int best = 1;
     double best_ms = 0;
-    for (int s : {1, 0, 2}) {
+    for (int s : {1, 0, 2, 3}) {
       const uint64_t cap = br_cap[s] ? br_cap[s] : 1;
       const double ms = (double)((B + cap - 1) / cap) * br_round_ms[s];
       if (s == 1 || ms < best_ms) {
@@ -105,11 +107,12 @@ struct vsp_keyset {
 struct vsp_context {
   int device = 0;
   int cus = 1;                    // compute units of the device
+  int8_t* mf_key = nullptr;       // bootstrapping key as balanced-byte Toeplitz rows (matrix-core form)
   uint64_t* bkn = nullptr;        // bootstrapping key, NTT domain: [n][TRGSW_NTT_U64]
   uint32_t* ksk = nullptr;        // key-switching key [N][t][4][n+1]; digit value 0 points at a zero row
   uint64_t* tw = nullptr;         // psi_u^j [32][32] then psi_u^-j [32][32]
   int* dev_err = nullptr;         // device error flags
-  vsp::Scratch abar, tlwe1, ntt_sel, mem_a, mem_b, mem_c, mem_d;
+  vsp::Scratch abar, tlwe1, ntt_sel, mem_a, mem_b, mem_c, mem_d, mf_work;
   vsp::Tuning tune;
   vsp::Profile prof;
   std::mutex mu;                  // serialises scratch growth
@@ -133,7 +136,7 @@ vsp_status check_no_overlap(const void* a, size_t abytes, const void* b, size_t 
 // Converts host keys (BK torus [n][2l][2][N], KSK [N][t][3][n+1]) into freshly allocated device
 // buffers in the kernels' layouts; on failure nothing stays allocated.
 vsp_status upload_keys(const vsp_context* ctx, const uint32_t* bk_host, const uint32_t* ksk_host, uint64_t** bkn,
-                       uint32_t** ksk);
+                       uint32_t** ksk, int8_t** mf_key = nullptr);
 
 // Grows a scratch buffer to at least `bytes` (synchronising the device before freeing).
 vsp_status scratch_reserve(vsp_context* ctx, Scratch& s, size_t bytes);
@@ -172,10 +175,21 @@ hipError_t launch_mux_combine(uint32_t* t, uint64_t B, hipStream_t st);
 // Blind rotation of B gates (abar from the prologue). Writes SE_0 (TLWE1 [B][N+1]) and/or
 // the accumulator (TRLWE [B][2][N]). waves: a shape of kBrWaveChoices, <= 0 the tuned choice.
 // bkn: the bootstrapping key to use (NULL: the context's); with keytab non-NULL gate g uses
-// keytab[kid[g]] instead (device arrays).
+// keytab[kid[g]] instead (device arrays). The matrix-core form (waves 32) needs the context's
+// own key and a workspace of mf_work_bytes(B, trlwe == NULL) bytes in mf_work; without them
+// the 8-gate form runs instead.
 hipError_t launch_blind_rotate(const vsp_context* ctx, const uint8_t* ops, const uint32_t* abar, uint32_t* tlwe1,
                                uint32_t* trlwe, uint64_t B, int waves, hipStream_t st, const uint64_t* bkn = nullptr,
-                               const uint64_t* const* keytab = nullptr, const uint8_t* kid = nullptr);
+                               const uint64_t* const* keytab = nullptr, const uint8_t* kid = nullptr,
+                               void* mf_work = nullptr);
+// Matrix-core form (blind_rotate_mfma.hip): key bytes, workspace bytes, key conversion from
+// the torus key [n][2l][2][N] on the device, and the launch sequence.
+hipError_t init_mf_kernel_attributes();
+size_t mf_key_bytes();
+size_t mf_work_bytes(uint64_t B, bool need_acc);
+hipError_t launch_mf_key(const uint32_t* bk, int8_t* E, hipStream_t st);
+hipError_t launch_blind_rotate_mfma(const vsp_context* ctx, const uint8_t* ops, const uint32_t* abar, uint32_t* tlwe1,
+                                    uint32_t* trlwe, uint64_t B, void* work, hipStream_t st);
 // Identity key switch TLWE1 [B][N+1] -> TLWE0 [B][n+1] (outputs scattered by idxo if given).
 // form: 0 one workgroup per gate, 1 row-stationary tiles, 2 LDS-staged split, -1 the tuned one.
 constexpr int kKsForms = 3;

@@ -1,0 +1,77 @@
+"""GPU parity of the matrix-core blind rotation (int8 MFMA products of digit rows and the
+key's Toeplitz blocks, Sec. 2.1.2 external product): bit-exact against the oracle and equal
+to the NTT forms, for the 4096-gate benchmark batch, ragged tiles and TRLWE outputs."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from paper_2010_09410_amd import VspError, client
+from paper_2010_09410_amd.device import to_host
+
+pytestmark = pytest.mark.gpu
+MATRIX, NTT8 = 32, 8
+TRUTH = {0: lambda a, b: 1 - (a & b), 1: lambda a, b: a & b, 2: lambda a, b: a | b, 3: lambda a, b: 1 - (a | b),
+         4: lambda a, b: a ^ b, 5: lambda a, b: 1 - (a ^ b), 6: lambda a, b: a & (1 - b), 7: lambda a, b: a | (1 - b),
+         8: lambda a, b: 1 - a}
+
+
+def run_with(gpu, B, waves, fn):
+    saved = gpu.tuning(B)
+    try:
+        gpu.set_tuning(B, waves, saved[1])
+        assert gpu.tuning(B)[0] == waves
+        return fn()
+    finally:
+        gpu.set_tuning(B, 0, saved[1])
+
+
+def test_matrix_form_benchmark_batch(gpu, keys):
+    """The 4096-gate batch: every output decrypts to the gate result, a sample is bit-exact
+    against the oracle, and the whole batch equals the 8-gate NTT form's."""
+    cfg = W.config2()
+    in0 = client.tlwe_encrypt_bits(keys["s0"], cfg["bits0"], *cfg["enc0"])
+    in1 = client.tlwe_encrypt_bits(keys["s0"], cfg["bits1"], *cfg["enc1"])
+    d0, d1, dops = gpu.tensor(in0), gpu.tensor(in1), gpu.tensor(cfg["ops"])
+    out = run_with(gpu, 4096, MATRIX, lambda: to_host(gpu.gates(dops, d0, d1)))
+    ref8 = run_with(gpu, 4096, NTT8, lambda: to_host(gpu.gates(dops, d0, d1)))
+    np.testing.assert_array_equal(out, ref8)
+    want = np.array([TRUTH[o](a, b) for o, a, b in zip(cfg["ops"], cfg["bits0"], cfg["bits1"])])
+    np.testing.assert_array_equal(client.tlwe_decrypt(keys["s0"], out), want)
+    idx = np.array([0, 31, 32, 2047, 4064, 4095] + list(W.rng(520).integers(0, 4096, 6)))
+    np.testing.assert_array_equal(out[idx], oracle.gates(keys["bk"], keys["ksk"], cfg["ops"][idx], in0[idx], in1[idx]))
+
+
+@pytest.mark.parametrize("B", [1, 33, 95])
+def test_matrix_form_ragged_tiles_with_not(gpu, keys, B):
+    """Batches that end inside a 32-gate tile, with NOT gates (which do not bootstrap) mixed in."""
+    cfg = W.gate_batch(40 + B, B)
+    g = W.rng(530 + B)
+    cfg["ops"] = g.integers(0, 9, B).astype(np.uint8)
+    in0 = client.tlwe_encrypt_bits(keys["s0"], cfg["bits0"], *cfg["enc0"])
+    in1 = client.tlwe_encrypt_bits(keys["s0"], cfg["bits1"], *cfg["enc1"])
+    d0, d1, dops = gpu.tensor(in0), gpu.tensor(in1), gpu.tensor(cfg["ops"])
+    out = run_with(gpu, B, MATRIX, lambda: to_host(gpu.gates(dops, d0, d1)))
+    np.testing.assert_array_equal(out, oracle.gates(keys["bk"], keys["ksk"], cfg["ops"], in0, in1))
+
+
+def test_matrix_form_trlwe_output(gpu, keys):
+    """Accumulator output: bit-exact against the oracle's TRLWE for bootstrapping gates; NOT
+    gates are reported as having no TRLWE form and their rows keep what the buffer held."""
+    B = 40
+    cfg = W.gate_batch(41, B)
+    ops = W.rng(540).integers(0, 9, B).astype(np.uint8)
+    in0 = client.tlwe_encrypt_bits(keys["s0"], cfg["bits0"], *cfg["enc0"])
+    in1 = client.tlwe_encrypt_bits(keys["s0"], cfg["bits1"], *cfg["enc1"])
+    fill = W.uniform_u32(W.rng(541), (B, 2, 1024))
+    d_out = gpu.tensor(fill)
+    run_with(gpu, B, MATRIX, lambda: gpu.bootstrap_trlwe(gpu.tensor(ops), gpu.tensor(in0), gpu.tensor(in1), out=d_out))
+    out = to_host(d_out)
+    with pytest.raises(VspError, match="invalid opcode"):  # NOT has no TRLWE form: reported, row untouched
+        gpu.sync()
+    for k in range(B):
+        if ops[k] == oracle.NOT:
+            np.testing.assert_array_equal(out[k], fill[k], err_msg=f"k={k}")
+        else:
+            lin, _ = oracle.gate_linear(int(ops[k]), in0[k], in1[k])
+            np.testing.assert_array_equal(out[k], oracle.bootstrap_to_trlwe(keys["bk"], lin), err_msg=f"k={k}")

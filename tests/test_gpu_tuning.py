@@ -12,7 +12,7 @@ from paper_2010_09410_amd import VspError, client
 from paper_2010_09410_amd.device import to_host
 
 pytestmark = pytest.mark.gpu
-SHAPES = [(4, 0), (4, 1), (4, 2), (8, 0), (8, 1), (8, 2), (3, 0), (3, 2)]
+SHAPES = [(4, 0), (4, 1), (4, 2), (8, 0), (8, 1), (8, 2), (3, 0), (3, 2), (32, 2), (32, 0)]
 
 
 def batch(keys, B, seed):
@@ -26,8 +26,8 @@ def batch(keys, B, seed):
 
 @pytest.mark.parametrize("B,sample", [(37, None), (300, 12)])
 def test_every_launch_shape_bit_identical(gpu, keys, B, sample):
-    """B=37 and B=300 are ragged for 4- and 8-gate workgroups and for 16-gate key-switch tiles;
-    shape 3 runs each gate on three waves."""
+    """B=37 and B=300 are ragged for 4- and 8-gate workgroups, 16-gate key-switch tiles and
+    32-gate matrix-core tiles; shape 3 runs each gate on three waves, 32 on the matrix cores."""
     _, saved_t = gpu.tuning(B)
     cfg, in0, in1 = batch(keys, B, 31 + B)
     d0, d1, dops = gpu.tensor(in0), gpu.tensor(in1), gpu.tensor(cfg["ops"])
@@ -65,15 +65,16 @@ def test_autotune_model_and_cache_round_trip(gpu, tmp_path):
         gpu.autotune(max_batch=64, cache_path=str(path))
         (key, entry), = json.loads(path.read_text()).items()
         assert key.startswith("gfx950")
-        assert entry["br_waves"] == [4, 8, 3] and list(entry["buckets"]) == list(BUCKETS)
-        cap4, cap8, capw = entry["br_cap"]
-        assert 256 <= cap4 < cap8 and capw >= 256 and all(ms > 0 for ms in entry["br_round_ms"])
+        assert entry["br_waves"] == [4, 8, 3, 32] and list(entry["buckets"]) == list(BUCKETS)
+        cap4, cap8, capw, capm = entry["br_cap"]
+        assert 256 <= cap4 < cap8 and capw >= 256 and capm >= cap8 and all(ms > 0 for ms in entry["br_round_ms"])
         assert all(t in (0, 1, 2) for t in entry["ks_form"])
         for b, t in zip(BUCKETS, entry["ks_form"]):
             assert gpu.tuning(b)[1] == t
         # the launch follows rounds x round time; a cache entry for this GPU is read back
-        for ms, small, large in (([1.0, 100.0, 100.0], 4, 4), ([100.0, 1.0, 100.0], 8, 8),
-                                 ([1.0, 1.5, 100.0], 4, 8), ([100.0, 100.0, 1.0], 3, 3)):
+        for ms, small, large in (([1.0, 100.0, 100.0, 100.0], 4, 4), ([100.0, 1.0, 100.0, 100.0], 8, 8),
+                                 ([1.0, 1.5, 100.0, 100.0], 4, 8), ([100.0, 100.0, 1.0, 100.0], 3, 3),
+                                 ([100.0, 100.0, 100.0, 1.0], 32, 32)):
             entry["br_round_ms"] = ms
             path.write_text(json.dumps({key: entry}))
             gpu.autotune(max_batch=64, cache_path=str(path))
