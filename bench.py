@@ -10,8 +10,9 @@ Keys and inputs are synthetic (seeded) and resident in HBM before the timed regi
 Prints one JSON line (rank 0). Extra fields: the per-gate rate (one launch sequence per
 gate), the batched / per-gate ratio, per-level p50/p99 latency of the 64-level circuit, a
 serving run (Poisson arrivals of layered circuits from 64 clients: throughput and p50/p99
-circuit latency), the integer-ALU and HBM rooflines of the blind-rotation kernel and the
-CPU oracle baseline.
+circuit latency), the roofline of the dominant kernel (the matrix-core step kernel against the
+int8 MFMA peak, or the NTT blind-rotation kernel against the integer-ALU peak, whichever form
+the autotuner picks for the batch) with the HBM side, and the CPU oracle baseline.
 """
 from __future__ import annotations
 
@@ -83,18 +84,46 @@ def br_hbm_bytes(B: int) -> int:
     return BK_NTT_BYTES + B * (1 + (N_LWE + 1) * 4 + (N_RING + 1) * 4)
 
 
-def br_fingerprint() -> str:
+# ---------------------------------------------------------------- matrix-core form
+# One step kernel launch computes, per tile of 32 gates and output polynomial, the three
+# half-size Toeplitz products of one Karatsuba level (P1, P2, P3: 3 x 512 x 512 multiply-adds)
+# for the 6 TRGSW rows and the 4 byte planes of the key, as int8 MFMA (2 ops per multiply-add).
+MF_TILE = 32
+MF_OPS_PER_TILE = 2 * MF_TILE * 2 * 3 * (N_RING // 2) ** 2 * 2 * GL * 4
+MF_A_TILE_BYTES = 2 * GL * 3 * (N_RING // 2) * MF_TILE      # digit operands of a tile (int8)
+MF_KEY_STEP_BYTES = 2 * GL * 2 * 4 * 3 * N_RING             # three key sequences per row, output, plane
+PEAK_INT8 = 5.0e15                                          # dense int8 MFMA, ops/s
+
+
+def mf_step_ops(B: int) -> int:
+    return (B + MF_TILE - 1) // MF_TILE * MF_OPS_PER_TILE
+
+
+def mf_step_hbm_bytes(B: int) -> int:
+    """Algorithmic HBM bytes of one step kernel launch: the digit operands and the step's key
+    read once, the accumulators read and written."""
+    return (B + MF_TILE - 1) // MF_TILE * MF_A_TILE_BYTES + MF_KEY_STEP_BYTES + B * 2 * N_RING * 4 * 2
+
+
+def src_fingerprint(files) -> str:
     h = hashlib.sha256()
-    for f in ("gl64.h", "ntt.h", "blind_rotate.h"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_2010_09410_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per blind-rotation launch from a committed rocprofv3 summary of this exact
-    kernel source (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), else None."""
-    fp = br_fingerprint()
+def br_fingerprint() -> str:
+    return src_fingerprint(("gl64.h", "ntt.h", "blind_rotate.h"))
+
+
+def mf_fingerprint() -> str:
+    return src_fingerprint(("gl64.h", "ntt.h", "vsp_internal.h", "blind_rotate_mfma.hip"))
+
+
+def measured_traffic(fp: str):
+    """HBM bytes per launch of the kernel whose sources have fingerprint fp, from a committed
+    rocprofv3 summary (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), else None."""
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.txt"))):
         fields = {}
         with open(path) as fh:
@@ -333,6 +362,7 @@ def main():
     dt = time.perf_counter() - t0
     br_ms, br_n = nv.vsp_profile_read(ctx.handle, 0)
     ks_ms, ks_n = nv.vsp_profile_read(ctx.handle, 1)
+    step_ms, step_n = nv.vsp_profile_read(ctx.handle, 3)
     nv.vsp_profile_enable(ctx.handle, False)
     ctx.sync()
     ms_per_step = dt * 1e3 / args.steps
@@ -402,19 +432,36 @@ def main():
         serving = dict(config=serving, light=light, light_4_key_sets=keyed)
 
     br_avg_ms = br_ms / max(br_n, 1)
-    achieved = B_GATES * LANE_OPS_PER_GATE / (br_avg_ms * 1e-3) / 1e12
-    traffic, traffic_src = measured_traffic()
-    hbm = br_hbm_bytes(B_GATES) / (br_avg_ms * 1e-3)
-    roof = {"bound": "alu", "kernel": f"k_blind_rotate<{br_waves}>", "achieved": round(achieved, 3),
-            "peak": round(PEAK_LANE_OPS / 1e12, 3), "unit": "T int32 lane-ops/s",
-            "frac": round(achieved * 1e12 / PEAK_LANE_OPS, 4), "traffic": traffic, "traffic_source": traffic_src,
-            "avg_launch_ms": round(br_avg_ms, 3), "lane_ops_per_gate": LANE_OPS_PER_GATE,
-            "hbm": {"achieved": round(hbm / 1e9, 1), "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                    "frac": round(hbm / HBM_PEAK, 4), "algorithmic_bytes_per_launch": br_hbm_bytes(B_GATES),
-                    "measured_GBps": None if traffic is None else round(traffic / (br_avg_ms * 1e-3) / 1e9, 1)},
-            "key_stream_GBps_requested": round(B_GATES * BK_NTT_BYTES / (br_avg_ms * 1e-3) / 1e9, 1),
-            "keyswitch_avg_ms": round(ks_ms / max(ks_n, 1), 3),
-            "launch": {"br_shape": br_waves, "keyswitch": ["gather", "tiled", "split"][ks_form], "autotune": tune}}
+    launch = {"br_shape": br_waves, "keyswitch": ["gather", "tiled", "split"][ks_form], "autotune": tune}
+    if br_waves == 32:
+        # matrix-core form: the dominant kernel is the step kernel (630 launches per batch)
+        mf_ms, mf_n = step_ms, step_n
+        mf_avg = mf_ms / max(mf_n, 1)
+        achieved = mf_step_ops(B_GATES) / (mf_avg * 1e-3)
+        traffic, traffic_src = measured_traffic(mf_fingerprint())
+        hbm = mf_step_hbm_bytes(B_GATES) / (mf_avg * 1e-3)
+        roof = {"bound": "mfma", "kernel": "k_mf_step", "achieved": round(achieved / 1e12, 1),
+                "peak": PEAK_INT8 / 1e12, "unit": "TOP/s (int8)", "frac": round(achieved / PEAK_INT8, 4),
+                "traffic": traffic, "traffic_source": traffic_src, "avg_launch_ms": round(mf_avg, 4),
+                "launches_per_batch": mf_n // max(args.steps, 1), "int8_ops_per_launch": mf_step_ops(B_GATES),
+                "hbm": {"achieved": round(hbm / 1e9, 1), "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                        "frac": round(hbm / HBM_PEAK, 4), "algorithmic_bytes_per_launch": mf_step_hbm_bytes(B_GATES),
+                        "measured_GBps": None if traffic is None else round(traffic / (mf_avg * 1e-3) / 1e9, 1)},
+                "blind_rotation_avg_ms": round(br_avg_ms, 3),
+                "keyswitch_avg_ms": round(ks_ms / max(ks_n, 1), 3), "launch": launch}
+    else:
+        achieved = B_GATES * LANE_OPS_PER_GATE / (br_avg_ms * 1e-3) / 1e12
+        traffic, traffic_src = measured_traffic(br_fingerprint())
+        hbm = br_hbm_bytes(B_GATES) / (br_avg_ms * 1e-3)
+        roof = {"bound": "alu", "kernel": f"k_blind_rotate<{br_waves}>", "achieved": round(achieved, 3),
+                "peak": round(PEAK_LANE_OPS / 1e12, 3), "unit": "T int32 lane-ops/s",
+                "frac": round(achieved * 1e12 / PEAK_LANE_OPS, 4), "traffic": traffic, "traffic_source": traffic_src,
+                "avg_launch_ms": round(br_avg_ms, 3), "lane_ops_per_gate": LANE_OPS_PER_GATE,
+                "hbm": {"achieved": round(hbm / 1e9, 1), "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                        "frac": round(hbm / HBM_PEAK, 4), "algorithmic_bytes_per_launch": br_hbm_bytes(B_GATES),
+                        "measured_GBps": None if traffic is None else round(traffic / (br_avg_ms * 1e-3) / 1e9, 1)},
+                "key_stream_GBps_requested": round(B_GATES * BK_NTT_BYTES / (br_avg_ms * 1e-3) / 1e9, 1),
+                "keyswitch_avg_ms": round(ks_ms / max(ks_n, 1), 3), "launch": launch}
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(s0, s1, bkd, kskd, cfg, in0, in1, args.cpu_gates)
@@ -424,7 +471,7 @@ def main():
         "metric": "gate bootstraps/sec on 1 MI355X, batched vs per-gate; p50/p99 per-level latency",
         "value": round(value, 1), "unit": "gate bootstraps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": "int8" if br_waves == 32 else "u64", "data": "synthetic",
         "config": {"workload": "4096 independent random gates (NAND/AND/OR/XOR/XNOR) on fresh TLWE, "
                                "n=630 N=1024 l=3 Bg=64 ks t=8 base=4, one batched launch",
                    "batch": B_GATES, "parallelism": "single GPU"},

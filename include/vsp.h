@@ -258,11 +258,13 @@ vsp_status vsp_tuning_set(vsp_context* ctx, uint64_t B, int br_waves, int ks_for
 
 /* Kernel-time instrumentation (for benchmarks): while enabled, every eager launch of the
  * blind-rotation, key-switch and gate-prologue kernels made by this context is bracketed by
- * HIP events on the stream it runs on. Enabling resets the totals. */
+ * HIP events on the stream it runs on (for the matrix-core form, also each of its step
+ * kernels). Enabling resets the totals. */
 vsp_status vsp_profile_enable(vsp_context* ctx, int on);
 
 /* Device time (ms, summed) and number of launches of kernel `which` since enabling:
- * 0 = blind rotation, 1 = key switch, 2 = gate prologue. Synchronises the device. */
+ * 0 = blind rotation, 1 = key switch, 2 = gate prologue, 3 = step kernel of the matrix-core
+ * blind rotation (one per CMUX step). Synchronises the device. */
 vsp_status vsp_profile_read(vsp_context* ctx, int which, double* total_ms, uint64_t* launches);
 
 /* Test entry: d_out[j] = C_j (ext) x_j for J (TRGSW, TRLWE) pairs, the external product

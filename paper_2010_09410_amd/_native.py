@@ -270,7 +270,8 @@ def vsp_profile_enable(ctx, on: bool) -> None:
 
 
 def vsp_profile_read(ctx, which: int):
-    """(total_ms, launches) of kernel class which: 0 blind rotation, 1 key switch, 2 prologue."""
+    """(total_ms, launches) of kernel class which: 0 blind rotation, 1 key switch, 2 prologue,
+    3 step kernel of the matrix-core blind rotation."""
     ms = ctypes.c_double()
     cnt = _u64()
     _call("vsp_profile_read", ctx, which, ctypes.byref(ms), ctypes.byref(cnt))

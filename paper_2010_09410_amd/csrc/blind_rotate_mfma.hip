@@ -4,23 +4,30 @@
 // without a transform).
 //
 // For one TRGSW row r (gadget level k of ACC polynomial h, r = 3h + k) and output polynomial
-// o, the product of the digit polynomial d with the key polynomial K in Z[X]/(X^N + 1) is
-//   out[i] = sum_j d[j] Kt[i - j],   Kt[t] = K[t] (t >= 0), -K[t + N] (t < 0),
-// a Toeplitz matrix-vector product. Over a batch of gates the digits form the rows of A
-// (gates x (6 rows x N)), the key's Toeplitz blocks form B ((6 x N) x (2 x N)), and
-// ACC += A B (mod 2^32) is one step. Exactness: the digits are in [-32, 31] and every key word
-// is split into four balanced signed bytes Kt = sum_b 2^{8b} c_b (c_b in [-128, 127], mod
-// 2^32); per byte plane the int32 sums are below 6 x 1024 x 32 x 128 < 2^25, and the planes
-// are folded by Horner's rule in the accumulators (plane 3 first, shift by 8 bits between
-// planes), the int32 wrap-around of the matrix cores being arithmetic mod 2^32.
+// o, the product of the digit polynomial x with the key polynomial K in Z[X]/(X^N + 1) is
+//   y[i] = sum_j x[j] Kt[i - j],   Kt[t] = K[t] (t >= 0), -K[t + N] (t < 0),
+// a Toeplitz matrix-vector product y = T x. With T split into blocks of N/2 (T11 = T00 for a
+// Toeplitz matrix) and x = (x0, x1), one level of the Karatsuba split needs three products of
+// size N/2 instead of four:
+//   P1 = T00 (x0 + x1),  P2 = (T01 - T00) x1,  P3 = (T10 - T00) x0,
+//   y0 = P1 + P2,        y1 = P1 + P3,
+// each again Toeplitz, with the sequences S1[t] = Kt[t], S2[t] = Kt[t - N/2] - Kt[t],
+// S3[t] = Kt[t + N/2] - Kt[t] for t in (-N/2, N/2). Over a batch the operands (x0 + x1, x1,
+// x0) of all gates form the rows of A, and the three Toeplitz blocks per (row, output) form
+// a block-diagonal B: 3/4 of the multiply-adds of the plain product.
+// Exactness: digits are in [-32, 31], so x0 + x1 is in [-64, 62]; key words are split into
+// four balanced signed bytes Kt = sum_b 2^{8b} c_b (c_b in [-128, 127], mod 2^32); per byte
+// plane the int32 sums are below 6 x 512 x 64 x 128 < 2^25, and the planes are folded by
+// Horner's rule in the accumulators (plane 3 first, shift by 8 bits between planes), the
+// int32 wrap-around of the matrix cores being arithmetic mod 2^32.
 //
 // A step is two launches: k_mf_digits writes A for the step (bytes in the lane order of the
-// MFMA operands), then k_mf_step computes the product for one tile of 32 gates and one output
-// polynomial per workgroup and adds it to ACC. The B operand is never stored as a matrix: a
-// 32 x 32 tile of a Toeplitz block depends only on its diagonal offset, so a lane reads its
-// sixteen bytes straight from the extended key row Kt (staged in LDS), and moving to the next
-// 32 input coefficients turns the tile of output block nb into that of block nb - 1, which
-// the wave already holds: one new B operand per four matrix instructions.
+// MFMA operands), then k_mf_step computes, for one tile of 32 gates and one output
+// polynomial per workgroup, P1, P2 and P3, combines them and adds y to ACC. B is never stored
+// as a matrix: a 32 x 32 tile of a Toeplitz block depends only on its diagonal offset, so a
+// lane reads its sixteen bytes straight from the sequence (staged in LDS), and moving to the
+// next 32 input coefficients turns the tile of output block nb into that of block nb - 1,
+// which the wave already holds: one new B operand per four matrix instructions.
 #include "vsp_internal.h"
 
 namespace vsp {
@@ -28,34 +35,51 @@ namespace vsp {
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
-constexpr int MF_ROWS = 2 * GADGET_L;  // TRGSW rows
-constexpr int MF_PLANES = 4;           // balanced bytes of a torus word
-constexpr int MF_E = 2 * RING_N;       // extended row Kt[t - N], t in [0, 2N)
-constexpr int MF_KB = RING_N / 32;     // 32-coefficient blocks of an input polynomial
+constexpr int MF_ROWS = 2 * GADGET_L;   // TRGSW rows
+constexpr int MF_PLANES = 4;            // balanced bytes of a torus word
+constexpr int MF_HALF = RING_N / 2;     // size of the three sub-products
+constexpr int MF_SUB = 3;               // sub-products P1, P2, P3
+constexpr int MF_S = RING_N;            // sequence S_s[t - N/2], t in [0, N) (t = 0 unused)
+constexpr int MF_KB = MF_HALF / 32;     // 32-coefficient blocks of a sub-product's input
 
-// Digit-operand bytes of one tile of MF_TILE gates: [row r][block kb][lane][16].
-constexpr size_t MF_A_TILE = (size_t)MF_TILE * MF_ROWS * RING_N;
+// Digit-operand bytes of one tile of MF_TILE gates: [row r][segment s][block kb][lane][16],
+// segment 0 holding x0 + x1, 1 x1, 2 x0 (the inputs of P1, P2, P3).
+constexpr size_t MF_A_ROW = (size_t)MF_SUB * MF_KB * 64 * 16;
+constexpr size_t MF_A_TILE = (size_t)MF_ROWS * MF_A_ROW;
 
-// Key bytes per step: [row r][output o][plane b][t].
-constexpr size_t MF_KEY_STEP = (size_t)MF_ROWS * 2 * MF_PLANES * MF_E;
+// Key bytes per step: [row r][output o][plane b][sub-product s][t].
+constexpr size_t MF_KEY_STEP = (size_t)MF_ROWS * 2 * MF_PLANES * MF_SUB * MF_S;
 
-// Extended key rows in balanced bytes: E[i][r][o][b][t] = byte b of Kt_{i,r,o}[t - N]
-// (Kt[-N] = 0), from the torus key bk [n][2l][2][N].
+// The three sequences of every (step, row, output) in balanced bytes, from the torus key
+// bk [n][2l][2][N]: E[i][r][o][b][s][t] = byte b of S_s[t - N/2].
+__device__ __forceinline__ u32 kt_word(const u32* K, int t) {  // Kt[t], t in (-N, N)
+  return t >= 0 ? K[t] : 0u - K[t + RING_N];
+}
+
 __global__ __launch_bounds__(256) void k_mf_key(const u32* __restrict__ bk, int8_t* __restrict__ E, uint64_t rows) {
   const uint64_t id = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-  if (id >= rows * MF_E) return;
-  const uint64_t row = id / MF_E;  // (i * 6 + r) * 2 + o
-  const int t = (int)(id - row * MF_E);
-  const int tau = t - RING_N;
-  u32 v = 0;
-  if (tau >= 0) v = bk[row * RING_N + tau];
-  else if (tau > -RING_N) v = 0u - bk[row * RING_N + tau + RING_N];
-  int8_t* out = E + row * MF_PLANES * MF_E + t;
+  if (id >= rows * MF_S) return;
+  const uint64_t row = id / MF_S;  // (i * 6 + r) * 2 + o
+  const int t = (int)(id - row * MF_S);
+  const int tau = t - MF_HALF;
+  const u32* K = bk + row * RING_N;
+  u32 v[MF_SUB] = {0u, 0u, 0u};
+  if (t > 0) {
+    const u32 k0 = kt_word(K, tau);
+    v[0] = k0;
+    v[1] = kt_word(K, tau - MF_HALF) - k0;
+    v[2] = kt_word(K, tau + MF_HALF) - k0;
+  }
+  int8_t* out = E + row * MF_PLANES * MF_SUB * MF_S + t;
 #pragma unroll
-  for (int b = 0; b < MF_PLANES; b++) {
-    const int8_t c = (int8_t)(v & 255u);  // v = c (mod 256), c in [-128, 127]
-    out[b * MF_E] = c;
-    v = (v - (u32)(int32_t)c) >> 8;
+  for (int s = 0; s < MF_SUB; s++) {
+    u32 w = v[s];
+#pragma unroll
+    for (int b = 0; b < MF_PLANES; b++) {
+      const int8_t c = (int8_t)(w & 255u);  // w = c (mod 256), c in [-128, 127]
+      out[((size_t)b * MF_SUB + s) * MF_S] = c;
+      w = (w - (u32)(int32_t)c) >> 8;
+    }
   }
 }
 
@@ -73,168 +97,190 @@ __global__ __launch_bounds__(256) void k_mf_init(const uint8_t* __restrict__ ops
 }
 
 // Digits of step i: for gate g, row r = 3h + k and coefficient j, digit k + 1 of
-// (X^{abar_i} ACC_h - ACC_h)[j], written as the A operand of the step's products. Byte q of
-// lane (m, kh) of block kb holds coefficient j = 32 kb + 16 kh + 15 - q of gate 32 mt + m
-// (the order that makes the B bytes of a lane ascend in the key row). Gates at or above B and
-// gates that do not bootstrap get zero digits.
-// Workgroup (mt, h, eighth e of the gates): for each of its 8 gates, thread t takes
-// coefficients 4t .. 4t + 3 (coalesced reads of ACC and of its rotation), and the bytes are
-// gathered in LDS in operand order, then written out as 128-byte runs.
+// x = (X^{abar_i} ACC_h - ACC_h), written as the A operand of the step's products: segment
+// 1 holds x1 = x[N/2 ..], segment 2 x0 = x[.. N/2], segment 0 their sum. In a segment, byte
+// q of lane (m, kh) of block kb holds local coefficient j = 32 kb + 16 kh + 15 - q of gate
+// 32 mt + m (the order that makes the B bytes of a lane ascend in the key sequence). Gates
+// at or above B and gates that do not bootstrap get zero digits.
+// Workgroup (mt, h, eighth e of the gates): thread t takes local coefficients 4 jg .. 4 jg + 3
+// (jg = t mod 128) of both halves for gates t / 128, t / 128 + 2, ... (coalesced reads of ACC
+// and of its rotation); the bytes are gathered in LDS in operand order, then written out as
+// 128-byte runs.
 constexpr int MF_DG = 8;  // gates per digit workgroup
 
 __global__ __launch_bounds__(256) void k_mf_digits(const uint8_t* __restrict__ ops, const u32* __restrict__ abar,
                                                     const u32* __restrict__ acc, int8_t* __restrict__ A, uint64_t B,
                                                     int step) {
-  __shared__ u32 sA[GADGET_L][MF_KB][2 * MF_DG][4];
+  __shared__ u32 sA[GADGET_L][MF_SUB][MF_KB][2 * MF_DG][4];
   const uint64_t mt = blockIdx.x;
   const int h = blockIdx.y, e = blockIdx.z, t = threadIdx.x;
-  const int kb = t >> 3, kh = (t >> 2) & 1, dw = 3 - (t & 3);
-  // all loads of the workgroup's gates first (their latencies overlap), then the digits
-  bool live[MF_DG];
-  int a[MF_DG];
-  uint4 own[MF_DG];
-  u32 rot[MF_DG][4];
+  const int jg = t & 127, kb = jg >> 3, kh = (jg >> 2) & 1, dw = 3 - (jg & 3);
+  constexpr int ROUNDS = MF_DG / 2;
+  // all loads first (their latencies overlap), then the digits
+  bool live[ROUNDS];
+  uint4 own[ROUNDS][2];
+  u32 rot[ROUNDS][2][4];
 #pragma unroll
-  for (int mm = 0; mm < MF_DG; mm++) {
+  for (int q = 0; q < ROUNDS; q++) {
+    const int mm = 2 * q + (t >> 7);
     const uint64_t g = mt * MF_TILE + (uint64_t)e * MF_DG + mm;
-    live[mm] = g < B && (!ops || op_bootstraps(ops[g]));
-    a[mm] = live[mm] ? (int)abar[g * TLWE0 + step] : 0;
-  }
-#pragma unroll
-  for (int mm = 0; mm < MF_DG; mm++) {
-    const uint64_t g = mt * MF_TILE + (uint64_t)e * MF_DG + mm;
+    live[q] = g < B && (!ops || op_bootstraps(ops[g]));
+    const int a = live[q] ? (int)abar[g * TLWE0 + step] : 0;
     const u32* p = acc + (g * 2 + h) * RING_N;
-    own[mm] = live[mm] ? reinterpret_cast<const uint4*>(p)[t] : make_uint4(0u, 0u, 0u, 0u);
 #pragma unroll
-    for (int s = 0; s < 4; s++) {
-      const int idx = (4 * t + 3 - s - a[mm]) & (2 * RING_N - 1);
-      const u32 r = live[mm] ? p[idx & (RING_N - 1)] : 0u;
-      rot[mm][s] = (idx & RING_N) ? 0u - r : r;
+    for (int half = 0; half < 2; half++) {
+      own[q][half] = live[q] ? reinterpret_cast<const uint4*>(p)[half * (MF_HALF / 4) + jg] : make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+      for (int s = 0; s < 4; s++) {
+        const int idx = (half * MF_HALF + 4 * jg + 3 - s - a) & (2 * RING_N - 1);
+        const u32 r = live[q] ? p[idx & (RING_N - 1)] : 0u;
+        rot[q][half][s] = (idx & RING_N) ? 0u - r : r;
+      }
     }
   }
 #pragma unroll
-  for (int mm = 0; mm < MF_DG; mm++) {
-    u32 w[GADGET_L] = {0u, 0u, 0u};
-    if (live[mm]) {
-      const u32 ov[4] = {own[mm].x, own[mm].y, own[mm].z, own[mm].w};
+  for (int q = 0; q < ROUNDS; q++) {
+    const int mm = 2 * q + (t >> 7);
+    u32 w[GADGET_L][MF_SUB] = {};
+    if (live[q]) {
+      const u32 ov0[4] = {own[q][0].x, own[q][0].y, own[q][0].z, own[q][0].w};
+      const u32 ov1[4] = {own[q][1].x, own[q][1].y, own[q][1].z, own[q][1].w};
 #pragma unroll
-      for (int s = 0; s < 4; s++) {  // byte s of the lane's dword: coefficient 4t + 3 - s
-        const u32 x = (rot[mm][s] - ov[3 - s]) + DECOMP_OFFSET;
+      for (int s = 0; s < 4; s++) {  // byte s of the lane's dword: local coefficient 4 jg + 3 - s
+        const u32 x0 = (rot[q][0][s] - ov0[3 - s]) + DECOMP_OFFSET;
+        const u32 x1 = (rot[q][1][s] - ov1[3 - s]) + DECOMP_OFFSET;
 #pragma unroll
-        for (int k = 0; k < GADGET_L; k++)
-          w[k] |= ((((x >> (32 - BG_BIT * (k + 1))) & 63u) - 32u) & 255u) << (8 * s);
+        for (int k = 0; k < GADGET_L; k++) {
+          const int sh = 32 - BG_BIT * (k + 1);
+          const u32 d0 = ((x0 >> sh) & 63u) - 32u, d1 = ((x1 >> sh) & 63u) - 32u;
+          w[k][0] |= ((d0 + d1) & 255u) << (8 * s);
+          w[k][1] |= (d1 & 255u) << (8 * s);
+          w[k][2] |= (d0 & 255u) << (8 * s);
+        }
       }
     }
 #pragma unroll
-    for (int k = 0; k < GADGET_L; k++) sA[k][kb][mm + MF_DG * kh][dw] = w[k];
+    for (int k = 0; k < GADGET_L; k++)
+#pragma unroll
+      for (int sg = 0; sg < MF_SUB; sg++) sA[k][sg][kb][mm + MF_DG * kh][dw] = w[k][sg];
   }
   __syncthreads();
-  // out: rows 3h .. 3h + 2, blocks kb, lanes e*8 + (0..7) and 32 + e*8 + (0..7)
-  const uint4* src = reinterpret_cast<const uint4*>(&sA[0][0][0][0]);
-  uint4* dst = reinterpret_cast<uint4*>(A + mt * MF_A_TILE) + (size_t)GADGET_L * h * MF_KB * 64;
-  for (int c = t; c < GADGET_L * MF_KB * 2 * MF_DG; c += 256) {
-    const int ll = c % (2 * MF_DG), rk = c / (2 * MF_DG);  // rk = k * MF_KB + kb
+  // out: rows 3h .. 3h + 2, every segment and block, lanes e*8 + (0..7) and 32 + e*8 + (0..7)
+  const uint4* src = reinterpret_cast<const uint4*>(&sA[0][0][0][0][0]);
+  uint4* dst = reinterpret_cast<uint4*>(A + mt * MF_A_TILE + (size_t)GADGET_L * h * MF_A_ROW);
+  for (int c = t; c < GADGET_L * MF_SUB * MF_KB * 2 * MF_DG; c += 256) {
+    const int ll = c % (2 * MF_DG), rk = c / (2 * MF_DG);  // rk = (k * 3 + segment) * MF_KB + kb
     const int lane = (ll % MF_DG) + MF_DG * e + 32 * (ll / MF_DG);
     dst[(size_t)rk * 64 + lane] = src[c];
   }
 }
 
-// ACC[g][o] += (A B)[g][o] for the 32 gates of tile blockIdx.x and output polynomial
-// o = blockIdx.y. Eight waves; wave w owns output coefficients [128 w, 128 w + 128) as four
-// 32 x 32 blocks nb. Lane (n, kh) of the B operand of block nb at input block kb holds
-// Kt[i - j] for i = 128 w + 32 nb + n and j = 32 kb + 16 kh + 15 - q, q = 0..15: the bytes
-// E[t0 + q] with t0 = N + 128 w + 32 (nb - kb) + n - 16 kh - 15, in [1, 2032].
-// The key row sits in LDS in sixteen copies, copy c shifted down by c bytes, so that the
-// sixteen bytes from t0 are one aligned 16-byte read of copy t0 mod 16 (the same copy for a
-// lane at every block kb, as t0 moves by 32).
-// The 24 passes (plane b from 3 down, row r) each stage the tile's 32 KB of row-r digits and
-// the copies of key row (r, o, b); the next pass's data is loaded into registers while the
-// current pass computes, and stored to the other buffer after it. Within a pass, the LDS
-// reads of block kb + 2 are issued before the four products of block kb; the B operands live
-// in a ring of eight registers (block nb at kb in slot (nb - kb) mod 8), so the Toeplitz shift
-// costs no moves.
-constexpr int MF_A_PASS_U4 = MF_KB * 64;               // 16-byte operands per row and tile
+// ACC[g][o] += y for the 32 gates of tile blockIdx.x and output polynomial o = blockIdx.y.
+// Twelve waves: wave w computes sub-product s = w / 4 for local outputs
+// [128 (w mod 4), 128 (w mod 4) + 128) as four 32 x 32 blocks nb. Lane (n, kh) of the B
+// operand of block nb at input block kb holds S_s[i - j] for i = 128 (w mod 4) + 32 nb + n and
+// j = 32 kb + 16 kh + 15 - q, q = 0..15: the bytes E_s[t0 + q] with
+// t0 = N/2 + 128 (w mod 4) + 32 (nb - kb) + n - 16 kh - 15, in [1, 1008].
+// Each sequence sits in LDS in four copies, copy c shifted down by c bytes, so that the
+// sixteen bytes from t0 are four aligned words of copy t0 mod 4 (the same copy for a lane at
+// every block kb, as t0 moves by 32).
+// The 24 passes (plane b from 3 down, row r) each stage the tile's 48 KB of row-r operands and
+// the copies of the three sequences (r, o, b); the next pass's data is loaded into registers
+// while the current pass computes, and stored to the other buffer after it. Within a pass the
+// LDS reads of block kb + 2 are issued before the four products of block kb; the B operands
+// live in a ring of eight registers (block nb at kb in slot (nb - kb) mod 8), so the Toeplitz
+// shift costs no moves. At the end P1 goes through LDS to the waves of P2 and P3, which add
+// y0 = P1 + P2 and y1 = P1 + P3 to ACC.
+constexpr int MF_WAVES = 12;
+constexpr int MF_THREADS = MF_WAVES * 64;
+constexpr int MF_A_PASS_U4 = (int)(MF_A_ROW / 16);      // 3072 16-byte operands per row and tile
 constexpr int MF_PASSES = MF_PLANES * MF_ROWS;
-constexpr int MF_COPY_U4 = MF_E / 16 + 1;               // one shifted copy and a 16-byte tail
-constexpr int MF_ECOPIES_U4 = 16 * MF_COPY_U4;
-constexpr size_t MF_STEP_LDS = 2 * (size_t)(MF_A_PASS_U4 + MF_ECOPIES_U4) * 16;
+constexpr int MF_COPY_U32 = MF_S / 4 + 4;                // one shifted copy and a 16-byte tail
+constexpr int MF_ECOPIES_U32 = MF_SUB * 4 * MF_COPY_U32;
+constexpr size_t MF_STEP_LDS = 2 * ((size_t)MF_A_PASS_U4 * 16 + (size_t)MF_ECOPIES_U32 * 4);
+static_assert(MF_A_PASS_U4 == 4 * MF_THREADS && MF_SUB * MF_S / 4 == MF_THREADS,
+              "four 16-byte operands and one key word per thread and pass");
+static_assert((size_t)4 * 4 * 16 * 64 * 4 <= 2 * (size_t)MF_A_PASS_U4 * 16, "P1 fits in the operand buffers");
 
-__global__ __launch_bounds__(512) void k_mf_step(const int8_t* __restrict__ Ek, const int8_t* __restrict__ A,
-                                                  u32* __restrict__ acc, const uint8_t* __restrict__ ops,
-                                                  uint64_t B) {
+__global__ __launch_bounds__(MF_THREADS) void k_mf_step(const int8_t* __restrict__ Ek, const int8_t* __restrict__ A,
+                                                         u32* __restrict__ acc, const uint8_t* __restrict__ ops,
+                                                         uint64_t B) {
   extern __shared__ uint4 mf_lds[];
-  uint4* abuf = mf_lds;                            // [2][MF_A_PASS_U4]
-  uint4* ebuf = mf_lds + 2 * MF_A_PASS_U4;         // [2][16 copies][MF_COPY_U4]
+  uint4* abuf = mf_lds;                                            // [2][MF_A_PASS_U4]
+  u32* ebuf = reinterpret_cast<u32*>(mf_lds + 2 * MF_A_PASS_U4);  // [2][3 sequences][4 copies][MF_COPY_U32]
   const uint64_t mt = blockIdx.x;
   const int o = blockIdx.y;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, n = lane & 31, kh = lane >> 5;
-  const int tb = RING_N + 128 * wave + n - 16 * kh - 15;
-  const int cp = tb & 15;                          // this lane's key copy
-  const int bofs = cp * MF_COPY_U4 + ((tb - cp) >> 4) - 2 * (MF_KB - 1);  // block kb, nb: + 2 (MF_KB - 1 - kb + nb)
+  const int sub = wave >> 2, wl = wave & 3;
+  const int tb = MF_HALF + 128 * wl + n - 16 * kh - 15;
+  const int cp = tb & 3;                                           // this lane's key copy
+  // word offset of block kb, nb: + 8 (MF_KB - 1 - kb + nb)
+  const int bofs = (sub * 4 + cp) * MF_COPY_U32 + ((tb - cp) >> 2) - 8 * (MF_KB - 1);
   const uint4* Ag = reinterpret_cast<const uint4*>(A + mt * MF_A_TILE);
   const u32* Eu = reinterpret_cast<const u32*>(Ek);
-  // pass p: plane b = 3 - p / 6, row r = p % 6; thread t stages dword t of every copy, which
-  // needs dwords t .. t + 4 of the row (zero past its end)
+  // pass p: plane b = 3 - p / 6, row r = p % 6. Thread t stages word t mod 256 of the copies of
+  // sequence t / 256, which needs words t mod 256 and the next one (zero past the end).
+  const int es = tid >> 8, ew = tid & 255;
   auto e_row = [&](int pass) {
-    return Eu + (((size_t)(pass % MF_ROWS) * 2 + o) * MF_PLANES + (MF_PLANES - 1 - pass / MF_ROWS)) * (MF_E / 4);
+    return Eu + ((((size_t)(pass % MF_ROWS) * 2 + o) * MF_PLANES + (MF_PLANES - 1 - pass / MF_ROWS)) * MF_SUB + es) *
+                    (MF_S / 4);
   };
-  auto stage_e = [&](uint4* dst, const u32 (&d)[5]) {
-    u32* dw = reinterpret_cast<u32*>(dst);
+  auto stage_e = [&](u32* dst, u32 d0, u32 d1) {
 #pragma unroll
-    for (int c = 0; c < 16; c++)
-      dw[c * MF_COPY_U4 * 4 + tid] = __builtin_amdgcn_alignbyte(d[(c >> 2) + 1], d[c >> 2], c & 3);
+    for (int c = 0; c < 4; c++) dst[(es * 4 + c) * MF_COPY_U32 + ew] = __builtin_amdgcn_alignbyte(d1, d0, c);
   };
-  if (tid < 32) {  // the tails of the copies of both buffers
-    ebuf[(tid >> 4) * MF_ECOPIES_U4 + (tid & 15) * MF_COPY_U4 + MF_E / 16] = make_uint4(0u, 0u, 0u, 0u);
+  if (tid < 2 * MF_SUB * 4 * 4) {  // the tails of all copies of both buffers
+    const int bufi = tid / (MF_SUB * 16), rest = tid % (MF_SUB * 16);
+    ebuf[bufi * MF_ECOPIES_U32 + (rest >> 2) * MF_COPY_U32 + MF_S / 4 + (rest & 3)] = 0u;
   }
   {
     const uint4* as = Ag + tid;
-    const uint4 x0 = as[0], x1 = as[512], x2 = as[1024], x3 = as[1536];
+    const uint4 x0 = as[0], x1 = as[MF_THREADS], x2 = as[2 * MF_THREADS], x3 = as[3 * MF_THREADS];
     const u32* er = e_row(0);
-    u32 d[5];
-#pragma unroll
-    for (int q = 0; q < 5; q++) d[q] = (tid + q < MF_E / 4) ? er[tid + q] : 0u;
+    const u32 d0 = er[ew], d1 = (ew + 1 < MF_S / 4) ? er[ew + 1] : 0u;
     abuf[tid] = x0;
-    abuf[tid + 512] = x1;
-    abuf[tid + 1024] = x2;
-    abuf[tid + 1536] = x3;
-    stage_e(ebuf, d);
+    abuf[tid + MF_THREADS] = x1;
+    abuf[tid + 2 * MF_THREADS] = x2;
+    abuf[tid + 3 * MF_THREADS] = x3;
+    stage_e(ebuf, d0, d1);
   }
   __syncthreads();
-  static_assert(MF_A_PASS_U4 == 4 * 512 && MF_E / 4 == 512, "four 16-byte loads and one key dword per thread and pass");
   v16i c[4];
 #pragma unroll
   for (int nb = 0; nb < 4; nb++)
 #pragma unroll
     for (int x = 0; x < 16; x++) c[nb][x] = 0;
-  auto run_pass = [&](int pass) {
+  for (int pass = 0; pass < MF_PASSES; pass++) {
     const int buf = pass & 1;
     const int nx = (pass + 1 < MF_PASSES) ? pass + 1 : pass;  // the last pass fetches itself again, unused
     const uint4* as = Ag + (size_t)(nx % MF_ROWS) * MF_A_PASS_U4 + tid;
-    const uint4 p0 = as[0], p1 = as[512], p2 = as[1024], p3 = as[1536];
-    u32 pd[5];
+    const uint4 p0 = as[0], p1 = as[MF_THREADS], p2 = as[2 * MF_THREADS], p3 = as[3 * MF_THREADS];
+    u32 pd0, pd1;
     {
       const u32* er = e_row(nx);
-#pragma unroll
-      for (int q = 0; q < 5; q++) pd[q] = (tid + q < MF_E / 4) ? er[tid + q] : 0u;
+      pd0 = er[ew];
+      pd1 = (ew + 1 < MF_S / 4) ? er[ew + 1] : 0u;
     }
-    const uint4* Ar = abuf + buf * MF_A_PASS_U4 + lane;
-    const uint4* Bp = ebuf + buf * MF_ECOPIES_U4 + bofs;
+    const uint4* Ar = abuf + buf * MF_A_PASS_U4 + sub * (MF_KB * 64) + lane;
+    const u32* Bp = ebuf + buf * MF_ECOPIES_U32 + bofs;
+    auto ldb = [&](int wofs) {
+      return v4i{(int)Bp[wofs], (int)Bp[wofs + 1], (int)Bp[wofs + 2], (int)Bp[wofs + 3]};
+    };
+    auto lda = [](const uint4& u) { return v4i{(int)u.x, (int)u.y, (int)u.z, (int)u.w}; };
     v4i R[8], Av[4];
-    auto ld = [](const uint4& u) { return v4i{(int)u.x, (int)u.y, (int)u.z, (int)u.w}; };
 #pragma unroll
-    for (int nb = 0; nb < 4; nb++) R[nb] = ld(Bp[2 * (MF_KB - 1 + nb)]);
-    R[7] = ld(Bp[2 * (MF_KB - 2)]);  // B_0 of block 1
-    Av[0] = ld(Ar[0]);
-    Av[1] = ld(Ar[64]);
+    for (int nb = 0; nb < 4; nb++) R[nb] = ldb(8 * (MF_KB - 1 + nb));
+    R[7] = ldb(8 * (MF_KB - 2));  // B_0 of block 1
+    Av[0] = lda(Ar[0]);
+    Av[1] = lda(Ar[64]);
     for (int k8 = 0; k8 < MF_KB; k8 += 8) {
 #pragma unroll
       for (int s8 = 0; s8 < 8; s8++) {
         // reads for block kb + 2 (the last two blocks re-read the last one, unused)
         const int kb = k8 + s8;
         const int kn = (kb + 2 < MF_KB) ? kb + 2 : MF_KB - 1;
-        Av[(s8 + 2) & 3] = ld(Ar[kn * 64]);
-        R[(6 - s8) & 7] = ld(Bp[2 * (MF_KB - 1 - kn)]);
+        Av[(s8 + 2) & 3] = lda(Ar[kn * 64]);
+        R[(6 - s8) & 7] = ldb(8 * (MF_KB - 1 - kn));
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int nb = 0; nb < 4; nb++)
@@ -252,34 +298,33 @@ __global__ __launch_bounds__(512) void k_mf_step(const int8_t* __restrict__ Ek, 
     if (pass + 1 < MF_PASSES) {
       uint4* ad = abuf + (buf ^ 1) * MF_A_PASS_U4 + tid;
       ad[0] = p0;
-      ad[512] = p1;
-      ad[1024] = p2;
-      ad[1536] = p3;
-      stage_e(ebuf + (buf ^ 1) * MF_ECOPIES_U4, pd);
+      ad[MF_THREADS] = p1;
+      ad[2 * MF_THREADS] = p2;
+      ad[3 * MF_THREADS] = p3;
+      stage_e(ebuf + (buf ^ 1) * MF_ECOPIES_U32, pd0, pd1);
     }
     __syncthreads();
-  };
-  for (int pass = 0; pass < MF_PASSES - 1; pass++) run_pass(pass);
-  // result (m, i): lane n + 32 kh, register x: m = 8 (x / 4) + 4 kh + x % 4, i = 128 w + 32 nb + n.
-  // The accumulator words are loaded before the last pass and updated after it.
-  u32 av[16][4];
-  bool live[16];
-#pragma unroll
-  for (int x = 0; x < 16; x++) {
-    const uint64_t g = mt * MF_TILE + 8 * (x >> 2) + 4 * kh + (x & 3);
-    live[x] = g < B && (!ops || op_bootstraps(ops[g]));
-    const u32* p = acc + (g * 2 + o) * RING_N + 128 * wave + n;
-#pragma unroll
-    for (int nb = 0; nb < 4; nb++) av[x][nb] = live[x] ? p[32 * nb] : 0u;
   }
-  run_pass(MF_PASSES - 1);
+  // P1 to LDS ([w mod 4][nb][x][lane]), then y0 = P1 + P2 (sub 1, outputs [0, N/2)) and
+  // y1 = P1 + P3 (sub 2, outputs [N/2, N)).
+  u32* p1buf = reinterpret_cast<u32*>(mf_lds);
+  if (sub == 0) {
+#pragma unroll
+    for (int nb = 0; nb < 4; nb++)
+#pragma unroll
+      for (int x = 0; x < 16; x++) p1buf[((wl * 4 + nb) * 16 + x) * 64 + lane] = (u32)c[nb][x];
+  }
+  __syncthreads();
+  if (sub == 0) return;
+  // result (m, i): lane n + 32 kh, register x: m = 8 (x / 4) + 4 kh + x % 4,
+  // i = (sub - 1) N/2 + 128 (w mod 4) + 32 nb + n
 #pragma unroll
   for (int x = 0; x < 16; x++) {
-    if (!live[x]) continue;
     const uint64_t g = mt * MF_TILE + 8 * (x >> 2) + 4 * kh + (x & 3);
-    u32* p = acc + (g * 2 + o) * RING_N + 128 * wave + n;
+    if (g >= B || (ops && !op_bootstraps(ops[g]))) continue;
+    u32* p = acc + (g * 2 + o) * RING_N + (sub - 1) * MF_HALF + 128 * wl + n;
 #pragma unroll
-    for (int nb = 0; nb < 4; nb++) p[32 * nb] = av[x][nb] + (u32)c[nb][x];
+    for (int nb = 0; nb < 4; nb++) p[32 * nb] += (u32)c[nb][x] + p1buf[((wl * 4 + nb) * 16 + x) * 64 + lane];
   }
 }
 
@@ -297,7 +342,7 @@ size_t mf_work_bytes(uint64_t B, bool need_acc) {
 
 hipError_t launch_mf_key(const uint32_t* bk, int8_t* E, hipStream_t st) {
   const uint64_t rows = (uint64_t)LWE_N * MF_ROWS * 2;
-  hipLaunchKernelGGL(k_mf_key, dim3((unsigned)((rows * MF_E + 255) / 256)), dim3(256), 0, st, bk, E, rows);
+  hipLaunchKernelGGL(k_mf_key, dim3((unsigned)((rows * MF_S + 255) / 256)), dim3(256), 0, st, bk, E, rows);
   return hipGetLastError();
 }
 
@@ -311,7 +356,8 @@ hipError_t launch_blind_rotate_mfma(const vsp_context* ctx, const uint8_t* ops, 
   for (int i = 0; i < LWE_N; i++) {
     hipLaunchKernelGGL(k_mf_digits, dim3((unsigned)tiles, 2, MF_TILE / MF_DG), dim3(256), 0, st, ops, abar, acc, A, B,
                        i);
-    hipLaunchKernelGGL(k_mf_step, dim3((unsigned)tiles, 2), dim3(512), MF_STEP_LDS, st,
+    ProfScope ps(ctx, 3, st);
+    hipLaunchKernelGGL(k_mf_step, dim3((unsigned)tiles, 2), dim3(MF_THREADS), MF_STEP_LDS, st,
                        ctx->mf_key + (size_t)i * MF_KEY_STEP, A, acc, ops, B);
   }
   hipError_t e = hipGetLastError();

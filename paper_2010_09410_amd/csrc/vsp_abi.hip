@@ -67,7 +67,7 @@ vsp_status scratch_reserve(vsp_context* ctx, Scratch& s, size_t bytes) {
   return VSP_OK;
 }
 
-ProfScope::ProfScope(vsp_context* c, int w, hipStream_t s) : ctx(c), which(w), st(s) {
+ProfScope::ProfScope(const vsp_context* c, int w, hipStream_t s) : ctx(c), which(w), st(s) {
   if (!ctx->prof.on) return;
   hipEvent_t e0;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
@@ -428,8 +428,8 @@ vsp_status vsp_profile_enable(vsp_context* ctx, int on) {
 vsp_status vsp_profile_read(vsp_context* ctx, int which, double* total_ms, uint64_t* launches) {
   vsp_status s = check_ctx(ctx);
   if (s) return s;
-  if (which < 0 || which > 2 || total_ms == nullptr || launches == nullptr)
-    return fail(VSP_E_ARG, "which must be 0, 1 or 2 and the outputs non-NULL");
+  if (which < 0 || which >= kProfClasses || total_ms == nullptr || launches == nullptr)
+    return fail(VSP_E_ARG, "which must be 0, 1, 2 or 3 and the outputs non-NULL");
   VSP_HIP(hipSetDevice(ctx->device));
   VSP_HIP(hipDeviceSynchronize());
   double t = 0;

@@ -54,7 +54,7 @@ constexpr uint64_t kBucket[kTuneBuckets] = {1, 16, 64, 256, 1024, 2048, 4096};
 //    the j range over workgroups.
 struct Tuning {
   uint64_t br_cap[kBrShapes] = {1024, 2048, 512, 4096};
-  float br_round_ms[kBrShapes] = {1.0f, 1.48f, 0.8f, 1e9f};  // the matrix-core form only once measured
+  float br_round_ms[kBrShapes] = {1.0f, 1.48f, 0.8f, 2.66f};
   int br_force[kTuneBuckets] = {0, 0, 0, 0, 0, 0, 0};
   int ks_form[kTuneBuckets] = {2, 2, 2, 2, 2, 2, 2};
   bool tuned = false;
@@ -88,10 +88,11 @@ struct Scratch {
 };
 
 // Event pairs bracketing instrumented launches (kernel classes: blind rotation, key switch,
-// prologue).
+// prologue, and each step kernel of the matrix-core blind rotation).
+constexpr int kProfClasses = 4;
 struct Profile {
   bool on = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[3];
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[kProfClasses];
 };
 
 }  // namespace vsp
@@ -114,7 +115,7 @@ struct vsp_context {
   int* dev_err = nullptr;         // device error flags
   vsp::Scratch abar, tlwe1, ntt_sel, mem_a, mem_b, mem_c, mem_d, mf_work;
   vsp::Tuning tune;
-  vsp::Profile prof;
+  mutable vsp::Profile prof;     // instrumentation, also recorded by launches on a const context
   std::mutex mu;                  // serialises scratch growth
 };
 
@@ -143,11 +144,11 @@ vsp_status scratch_reserve(vsp_context* ctx, Scratch& s, size_t bytes);
 
 // Records an event pair around one launch of kernel class `which` when profiling is on.
 struct ProfScope {
-  vsp_context* ctx;
+  const vsp_context* ctx;
   int which;
   hipStream_t st;
   hipEvent_t e1 = nullptr;
-  ProfScope(vsp_context* c, int w, hipStream_t s);
+  ProfScope(const vsp_context* c, int w, hipStream_t s);
   ~ProfScope();
 };
 
