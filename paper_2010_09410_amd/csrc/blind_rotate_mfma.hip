@@ -21,9 +21,10 @@
 // Horner's rule in the accumulators (plane 3 first, shift by 8 bits between planes), the
 // int32 wrap-around of the matrix cores being arithmetic mod 2^32.
 //
-// A step is two launches: k_mf_digits writes A for the step (bytes in the lane order of the
-// MFMA operands), then k_mf_step computes, for one tile of 32 gates and one output
-// polynomial per workgroup, P1, P2 and P3, combines them and adds y to ACC. B is never stored
+// A step is one launch of k_mf_step: for one tile of 32 gates and one output polynomial per
+// workgroup it computes P1, P2 and P3, combines them, adds y to ACC, and writes the next
+// step's A rows that depend on that polynomial (bytes in the lane order of the MFMA
+// operands). k_mf_digits writes the first step's A. B is never stored
 // as a matrix: a 32 x 32 tile of a Toeplitz block depends only on its diagonal offset, so a
 // lane reads its sixteen bytes straight from the sequence (staged in LDS), and moving to the
 // next 32 input coefficients turns the tile of output block nb into that of block nb - 1,
@@ -106,6 +107,26 @@ __global__ __launch_bounds__(256) void k_mf_init(const uint8_t* __restrict__ ops
 // (jg = t mod 128) of both halves for gates t / 128, t / 128 + 2, ... (coalesced reads of ACC
 // and of its rotation); the bytes are gathered in LDS in operand order, then written out as
 // 128-byte runs.
+// The digit bytes of one (gate, quad of local coefficients jg, level k) for the three segments
+// (packed four coefficients per word as in the operand layout), from the rotated and plain
+// values of both halves.
+__device__ __forceinline__ void mf_digit_words(const u32 (&rot0)[4], const u32 (&own0)[4], const u32 (&rot1)[4],
+                                               const u32 (&own1)[4], u32 (&w)[GADGET_L][MF_SUB]) {
+#pragma unroll
+  for (int s = 0; s < 4; s++) {  // byte s of the word: local coefficient 4 jg + 3 - s
+    const u32 x0 = (rot0[s] - own0[3 - s]) + DECOMP_OFFSET;
+    const u32 x1 = (rot1[s] - own1[3 - s]) + DECOMP_OFFSET;
+#pragma unroll
+    for (int k = 0; k < GADGET_L; k++) {
+      const int sh = 32 - BG_BIT * (k + 1);
+      const u32 d0 = ((x0 >> sh) & 63u) - 32u, d1 = ((x1 >> sh) & 63u) - 32u;
+      w[k][0] |= ((d0 + d1) & 255u) << (8 * s);
+      w[k][1] |= (d1 & 255u) << (8 * s);
+      w[k][2] |= (d0 & 255u) << (8 * s);
+    }
+  }
+}
+
 constexpr int MF_DG = 8;  // gates per digit workgroup
 
 __global__ __launch_bounds__(256) void k_mf_digits(const uint8_t* __restrict__ ops, const u32* __restrict__ abar,
@@ -145,19 +166,7 @@ __global__ __launch_bounds__(256) void k_mf_digits(const uint8_t* __restrict__ o
     if (live[q]) {
       const u32 ov0[4] = {own[q][0].x, own[q][0].y, own[q][0].z, own[q][0].w};
       const u32 ov1[4] = {own[q][1].x, own[q][1].y, own[q][1].z, own[q][1].w};
-#pragma unroll
-      for (int s = 0; s < 4; s++) {  // byte s of the lane's dword: local coefficient 4 jg + 3 - s
-        const u32 x0 = (rot[q][0][s] - ov0[3 - s]) + DECOMP_OFFSET;
-        const u32 x1 = (rot[q][1][s] - ov1[3 - s]) + DECOMP_OFFSET;
-#pragma unroll
-        for (int k = 0; k < GADGET_L; k++) {
-          const int sh = 32 - BG_BIT * (k + 1);
-          const u32 d0 = ((x0 >> sh) & 63u) - 32u, d1 = ((x1 >> sh) & 63u) - 32u;
-          w[k][0] |= ((d0 + d1) & 255u) << (8 * s);
-          w[k][1] |= (d1 & 255u) << (8 * s);
-          w[k][2] |= (d0 & 255u) << (8 * s);
-        }
-      }
+      mf_digit_words(rot[q][0], ov0, rot[q][1], ov1, w);
     }
 #pragma unroll
     for (int k = 0; k < GADGET_L; k++)
@@ -197,14 +206,21 @@ constexpr int MF_A_PASS_U4 = (int)(MF_A_ROW / 16);      // 3072 16-byte operands
 constexpr int MF_PASSES = MF_PLANES * MF_ROWS;
 constexpr int MF_COPY_U32 = MF_S / 4 + 4;                // one shifted copy and a 16-byte tail
 constexpr int MF_ECOPIES_U32 = MF_SUB * 4 * MF_COPY_U32;
-constexpr size_t MF_STEP_LDS = 2 * ((size_t)MF_A_PASS_U4 * 16 + (size_t)MF_ECOPIES_U32 * 4);
+constexpr size_t MF_PASS_LDS = 2 * ((size_t)MF_A_PASS_U4 * 16 + (size_t)MF_ECOPIES_U32 * 4);
+constexpr size_t MF_NEXT_LDS = GADGET_L * MF_A_ROW;        // next step's operands of rows 3o .. 3o + 2
+constexpr size_t MF_STEP_LDS = MF_PASS_LDS > MF_NEXT_LDS ? MF_PASS_LDS : MF_NEXT_LDS;
 static_assert(MF_A_PASS_U4 == 4 * MF_THREADS && MF_SUB * MF_S / 4 == MF_THREADS,
               "four 16-byte operands and one key word per thread and pass");
 static_assert((size_t)4 * 4 * 16 * 64 * 4 <= 2 * (size_t)MF_A_PASS_U4 * 16, "P1 fits in the operand buffers");
 
+// Step kernel. With next_step >= 0 the workgroup then writes the digit operands of step
+// next_step for rows 3o .. 3o + 2 of its tile into Anext: they depend only on the updated
+// polynomial o of its own 32 gates, which it has just written, so no other workgroup is
+// involved (the other output polynomial's workgroup writes rows 3(1 - o) ..).
 __global__ __launch_bounds__(MF_THREADS) void k_mf_step(const int8_t* __restrict__ Ek, const int8_t* __restrict__ A,
                                                          u32* __restrict__ acc, const uint8_t* __restrict__ ops,
-                                                         uint64_t B) {
+                                                         uint64_t B, int8_t* __restrict__ Anext,
+                                                         const u32* __restrict__ abar, int next_step) {
   extern __shared__ uint4 mf_lds[];
   uint4* abuf = mf_lds;                                            // [2][MF_A_PASS_U4]
   u32* ebuf = reinterpret_cast<u32*>(mf_lds + 2 * MF_A_PASS_U4);  // [2][3 sequences][4 copies][MF_COPY_U32]
@@ -315,17 +331,52 @@ __global__ __launch_bounds__(MF_THREADS) void k_mf_step(const int8_t* __restrict
       for (int x = 0; x < 16; x++) p1buf[((wl * 4 + nb) * 16 + x) * 64 + lane] = (u32)c[nb][x];
   }
   __syncthreads();
-  if (sub == 0) return;
-  // result (m, i): lane n + 32 kh, register x: m = 8 (x / 4) + 4 kh + x % 4,
-  // i = (sub - 1) N/2 + 128 (w mod 4) + 32 nb + n
+  if (sub != 0) {
+    // result (m, i): lane n + 32 kh, register x: m = 8 (x / 4) + 4 kh + x % 4,
+    // i = (sub - 1) N/2 + 128 (w mod 4) + 32 nb + n
 #pragma unroll
-  for (int x = 0; x < 16; x++) {
-    const uint64_t g = mt * MF_TILE + 8 * (x >> 2) + 4 * kh + (x & 3);
-    if (g >= B || (ops && !op_bootstraps(ops[g]))) continue;
-    u32* p = acc + (g * 2 + o) * RING_N + (sub - 1) * MF_HALF + 128 * wl + n;
+    for (int x = 0; x < 16; x++) {
+      const uint64_t g = mt * MF_TILE + 8 * (x >> 2) + 4 * kh + (x & 3);
+      if (g >= B || (ops && !op_bootstraps(ops[g]))) continue;
+      u32* p = acc + (g * 2 + o) * RING_N + (sub - 1) * MF_HALF + 128 * wl + n;
 #pragma unroll
-    for (int nb = 0; nb < 4; nb++) p[32 * nb] += (u32)c[nb][x] + p1buf[((wl * 4 + nb) * 16 + x) * 64 + lane];
+      for (int nb = 0; nb < 4; nb++) p[32 * nb] += (u32)c[nb][x] + p1buf[((wl * 4 + nb) * 16 + x) * 64 + lane];
+    }
   }
+  if (next_step < 0) return;
+  // the updated polynomial o of the tile's gates is written (and visible to the workgroup)
+  // and P1 has been read: the LDS becomes the staging area of the next step's operands
+  __syncthreads();
+  u32* sA = reinterpret_cast<u32*>(mf_lds);  // [level k][segment][kb][lane][4 words]
+  for (int it = tid; it < MF_TILE * (MF_HALF / 4); it += MF_THREADS) {
+    const int m = it >> 7, jg = it & 127;
+    const uint64_t g = mt * MF_TILE + m;
+    u32 w[GADGET_L][MF_SUB] = {};
+    if (g < B && (!ops || op_bootstraps(ops[g]))) {
+      const int a = (int)abar[g * TLWE0 + next_step];
+      const u32* p = acc + (g * 2 + o) * RING_N;
+      const uint4 u0 = reinterpret_cast<const uint4*>(p)[jg], u1 = reinterpret_cast<const uint4*>(p)[MF_HALF / 4 + jg];
+      const u32 own0[4] = {u0.x, u0.y, u0.z, u0.w}, own1[4] = {u1.x, u1.y, u1.z, u1.w};
+      u32 rot0[4], rot1[4];
+#pragma unroll
+      for (int s = 0; s < 4; s++) {
+        const int i0 = (4 * jg + 3 - s - a) & (2 * RING_N - 1), i1 = (MF_HALF + 4 * jg + 3 - s - a) & (2 * RING_N - 1);
+        const u32 r0 = p[i0 & (RING_N - 1)], r1 = p[i1 & (RING_N - 1)];
+        rot0[s] = (i0 & RING_N) ? 0u - r0 : r0;
+        rot1[s] = (i1 & RING_N) ? 0u - r1 : r1;
+      }
+      mf_digit_words(rot0, own0, rot1, own1, w);
+    }
+    const int kb = jg >> 3, ln = m + 32 * ((jg >> 2) & 1), dw = 3 - (jg & 3);
+#pragma unroll
+    for (int k = 0; k < GADGET_L; k++)
+#pragma unroll
+      for (int sg = 0; sg < MF_SUB; sg++) sA[(((k * MF_SUB + sg) * MF_KB + kb) * 64 + ln) * 4 + dw] = w[k][sg];
+  }
+  __syncthreads();
+  const uint4* src = reinterpret_cast<const uint4*>(sA);
+  uint4* dst = reinterpret_cast<uint4*>(Anext + mt * MF_A_TILE + (size_t)GADGET_L * o * MF_A_ROW);
+  for (int c2 = tid; c2 < (int)(MF_NEXT_LDS / 16); c2 += MF_THREADS) dst[c2] = src[c2];
 }
 
 hipError_t init_mf_kernel_attributes() {
@@ -337,7 +388,7 @@ size_t mf_key_bytes() { return (size_t)LWE_N * MF_KEY_STEP; }
 
 size_t mf_work_bytes(uint64_t B, bool need_acc) {
   const uint64_t tiles = (B + MF_TILE - 1) / MF_TILE;
-  return tiles * MF_A_TILE + (need_acc ? (size_t)B * 2 * RING_N * 4 : 0);
+  return 2 * tiles * MF_A_TILE + (need_acc ? (size_t)B * 2 * RING_N * 4 : 0);
 }
 
 hipError_t launch_mf_key(const uint32_t* bk, int8_t* E, hipStream_t st) {
@@ -350,15 +401,18 @@ hipError_t launch_blind_rotate_mfma(const vsp_context* ctx, const uint8_t* ops, 
                                     uint32_t* trlwe, uint64_t B, void* work, hipStream_t st) {
   if (B == 0) return hipSuccess;
   const uint64_t tiles = (B + MF_TILE - 1) / MF_TILE;
-  int8_t* A = static_cast<int8_t*>(work);
-  u32* acc = trlwe ? trlwe : reinterpret_cast<u32*>(A + tiles * MF_A_TILE);
+  // operands of even steps in A[0], of odd steps in A[1]: step i reads A[i % 2] and writes
+  // the operands of step i + 1 into the other one
+  int8_t* Ab[2] = {static_cast<int8_t*>(work), static_cast<int8_t*>(work) + tiles * MF_A_TILE};
+  u32* acc = trlwe ? trlwe : reinterpret_cast<u32*>(Ab[1] + tiles * MF_A_TILE);
   hipLaunchKernelGGL(k_mf_init, dim3((unsigned)((B * 2 * RING_N + 255) / 256)), dim3(256), 0, st, ops, abar, acc, B);
+  hipLaunchKernelGGL(k_mf_digits, dim3((unsigned)tiles, 2, MF_TILE / MF_DG), dim3(256), 0, st, ops, abar, acc, Ab[0], B,
+                     0);
   for (int i = 0; i < LWE_N; i++) {
-    hipLaunchKernelGGL(k_mf_digits, dim3((unsigned)tiles, 2, MF_TILE / MF_DG), dim3(256), 0, st, ops, abar, acc, A, B,
-                       i);
     ProfScope ps(ctx, 3, st);
     hipLaunchKernelGGL(k_mf_step, dim3((unsigned)tiles, 2), dim3(MF_THREADS), MF_STEP_LDS, st,
-                       ctx->mf_key + (size_t)i * MF_KEY_STEP, A, acc, ops, B);
+                       ctx->mf_key + (size_t)i * MF_KEY_STEP, Ab[i & 1], acc, ops, B, Ab[(i + 1) & 1], abar,
+                       i + 1 < LWE_N ? i + 1 : -1);
   }
   hipError_t e = hipGetLastError();
   if (e == hipSuccess && tlwe1) e = launch_sample_extract(acc, tlwe1, B, 1, st);
