@@ -204,10 +204,13 @@ constexpr int MF_WAVES = 12;
 constexpr int MF_THREADS = MF_WAVES * 64;
 constexpr int MF_A_PASS_U4 = (int)(MF_A_ROW / 16);      // 3072 16-byte operands per row and tile
 constexpr int MF_PASSES = MF_PLANES * MF_ROWS;
-constexpr int MF_COPY_U32 = MF_S / 4 + 4;                // one shifted copy and a 16-byte tail
+// one shifted copy (256 words read) padded to 264 words: 264 = 8 (mod 32), so the 32 lanes of
+// a word read (copies t0 mod 4, words t0 / 4 over eight consecutive values) hit 32 banks
+constexpr int MF_COPY_U32 = MF_S / 4 + 8;
 constexpr int MF_ECOPIES_U32 = MF_SUB * 4 * MF_COPY_U32;
 constexpr size_t MF_PASS_LDS = 2 * ((size_t)MF_A_PASS_U4 * 16 + (size_t)MF_ECOPIES_U32 * 4);
-constexpr size_t MF_NEXT_LDS = GADGET_L * MF_A_ROW;        // next step's operands of rows 3o .. 3o + 2
+constexpr int MF_SROW = 65;                                 // staging row: 64 lanes and a pad word
+constexpr size_t MF_NEXT_LDS = (size_t)GADGET_L * MF_SUB * MF_KB * 4 * MF_SROW * 4;  // next step's rows 3o .. 3o + 2
 constexpr size_t MF_STEP_LDS = MF_PASS_LDS > MF_NEXT_LDS ? MF_PASS_LDS : MF_NEXT_LDS;
 static_assert(MF_A_PASS_U4 == 4 * MF_THREADS && MF_SUB * MF_S / 4 == MF_THREADS,
               "four 16-byte operands and one key word per thread and pass");
@@ -347,36 +350,63 @@ __global__ __launch_bounds__(MF_THREADS) void k_mf_step(const int8_t* __restrict
   // the updated polynomial o of the tile's gates is written (and visible to the workgroup)
   // and P1 has been read: the LDS becomes the staging area of the next step's operands
   __syncthreads();
-  u32* sA = reinterpret_cast<u32*>(mf_lds);  // [level k][segment][kb][lane][4 words]
-  for (int it = tid; it < MF_TILE * (MF_HALF / 4); it += MF_THREADS) {
-    const int m = it >> 7, jg = it & 127;
-    const uint64_t g = mt * MF_TILE + m;
-    u32 w[GADGET_L][MF_SUB] = {};
-    if (g < B && (!ops || op_bootstraps(ops[g]))) {
-      const int a = (int)abar[g * TLWE0 + next_step];
-      const u32* p = acc + (g * 2 + o) * RING_N;
-      const uint4 u0 = reinterpret_cast<const uint4*>(p)[jg], u1 = reinterpret_cast<const uint4*>(p)[MF_HALF / 4 + jg];
-      const u32 own0[4] = {u0.x, u0.y, u0.z, u0.w}, own1[4] = {u1.x, u1.y, u1.z, u1.w};
-      u32 rot0[4], rot1[4];
+  // item (m, jg): gate m, local coefficient quad jg of both halves; lanes take consecutive
+  // quads of one gate (coalesced reads of ACC and of its rotation). All loads are issued
+  // before any digit is formed. The words are staged as [k][segment][kb][word dw][lane] with
+  // rows of 65 words (two-way bank conflicts at most), and the write-out gathers each lane's
+  // four words into its 16-byte operand.
+  constexpr int ITEMS = MF_TILE * (MF_HALF / 4);
+  constexpr int PER_T = (ITEMS + MF_THREADS - 1) / MF_THREADS;
+  u32* sA = reinterpret_cast<u32*>(mf_lds);
+  int av[PER_T];
+  bool lv[PER_T];
+#pragma unroll
+  for (int q = 0; q < PER_T; q++) {
+    const int it = tid + q * MF_THREADS;
+    const uint64_t g = mt * MF_TILE + (it >> 7);
+    lv[q] = it < ITEMS && g < B && (!ops || op_bootstraps(ops[g]));
+    av[q] = lv[q] ? (int)abar[g * TLWE0 + next_step] : 0;
+  }
+  u32 own[PER_T][2][4], rot[PER_T][2][4];
+#pragma unroll
+  for (int q = 0; q < PER_T; q++) {
+    const int it = tid + q * MF_THREADS, m = it >> 7, jg = it & 127;
+    const u32* p = acc + ((mt * MF_TILE + m) * 2 + o) * RING_N;
+#pragma unroll
+    for (int half = 0; half < 2; half++) {
+      const uint4 u = lv[q] ? reinterpret_cast<const uint4*>(p)[half * (MF_HALF / 4) + jg] : make_uint4(0u, 0u, 0u, 0u);
+      own[q][half][0] = u.x;
+      own[q][half][1] = u.y;
+      own[q][half][2] = u.z;
+      own[q][half][3] = u.w;
 #pragma unroll
       for (int s = 0; s < 4; s++) {
-        const int i0 = (4 * jg + 3 - s - a) & (2 * RING_N - 1), i1 = (MF_HALF + 4 * jg + 3 - s - a) & (2 * RING_N - 1);
-        const u32 r0 = p[i0 & (RING_N - 1)], r1 = p[i1 & (RING_N - 1)];
-        rot0[s] = (i0 & RING_N) ? 0u - r0 : r0;
-        rot1[s] = (i1 & RING_N) ? 0u - r1 : r1;
+        const int ix = (half * MF_HALF + 4 * jg + 3 - s - av[q]) & (2 * RING_N - 1);
+        const u32 r = lv[q] ? p[ix & (RING_N - 1)] : 0u;
+        rot[q][half][s] = (ix & RING_N) ? 0u - r : r;
       }
-      mf_digit_words(rot0, own0, rot1, own1, w);
     }
+  }
+#pragma unroll
+  for (int q = 0; q < PER_T; q++) {
+    const int it = tid + q * MF_THREADS;
+    if (it >= ITEMS) break;
+    const int m = it >> 7, jg = it & 127;
+    u32 w[GADGET_L][MF_SUB] = {};
+    if (lv[q]) mf_digit_words(rot[q][0], own[q][0], rot[q][1], own[q][1], w);
     const int kb = jg >> 3, ln = m + 32 * ((jg >> 2) & 1), dw = 3 - (jg & 3);
 #pragma unroll
     for (int k = 0; k < GADGET_L; k++)
 #pragma unroll
-      for (int sg = 0; sg < MF_SUB; sg++) sA[(((k * MF_SUB + sg) * MF_KB + kb) * 64 + ln) * 4 + dw] = w[k][sg];
+      for (int sg = 0; sg < MF_SUB; sg++) sA[(((k * MF_SUB + sg) * MF_KB + kb) * 4 + dw) * MF_SROW + ln] = w[k][sg];
   }
   __syncthreads();
-  const uint4* src = reinterpret_cast<const uint4*>(sA);
   uint4* dst = reinterpret_cast<uint4*>(Anext + mt * MF_A_TILE + (size_t)GADGET_L * o * MF_A_ROW);
-  for (int c2 = tid; c2 < (int)(MF_NEXT_LDS / 16); c2 += MF_THREADS) dst[c2] = src[c2];
+  for (int c2 = tid; c2 < GADGET_L * MF_SUB * MF_KB * 64; c2 += MF_THREADS) {
+    const int ln = c2 & 63, row = c2 >> 6;  // row = (k * 3 + segment) * MF_KB + kb
+    const u32* sw = sA + row * 4 * MF_SROW + ln;
+    dst[c2] = make_uint4(sw[0], sw[MF_SROW], sw[2 * MF_SROW], sw[3 * MF_SROW]);
+  }
 }
 
 hipError_t init_mf_kernel_attributes() {
