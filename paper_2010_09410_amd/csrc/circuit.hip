@@ -19,6 +19,7 @@ struct vsp_circuit {
   uint32_t* d_wires = nullptr;       // [ninputs + ngates][n+1]
   uint32_t* d_abar = nullptr;        // [maxw][n+1]
   uint32_t* d_tlwe1 = nullptr;       // [maxw][N+1]
+  void* d_mf = nullptr;              // matrix-core workspace, when some level is wide enough to use that form
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -38,7 +39,8 @@ hipError_t launch_level(vsp_circuit* c, uint64_t L, hipStream_t st) {
     const uint32_t* io = c->d_idx + 2 * c->ngates + o;
     const uint8_t* ops = c->d_ops + o;
     e = launch_gate_prologue(c->ctx, ops, c->d_wires, c->d_wires, i0, i1, io, c->d_abar, c->d_wires, w, st);
-    if (e == hipSuccess) e = launch_blind_rotate(c->ctx, ops, c->d_abar, c->d_tlwe1, nullptr, w, 0, st);
+    if (e == hipSuccess)
+      e = launch_blind_rotate(c->ctx, ops, c->d_abar, c->d_tlwe1, nullptr, w, 0, st, nullptr, nullptr, nullptr, c->d_mf);
     if (e == hipSuccess) e = launch_keyswitch(c->ctx, ops, c->d_tlwe1, io, c->d_wires, w, st);
   }
   return e;
@@ -51,7 +53,7 @@ void free_circuit(vsp_circuit* c) {
   if (c->exec) (void)hipGraphExecDestroy(c->exec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
   if (c->cap) (void)hipStreamDestroy(c->cap);
-  for (void* p : {(void*)c->d_ops, (void*)c->d_idx, (void*)c->d_wires, (void*)c->d_abar, (void*)c->d_tlwe1})
+  for (void* p : {(void*)c->d_ops, (void*)c->d_idx, (void*)c->d_wires, (void*)c->d_abar, (void*)c->d_tlwe1, c->d_mf})
     if (p) (void)hipFree(p);
   delete c;
 }
@@ -128,6 +130,10 @@ vsp_status vsp_circuit_create(vsp_context* ctx, const vsp_gate_desc* gates, uint
     return bail(hip_fail(e, "hipMalloc(wires)"));
   if ((e = hipMalloc(&c->d_abar, wmax * T0B)) != hipSuccess) return bail(hip_fail(e, "hipMalloc"));
   if ((e = hipMalloc(&c->d_tlwe1, wmax * (RING_N + 1) * 4)) != hipSuccess) return bail(hip_fail(e, "hipMalloc"));
+  bool matrix = false;  // the launch choice is fixed when the level sequence is captured below
+  for (uint64_t L = 0; L < nlev && ctx->mf_key; L++)
+    matrix |= ctx->tune.br_waves(std::min<uint64_t>(kMaxLaunch, c->off[L + 1] - c->off[L])) == 32;
+  if (matrix && (e = hipMalloc(&c->d_mf, mf_work_bytes(wmax, true))) != hipSuccess) return bail(hip_fail(e, "hipMalloc"));
   if (ngates) {
     if ((e = hipMemcpy(c->d_ops, hops.data(), ngates, hipMemcpyHostToDevice)) != hipSuccess) return bail(hip_fail(e, "upload"));
     if ((e = hipMemcpy(c->d_idx, hidx.data(), 3 * ngates * 4, hipMemcpyHostToDevice)) != hipSuccess)

@@ -72,6 +72,7 @@ struct vsp_server {
   std::map<uint64_t, Request*> all;
   size_t rr = 0;
   Slot slots[2];
+  void* mf_work = nullptr;  // matrix-core workspace (the batches run one after the other on st)
   struct Cand {
     uint8_t key, op;
     uint32_t i0, i1, io;
@@ -269,7 +270,7 @@ void worker_loop(vsp_server* s) {
                                         sl.d_abar, s->arena, nb, st);
     if (e == hipSuccess)
       e = launch_blind_rotate(s->ctx, sl.d_ops, sl.d_abar, sl.d_tlwe1, nullptr, nb, 0, st, sl.h_keytab[0],
-                              nk > 1 ? sl.d_keytab : nullptr, nk > 1 ? sl.d_kid : nullptr);
+                              nk > 1 ? sl.d_keytab : nullptr, nk > 1 ? sl.d_kid : nullptr, s->mf_work);
     for (size_t k = 0; k < nk && e == hipSuccess; k++) {
       const uint64_t a = start[k], n = start[k + 1] - start[k];
       e = launch_keyswitch(s->ctx, sl.d_ops + a, sl.d_tlwe1 + a * (RING_N + 1), sl.d_idx + 2 * M + a, s->arena, n, st,
@@ -298,6 +299,7 @@ void free_server(vsp_server* s) {
       if (p) (void)hipFree(p);
     if (sl.ev) (void)hipEventDestroy(sl.ev);
   }
+  if (s->mf_work) (void)hipFree(s->mf_work);
   if (s->arena) (void)hipFree(s->arena);
   if (s->st) (void)hipStreamDestroy(s->st);
   for (auto& kv : s->all) delete kv.second;
@@ -343,6 +345,8 @@ vsp_status vsp_server_create(vsp_context* ctx, uint64_t mem_budget_bytes, uint64
     if ((e = hipMalloc(&sl.d_tlwe1, max_batch * (RING_N + 1) * 4)) != hipSuccess) return bail(hip_fail(e, "hipMalloc"));
     if ((e = hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming)) != hipSuccess) return bail(hip_fail(e, "event"));
   }
+  if (ctx->mf_key && (e = hipMalloc(&s->mf_work, mf_work_bytes(max_batch, true))) != hipSuccess)
+    return bail(hip_fail(e, "hipMalloc(matrix-core workspace)"));
   s->worker = std::thread(worker_loop, s);
   *out = s;
   return VSP_OK;

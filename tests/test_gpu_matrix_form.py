@@ -75,3 +75,33 @@ def test_matrix_form_trlwe_output(gpu, keys):
         else:
             lin, _ = oracle.gate_linear(int(ops[k]), in0[k], in1[k])
             np.testing.assert_array_equal(out[k], oracle.bootstrap_to_trlwe(keys["bk"], lin), err_msg=f"k={k}")
+
+
+def test_matrix_form_in_circuits_and_server(gpu, keys):
+    """Circuits (levels captured in a HIP graph) and the server use the matrix-core form when
+    the tuning picks it for their widths; their wires equal those of the NTT form."""
+    from test_gpu_server import requests, wait
+    buckets = (1, 16, 64)
+    saved = {b: gpu.tuning(b) for b in buckets}
+    reqs = requests(keys, 3, 860)
+    try:
+        results = {}
+        for form in (NTT8, MATRIX):
+            for b in buckets:
+                gpu.set_tuning(b, form, saved[b][1])
+            circ_out = []
+            for c, inputs in reqs:
+                circ = gpu.circuit(c["gates"], c["ninputs"])
+                circ_out.append(to_host(circ.run(gpu.tensor(inputs))))
+                gpu.sync()
+                circ.close()
+            srv = gpu.server(mem_budget_bytes=64 << 20, max_batch=64)
+            tickets = [srv.submit(c["gates"], c["ninputs"], inputs) for c, inputs in reqs]
+            srv_out = [wait(srv, t, c["ninputs"] + len(c["gates"]))[0] for t, (c, _) in zip(tickets, reqs)]
+            srv.close()
+            results[form] = (circ_out, srv_out)
+    finally:
+        for b in buckets:
+            gpu.set_tuning(b, 0, saved[b][1])
+    for a, m in zip(results[NTT8][0] + results[NTT8][1], results[MATRIX][0] + results[MATRIX][1]):
+        np.testing.assert_array_equal(m, a)
