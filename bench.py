@@ -432,7 +432,7 @@ def main():
         serving = dict(config=serving, light=light, light_4_key_sets=keyed)
 
     br_avg_ms = br_ms / max(br_n, 1)
-    launch = {"br_shape": br_waves, "keyswitch": ["gather", "tiled", "split"][ks_form], "autotune": tune}
+    launch = {"br_shape": br_waves, "keyswitch": ["gather", "tiled", "split", "matrix"][ks_form], "autotune": tune}
     if br_waves == 32:
         # matrix-core form: the dominant kernel is the step kernel (630 launches per batch)
         mf_ms, mf_n = step_ms, step_n

@@ -236,10 +236,12 @@ vsp_status vsp_mux(vsp_context* ctx, const uint32_t* d_sel, const uint32_t* d_in
  * one round holds 16 gates per compute unit; used by vsp_gates and vsp_bootstrap_trlwe with the
  * context's own key, the other callers run the 8-gate form in its place; it needs a workspace
  * of 14 KiB per gate, grown on demand). This call times one full round of each shape on random
- * ciphertexts, and times the three key-switch forms (0: one workgroup per gate gathering its
+ * ciphertexts, and times the four key-switch forms (0: one workgroup per gate gathering its
  * key rows; 1: tiles of 16 gates reading each key row once and selecting in registers;
  * 2: tiles of 16 gates staging key rows through LDS, with the j range split over workgroups
- * and atomic accumulation) for each batch-size bucket up to max_batch (buckets end at 1, 16,
+ * and atomic accumulation; 3: int8 MFMA products of one-hot digit rows with the key's byte
+ * planes, for the context's own key, other keys running form 2) for each batch-size bucket up
+ * to max_batch (buckets end at 1, 16,
  * 64, 256, 1024, 2048, 4096 gates; larger batches share the last). Every candidate must give
  * bit-identical outputs (else VSP_E_HIP). Later launches pick the shape with the fewest
  * rounds x round time, and the faster key switch for their bucket. With cache_path non-NULL
@@ -249,11 +251,11 @@ vsp_status vsp_autotune(vsp_context* ctx, uint64_t max_batch, const char* cache_
 
 /* The launch choice for a batch of B gates: *br_waves (4 or 8 gates per workgroup at one wave
  * per gate, 3 for one gate per workgroup on three waves, 32 for the matrix-core form),
- * *ks_form (0, 1 or 2). */
+ * *ks_form (0, 1, 2 or 3). */
 vsp_status vsp_tuning_get(const vsp_context* ctx, uint64_t B, int* br_waves, int* ks_form);
 
 /* Pin the launch choice for the bucket containing B: br_waves 3, 4, 8 or 32 (0 returns that
- * bucket to the round-time model), ks_form 0, 1 or 2. Results are the same for every choice. */
+ * bucket to the round-time model), ks_form 0, 1, 2 or 3. Results are the same for every choice. */
 vsp_status vsp_tuning_set(vsp_context* ctx, uint64_t B, int br_waves, int ks_form);
 
 /* Kernel-time instrumentation (for benchmarks): while enabled, every eager launch of the

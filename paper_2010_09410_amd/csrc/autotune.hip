@@ -239,7 +239,7 @@ vsp_status vsp_tuning_set(vsp_context* ctx, uint64_t B, int br_waves, int ks_for
   if (ctx == nullptr) return fail(VSP_E_ARG, "context is NULL");
   if ((br_waves != 0 && br_waves != 3 && br_waves != 4 && br_waves != 8 && br_waves != 32) || ks_form < 0 ||
       ks_form >= kKsForms)
-    return fail(VSP_E_ARG, "br_waves must be 0 (model), 3, 4, 8 or 32 and ks_form 0, 1 or 2");
+    return fail(VSP_E_ARG, "br_waves must be 0 (model), 3, 4, 8 or 32 and ks_form 0, 1, 2 or 3");
   const int b = Tuning::bucket(B == 0 ? 1 : B);
   ctx->tune.br_force[b] = br_waves;
   ctx->tune.ks_form[b] = ks_form;

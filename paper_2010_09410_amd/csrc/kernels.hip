@@ -401,6 +401,10 @@ hipError_t launch_keyswitch(const vsp_context* ctx, const uint8_t* ops, const ui
   if (B == 0) return hipSuccess;
   if (ksk == nullptr) ksk = ctx->ksk;
   if (form < 0) form = ctx->tune.ks_form_for(B);
+  if (form == 3) {
+    if (ksk == ctx->ksk && ctx->ks_mf != nullptr) return launch_keyswitch_mfma(ctx->ks_mf, ops, tlwe1, idxo, out, B, st);
+    form = 2;
+  }
   if (form == 2) {
     constexpr int G = 16;
     const uint64_t tiles = (B + G - 1) / G;

@@ -129,18 +129,20 @@ static bool make_tables(std::vector<u64>& tw) {
 }
 
 vsp_status upload_keys(const vsp_context* ctx, const uint32_t* bk_host, const uint32_t* ksk_host, uint64_t** bkn,
-                       uint32_t** ksk, int8_t** mf_key) {
+                       uint32_t** ksk, int8_t** mf_key, int8_t** ks_mf) {
   *bkn = nullptr;
   *ksk = nullptr;
   if (mf_key) *mf_key = nullptr;
+  if (ks_mf) *ks_mf = nullptr;
   const size_t bk_words = (size_t)LWE_N * 2 * GADGET_L * 2 * RING_N;
   const size_t ksk_rows = (size_t)RING_N * KS_T * 4;
   uint64_t* b = nullptr;
   uint32_t* k = nullptr;
   uint32_t* tmp = nullptr;
   int8_t* E = nullptr;
+  int8_t* KM = nullptr;
   auto undo = [&](vsp_status st) {
-    for (void* p : {(void*)b, (void*)k, (void*)tmp, (void*)E})
+    for (void* p : {(void*)b, (void*)k, (void*)tmp, (void*)E, (void*)KM})
       if (p) (void)hipFree(p);
     return st;
   };
@@ -166,9 +168,15 @@ vsp_status upload_keys(const vsp_context* ctx, const uint32_t* bk_host, const ui
       std::memcpy(&k4[(jp * 4 + v) * (LWE_N + 1)], &ksk_host[(jp * 3 + (v - 1)) * (LWE_N + 1)], (LWE_N + 1) * 4);
   if ((e = hipMemcpy(k, k4.data(), k4.size() * 4, hipMemcpyHostToDevice)) != hipSuccess)
     return undo(hip_fail(e, "upload ksk"));
+  if (ks_mf) {
+    if ((e = hipMalloc(&KM, ks_mf_key_bytes())) != hipSuccess) return undo(hip_fail(e, "hipMalloc(ks bytes)"));
+    if ((e = launch_ks_mfkey(k, KM, nullptr)) != hipSuccess || (e = hipDeviceSynchronize()) != hipSuccess)
+      return undo(hip_fail(e, "key-switching key conversion"));
+  }
   *bkn = b;
   *ksk = k;
   if (mf_key) *mf_key = E;
+  if (ks_mf) *ks_mf = KM;
   return VSP_OK;
 }
 
@@ -234,7 +242,8 @@ vsp_status vsp_context_create(const vsp_params* params, const uint32_t* bk_host,
   if ((e = hipMemcpy(ctx->tw, tw.data(), tw.size() * 8, hipMemcpyHostToDevice)) != hipSuccess)
     return cleanup(hip_fail(e, "upload twiddles"));
   if ((e = hipMemset(ctx->dev_err, 0, 256)) != hipSuccess) return cleanup(hip_fail(e, "clear flags"));
-  if (vsp_status st = upload_keys(ctx, bk_host, ksk_host, &ctx->bkn, &ctx->ksk, &ctx->mf_key)) return cleanup(st);
+  if (vsp_status st = upload_keys(ctx, bk_host, ksk_host, &ctx->bkn, &ctx->ksk, &ctx->mf_key, &ctx->ks_mf))
+    return cleanup(st);
   *out = ctx;
   return VSP_OK;
 }
@@ -244,7 +253,8 @@ vsp_status vsp_context_destroy(vsp_context* ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
   profile_clear(ctx);
-  for (void* p : {(void*)ctx->bkn, (void*)ctx->ksk, (void*)ctx->mf_key, (void*)ctx->tw, (void*)ctx->dev_err,
+  for (void* p : {(void*)ctx->bkn, (void*)ctx->ksk, (void*)ctx->mf_key, (void*)ctx->ks_mf, (void*)ctx->tw,
+                  (void*)ctx->dev_err,
                   ctx->abar.ptr, ctx->tlwe1.ptr, ctx->ntt_sel.ptr, ctx->mem_a.ptr, ctx->mem_b.ptr, ctx->mem_c.ptr,
                   ctx->mem_d.ptr, ctx->mf_work.ptr})
     if (p) (void)hipFree(p);

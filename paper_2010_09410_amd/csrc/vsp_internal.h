@@ -51,7 +51,8 @@ constexpr uint64_t kBucket[kTuneBuckets] = {1, 16, 64, 256, 1024, 2048, 4096};
 //    (ties: the 8-gate workgroup). br_force[b] != 0 pins the shape for bucket b.
 //  * Key switch: per bucket, form 0 gathers key rows per gate, 1 reads them once per tile of
 //    gates and selects in registers, 2 stages them through LDS for a tile of gates and splits
-//    the j range over workgroups.
+//    the j range over workgroups, 3 runs on the matrix cores (one-hot digit rows times the
+//    key's byte planes).
 struct Tuning {
   uint64_t br_cap[kBrShapes] = {1024, 2048, 512, 4096};
   float br_round_ms[kBrShapes] = {1.0f, 1.48f, 0.8f, 2.66f};
@@ -109,6 +110,7 @@ struct vsp_context {
   int device = 0;
   int cus = 1;                    // compute units of the device
   int8_t* mf_key = nullptr;       // bootstrapping key as balanced-byte Toeplitz rows (matrix-core form)
+  int8_t* ks_mf = nullptr;        // key-switching key as balanced bytes in MFMA operand order (key-switch form 3)
   uint64_t* bkn = nullptr;        // bootstrapping key, NTT domain: [n][TRGSW_NTT_U64]
   uint32_t* ksk = nullptr;        // key-switching key [N][t][4][n+1]; digit value 0 points at a zero row
   uint64_t* tw = nullptr;         // psi_u^j [32][32] then psi_u^-j [32][32]
@@ -137,7 +139,7 @@ vsp_status check_no_overlap(const void* a, size_t abytes, const void* b, size_t 
 // Converts host keys (BK torus [n][2l][2][N], KSK [N][t][3][n+1]) into freshly allocated device
 // buffers in the kernels' layouts; on failure nothing stays allocated.
 vsp_status upload_keys(const vsp_context* ctx, const uint32_t* bk_host, const uint32_t* ksk_host, uint64_t** bkn,
-                       uint32_t** ksk, int8_t** mf_key = nullptr);
+                       uint32_t** ksk, int8_t** mf_key = nullptr, int8_t** ks_mf = nullptr);
 
 // Grows a scratch buffer to at least `bytes` (synchronising the device before freeing).
 vsp_status scratch_reserve(vsp_context* ctx, Scratch& s, size_t bytes);
@@ -189,11 +191,17 @@ hipError_t init_mf_kernel_attributes();
 size_t mf_key_bytes();
 size_t mf_work_bytes(uint64_t B, bool need_acc);
 hipError_t launch_mf_key(const uint32_t* bk, int8_t* E, hipStream_t st);
+// Matrix-core key switch (keyswitch_mfma.hip).
+size_t ks_mf_key_bytes();
+hipError_t launch_ks_mfkey(const uint32_t* ksk, int8_t* KB, hipStream_t st);
+hipError_t launch_keyswitch_mfma(const int8_t* KB, const uint8_t* ops, const uint32_t* tlwe1, const uint32_t* idxo,
+                                 uint32_t* out, uint64_t B, hipStream_t st);
 hipError_t launch_blind_rotate_mfma(const vsp_context* ctx, const uint8_t* ops, const uint32_t* abar, uint32_t* tlwe1,
                                     uint32_t* trlwe, uint64_t B, void* work, hipStream_t st);
 // Identity key switch TLWE1 [B][N+1] -> TLWE0 [B][n+1] (outputs scattered by idxo if given).
-// form: 0 one workgroup per gate, 1 row-stationary tiles, 2 LDS-staged split, -1 the tuned one.
-constexpr int kKsForms = 3;
+// form: 0 one workgroup per gate, 1 row-stationary tiles, 2 LDS-staged split, 3 matrix cores
+// (the context's own key only; other keys run form 2), -1 the tuned one.
+constexpr int kKsForms = 4;
 // ksk: the key-switching key to use (NULL: the context's).
 hipError_t launch_keyswitch(const vsp_context* ctx, const uint8_t* ops, const uint32_t* tlwe1, const uint32_t* idxo,
                             uint32_t* out, uint64_t B, hipStream_t st, int form = -1, const uint32_t* ksk = nullptr);

@@ -16,10 +16,10 @@ TRUTH = {0: lambda a, b: 1 - (a & b), 1: lambda a, b: a & b, 2: lambda a, b: a |
          8: lambda a, b: 1 - a}
 
 
-def run_with(gpu, B, waves, fn):
+def run_with(gpu, B, waves, fn, ks=None):
     saved = gpu.tuning(B)
     try:
-        gpu.set_tuning(B, waves, saved[1])
+        gpu.set_tuning(B, waves, saved[1] if ks is None else ks)
         assert gpu.tuning(B)[0] == waves
         return fn()
     finally:
@@ -28,14 +28,18 @@ def run_with(gpu, B, waves, fn):
 
 def test_matrix_form_benchmark_batch(gpu, keys):
     """The 4096-gate batch: every output decrypts to the gate result, a sample is bit-exact
-    against the oracle, and the whole batch equals the 8-gate NTT form's."""
+    against the oracle, and the whole batch equals the 8-gate NTT form's, with the LDS-staged
+    and the matrix-core key switch."""
     cfg = W.config2()
     in0 = client.tlwe_encrypt_bits(keys["s0"], cfg["bits0"], *cfg["enc0"])
     in1 = client.tlwe_encrypt_bits(keys["s0"], cfg["bits1"], *cfg["enc1"])
     d0, d1, dops = gpu.tensor(in0), gpu.tensor(in1), gpu.tensor(cfg["ops"])
-    out = run_with(gpu, 4096, MATRIX, lambda: to_host(gpu.gates(dops, d0, d1)))
-    ref8 = run_with(gpu, 4096, NTT8, lambda: to_host(gpu.gates(dops, d0, d1)))
+    out = run_with(gpu, 4096, MATRIX, lambda: to_host(gpu.gates(dops, d0, d1)), ks=2)
+    ref8 = run_with(gpu, 4096, NTT8, lambda: to_host(gpu.gates(dops, d0, d1)), ks=2)
     np.testing.assert_array_equal(out, ref8)
+    # the matrix-core key switch (form 3) as well
+    out3 = run_with(gpu, 4096, MATRIX, lambda: to_host(gpu.gates(dops, d0, d1)), ks=3)
+    np.testing.assert_array_equal(out3, ref8)
     want = np.array([TRUTH[o](a, b) for o, a, b in zip(cfg["ops"], cfg["bits0"], cfg["bits1"])])
     np.testing.assert_array_equal(client.tlwe_decrypt(keys["s0"], out), want)
     idx = np.array([0, 31, 32, 2047, 4064, 4095] + list(W.rng(520).integers(0, 4096, 6)))
@@ -51,8 +55,10 @@ def test_matrix_form_ragged_tiles_with_not(gpu, keys, B):
     in0 = client.tlwe_encrypt_bits(keys["s0"], cfg["bits0"], *cfg["enc0"])
     in1 = client.tlwe_encrypt_bits(keys["s0"], cfg["bits1"], *cfg["enc1"])
     d0, d1, dops = gpu.tensor(in0), gpu.tensor(in1), gpu.tensor(cfg["ops"])
-    out = run_with(gpu, B, MATRIX, lambda: to_host(gpu.gates(dops, d0, d1)))
-    np.testing.assert_array_equal(out, oracle.gates(keys["bk"], keys["ksk"], cfg["ops"], in0, in1))
+    ref = oracle.gates(keys["bk"], keys["ksk"], cfg["ops"], in0, in1)
+    for ks in (2, 3):
+        out = run_with(gpu, B, MATRIX, lambda: to_host(gpu.gates(dops, d0, d1)), ks=ks)
+        np.testing.assert_array_equal(out, ref, err_msg=f"key-switch form {ks}")
 
 
 def test_matrix_form_trlwe_output(gpu, keys):
@@ -78,17 +84,18 @@ def test_matrix_form_trlwe_output(gpu, keys):
 
 
 def test_matrix_form_in_circuits_and_server(gpu, keys):
-    """Circuits (levels captured in a HIP graph) and the server use the matrix-core form when
-    the tuning picks it for their widths; their wires equal those of the NTT form."""
+    """Circuits (levels captured in a HIP graph) and the server use the matrix-core blind
+    rotation and key switch (outputs scattered by wire index) when the tuning picks them for
+    their widths; their wires equal those of the NTT form and the LDS-staged key switch."""
     from test_gpu_server import requests, wait
     buckets = (1, 16, 64)
     saved = {b: gpu.tuning(b) for b in buckets}
     reqs = requests(keys, 3, 860)
     try:
         results = {}
-        for form in (NTT8, MATRIX):
+        for form, ks in ((NTT8, 2), (MATRIX, 3)):
             for b in buckets:
-                gpu.set_tuning(b, form, saved[b][1])
+                gpu.set_tuning(b, form, ks)
             circ_out = []
             for c, inputs in reqs:
                 circ = gpu.circuit(c["gates"], c["ninputs"])

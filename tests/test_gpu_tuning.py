@@ -12,7 +12,7 @@ from paper_2010_09410_amd import VspError, client
 from paper_2010_09410_amd.device import to_host
 
 pytestmark = pytest.mark.gpu
-SHAPES = [(4, 0), (4, 1), (4, 2), (8, 0), (8, 1), (8, 2), (3, 0), (3, 2), (32, 2), (32, 0)]
+SHAPES = [(4, 0), (4, 1), (4, 2), (8, 0), (8, 1), (8, 2), (3, 0), (3, 2), (32, 2), (32, 0), (8, 3), (32, 3)]
 
 
 def batch(keys, B, seed):
@@ -52,7 +52,7 @@ def test_tuning_set_rejects_unknown_shapes(gpu):
     with pytest.raises(VspError):
         gpu.set_tuning(64, 2, 0)
     with pytest.raises(VspError):
-        gpu.set_tuning(64, 8, 3)
+        gpu.set_tuning(64, 8, 4)
 
 
 BUCKETS = (1, 16, 64, 256, 1024, 2048, 4096)
@@ -68,7 +68,7 @@ def test_autotune_model_and_cache_round_trip(gpu, tmp_path):
         assert entry["br_waves"] == [4, 8, 3, 32] and list(entry["buckets"]) == list(BUCKETS)
         cap4, cap8, capw, capm = entry["br_cap"]
         assert 256 <= cap4 < cap8 and capw >= 256 and capm >= cap8 and all(ms > 0 for ms in entry["br_round_ms"])
-        assert all(t in (0, 1, 2) for t in entry["ks_form"])
+        assert all(t in (0, 1, 2, 3) for t in entry["ks_form"])
         for b, t in zip(BUCKETS, entry["ks_form"]):
             assert gpu.tuning(b)[1] == t
         # the launch follows rounds x round time; a cache entry for this GPU is read back
