@@ -12,7 +12,9 @@
 // a'_j in registers. The key bytes are stored in the lane order of the other operand,
 // [plane][j][column tile][lane][16], so a wave's load of one block is 1 KiB contiguous.
 // A workgroup of four waves takes 128 gates and 64 output columns; wave s takes j in
-// [256 s, 256 s + 256), and the four partial sums meet in LDS.
+// [256 s, 256 s + 256), and the four partial sums meet in LDS. The digits of a gate depend only
+// on the top 16 bits of a'_j + 2^15 (a gate that does not bootstrap gets digits of 0, i.e. the
+// zero key row, and its output is not written).
 #include "vsp_internal.h"
 
 namespace vsp {
@@ -53,22 +55,22 @@ __global__ __launch_bounds__(256) void k_ks_mfkey(const u32* __restrict__ ksk, i
   reinterpret_cast<u32*>(KB)[id] = word;
 }
 
+// The top 16 bits of each rounded a'_j (all the digits need) are staged per wave in LDS as
+// [j][gate] u16 for chunks of KM_JC coefficients, rows padded to spread the banks; the key
+// operands stream from global memory three blocks ahead.
+constexpr int KM_JC = 64;
+constexpr int KM_HROW = KM_GATES + 2;  // u16 per staged row
+
 __global__ __launch_bounds__(256, 2) void k_ks_mfma(const int8_t* __restrict__ KB, const uint8_t* __restrict__ ops,
-                                                  const u32* __restrict__ tlwe1, const u32* __restrict__ idxo,
-                                                  u32* __restrict__ out, uint64_t B) {
-  __shared__ int red[4 * KM_COLS * 16][64];  // one wave's partial sums at a time
+                                                     const u32* __restrict__ tlwe1, const u32* __restrict__ idxo,
+                                                     u32* __restrict__ out, uint64_t B) {
+  __shared__ uint16_t hs[KM_SPLIT][KM_JC][KM_HROW];
+  static_assert(sizeof(hs) >= (size_t)4 * KM_COLS * 16 * 64 * 4, "the partial sums fit in the staging area");
   const int s = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int m = lane & 31, kh = lane >> 5;
   const uint64_t g0 = (uint64_t)blockIdx.x * KM_GATES;
   const int ct0 = blockIdx.y * KM_COLS;
   const int j0 = s * KM_JR;
-  // this lane's gate of each tile (rows of A), or none
-  const u32* arow[4];
-#pragma unroll
-  for (int t = 0; t < 4; t++) {
-    const uint64_t g = g0 + 32 * t + m;
-    arow[t] = (g < B && (!ops || op_bootstraps(ops[g]))) ? tlwe1 + g * TLWE1 : nullptr;
-  }
   const uint4* kb = reinterpret_cast<const uint4*>(KB) + lane;  // + ((b * N + j) * KM_CT + ct) * 64
   ks_v16i acc[4][KM_COLS];
 #pragma unroll
@@ -77,31 +79,47 @@ __global__ __launch_bounds__(256, 2) void k_ks_mfma(const int8_t* __restrict__ K
     for (int u = 0; u < KM_COLS; u++)
 #pragma unroll
       for (int x = 0; x < 16; x++) acc[t][u][x] = 0;
+  uint16_t(*h)[KM_HROW] = hs[s];
   for (int b = KM_PLANES - 1; b >= 0; b--) {
     const uint4* kp = kb + ((size_t)b * RING_N * KM_CT + ct0) * 64;
-    // key operands of the next block in flight while this one multiplies
-    uint4 bn[KM_COLS];
+    auto ldb = [&](int j, uint4 (&r)[KM_COLS]) {
 #pragma unroll
-    for (int u = 0; u < KM_COLS; u++) bn[u] = kp[((size_t)j0 * KM_CT + u) * 64];
-#pragma unroll 1
-    for (int j = j0; j < j0 + KM_JR; j++) {
-      ks_v4i bv[KM_COLS];
-#pragma unroll
-      for (int u = 0; u < KM_COLS; u++) bv[u] = ks_v4i{(int)bn[u].x, (int)bn[u].y, (int)bn[u].z, (int)bn[u].w};
-      if (j + 1 < j0 + KM_JR) {
-#pragma unroll
-        for (int u = 0; u < KM_COLS; u++) bn[u] = kp[((size_t)(j + 1) * KM_CT + u) * 64];
+      for (int u = 0; u < KM_COLS; u++) r[u] = kp[((size_t)j * KM_CT + u) * 64];
+    };
+    uint4 bq[4][KM_COLS];  // block j in slot (j - j0) mod 4
+    ldb(j0, bq[0]);
+    ldb(j0 + 1, bq[1]);
+    ldb(j0 + 2, bq[2]);
+    for (int jc = j0; jc < j0 + KM_JR; jc += KM_JC) {
+      // stage the digits' source bits of this wave's gates for jc .. jc + KM_JC - 1
+      wave_lds_sync();
+#pragma unroll 8
+      for (int gi = 0; gi < KM_GATES; gi++) {
+        const uint64_t g = g0 + gi;
+        const u32 x = (g < B) ? tlwe1[g * TLWE1 + jc + lane] : 0u;
+        h[lane][gi] = (uint16_t)((x + (1u << 15)) >> 16);
       }
+      wave_lds_sync();
+      for (int jj = 0; jj < KM_JC; jj += 4) {
 #pragma unroll
-      for (int t = 0; t < 4; t++) {
-        ks_v4i av = {0, 0, 0, 0};
-        if (arow[t]) {
-          const u32 ah = arow[t][j] + (1u << 15);
+        for (int r = 0; r < 4; r++) {
+          const int j = jc + jj + r;
+          if (j + 3 < j0 + KM_JR) ldb(j + 3, bq[(r + 3) & 3]);
+          ks_v4i bv[KM_COLS];
 #pragma unroll
-          for (int w = 0; w < 4; w++) av[w] = (int)(1u << (8 * ((ah >> (30 - 2 * (4 * kh + w))) & 3u)));
+          for (int u = 0; u < KM_COLS; u++)
+            bv[u] = ks_v4i{(int)bq[r][u].x, (int)bq[r][u].y, (int)bq[r][u].z, (int)bq[r][u].w};
+#pragma unroll
+          for (int t = 0; t < 4; t++) {
+            const u32 hv = h[jj + r][32 * t + m];
+            ks_v4i av;
+#pragma unroll
+            for (int w = 0; w < 4; w++) av[w] = (int)(1u << (8 * ((hv >> (14 - 2 * (4 * kh + w))) & 3u)));
+#pragma unroll
+            for (int u = 0; u < KM_COLS; u++)
+              acc[t][u] = __builtin_amdgcn_mfma_i32_32x32x32_i8(av, bv[u], acc[t][u], 0, 0, 0);
+          }
         }
-#pragma unroll
-        for (int u = 0; u < KM_COLS; u++) acc[t][u] = __builtin_amdgcn_mfma_i32_32x32x32_i8(av, bv[u], acc[t][u], 0, 0, 0);
       }
     }
     if (b > 0) {
@@ -114,6 +132,8 @@ __global__ __launch_bounds__(256, 2) void k_ks_mfma(const int8_t* __restrict__ K
     }
   }
   // the partial sums of waves 1..3 through LDS to wave 0, one wave at a time
+  int(*red)[64] = reinterpret_cast<int(*)[64]>(&hs[0][0][0]);
+  __syncthreads();  // every wave is done with its staging rows
   for (int q = 1; q < KM_SPLIT; q++) {
     if (s == q) {
 #pragma unroll

@@ -57,7 +57,7 @@ struct Tuning {
   uint64_t br_cap[kBrShapes] = {1024, 2048, 512, 4096};
   float br_round_ms[kBrShapes] = {1.0f, 1.48f, 0.8f, 2.66f};
   int br_force[kTuneBuckets] = {0, 0, 0, 0, 0, 0, 0};
-  int ks_form[kTuneBuckets] = {2, 2, 2, 2, 2, 2, 2};
+  int ks_form[kTuneBuckets] = {2, 2, 2, 2, 3, 3, 3};
   bool tuned = false;
   static int bucket(uint64_t B) {
     int b = 0;
