@@ -87,8 +87,10 @@ const char* vsp_last_error(void);
 /* Create a context on HIP device `device`: validates params, uploads the bootstrapping key
  * bk_host [n][2l][2][N] (BK[i] = TRGSW_{s1}(s0[i]), Sec. 2.1.2 "Bootstrapping Key") and the
  * key-switching key ksk_host [N][t][base-1][n+1] (entry [j][p][v-1] = TLWE_{s0}(v s1[j] /
- * base^(p+1))), converts the bootstrapping key to the NTT domain on the device, and
- * returns it in *out. Host arrays are copied; the caller keeps them. Synchronous. */
+ * base^(p+1))), converts the bootstrapping key to the NTT domain and to the byte-plane forms
+ * of the matrix-core blind rotation and key switch on the device (about 300 MB of device
+ * memory in all), and returns it in *out. Host arrays are copied; the caller keeps them.
+ * Synchronous. */
 vsp_status vsp_context_create(const vsp_params* params, const uint32_t* bk_host, const uint32_t* ksk_host,
                               int device, vsp_context** out);
 
@@ -235,7 +237,7 @@ vsp_status vsp_mux(vsp_context* ctx, const uint32_t* d_sel, const uint32_t* d_in
  * MFMA products of the batch's digit rows with the key's Toeplitz blocks (tiles of 32 gates;
  * one round holds 16 gates per compute unit; used by vsp_gates and vsp_bootstrap_trlwe with the
  * context's own key, the other callers run the 8-gate form in its place; it needs a workspace
- * of 14 KiB per gate, grown on demand). This call times one full round of each shape on random
+ * of 26 KiB per gate (18 KiB when the output is the TRLWE accumulator), grown on demand). This call times one full round of each shape on random
  * ciphertexts, and times the four key-switch forms (0: one workgroup per gate gathering its
  * key rows; 1: tiles of 16 gates reading each key row once and selecting in registers;
  * 2: tiles of 16 gates staging key rows through LDS, with the j range split over workgroups
