@@ -193,7 +193,7 @@ __global__ __launch_bounds__(256) void k_mf_digits(const uint8_t* __restrict__ o
 // Each sequence sits in LDS in four copies, copy c shifted down by c bytes, so that the
 // sixteen bytes from t0 are four aligned words of copy t0 mod 4 (the same copy for a lane at
 // every block kb, as t0 moves by 32).
-// The 24 passes (plane b from 3 down, row r) each stage the tile's 48 KB of row-r operands and
+// The 24 passes (plane b from 3 down, the six rows r) each stage the tile's 48 KB of row-r operands and
 // the copies of the three sequences (r, o, b); the next pass's data is loaded into registers
 // while the current pass computes, and stored to the other buffer after it. Within a pass the
 // LDS reads of block kb + 2 are issued before the four products of block kb; the B operands
@@ -215,6 +215,14 @@ constexpr size_t MF_STEP_LDS = MF_PASS_LDS > MF_NEXT_LDS ? MF_PASS_LDS : MF_NEXT
 static_assert(MF_A_PASS_U4 == 4 * MF_THREADS && MF_SUB * MF_S / 4 == MF_THREADS,
               "four 16-byte operands and one key word per thread and pass");
 static_assert((size_t)4 * 4 * 16 * 64 * 4 <= 2 * (size_t)MF_A_PASS_U4 * 16, "P1 fits in the operand buffers");
+
+// Row of pass p: the six rows of a byte plane in any order give the same plane sum, so odd
+// planes take them backwards and the rows a plane ends with are still in L2 when the next
+// one starts.
+__device__ __forceinline__ int mf_pass_row(int pass) {
+  const int r = pass % MF_ROWS;
+  return ((pass / MF_ROWS) & 1) ? MF_ROWS - 1 - r : r;
+}
 
 // Step kernel. With next_step >= 0 the workgroup then writes the digit operands of step
 // next_step for rows 3o .. 3o + 2 of its tile into Anext: they depend only on the updated
@@ -241,7 +249,7 @@ __global__ __launch_bounds__(MF_THREADS) void k_mf_step(const int8_t* __restrict
   // sequence t / 256, which needs words t mod 256 and the next one (zero past the end).
   const int es = tid >> 8, ew = tid & 255;
   auto e_row = [&](int pass) {
-    return Eu + ((((size_t)(pass % MF_ROWS) * 2 + o) * MF_PLANES + (MF_PLANES - 1 - pass / MF_ROWS)) * MF_SUB + es) *
+    return Eu + ((((size_t)mf_pass_row(pass) * 2 + o) * MF_PLANES + (MF_PLANES - 1 - pass / MF_ROWS)) * MF_SUB + es) *
                     (MF_S / 4);
   };
   auto stage_e = [&](u32* dst, u32 d0, u32 d1) {
@@ -272,7 +280,7 @@ __global__ __launch_bounds__(MF_THREADS) void k_mf_step(const int8_t* __restrict
   for (int pass = 0; pass < MF_PASSES; pass++) {
     const int buf = pass & 1;
     const int nx = (pass + 1 < MF_PASSES) ? pass + 1 : pass;  // the last pass fetches itself again, unused
-    const uint4* as = Ag + (size_t)(nx % MF_ROWS) * MF_A_PASS_U4 + tid;
+    const uint4* as = Ag + (size_t)mf_pass_row(nx) * MF_A_PASS_U4 + tid;
     const uint4 p0 = as[0], p1 = as[MF_THREADS], p2 = as[2 * MF_THREADS], p3 = as[3 * MF_THREADS];
     u32 pd0, pd1;
     {
