@@ -342,16 +342,42 @@ __global__ __launch_bounds__(MF_THREADS) void k_mf_step(const int8_t* __restrict
       for (int x = 0; x < 16; x++) p1buf[((wl * 4 + nb) * 16 + x) * 64 + lane] = (u32)c[nb][x];
   }
   __syncthreads();
+  // Loads below are unconditional, with the gate index clamped into the batch: a guarded load
+  // becomes a branch after which the compiler waits for it, one round trip per gate.
   if (sub != 0) {
     // result (m, i): lane n + 32 kh, register x: m = 8 (x / 4) + 4 kh + x % 4,
     // i = (sub - 1) N/2 + 128 (w mod 4) + 32 nb + n
+    uint8_t opv[16];
 #pragma unroll
-    for (int x = 0; x < 16; x++) {
-      const uint64_t g = mt * MF_TILE + 8 * (x >> 2) + 4 * kh + (x & 3);
-      if (g >= B || (ops && !op_bootstraps(ops[g]))) continue;
-      u32* p = acc + (g * 2 + o) * RING_N + (sub - 1) * MF_HALF + 128 * wl + n;
+    for (int x = 0; x < 16; x++) opv[x] = 0;  // a bootstrapping gate type
+    if (ops) {
 #pragma unroll
-      for (int nb = 0; nb < 4; nb++) p[32 * nb] += (u32)c[nb][x] + p1buf[((wl * 4 + nb) * 16 + x) * 64 + lane];
+      for (int x = 0; x < 16; x++) {
+        const uint64_t g = mt * MF_TILE + 8 * (x >> 2) + 4 * kh + (x & 3);
+        opv[x] = ops[g < B ? g : 0];
+      }
+    }
+#pragma unroll
+    for (int x0 = 0; x0 < 16; x0 += 8) {
+      u32 v[8][4];
+#pragma unroll
+      for (int xi = 0; xi < 8; xi++) {
+        const int x = x0 + xi;
+        const uint64_t g = mt * MF_TILE + 8 * (x >> 2) + 4 * kh + (x & 3);
+        const u32* p = acc + ((g < B ? g : 0) * 2 + o) * RING_N + (sub - 1) * MF_HALF + 128 * wl + n;
+#pragma unroll
+        for (int nb = 0; nb < 4; nb++) v[xi][nb] = p[32 * nb];
+      }
+#pragma unroll
+      for (int xi = 0; xi < 8; xi++) {
+        const int x = x0 + xi;
+        const uint64_t g = mt * MF_TILE + 8 * (x >> 2) + 4 * kh + (x & 3);
+        if (g >= B || !op_bootstraps(opv[x])) continue;
+        u32* p = acc + (g * 2 + o) * RING_N + (sub - 1) * MF_HALF + 128 * wl + n;
+#pragma unroll
+        for (int nb = 0; nb < 4; nb++)
+          p[32 * nb] = v[xi][nb] + (u32)c[nb][x] + p1buf[((wl * 4 + nb) * 16 + x) * 64 + lane];
+      }
     }
   }
   if (next_step < 0) return;
@@ -368,21 +394,33 @@ __global__ __launch_bounds__(MF_THREADS) void k_mf_step(const int8_t* __restrict
   u32* sA = reinterpret_cast<u32*>(mf_lds);
   int av[PER_T];
   bool lv[PER_T];
+  uint8_t opq[PER_T];
+#pragma unroll
+  for (int q = 0; q < PER_T; q++) opq[q] = 0;
+  if (ops) {
+#pragma unroll
+    for (int q = 0; q < PER_T; q++) {
+      const uint64_t g = mt * MF_TILE + ((tid + q * MF_THREADS) >> 7);
+      opq[q] = ops[g < B ? g : 0];
+    }
+  }
 #pragma unroll
   for (int q = 0; q < PER_T; q++) {
     const int it = tid + q * MF_THREADS;
     const uint64_t g = mt * MF_TILE + (it >> 7);
-    lv[q] = it < ITEMS && g < B && (!ops || op_bootstraps(ops[g]));
-    av[q] = lv[q] ? (int)abar[g * TLWE0 + next_step] : 0;
+    lv[q] = it < ITEMS && g < B && op_bootstraps(opq[q]);
+    av[q] = (int)abar[(g < B ? g : 0) * TLWE0 + next_step];
   }
+  // (the values of a gate that is not live are loaded from gate 0 and never used)
   u32 own[PER_T][2][4], rot[PER_T][2][4];
 #pragma unroll
   for (int q = 0; q < PER_T; q++) {
     const int it = tid + q * MF_THREADS, m = it >> 7, jg = it & 127;
-    const u32* p = acc + ((mt * MF_TILE + m) * 2 + o) * RING_N;
+    const uint64_t g = mt * MF_TILE + m;
+    const u32* p = acc + ((g < B ? g : 0) * 2 + o) * RING_N;
 #pragma unroll
     for (int half = 0; half < 2; half++) {
-      const uint4 u = lv[q] ? reinterpret_cast<const uint4*>(p)[half * (MF_HALF / 4) + jg] : make_uint4(0u, 0u, 0u, 0u);
+      const uint4 u = reinterpret_cast<const uint4*>(p)[half * (MF_HALF / 4) + jg];
       own[q][half][0] = u.x;
       own[q][half][1] = u.y;
       own[q][half][2] = u.z;
@@ -390,7 +428,7 @@ __global__ __launch_bounds__(MF_THREADS) void k_mf_step(const int8_t* __restrict
 #pragma unroll
       for (int s = 0; s < 4; s++) {
         const int ix = (half * MF_HALF + 4 * jg + 3 - s - av[q]) & (2 * RING_N - 1);
-        const u32 r = lv[q] ? p[ix & (RING_N - 1)] : 0u;
+        const u32 r = p[ix & (RING_N - 1)];
         rot[q][half][s] = (ix & RING_N) ? 0u - r : r;
       }
     }

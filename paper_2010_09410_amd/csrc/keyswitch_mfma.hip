@@ -56,8 +56,10 @@ __global__ __launch_bounds__(256) void k_ks_mfkey(const u32* __restrict__ ksk, i
 }
 
 // The top 16 bits of each rounded a'_j (all the digits need) are staged per wave in LDS as
-// [j][gate] u16 for chunks of KM_JC coefficients, rows padded to spread the banks; the key
-// operands stream from global memory three blocks ahead.
+// [j][gate] u16 for chunks of KM_JC coefficients, rows padded to spread the banks, with 32
+// gates' loads in flight at once; the key operands stream from global memory three blocks
+// ahead. Every load is unconditional (gate index clamped, the last three key blocks re-read
+// and unused): a guarded load becomes a branch, after which the compiler waits for it.
 constexpr int KM_JC = 64;
 constexpr int KM_HROW = KM_GATES + 2;  // u16 per staged row
 
@@ -93,18 +95,24 @@ __global__ __launch_bounds__(256, 2) void k_ks_mfma(const int8_t* __restrict__ K
     for (int jc = j0; jc < j0 + KM_JR; jc += KM_JC) {
       // stage the digits' source bits of this wave's gates for jc .. jc + KM_JC - 1
       wave_lds_sync();
-#pragma unroll 8
-      for (int gi = 0; gi < KM_GATES; gi++) {
-        const uint64_t g = g0 + gi;
-        const u32 x = (g < B) ? tlwe1[g * TLWE1 + jc + lane] : 0u;
-        h[lane][gi] = (uint16_t)((x + (1u << 15)) >> 16);
+#pragma unroll 1
+      for (int q0 = 0; q0 < KM_GATES; q0 += 32) {
+        u32 v[32];
+#pragma unroll
+        for (int q = 0; q < 32; q++) {
+          const uint64_t g = g0 + q0 + q;
+          v[q] = tlwe1[(g < B ? g : 0) * TLWE1 + jc + lane];
+        }
+#pragma unroll
+        for (int q = 0; q < 32; q++)
+          h[lane][q0 + q] = (g0 + q0 + q < B) ? (uint16_t)((v[q] + (1u << 15)) >> 16) : (uint16_t)0;
       }
       wave_lds_sync();
       for (int jj = 0; jj < KM_JC; jj += 4) {
 #pragma unroll
         for (int r = 0; r < 4; r++) {
           const int j = jc + jj + r;
-          if (j + 3 < j0 + KM_JR) ldb(j + 3, bq[(r + 3) & 3]);
+          ldb(j + 3 < j0 + KM_JR ? j + 3 : j0 + KM_JR - 1, bq[(r + 3) & 3]);
           ks_v4i bv[KM_COLS];
 #pragma unroll
           for (int u = 0; u < KM_COLS; u++)
