@@ -252,6 +252,34 @@ __global__ __launch_bounds__(256) void k_keyswitch(const u32* __restrict__ ksk, 
   if (has2) o[c2] = (c2 == LWE_N ? b : 0u) - acc2;
 }
 
+// Gate types and output rows of a tile's G gates, loaded together (unconditionally, index
+// clamped into the batch: a guarded load becomes a branch after which the compiler waits for
+// it, one round trip per gate).
+template <int G>
+__device__ __forceinline__ void tile_rows(const uint8_t* ops, const u32* idxo, uint64_t g0, int ng, bool (&live)[G],
+                                          uint64_t (&ro)[G]) {
+  uint8_t opv[G];
+  u32 iv[G];
+#pragma unroll
+  for (int g = 0; g < G; g++) {
+    opv[g] = 0;  // a bootstrapping gate type
+    iv[g] = 0;
+  }
+  if (ops) {
+#pragma unroll
+    for (int g = 0; g < G; g++) opv[g] = ops[g0 + (g < ng ? g : 0)];
+  }
+  if (idxo) {
+#pragma unroll
+    for (int g = 0; g < G; g++) iv[g] = idxo[g0 + (g < ng ? g : 0)];
+  }
+#pragma unroll
+  for (int g = 0; g < G; g++) {
+    live[g] = g < ng && op_bootstraps(opv[g]);
+    ro[g] = idxo ? (uint64_t)iv[g] : g0 + g;
+  }
+}
+
 // Row-stationary form: a workgroup takes a tile of G gates; for every (j, p) it loads the
 // three key rows once (3 coefficients per thread) and applies them to all G gates, whose
 // digits are wave-uniform values. The key is then read once per tile instead of once per
@@ -272,7 +300,7 @@ __global__ __launch_bounds__(256) void k_keyswitch_tiled(const u32* __restrict__
     u32 ahat[G];
 #pragma unroll
     for (int g = 0; g < G; g++)
-      ahat[g] = (g < ng ? __builtin_amdgcn_readfirstlane(tlwe1[(g0 + g) * TLWE1 + j]) : 0u) + (1u << 15);
+      ahat[g] = __builtin_amdgcn_readfirstlane(tlwe1[(g0 + (g < ng ? g : 0)) * TLWE1 + j]) + (1u << 15);
     const u32* base = ksk + (size_t)j * KS_T * 4 * TLWE0;
 #pragma unroll 2
     for (int p = 0; p < KS_T; p++) {
@@ -289,12 +317,14 @@ __global__ __launch_bounds__(256) void k_keyswitch_tiled(const u32* __restrict__
       }
     }
   }
+  bool live[G];
+  uint64_t ro[G];
+  tile_rows<G>(ops, idxo, g0, ng, live, ro);
 #pragma unroll
   for (int g = 0; g < G; g++) {
     const uint64_t gg = g0 + g;
-    if (g < ng && (!ops || op_bootstraps(ops[gg]))) {
-      const uint64_t ro = idxo ? idxo[gg] : gg;
-      u32* o = out + ro * TLWE0;
+    if (live[g]) {
+      u32* o = out + ro[g] * TLWE0;
       o[c0] = 0u - acc[g][0];
       o[c1] = 0u - acc[g][1];
       if (has2) o[c2] = (c2 == LWE_N ? tlwe1[gg * TLWE1 + RING_N] : 0u) - acc[g][2];
@@ -364,7 +394,7 @@ __global__ __launch_bounds__(256) void k_keyswitch_split(const u32* __restrict__
   for (int j = j0; j < j1; j++) {
     u32 ahat[G];
 #pragma unroll
-    for (int g = 0; g < G; g++) ahat[g] = (g < ng ? tlwe1[(g0 + g) * TLWE1 + j] : 0u) + (1u << 15);
+    for (int g = 0; g < G; g++) ahat[g] = tlwe1[(g0 + (g < ng ? g : 0)) * TLWE1 + j] + (1u << 15);  // unconditional
 #pragma unroll 1
     for (int p = 0; p < KS_T; p++) {
       const bool more = (p + 1 < KS_T) || (j + 1 < j1);
@@ -383,12 +413,13 @@ __global__ __launch_bounds__(256) void k_keyswitch_split(const u32* __restrict__
       buf ^= 1;
     }
   }
+  bool live[G];
+  uint64_t ro[G];
+  tile_rows<G>(ops, idxo, g0, ng, live, ro);
 #pragma unroll
   for (int g = 0; g < G; g++) {
-    const uint64_t gg = g0 + g;
-    if (g < ng && (!ops || op_bootstraps(ops[gg]))) {
-      const uint64_t ro = idxo ? idxo[gg] : gg;
-      u32* o = out + ro * TLWE0;
+    if (live[g]) {
+      u32* o = out + ro[g] * TLWE0;
       __hip_atomic_fetch_add(&o[c0], 0u - acc[g][0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_fetch_add(&o[c1], 0u - acc[g][1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (c2 < TLWE0) __hip_atomic_fetch_add(&o[c2], 0u - acc[g][2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

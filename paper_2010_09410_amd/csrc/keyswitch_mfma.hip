@@ -164,19 +164,50 @@ __global__ __launch_bounds__(256, 2) void k_ks_mfma(const int8_t* __restrict__ K
   }
   if (s != 0) return;
   // result (gate, column): lane n + 32 kh, register x: gate row 8 (x / 4) + 4 kh + x % 4 of the
-  // tile, column 32 ct + n
+  // tile, column 32 ct + n. Per tile, the gate types, output rows and b' of the lane's 16 gates
+  // are loaded together first (unconditionally, gate index clamped).
+  const bool has_b = ct0 + KM_COLS > LWE_N / 32;  // this workgroup writes column n (the b part)
 #pragma unroll
   for (int t = 0; t < 4; t++) {
+    uint8_t opv[16];
+    u32 rov[16], bv[16];
 #pragma unroll
     for (int x = 0; x < 16; x++) {
       const uint64_t g = g0 + 32 * t + 8 * (x >> 2) + 4 * kh + (x & 3);
-      if (g >= B || (ops && !op_bootstraps(ops[g]))) continue;
-      const uint64_t ro = idxo ? idxo[g] : g;
+      opv[x] = 0;  // a bootstrapping gate type
+      rov[x] = (u32)g;
+      bv[x] = 0;
+    }
+    if (ops) {
+#pragma unroll
+      for (int x = 0; x < 16; x++) {
+        const uint64_t g = g0 + 32 * t + 8 * (x >> 2) + 4 * kh + (x & 3);
+        opv[x] = ops[g < B ? g : 0];
+      }
+    }
+    if (idxo) {
+#pragma unroll
+      for (int x = 0; x < 16; x++) {
+        const uint64_t g = g0 + 32 * t + 8 * (x >> 2) + 4 * kh + (x & 3);
+        rov[x] = idxo[g < B ? g : 0];
+      }
+    }
+    if (has_b) {
+#pragma unroll
+      for (int x = 0; x < 16; x++) {
+        const uint64_t g = g0 + 32 * t + 8 * (x >> 2) + 4 * kh + (x & 3);
+        bv[x] = tlwe1[(g < B ? g : 0) * TLWE1 + RING_N];
+      }
+    }
+#pragma unroll
+    for (int x = 0; x < 16; x++) {
+      const uint64_t g = g0 + 32 * t + 8 * (x >> 2) + 4 * kh + (x & 3);
+      if (g >= B || !op_bootstraps(opv[x])) continue;
 #pragma unroll
       for (int u = 0; u < KM_COLS; u++) {
         const int c = 32 * (ct0 + u) + m;
         if (c >= TLWE0) continue;
-        out[ro * TLWE0 + c] = ((c == LWE_N) ? tlwe1[g * TLWE1 + RING_N] : 0u) - (u32)acc[t][u][x];
+        out[(uint64_t)rov[x] * TLWE0 + c] = ((c == LWE_N) ? bv[x] : 0u) - (u32)acc[t][u][x];
       }
     }
   }
