@@ -61,6 +61,24 @@ def test_matrix_form_ragged_tiles_with_not(gpu, keys, B):
         np.testing.assert_array_equal(out, ref, err_msg=f"key-switch form {ks}")
 
 
+def test_matrix_form_beyond_one_round(gpu, keys):
+    """4,129 gates: more tiles than one round of the chip holds and a ragged last tile, with
+    NOT gates; the matrix form with both key switches equals the 8-gate NTT form over the
+    whole batch, and samples from the last tile are bit-exact against the oracle."""
+    B = 4096 + 33
+    cfg = W.gate_batch(60, B)
+    cfg["ops"] = W.rng(560).integers(0, 9, B).astype(np.uint8)
+    in0 = client.tlwe_encrypt_bits(keys["s0"], cfg["bits0"], *cfg["enc0"])
+    in1 = client.tlwe_encrypt_bits(keys["s0"], cfg["bits1"], *cfg["enc1"])
+    d0, d1, dops = gpu.tensor(in0), gpu.tensor(in1), gpu.tensor(cfg["ops"])
+    ref8 = run_with(gpu, B, NTT8, lambda: to_host(gpu.gates(dops, d0, d1)), ks=2)
+    for ks in (2, 3):
+        out = run_with(gpu, B, MATRIX, lambda: to_host(gpu.gates(dops, d0, d1)), ks=ks)
+        np.testing.assert_array_equal(out, ref8, err_msg=f"key-switch form {ks}")
+    idx = np.array([4095, 4096, 4100, B - 1])
+    np.testing.assert_array_equal(ref8[idx], oracle.gates(keys["bk"], keys["ksk"], cfg["ops"][idx], in0[idx], in1[idx]))
+
+
 def test_matrix_form_trlwe_output(gpu, keys):
     """Accumulator output: bit-exact against the oracle's TRLWE for bootstrapping gates; NOT
     gates are reported as having no TRLWE form and their rows keep what the buffer held."""
