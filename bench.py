@@ -93,6 +93,7 @@ MF_OPS_PER_TILE = 2 * MF_TILE * 2 * 3 * (N_RING // 2) ** 2 * 2 * GL * 4
 MF_A_TILE_BYTES = 2 * GL * 3 * (N_RING // 2) * MF_TILE      # digit operands of a tile (int8)
 MF_KEY_STEP_BYTES = 2 * GL * 2 * 4 * 3 * N_RING             # three key sequences per row, output, plane
 PEAK_INT8 = 5.0e15                                          # dense int8 MFMA, ops/s
+PROF_PERIOD = 16                                            # event-timed launches: one in PROF_PERIOD
 
 
 def mf_step_ops(B: int) -> int:
@@ -353,7 +354,10 @@ def main():
     for _ in range(args.warmup):
         ctx.gates(ops_d, a_d, b_d, out=out)
     ctx.sync()
-    nv.vsp_profile_enable(ctx.handle, True)
+    # kernel times live over the timed region, from HIP events around every PROF_PERIOD-th
+    # launch of each kind (event pairs around all 630 step launches of a batch would cost
+    # about 6% of its time)
+    nv.vsp_profile_enable(ctx.handle, PROF_PERIOD)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -443,7 +447,8 @@ def main():
         roof = {"bound": "mfma", "kernel": "k_mf_step", "achieved": round(achieved / 1e12, 1),
                 "peak": PEAK_INT8 / 1e12, "unit": "TOP/s (int8)", "frac": round(achieved / PEAK_INT8, 4),
                 "traffic": traffic, "traffic_source": traffic_src, "avg_launch_ms": round(mf_avg, 4),
-                "launches_per_batch": mf_n // max(args.steps, 1), "int8_ops_per_launch": mf_step_ops(B_GATES),
+                "launches_per_batch": N_LWE, "timed_launches": mf_n, "event_sample_period": PROF_PERIOD,
+                "int8_ops_per_launch": mf_step_ops(B_GATES),
                 "hbm": {"achieved": round(hbm / 1e9, 1), "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                         "frac": round(hbm / HBM_PEAK, 4), "algorithmic_bytes_per_launch": mf_step_hbm_bytes(B_GATES),
                         "measured_GBps": None if traffic is None else round(traffic / (mf_avg * 1e-3) / 1e9, 1)},

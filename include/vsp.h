@@ -260,15 +260,19 @@ vsp_status vsp_tuning_get(const vsp_context* ctx, uint64_t B, int* br_waves, int
  * bucket to the round-time model), ks_form 0, 1, 2 or 3. Results are the same for every choice. */
 vsp_status vsp_tuning_set(vsp_context* ctx, uint64_t B, int br_waves, int ks_form);
 
-/* Kernel-time instrumentation (for benchmarks): while enabled, every eager launch of the
- * blind-rotation, key-switch and gate-prologue kernels made by this context is bracketed by
- * HIP events on the stream it runs on (for the matrix-core form, also each of its step
- * kernels). Enabling resets the totals. */
+/* Kernel-time instrumentation (for benchmarks): with on >= 1, eager launches of the
+ * blind-rotation, key-switch and gate-prologue kernels made by this context are bracketed by
+ * HIP events on the stream they run on (for the matrix-core form, also its step kernels):
+ * every launch with on = 1, every on-th launch of each kind with on > 1 (event pairs around
+ * each of the 630 step launches of a batch cost several percent of its time; sampling keeps
+ * the measurement live at a fraction of that). on = 0 disables, on < 0 is VSP_E_ARG.
+ * Enabling resets the totals. */
 vsp_status vsp_profile_enable(vsp_context* ctx, int on);
 
-/* Device time (ms, summed) and number of launches of kernel `which` since enabling:
- * 0 = blind rotation, 1 = key switch, 2 = gate prologue, 3 = step kernel of the matrix-core
- * blind rotation (one per CMUX step). Synchronises the device. */
+/* Device time (ms, summed) and number of instrumented launches of kernel `which` since
+ * enabling (all launches, or the sampled ones with a period): 0 = blind rotation, 1 = key
+ * switch, 2 = gate prologue, 3 = step kernel of the matrix-core blind rotation (one per CMUX
+ * step). Synchronises the device. */
 vsp_status vsp_profile_read(vsp_context* ctx, int which, double* total_ms, uint64_t* launches);
 
 /* Test entry: d_out[j] = C_j (ext) x_j for J (TRGSW, TRLWE) pairs, the external product

@@ -265,8 +265,9 @@ def vsp_tuning_set(ctx, B: int, br_waves: int, ks_form: int) -> None:
     _call("vsp_tuning_set", ctx, B, br_waves, ks_form)
 
 
-def vsp_profile_enable(ctx, on: bool) -> None:
-    _call("vsp_profile_enable", ctx, 1 if on else 0)
+def vsp_profile_enable(ctx, on) -> None:
+    """on: False/0 off, True/1 every launch, k > 1 every k-th launch of each kind."""
+    _call("vsp_profile_enable", ctx, int(on))
 
 
 def vsp_profile_read(ctx, which: int):

@@ -68,7 +68,7 @@ vsp_status scratch_reserve(vsp_context* ctx, Scratch& s, size_t bytes) {
 }
 
 ProfScope::ProfScope(const vsp_context* c, int w, hipStream_t s) : ctx(c), which(w), st(s) {
-  if (!ctx->prof.on) return;
+  if (!ctx->prof.on || ctx->prof.seen[which]++ % (uint64_t)ctx->prof.period != 0) return;
   hipEvent_t e0;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     (void)hipGetLastError();
@@ -429,9 +429,12 @@ vsp_status vsp_profile_enable(vsp_context* ctx, int on) {
   vsp_status s = check_ctx(ctx);
   if (s) return s;
   VSP_HIP(hipSetDevice(ctx->device));
+  if (on < 0) return fail(VSP_E_ARG, "on must be 0 (off), 1 (every launch) or a sampling period");
   VSP_HIP(hipDeviceSynchronize());
   profile_clear(ctx);
   ctx->prof.on = on != 0;
+  ctx->prof.period = on > 1 ? on : 1;
+  for (auto& n : ctx->prof.seen) n = 0;
   return VSP_OK;
 }
 

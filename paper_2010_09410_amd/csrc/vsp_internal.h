@@ -93,6 +93,8 @@ struct Scratch {
 constexpr int kProfClasses = 4;
 struct Profile {
   bool on = false;
+  int period = 1;                  // instrument every period-th launch of each class
+  uint64_t seen[kProfClasses] = {};  // launches of each class since enabling
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[kProfClasses];
 };
 

@@ -83,3 +83,26 @@ def test_autotune_model_and_cache_round_trip(gpu, tmp_path):
     finally:
         for b, t in saved.items():
             gpu.set_tuning(b, 0, t)
+
+
+def test_profile_sampling(gpu, keys):
+    """Kernel-time instrumentation: every launch with on = 1, every k-th launch of each kind
+    with on = k, none after disabling; a negative setting is an argument error."""
+    from paper_2010_09410_amd import _native as nv
+    cfg, in0, in1 = batch(keys, 8, 7)
+    d0, d1, dops = gpu.tensor(in0), gpu.tensor(in1), gpu.tensor(cfg["ops"])
+    out = gpu.gates(dops, d0, d1)
+    try:
+        for period, want in ((1, 8), (3, 3), (8, 1)):
+            nv.vsp_profile_enable(gpu.handle, period)
+            for _ in range(8):
+                gpu.gates(dops, d0, d1, out=out)
+            ms, n = nv.vsp_profile_read(gpu.handle, 0)
+            assert n == want and ms > 0, (period, n, ms)
+        nv.vsp_profile_enable(gpu.handle, 0)
+        gpu.gates(dops, d0, d1, out=out)
+        assert nv.vsp_profile_read(gpu.handle, 0)[1] == 0
+        with pytest.raises(VspError):
+            nv.vsp_profile_enable(gpu.handle, -1)
+    finally:
+        nv.vsp_profile_enable(gpu.handle, 0)
