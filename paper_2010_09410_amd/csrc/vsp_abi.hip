@@ -214,7 +214,7 @@ vsp_status vsp_context_create(const vsp_params* params, const uint32_t* bk_host,
     return fail(VSP_E_ARG, "params, bk_host and ksk_host must not be NULL");
   if (params->n != LWE_N || params->N != RING_N || params->k != 1 || params->l != GADGET_L ||
       params->bg_bits != BG_BIT || params->ks_t != KS_T || params->ks_basebit != KS_BASEBIT)
-    return fail(VSP_E_PARAMS, "this build supports n=630 N=1024 k=1 l=3 bg_bits=6 ks_t=8 ks_basebit=2 only");
+    return fail(VSP_E_PARAMS, "the library supports n=630 N=1024 k=1 l=3 bg_bits=6 ks_t=8 ks_basebit=2 only");
   int ndev = 0;
   VSP_HIP(hipGetDeviceCount(&ndev));
   if (device < 0 || device >= ndev) return fail(VSP_E_ARG, "no such device");
