@@ -13,8 +13,8 @@
 // [plane][j][column tile][lane][16], so a wave's load of one block is 1 KiB contiguous.
 // A workgroup of four waves takes 128 gates and 64 output columns; wave s takes j in
 // [256 s, 256 s + 256), and the four partial sums meet in LDS. The digits of a gate depend only
-// on the top 16 bits of a'_j + 2^15 (a gate that does not bootstrap gets digits of 0, i.e. the
-// zero key row, and its output is not written).
+// on the top 16 bits of a'_j + 2^15. Rows past the batch get digits of 0 (the zero key row);
+// a gate that does not bootstrap is computed like the others and its output is not written.
 #include "vsp_internal.h"
 
 namespace vsp {
