@@ -198,8 +198,9 @@ __global__ __launch_bounds__(256) void k_mf_digits(const uint8_t* __restrict__ o
 // while the current pass computes, and stored to the other buffer after it. Within a pass the
 // LDS reads of block kb + 2 are issued before the four products of block kb; the B operands
 // live in a ring of eight registers (block nb at kb in slot (nb - kb) mod 8), so the Toeplitz
-// shift costs no moves. At the end P1 goes through LDS to the waves of P2 and P3, which add
-// y0 = P1 + P2 and y1 = P1 + P3 to ACC.
+// shift costs no moves. At the end P1 goes through LDS to the waves of P2 and P3, which form
+// y0 = P1 + P2 and y1 = P1 + P3 in LDS; the workgroup adds y to ACC and keeps the updated
+// polynomial in LDS, where the next step's digits are formed.
 constexpr int MF_WAVES = 12;
 constexpr int MF_THREADS = MF_WAVES * 64;
 constexpr int MF_A_PASS_U4 = (int)(MF_A_ROW / 16);      // 3072 16-byte operands per row and tile
@@ -209,9 +210,9 @@ constexpr int MF_PASSES = MF_PLANES * MF_ROWS;
 constexpr int MF_COPY_U32 = MF_S / 4 + 8;
 constexpr int MF_ECOPIES_U32 = MF_SUB * 4 * MF_COPY_U32;
 constexpr size_t MF_PASS_LDS = 2 * ((size_t)MF_A_PASS_U4 * 16 + (size_t)MF_ECOPIES_U32 * 4);
-constexpr int MF_SROW = 65;                                 // staging row: 64 lanes and a pad word
-constexpr size_t MF_NEXT_LDS = (size_t)GADGET_L * MF_SUB * MF_KB * 4 * MF_SROW * 4;  // next step's rows 3o .. 3o + 2
-constexpr size_t MF_STEP_LDS = MF_PASS_LDS > MF_NEXT_LDS ? MF_PASS_LDS : MF_NEXT_LDS;
+constexpr int MF_PROW = RING_N + 1;
+constexpr size_t MF_POLY_LDS = (size_t)MF_TILE * MF_PROW * 4;
+constexpr size_t MF_STEP_LDS = MF_PASS_LDS > MF_POLY_LDS ? MF_PASS_LDS : MF_POLY_LDS;
 static_assert(MF_A_PASS_U4 == 4 * MF_THREADS && MF_SUB * MF_S / 4 == MF_THREADS,
               "four 16-byte operands and one key word per thread and pass");
 static_assert((size_t)4 * 4 * 16 * 64 * 4 <= 2 * (size_t)MF_A_PASS_U4 * 16, "P1 fits in the operand buffers");
@@ -332,8 +333,8 @@ __global__ __launch_bounds__(MF_THREADS) void k_mf_step(const int8_t* __restrict
     }
     __syncthreads();
   }
-  // P1 to LDS ([w mod 4][nb][x][lane]), then y0 = P1 + P2 (sub 1, outputs [0, N/2)) and
-  // y1 = P1 + P3 (sub 2, outputs [N/2, N)).
+  // P1 to LDS ([w mod 4][nb][x][lane]); the P2 and P3 waves add it: y0 = P1 + P2 (sub 1,
+  // outputs [0, N/2)), y1 = P1 + P3 (sub 2, outputs [N/2, N)).
   u32* p1buf = reinterpret_cast<u32*>(mf_lds);
   if (sub == 0) {
 #pragma unroll
@@ -342,116 +343,108 @@ __global__ __launch_bounds__(MF_THREADS) void k_mf_step(const int8_t* __restrict
       for (int x = 0; x < 16; x++) p1buf[((wl * 4 + nb) * 16 + x) * 64 + lane] = (u32)c[nb][x];
   }
   __syncthreads();
-  // Loads below are unconditional, with the gate index clamped into the batch: a guarded load
-  // becomes a branch after which the compiler waits for it, one round trip per gate.
   if (sub != 0) {
-    // result (m, i): lane n + 32 kh, register x: m = 8 (x / 4) + 4 kh + x % 4,
-    // i = (sub - 1) N/2 + 128 (w mod 4) + 32 nb + n
-    uint8_t opv[16];
 #pragma unroll
-    for (int x = 0; x < 16; x++) opv[x] = 0;  // a bootstrapping gate type
+    for (int nb = 0; nb < 4; nb++)
+#pragma unroll
+      for (int x = 0; x < 16; x++) c[nb][x] = (int)((u32)c[nb][x] + p1buf[((wl * 4 + nb) * 16 + x) * 64 + lane]);
+  }
+  __syncthreads();
+  // y to LDS as rows of MF_PROW words per gate: result (m, i) is lane n + 32 kh, register x of
+  // block nb with m = 8 (x / 4) + 4 kh + x % 4, i = (sub - 1) N/2 + 128 (w mod 4) + 32 nb + n
+  u32* poly = reinterpret_cast<u32*>(mf_lds);
+  if (sub != 0) {
+#pragma unroll
+    for (int nb = 0; nb < 4; nb++)
+#pragma unroll
+      for (int x = 0; x < 16; x++)
+        poly[(8 * (x >> 2) + 4 * kh + (x & 3)) * MF_PROW + (sub - 1) * MF_HALF + 128 * wl + 32 * nb + n] = (u32)c[nb][x];
+  }
+  __syncthreads();
+  // ACC += y for the gates that bootstrap (coalesced, all loads in flight first); the updated
+  // polynomial stays in LDS for the next step's digits. Loads here and below are unconditional,
+  // with the gate index clamped into the batch: a guarded load becomes a branch after which the
+  // compiler waits for it, one round trip per load.
+  {
+    constexpr int PER = MF_TILE * RING_N / MF_THREADS + 1;
+    u32 av[PER];
+    bool lv[PER];
+    uint8_t opv[PER];
+#pragma unroll
+    for (int q = 0; q < PER; q++) opv[q] = 0;
     if (ops) {
 #pragma unroll
-      for (int x = 0; x < 16; x++) {
-        const uint64_t g = mt * MF_TILE + 8 * (x >> 2) + 4 * kh + (x & 3);
-        opv[x] = ops[g < B ? g : 0];
+      for (int q = 0; q < PER; q++) {
+        const uint64_t g = mt * MF_TILE + ((tid + q * MF_THREADS) >> 10);
+        opv[q] = ops[g < B ? g : 0];
       }
     }
 #pragma unroll
-    for (int x0 = 0; x0 < 16; x0 += 8) {
-      u32 v[8][4];
+    for (int q = 0; q < PER; q++) {
+      const int idx = tid + q * MF_THREADS;
+      const uint64_t g = mt * MF_TILE + (idx >> 10);
+      const uint64_t gc = g < B ? g : 0;
+      lv[q] = idx < MF_TILE * RING_N && g < B && op_bootstraps(opv[q]);
+      av[q] = acc[(gc * 2 + o) * RING_N + (idx & (RING_N - 1))];
+    }
 #pragma unroll
-      for (int xi = 0; xi < 8; xi++) {
-        const int x = x0 + xi;
-        const uint64_t g = mt * MF_TILE + 8 * (x >> 2) + 4 * kh + (x & 3);
-        const u32* p = acc + ((g < B ? g : 0) * 2 + o) * RING_N + (sub - 1) * MF_HALF + 128 * wl + n;
-#pragma unroll
-        for (int nb = 0; nb < 4; nb++) v[xi][nb] = p[32 * nb];
-      }
-#pragma unroll
-      for (int xi = 0; xi < 8; xi++) {
-        const int x = x0 + xi;
-        const uint64_t g = mt * MF_TILE + 8 * (x >> 2) + 4 * kh + (x & 3);
-        if (g >= B || !op_bootstraps(opv[x])) continue;
-        u32* p = acc + (g * 2 + o) * RING_N + (sub - 1) * MF_HALF + 128 * wl + n;
-#pragma unroll
-        for (int nb = 0; nb < 4; nb++)
-          p[32 * nb] = v[xi][nb] + (u32)c[nb][x] + p1buf[((wl * 4 + nb) * 16 + x) * 64 + lane];
-      }
+    for (int q = 0; q < PER; q++) {
+      if (!lv[q]) continue;
+      const int idx = tid + q * MF_THREADS, m = idx >> 10, i = idx & (RING_N - 1);
+      u32* pp = poly + m * MF_PROW + i;
+      const u32 v = av[q] + *pp;
+      *pp = v;
+      acc[((mt * MF_TILE + m) * 2 + o) * RING_N + i] = v;
     }
   }
   if (next_step < 0) return;
-  // the updated polynomial o of the tile's gates is written (and visible to the workgroup)
-  // and P1 has been read: the LDS becomes the staging area of the next step's operands
   __syncthreads();
-  // item (m, jg): gate m, local coefficient quad jg of both halves; lanes take consecutive
-  // quads of one gate (coalesced reads of ACC and of its rotation). All loads are issued
-  // before any digit is formed. The words are staged as [k][segment][kb][word dw][lane] with
-  // rows of 65 words (two-way bank conflicts at most), and the write-out gathers each lane's
-  // four words into its 16-byte operand.
-  constexpr int ITEMS = MF_TILE * (MF_HALF / 4);
-  constexpr int PER_T = (ITEMS + MF_THREADS - 1) / MF_THREADS;
-  u32* sA = reinterpret_cast<u32*>(mf_lds);
-  int av[PER_T];
-  bool lv[PER_T];
-  uint8_t opq[PER_T];
-#pragma unroll
-  for (int q = 0; q < PER_T; q++) opq[q] = 0;
-  if (ops) {
-#pragma unroll
-    for (int q = 0; q < PER_T; q++) {
-      const uint64_t g = mt * MF_TILE + ((tid + q * MF_THREADS) >> 7);
-      opq[q] = ops[g < B ? g : 0];
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < PER_T; q++) {
-    const int it = tid + q * MF_THREADS;
-    const uint64_t g = mt * MF_TILE + (it >> 7);
-    lv[q] = it < ITEMS && g < B && op_bootstraps(opq[q]);
-    av[q] = (int)abar[(g < B ? g : 0) * TLWE0 + next_step];
-  }
-  // (the values of a gate that is not live are loaded from gate 0 and never used)
-  u32 own[PER_T][2][4], rot[PER_T][2][4];
-#pragma unroll
-  for (int q = 0; q < PER_T; q++) {
-    const int it = tid + q * MF_THREADS, m = it >> 7, jg = it & 127;
+  // Digits of step next_step for rows 3o .. 3o + 2: a 64-lane group per input block kb, lane
+  // (m, kh) forming the 16-byte operand of gate m (local coefficients j = 32 kb + 16 kh + 15 - q,
+  // q = 0..15, of both halves) for the three levels and segments from the polynomial in LDS;
+  // each group writes nine 1 KiB operand rows. Gates at or above B and gates that do not
+  // bootstrap get zero digits.
+  {
+    const int m = lane & 31;
     const uint64_t g = mt * MF_TILE + m;
-    const u32* p = acc + ((g < B ? g : 0) * 2 + o) * RING_N;
+    const uint64_t gc = g < B ? g : 0;
+    const uint8_t op0 = ops ? ops[gc] : (uint8_t)0;
+    const bool live = g < B && op_bootstraps(op0);
+    const int a = (int)abar[gc * TLWE0 + next_step];
+    const u32* pm = poly + m * MF_PROW;
+    uint4* dst = reinterpret_cast<uint4*>(Anext + mt * MF_A_TILE + (size_t)GADGET_L * o * MF_A_ROW) + lane;
+    for (int kb = wave; kb < MF_KB; kb += MF_WAVES) {
+      u32 w[GADGET_L][MF_SUB][4] = {};
+      if (live) {
 #pragma unroll
-    for (int half = 0; half < 2; half++) {
-      const uint4 u = reinterpret_cast<const uint4*>(p)[half * (MF_HALF / 4) + jg];
-      own[q][half][0] = u.x;
-      own[q][half][1] = u.y;
-      own[q][half][2] = u.z;
-      own[q][half][3] = u.w;
+        for (int wi = 0; wi < 4; wi++) {
 #pragma unroll
-      for (int s = 0; s < 4; s++) {
-        const int ix = (half * MF_HALF + 4 * jg + 3 - s - av[q]) & (2 * RING_N - 1);
-        const u32 r = p[ix & (RING_N - 1)];
-        rot[q][half][s] = (ix & RING_N) ? 0u - r : r;
+          for (int s = 0; s < 4; s++) {
+            const int j = 32 * kb + 16 * kh + 15 - 4 * wi - s;
+            u32 x[2];
+#pragma unroll
+            for (int half = 0; half < 2; half++) {
+              const int ix = (half * MF_HALF + j - a) & (2 * RING_N - 1);
+              const u32 r = pm[ix & (RING_N - 1)];
+              x[half] = ((ix & RING_N) ? 0u - r : r) - pm[half * MF_HALF + j] + DECOMP_OFFSET;
+            }
+#pragma unroll
+            for (int k = 0; k < GADGET_L; k++) {
+              const int sh = 32 - BG_BIT * (k + 1);
+              const u32 d0 = ((x[0] >> sh) & 63u) - 32u, d1 = ((x[1] >> sh) & 63u) - 32u;
+              w[k][0][wi] |= ((d0 + d1) & 255u) << (8 * s);
+              w[k][1][wi] |= (d1 & 255u) << (8 * s);
+              w[k][2][wi] |= (d0 & 255u) << (8 * s);
+            }
+          }
+        }
       }
+#pragma unroll
+      for (int k = 0; k < GADGET_L; k++)
+#pragma unroll
+        for (int sg = 0; sg < MF_SUB; sg++)
+          dst[((k * MF_SUB + sg) * MF_KB + kb) * 64] = make_uint4(w[k][sg][0], w[k][sg][1], w[k][sg][2], w[k][sg][3]);
     }
-  }
-#pragma unroll
-  for (int q = 0; q < PER_T; q++) {
-    const int it = tid + q * MF_THREADS;
-    if (it >= ITEMS) break;
-    const int m = it >> 7, jg = it & 127;
-    u32 w[GADGET_L][MF_SUB] = {};
-    if (lv[q]) mf_digit_words(rot[q][0], own[q][0], rot[q][1], own[q][1], w);
-    const int kb = jg >> 3, ln = m + 32 * ((jg >> 2) & 1), dw = 3 - (jg & 3);
-#pragma unroll
-    for (int k = 0; k < GADGET_L; k++)
-#pragma unroll
-      for (int sg = 0; sg < MF_SUB; sg++) sA[(((k * MF_SUB + sg) * MF_KB + kb) * 4 + dw) * MF_SROW + ln] = w[k][sg];
-  }
-  __syncthreads();
-  uint4* dst = reinterpret_cast<uint4*>(Anext + mt * MF_A_TILE + (size_t)GADGET_L * o * MF_A_ROW);
-  for (int c2 = tid; c2 < GADGET_L * MF_SUB * MF_KB * 64; c2 += MF_THREADS) {
-    const int ln = c2 & 63, row = c2 >> 6;  // row = (k * 3 + segment) * MF_KB + kb
-    const u32* sw = sA + row * 4 * MF_SROW + ln;
-    dst[c2] = make_uint4(sw[0], sw[MF_SROW], sw[2 * MF_SROW], sw[3 * MF_SROW]);
   }
 }
 
