@@ -253,7 +253,9 @@ vsp_status vsp_autotune(vsp_context* ctx, uint64_t max_batch, const char* cache_
 
 /* The launch choice for a batch of B gates: *br_waves (4 or 8 gates per workgroup at one wave
  * per gate, 3 for one gate per workgroup on three waves, 32 for the matrix-core form),
- * *ks_form (0, 1, 2 or 3). */
+ * *ks_form (0, 1, 2 or 3). Before vsp_autotune (or after it returned a bucket to the model),
+ * the blind-rotation shape comes from the round-time model with default round times, and the
+ * key switch is form 2 up to 256 gates and form 3 above. */
 vsp_status vsp_tuning_get(const vsp_context* ctx, uint64_t B, int* br_waves, int* ks_form);
 
 /* Pin the launch choice for the bucket containing B: br_waves 3, 4, 8 or 32 (0 returns that
