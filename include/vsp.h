@@ -262,20 +262,30 @@ vsp_status vsp_tuning_get(const vsp_context* ctx, uint64_t B, int* br_waves, int
  * bucket to the round-time model), ks_form 0, 1, 2 or 3. Results are the same for every choice. */
 vsp_status vsp_tuning_set(vsp_context* ctx, uint64_t B, int br_waves, int ks_form);
 
-/* Kernel-time instrumentation (for benchmarks): with on >= 1, eager launches of the
- * blind-rotation, key-switch and gate-prologue kernels made by this context are bracketed by
- * HIP events on the stream they run on (for the matrix-core form, also its step kernels):
- * every launch with on = 1, every on-th launch of each kind with on > 1 (event pairs around
- * each of the 630 step launches of a batch cost several percent of its time; sampling keeps
- * the measurement live at a fraction of that). on = 0 disables, on < 0 is VSP_E_ARG.
- * Enabling resets the totals. */
+/* Kernel-time instrumentation (for benchmarks): with on >= 1, the blind-rotation, key-switch
+ * and gate-prologue launches made by vsp_gates / vsp_bootstrap_trlwe / vsp_mux on the calling
+ * thread are bracketed by HIP events on the stream they run on; for the matrix-core form one
+ * more event pair brackets the whole sequence of its 630 step launches. Every call with
+ * on = 1, every on-th call of each kind with on > 1. Launches under stream capture, from
+ * circuits, memory calls and the server are never instrumented. on = 0 disables, on < 0 is
+ * VSP_E_ARG. Enabling resets the totals. */
 vsp_status vsp_profile_enable(vsp_context* ctx, int on);
 
-/* Device time (ms, summed) and number of instrumented launches of kernel `which` since
- * enabling (all launches, or the sampled ones with a period): 0 = blind rotation, 1 = key
- * switch, 2 = gate prologue, 3 = step kernel of the matrix-core blind rotation (one per CMUX
- * step). Synchronises the device. */
+/* Device time (ms, summed) and number of kernel launches it covers, for kernel `which` since
+ * enabling: 0 = blind rotation, 1 = key switch, 2 = gate prologue, 3 = step kernel of the
+ * matrix-core blind rotation (630 launches per bracketed sequence, so total / launches is the
+ * average step launch including the gaps between launches). Synchronises the device. */
 vsp_status vsp_profile_read(vsp_context* ctx, int which, double* total_ms, uint64_t* launches);
+
+/* Measurement entry: the device's throughput of the arithmetic modulo the NTT prime
+ * p = 2^64 - 2^32 + 1 that the transform-domain blind rotation is built from (the polynomial
+ * products of the external product, Sec. 2.1.2, computed by NTT over the prime of Sec. 6.2(a)):
+ * general products and lazy sums mod p, each in independent register-resident chains at full
+ * occupancy with `iters` operations per chain (16 <= iters <= 2^24), timed with HIP events.
+ * Writes operations per second to *mulmod_per_s and *addmod_per_s. Allocates and frees its
+ * own small buffers and synchronises the device; VSP_E_ARG for NULL outputs, a bad device
+ * or iters out of range. */
+vsp_status vsp_measure_modp(int device, uint32_t iters, double* mulmod_per_s, double* addmod_per_s);
 
 /* Test entry: d_out[j] = C_j (ext) x_j for J (TRGSW, TRLWE) pairs, the external product
  * at the heart of CMUX (Sec. 2.1.2 "CMUX"). d_trgsw [J][2l][2][N], d_x and d_out [J][2][N]. */

@@ -76,6 +76,7 @@ SIGNATURES = {
     "vsp_tuning_set": (_st, [_vp, _u64, _i32, _i32]),
     "vsp_profile_enable": (_st, [_vp, _i32]),
     "vsp_profile_read": (_st, [_vp, _i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_u64)]),
+    "vsp_measure_modp": (_st, [_i32, ctypes.c_uint32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "vsp_debug_external_product": (_st, [_vp, _vp, _vp, _vp, _u64, _vp]),
     "vsp_debug_polymul": (_st, [_vp, _vp, _vp, _vp, _u64, _vp]),
 }
@@ -277,6 +278,13 @@ def vsp_profile_read(ctx, which: int):
     cnt = _u64()
     _call("vsp_profile_read", ctx, which, ctypes.byref(ms), ctypes.byref(cnt))
     return ms.value, cnt.value
+
+
+def vsp_measure_modp(device: int = 0, iters: int = 4096):
+    """(general products mod p per second, lazy sums mod p per second) on the whole device."""
+    mul, add = ctypes.c_double(), ctypes.c_double()
+    _call("vsp_measure_modp", device, iters, ctypes.byref(mul), ctypes.byref(add))
+    return mul.value, add.value
 
 
 def vsp_debug_external_product(ctx, d_trgsw, d_x, d_out, J, stream=None) -> None:

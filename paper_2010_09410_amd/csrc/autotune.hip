@@ -1,10 +1,10 @@
 // Autotuner for the batched launches. On random ciphertexts it times one full round of gates
-// for each blind-rotation workgroup shape (4 or 8 gates per workgroup at one wave per gate, or
-// one gate on three waves; the launch then picks the shape with the fewest rounds x round
-// time for its batch) and the three key-switch forms
-// (one workgroup per gate, row-stationary tiles, LDS-staged split) per batch-size bucket. Every
-// candidate must produce bit-identical outputs. The result can be cached in a small JSON file
-// keyed by the GPU.
+// for each blind-rotation form (4 or 8 gates per workgroup at one wave per gate, one gate on
+// three waves, and the matrix-core form; a launch then picks the form with the fewest rounds x
+// round time for its batch) and the four key-switch forms (one workgroup per gate,
+// row-stationary tiles, LDS-staged split, matrix cores) per batch-size bucket. Every candidate
+// must produce bit-identical outputs. The result can be cached in a small JSON file keyed by
+// the GPU; a cache written for another list of forms is ignored.
 #include <cstdio>
 #include <cstring>
 #include <fstream>
@@ -74,10 +74,15 @@ bool read_cache(const std::string& path, const std::string& key, Tuning& t) {
   const std::string s = ss.str();
   const size_t at = s.find("\"" + key + "\"");
   if (at == std::string::npos) return false;
-  double cap[kBrShapes], ms[kBrShapes], ks[kTuneBuckets];
-  if (!read_numbers(s, at, "br_cap", cap, kBrShapes) || !read_numbers(s, at, "br_round_ms", ms, kBrShapes) ||
+  double shapes[kBrShapes], cap[kBrShapes], ms[kBrShapes], ks[kTuneBuckets], buckets[kTuneBuckets];
+  if (!read_numbers(s, at, "br_waves", shapes, kBrShapes) || !read_numbers(s, at, "br_cap", cap, kBrShapes) ||
+      !read_numbers(s, at, "br_round_ms", ms, kBrShapes) || !read_numbers(s, at, "buckets", buckets, kTuneBuckets) ||
       !read_numbers(s, at, "ks_form", ks, kTuneBuckets))
     return false;
+  for (int i = 0; i < kBrShapes; i++)
+    if (shapes[i] != kBrWaveChoices[i]) return false;  // written for another list of forms
+  for (int b = 0; b < kTuneBuckets; b++)
+    if (buckets[b] != (double)kBucket[b]) return false;
   Tuning n = t;  // keeps forced shapes
   for (int i = 0; i < kBrShapes; i++) {
     if (!(cap[i] >= 1 && cap[i] < 1e9 && ms[i] > 0 && ms[i] < 1e9)) return false;
@@ -85,7 +90,7 @@ bool read_cache(const std::string& path, const std::string& key, Tuning& t) {
     n.br_round_ms[i] = (float)ms[i];
   }
   for (int b = 0; b < kTuneBuckets; b++) {
-    if (!(ks[b] == 0 || ks[b] == 1 || ks[b] == 2)) return false;
+    if (!(ks[b] >= 0 && ks[b] < kKsForms && ks[b] == (double)(int)ks[b])) return false;
     n.ks_form[b] = (int)ks[b];
   }
   n.tuned = true;

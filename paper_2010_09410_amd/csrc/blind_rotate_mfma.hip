@@ -467,7 +467,7 @@ hipError_t launch_mf_key(const uint32_t* bk, int8_t* E, hipStream_t st) {
 }
 
 hipError_t launch_blind_rotate_mfma(const vsp_context* ctx, const uint8_t* ops, const uint32_t* abar, uint32_t* tlwe1,
-                                    uint32_t* trlwe, uint64_t B, void* work, hipStream_t st) {
+                                    uint32_t* trlwe, uint64_t B, void* work, hipStream_t st, bool instrument) {
   if (B == 0) return hipSuccess;
   const uint64_t tiles = (B + MF_TILE - 1) / MF_TILE;
   // operands of even steps in A[0], of odd steps in A[1]: step i reads A[i % 2] and writes
@@ -477,11 +477,14 @@ hipError_t launch_blind_rotate_mfma(const vsp_context* ctx, const uint8_t* ops, 
   hipLaunchKernelGGL(k_mf_init, dim3((unsigned)((B * 2 * RING_N + 255) / 256)), dim3(256), 0, st, ops, abar, acc, B);
   hipLaunchKernelGGL(k_mf_digits, dim3((unsigned)tiles, 2, MF_TILE / MF_DG), dim3(256), 0, st, ops, abar, acc, Ab[0], B,
                      0);
-  for (int i = 0; i < LWE_N; i++) {
-    ProfScope ps(ctx, 3, st);
-    hipLaunchKernelGGL(k_mf_step, dim3((unsigned)tiles, 2), dim3(MF_THREADS), MF_STEP_LDS, st,
-                       ctx->mf_key + (size_t)i * MF_KEY_STEP, Ab[i & 1], acc, ops, B, Ab[(i + 1) & 1], abar,
-                       i + 1 < LWE_N ? i + 1 : -1);
+  {
+    // one event pair around the whole step sequence: its duration / LWE_N is the average step
+    // launch including the gaps between launches (an upper bound on the kernel's own time)
+    ProfScope ps(instrument ? ctx : nullptr, 3, st, LWE_N);
+    for (int i = 0; i < LWE_N; i++)
+      hipLaunchKernelGGL(k_mf_step, dim3((unsigned)tiles, 2), dim3(MF_THREADS), MF_STEP_LDS, st,
+                         ctx->mf_key + (size_t)i * MF_KEY_STEP, Ab[i & 1], acc, ops, B, Ab[(i + 1) & 1], abar,
+                         i + 1 < LWE_N ? i + 1 : -1);
   }
   hipError_t e = hipGetLastError();
   if (e == hipSuccess && tlwe1) e = launch_sample_extract(acc, tlwe1, B, 1, st);

@@ -195,13 +195,13 @@ hipError_t blind_rotate_capacity(int device, uint64_t (&cap)[kBrShapes]) {
 
 hipError_t launch_blind_rotate(const vsp_context* ctx, const uint8_t* ops, const uint32_t* abar, uint32_t* tlwe1,
                                uint32_t* trlwe, uint64_t B, int waves, hipStream_t st, const uint64_t* bkn,
-                               const uint64_t* const* keytab, const uint8_t* kid, void* mf_work) {
+                               const uint64_t* const* keytab, const uint8_t* kid, void* mf_work, bool instrument) {
   if (B == 0) return hipSuccess;
   if (bkn == nullptr) bkn = ctx->bkn;
   if (waves <= 0) waves = ctx->tune.br_waves(B);
   if (waves == 32) {
     if (keytab == nullptr && bkn == ctx->bkn && mf_work != nullptr && ctx->mf_key != nullptr)
-      return launch_blind_rotate_mfma(ctx, ops, abar, tlwe1, trlwe, B, mf_work, st);
+      return launch_blind_rotate_mfma(ctx, ops, abar, tlwe1, trlwe, B, mf_work, st, instrument);
     waves = 8;
   }
   if (waves == 3) {

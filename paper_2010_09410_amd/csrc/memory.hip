@@ -1,6 +1,5 @@
 // CMUX Memory (Sec. 8): ROM reads by a packed LUT (CMUX tree + rotation CMUXes), RAM reads
 // by per-bit CMUX trees, and the RAM write (read unit, control unit, write bars, refresh).
-#include <vector>
 
 #include "vsp_internal.h"
 
@@ -382,6 +381,26 @@ static hipError_t run_trees(const vsp_context* ctx, const uint64_t* sel, uint64_
   return hipSuccess;
 }
 
+// Input-wire and opcode tables of the control unit's 2w gates over the rows
+// src = [f, x_0 .. x_{w-1}, r_0 .. r_{w-1}]: gate i < w is AND(f, x_i), gate w + i is
+// ANDNOT(r_i, f) (idx0 = idx[0, 2w), idx1 = idx[2w, 4w)). Written on the device so that the
+// write stays asynchronous.
+__global__ void k_ram_control_tables(uint32_t* __restrict__ idx, uint8_t* __restrict__ ops, uint32_t w) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= w) return;
+  idx[i] = 0;
+  idx[2 * w + i] = 1 + i;
+  idx[w + i] = 1 + w + i;
+  idx[3 * w + i] = 0;
+  ops[i] = VSP_AND;
+  ops[w + i] = VSP_ANDNOT;
+}
+
+static hipError_t launch_ram_control_tables(uint32_t* idx, uint8_t* ops, uint32_t w, hipStream_t st) {
+  hipLaunchKernelGGL(k_ram_control_tables, dim3((w + 255) / 256), dim3(256), 0, st, idx, ops, w);
+  return hipGetLastError();
+}
+
 }  // namespace vsp
 
 using namespace vsp;
@@ -526,18 +545,7 @@ vsp_status vsp_ram_write(vsp_context* ctx, uint32_t* d_ram, uint32_t v, uint32_t
   if ((e = hipMemcpyAsync(src, d_flag, T0, hipMemcpyDeviceToDevice, st)) != hipSuccess) return hip_fail(e, "copy flag");
   if ((e = hipMemcpyAsync(src + (LWE_N + 1), d_data, (size_t)w * T0, hipMemcpyDeviceToDevice, st)) != hipSuccess)
     return hip_fail(e, "copy data");
-  std::vector<uint32_t> hidx(6 * (size_t)w);
-  std::vector<uint8_t> hops(2 * (size_t)w);
-  for (uint32_t i = 0; i < w; i++) {
-    hidx[i] = 0;                          hidx[2 * w + i] = 1 + i;          // AND(f, x_i)
-    hidx[w + i] = 1 + w + i;              hidx[3 * w + i] = 0;              // ANDNOT(r_i, f)
-    hops[i] = VSP_AND;                    hops[w + i] = VSP_ANDNOT;
-  }
-  if ((e = hipMemcpyAsync(idx, hidx.data(), hidx.size() * 4, hipMemcpyHostToDevice, st)) != hipSuccess)
-    return hip_fail(e, "upload indices");
-  if ((e = hipMemcpyAsync(ops, hops.data(), hops.size(), hipMemcpyHostToDevice, st)) != hipSuccess)
-    return hip_fail(e, "upload ops");
-  if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "sync");  // host vectors go out of scope
+  if ((e = launch_ram_control_tables(idx, ops, w, st)) != hipSuccess) return hip_fail(e, "control tables");
   if ((e = launch_gate_prologue(ctx, ops, src, src, idx, idx + 2 * w, nullptr, abar, nullptr, 2 * (uint64_t)w, st,
                                 false)) != hipSuccess)
     return hip_fail(e, "control prologue");

@@ -67,8 +67,14 @@ vsp_status scratch_reserve(vsp_context* ctx, Scratch& s, size_t bytes) {
   return VSP_OK;
 }
 
-ProfScope::ProfScope(const vsp_context* c, int w, hipStream_t s) : ctx(c), which(w), st(s) {
-  if (!ctx->prof.on || ctx->prof.seen[which]++ % (uint64_t)ctx->prof.period != 0) return;
+ProfScope::ProfScope(const vsp_context* c, int w, hipStream_t s, uint32_t launches) : ctx(c), which(w), st(s) {
+  if (ctx == nullptr || !ctx->prof.on) return;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
+    (void)hipGetLastError();
+    return;
+  }
+  if (ctx->prof.seen[which]++ % (uint64_t)ctx->prof.period != 0) return;
   hipEvent_t e0;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     (void)hipGetLastError();
@@ -76,7 +82,7 @@ ProfScope::ProfScope(const vsp_context* c, int w, hipStream_t s) : ctx(c), which
     return;
   }
   (void)hipEventRecord(e0, st);
-  ctx->prof.ev[which].push_back({e0, e1});
+  ctx->prof.ev[which].push_back({e0, e1, launches});
 }
 
 ProfScope::~ProfScope() {
@@ -86,8 +92,8 @@ ProfScope::~ProfScope() {
 static void profile_clear(vsp_context* ctx) {
   for (auto& v : ctx->prof.ev) {
     for (auto& p : v) {
-      (void)hipEventDestroy(p.first);
-      (void)hipEventDestroy(p.second);
+      (void)hipEventDestroy(p.e0);
+      (void)hipEventDestroy(p.e1);
     }
     v.clear();
   }
@@ -318,7 +324,7 @@ static vsp_status gates_impl(vsp_context* ctx, const uint8_t* d_ops, const uint3
       if (e != hipSuccess) return hip_fail(e, "gate prologue");
       {
         ProfScope ps(ctx, 0, st);
-        e = launch_blind_rotate(ctx, ops, abar, nullptr, o, nb, 0, st, nullptr, nullptr, nullptr, mfw);
+        e = launch_blind_rotate(ctx, ops, abar, nullptr, o, nb, 0, st, nullptr, nullptr, nullptr, mfw, true);
       }
       if (e != hipSuccess) return hip_fail(e, "blind rotation");
     } else {
@@ -330,7 +336,7 @@ static vsp_status gates_impl(vsp_context* ctx, const uint8_t* d_ops, const uint3
       if (e != hipSuccess) return hip_fail(e, "gate prologue");
       {
         ProfScope ps(ctx, 0, st);
-        e = launch_blind_rotate(ctx, ops, abar, t1, nullptr, nb, 0, st, nullptr, nullptr, nullptr, mfw);
+        e = launch_blind_rotate(ctx, ops, abar, t1, nullptr, nb, 0, st, nullptr, nullptr, nullptr, mfw, true);
       }
       if (e != hipSuccess) return hip_fail(e, "blind rotation");
       {
@@ -446,13 +452,15 @@ vsp_status vsp_profile_read(vsp_context* ctx, int which, double* total_ms, uint6
   VSP_HIP(hipSetDevice(ctx->device));
   VSP_HIP(hipDeviceSynchronize());
   double t = 0;
+  uint64_t n = 0;
   for (auto& p : ctx->prof.ev[which]) {
     float ms = 0;
-    VSP_HIP(hipEventElapsedTime(&ms, p.first, p.second));
+    VSP_HIP(hipEventElapsedTime(&ms, p.e0, p.e1));
     t += ms;
+    n += p.launches;
   }
   *total_ms = t;
-  *launches = ctx->prof.ev[which].size();
+  *launches = n;
   return VSP_OK;
 }
 

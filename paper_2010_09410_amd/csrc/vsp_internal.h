@@ -89,13 +89,19 @@ struct Scratch {
 };
 
 // Event pairs bracketing instrumented launches (kernel classes: blind rotation, key switch,
-// prologue, and each step kernel of the matrix-core blind rotation).
+// prologue, and the step kernels of the matrix-core blind rotation, whose pair brackets the
+// whole sequence of one blind rotation's step launches). Only eager calls from the caller's
+// thread record them (not launches under stream capture, nor the server's worker thread).
 constexpr int kProfClasses = 4;
+struct ProfEvent {
+  hipEvent_t e0, e1;
+  uint32_t launches;  // kernel launches between e0 and e1
+};
 struct Profile {
   bool on = false;
   int period = 1;                  // instrument every period-th launch of each class
   uint64_t seen[kProfClasses] = {};  // launches of each class since enabling
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[kProfClasses];
+  std::vector<ProfEvent> ev[kProfClasses];
 };
 
 }  // namespace vsp
@@ -146,13 +152,14 @@ vsp_status upload_keys(const vsp_context* ctx, const uint32_t* bk_host, const ui
 // Grows a scratch buffer to at least `bytes` (synchronising the device before freeing).
 vsp_status scratch_reserve(vsp_context* ctx, Scratch& s, size_t bytes);
 
-// Records an event pair around one launch of kernel class `which` when profiling is on.
+// Records an event pair around `launches` launches of kernel class `which` when profiling is
+// on and the stream is not being captured.
 struct ProfScope {
   const vsp_context* ctx;
   int which;
   hipStream_t st;
   hipEvent_t e1 = nullptr;
-  ProfScope(const vsp_context* c, int w, hipStream_t s);
+  ProfScope(const vsp_context* c, int w, hipStream_t s, uint32_t launches = 1);
   ~ProfScope();
 };
 
@@ -186,7 +193,7 @@ hipError_t launch_mux_combine(uint32_t* t, uint64_t B, hipStream_t st);
 hipError_t launch_blind_rotate(const vsp_context* ctx, const uint8_t* ops, const uint32_t* abar, uint32_t* tlwe1,
                                uint32_t* trlwe, uint64_t B, int waves, hipStream_t st, const uint64_t* bkn = nullptr,
                                const uint64_t* const* keytab = nullptr, const uint8_t* kid = nullptr,
-                               void* mf_work = nullptr);
+                               void* mf_work = nullptr, bool instrument = false);
 // Matrix-core form (blind_rotate_mfma.hip): key bytes, workspace bytes, key conversion from
 // the torus key [n][2l][2][N] on the device, and the launch sequence.
 hipError_t init_mf_kernel_attributes();
@@ -198,8 +205,10 @@ size_t ks_mf_key_bytes();
 hipError_t launch_ks_mfkey(const uint32_t* ksk, int8_t* KB, hipStream_t st);
 hipError_t launch_keyswitch_mfma(const int8_t* KB, const uint8_t* ops, const uint32_t* tlwe1, const uint32_t* idxo,
                                  uint32_t* out, uint64_t B, hipStream_t st);
+// With instrument set (eager calls from the caller's thread only), one event pair of class 3
+// brackets the step launches.
 hipError_t launch_blind_rotate_mfma(const vsp_context* ctx, const uint8_t* ops, const uint32_t* abar, uint32_t* tlwe1,
-                                    uint32_t* trlwe, uint64_t B, void* work, hipStream_t st);
+                                    uint32_t* trlwe, uint64_t B, void* work, hipStream_t st, bool instrument = false);
 // Identity key switch TLWE1 [B][N+1] -> TLWE0 [B][n+1] (outputs scattered by idxo if given).
 // form: 0 one workgroup per gate, 1 row-stationary tiles, 2 LDS-staged split, 3 matrix cores
 // (the context's own key only; other keys run form 2), -1 the tuned one.

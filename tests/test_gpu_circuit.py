@@ -1,6 +1,6 @@
 """Levelled circuits on the GPU: full bit-exact parity on a small layered DAG, graph replay ==
-eager launches, and the 64-level / ~65k-gate DAG decrypted in full with sampled gate-local
-parity (the oracle recomputes sampled gates from the GPU's own input wires)."""
+eager launches, and the 64-level / 75k-gate DAG decrypted in full with gate-local parity of
+two sampled gates per level (the oracle recomputes them from the GPU's own input wires)."""
 from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
@@ -83,8 +83,12 @@ def test_config3_full_decrypt_and_sampled_parity(gpu, keys):
     wires = to_host(circ.run(gpu.tensor(inputs)))
     gpu.sync()
     np.testing.assert_array_equal(client.tlwe_decrypt(keys["s0"], wires), plaintext_eval(c["gates"], c["bits"]))
+    # gate-local parity: two random gates of every level (plus the first and last gate), the
+    # oracle fed the GPU's own input wires
     g = W.rng(701)
-    sample = np.concatenate([[0, len(c["gates"]) - 1], g.integers(0, len(c["gates"]), 10)])
+    per_level = [g.choice(np.nonzero(c["level"] == L)[0], 2, replace=False) for L in range(64)]
+    sample = np.unique(np.concatenate([[0, len(c["gates"]) - 1], *per_level]))
+    assert np.array_equal(np.unique(c["level"][sample]), np.arange(64))
     ops = c["gates"][sample, 0].astype(np.uint8)
     ref = oracle.gates(keys["bk"], keys["ksk"], ops, wires[c["gates"][sample, 1]], wires[c["gates"][sample, 2]])
     np.testing.assert_array_equal(wires[c["ninputs"] + sample], ref)

@@ -1,0 +1,58 @@
+"""Every gate of the 4096-gate benchmark batch against the CPU oracle, in every blind-rotation
+form and key-switch form that can run it. The oracle's outputs for this batch are committed as
+per-gate SHA-256 digests (tests/golden/config2_oracle_digest.json, written by
+tests/golden/make_config2_digest.py from the oracle alone); the test first checks that it
+encrypted the same inputs, then compares all 4096 output rows."""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from paper_2010_09410_amd import client
+from paper_2010_09410_amd.device import to_host
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLDEN = os.path.join(HERE, "golden", "config2_oracle_digest.json")
+B = 4096
+
+# (blind-rotation shape, key-switch form): the matrix-core form, the 8-, 4- and 3-wave NTT
+# forms; key-switch forms 3 (matrix cores), 2 (LDS-staged split), 1 (row tiles), 0 (gather).
+FORMS = [(32, 3), (32, 2), (8, 3), (8, 2), (4, 1), (3, 0)]
+
+
+def row_digest(row) -> str:
+    return hashlib.sha256(np.ascontiguousarray(row, dtype="<u4").tobytes()).hexdigest()[:16]
+
+
+@pytest.fixture(scope="module")
+def batch(keys):
+    doc = json.load(open(GOLDEN))
+    cfg = W.config2(B)
+    in0 = client.tlwe_encrypt_bits(keys["s0"], cfg["bits0"], *cfg["enc0"])
+    in1 = client.tlwe_encrypt_bits(keys["s0"], cfg["bits1"], *cfg["enc1"])
+    inputs = hashlib.sha256(np.ascontiguousarray(cfg["ops"]).tobytes() + in0.astype("<u4").tobytes()
+                            + in1.astype("<u4").tobytes()).hexdigest()
+    assert inputs == doc["inputs_sha256"], "the encrypted inputs differ from the ones the digests were made from"
+    return cfg, in0, in1, doc
+
+
+@pytest.mark.parametrize("waves,ks", FORMS)
+def test_every_gate_matches_oracle(gpu, batch, waves, ks):
+    cfg, in0, in1, doc = batch
+    d0, d1, dops = gpu.tensor(in0), gpu.tensor(in1), gpu.tensor(cfg["ops"])
+    saved = gpu.tuning(B)
+    try:
+        gpu.set_tuning(B, waves, ks)
+        assert gpu.tuning(B) == (waves, ks)
+        out = to_host(gpu.gates(dops, d0, d1))
+        gpu.sync()
+    finally:
+        gpu.set_tuning(B, 0, saved[1])
+    want = doc["gate_sha256_prefix"]
+    bad = [k for k in range(B) if row_digest(out[k]) != want[k]]
+    assert not bad, f"{len(bad)} of {B} gates differ from the oracle (shape {waves}, key switch {ks}); first {bad[:8]}"
+    assert hashlib.sha256(out.astype("<u4").tobytes()).hexdigest() == doc["outputs_sha256"]

@@ -1,5 +1,8 @@
 """GPU parity of CMUX Memory (Sec. 8): ROM reads, RAM reads and the RAM write, bit-exact
-against the oracle, plus the 512-word ROM / 256-address RAM workload decrypted in full."""
+against the oracle. At the workload's own sizes (512-word ROM, 256 reads; RAM v = 8, w = 8)
+every ROM read, sixteen RAM reads with encrypted selectors and 263 write bars (one whole bit
+block and every bit at the written address) are compared with the oracle, and every read and
+every written cell is decrypted."""
 import numpy as np
 import pytest
 
@@ -30,9 +33,9 @@ def test_rom_read_parity_and_full_workload(gpu, keys):
     gpu.sync()
     bits = (wl["words"][wl["addr"]][:, None] >> np.arange(32)[None, :]) & 1
     np.testing.assert_array_equal(client.tlwe_decrypt(keys["s0"], out), bits)
-    idx = [0, 1, 131, 255]
-    ref = oracle.rom_reads(keys["ksk"], rom, sel[idx])
-    np.testing.assert_array_equal(out[idx], ref)
+    ref = oracle.rom_reads(keys["ksk"], rom, sel)                           # all 256 reads
+    bad = np.nonzero((out != ref).any(axis=(1, 2)))[0]
+    assert bad.size == 0, f"{bad.size} of 256 ROM reads differ from the oracle, first {bad[:8]}"
 
 
 def test_rom_read_small_and_single_cell(gpu, keys):
@@ -69,6 +72,21 @@ def test_ram_read_parity(gpu, keys):
     np.testing.assert_array_equal(client.tlwe_decrypt(keys["s0"], out), contents[:, addr].T)
 
 
+def test_ram_read_full_size_encrypted_selectors(gpu, keys):
+    """v = 8, w = 8 (2,048 cells): sixteen reads at uniform addresses with encrypted selectors,
+    bit-exact against the oracle and decrypting to the stored bits."""
+    s1 = keys["s1"]
+    wl = W.ram_workload(v=8, w=8, reads=16, flag=1)
+    ca, ce = wl["cells"]
+    ram = client.trlwe_encrypt_torus(s1, client.ram_cell_messages(wl["contents"]), ca, ce)
+    sa, se = wl["rsel"]
+    sel = client.trgsw_encrypt(s1, (wl["raddr"][:, None] >> np.arange(8)[None, :]) & 1, sa, se)
+    out = to_host(gpu.ram_read(gpu.tensor(ram), gpu.tensor(sel)))
+    gpu.sync()
+    np.testing.assert_array_equal(client.tlwe_decrypt(keys["s0"], out), wl["contents"][:, wl["raddr"]].T)
+    np.testing.assert_array_equal(out, oracle.ram_reads(keys["ksk"], ram, sel))
+
+
 def encrypted_ram(keys, wl):
     s0, s1 = keys["s0"], keys["s1"]
     v, w = wl["v"], wl["w"]
@@ -94,8 +112,9 @@ def test_ram_write_parity_small(gpu, keys, flag):
 
 
 def test_ram_write_then_read_full_workload(gpu, keys):
-    """v = 8, w = 8: write under f = 1, then read every address back; sampled write bars are
-    bit-exact against the oracle given the oracle's own control-unit output."""
+    """v = 8, w = 8: write under f = 1, then read every address back; 263 write bars (the whole
+    block of bit 3 and every bit at the written address) are bit-exact against the oracle given
+    the oracle's own read-unit and control-unit outputs."""
     s0, s1 = keys["s0"], keys["s1"]
     wl = W.ram_workload(v=8, w=8, reads=1, flag=1)
     ram, sel, fl, data = encrypted_ram(keys, wl)
@@ -112,9 +131,11 @@ def test_ram_write_then_read_full_workload(gpu, keys):
     # sampled bars against the oracle (read unit and control unit recomputed on the CPU)
     rd = oracle.ram_read(keys["ksk"], ram, sel)
     u = oracle.ram_control(keys["bk"], fl, data, rd)
-    idx = np.array([wl["waddr"], 256 + wl["waddr"], 7 * 256 + 3, 1000])
+    idx = np.unique(np.r_[3 * 256 + np.arange(256), np.arange(8) * 256 + wl["waddr"]])
+    assert idx.size == 263
     bars = oracle.ram_write_bars(keys["bk"], keys["ksk"], ram, sel, u, idx)
-    np.testing.assert_array_equal(new.reshape(-1, 2, N)[idx], bars)
+    bad = idx[(new.reshape(-1, 2, N)[idx] != bars).any(axis=(1, 2))]
+    assert bad.size == 0, f"{bad.size} of {idx.size} write bars differ from the oracle, first {bad[:8]}"
 
 
 def test_memory_size_limits_rejected(gpu):

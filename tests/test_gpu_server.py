@@ -126,3 +126,42 @@ def test_per_client_key_sets(gpu, keys):
         gpu.sync()
         circ.close()
     kb.close()
+
+
+TRUTH = {0: lambda a, b: 1 - (a & b), 1: lambda a, b: a & b, 2: lambda a, b: a | b, 3: lambda a, b: 1 - (a | b),
+         4: lambda a, b: a ^ b, 5: lambda a, b: 1 - (a ^ b), 6: lambda a, b: a & (1 - b), 7: lambda a, b: a | (1 - b),
+         8: lambda a, b: 1 - a}
+
+
+def test_served_trace_decrypts_and_matches_oracle(gpu, keys):
+    """The first 24 circuits of the serving workload (64 clients, log-uniform sizes in
+    [100, 20000], Poisson arrivals at 50/s), all submitted at once so that their ready gates
+    share batches: every wire of every circuit decrypts to the plaintext evaluation, and two
+    random gates per circuit are bit-exact against the oracle fed the served input wires."""
+    import oracle
+    trace = W.serving_trace(rate=50.0, duration=10.0)[:24]
+    assert len(trace) == 24
+    enc = [client.tlwe_encrypt_bits(keys["s0"], r["bits"], *W.tlwe_draws(W.rng(r["enc_seed"]), r["ninputs"]))
+           for r in trace]
+    srv = gpu.server(mem_budget_bytes=2 << 30, max_batch=4096)
+    tickets = [srv.submit(r["gates"], r["ninputs"], e) for r, e in zip(trace, enc)]
+    served = [wait(srv, t, r["ninputs"] + len(r["gates"]), timeout=300.0)[0] for t, r in zip(tickets, trace)]
+    gates, batches, _ = srv.stats()
+    srv.close()
+    assert gates == sum(len(r["gates"]) for r in trace)
+    assert batches < sum(int(r["level"].max()) + 1 for r in trace)     # circuits shared batches
+    g = W.rng(870)
+    ops, a, b, got = [], [], [], []
+    for r, wires in zip(trace, served):
+        plain = [int(x) for x in r["bits"]]
+        for op, i0, i1 in r["gates"]:
+            plain.append(TRUTH[int(op)](plain[i0], plain[i1]))
+        np.testing.assert_array_equal(client.tlwe_decrypt(keys["s0"], wires), np.array(plain, dtype=np.uint8))
+        for k in g.choice(len(r["gates"]), 2, replace=False):
+            op, i0, i1 = r["gates"][k]
+            ops.append(op)
+            a.append(wires[i0])
+            b.append(wires[i1])
+            got.append(wires[r["ninputs"] + k])
+    ref = oracle.gates(keys["bk"], keys["ksk"], np.array(ops, np.uint8), np.array(a), np.array(b))
+    np.testing.assert_array_equal(np.array(got), ref)

@@ -85,6 +85,32 @@ def test_autotune_model_and_cache_round_trip(gpu, tmp_path):
             gpu.set_tuning(b, 0, t)
 
 
+def test_autotune_cache_read_back_with_every_key_switch_form(gpu, tmp_path):
+    """A cache entry naming every key-switch form (the matrix-core form 3 included) is read
+    back as written, without measuring again (the file is left as it was); an entry written for
+    another list of blind-rotation forms is ignored, measured again and rewritten."""
+    saved = {b: gpu.tuning(b)[1] for b in BUCKETS}
+    path = tmp_path / "tune.json"
+    try:
+        gpu.autotune(max_batch=64, cache_path=str(path))
+        (key, entry), = json.loads(path.read_text()).items()
+        entry["ks_form"] = [3, 2, 3, 1, 3, 0, 3]
+        text = json.dumps({key: entry})
+        path.write_text(text)
+        gpu.autotune(max_batch=64, cache_path=str(path))
+        assert path.read_text() == text
+        for b, t in zip(BUCKETS, entry["ks_form"]):
+            assert gpu.tuning(b)[1] == t
+        shapes = list(entry["br_waves"])
+        entry["br_waves"] = shapes[:-1] + [shapes[-1] + 1]
+        path.write_text(json.dumps({key: entry}))
+        gpu.autotune(max_batch=64, cache_path=str(path))
+        assert json.loads(path.read_text())[key]["br_waves"] == shapes
+    finally:
+        for b, t in saved.items():
+            gpu.set_tuning(b, 0, t)
+
+
 def test_profile_sampling(gpu, keys):
     """Kernel-time instrumentation: every launch with on = 1, every k-th launch of each kind
     with on = k, none after disabling; a negative setting is an argument error."""

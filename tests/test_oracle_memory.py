@@ -143,6 +143,30 @@ def test_ram_write_then_read_encrypted(keys, flag):
         np.testing.assert_array_equal(oracle.tlwe_decrypt(s0, out[A]), expect[:, A])
 
 
+def test_write_bars_equal_the_full_write(keys):
+    """The sampled write-bar routine (the checker of large RAM writes) over every (bit,
+    address) pair, in a shuffled order and again for a repeated subset, returns exactly the
+    cells of the whole RAM write, given the read unit's and the control unit's outputs."""
+    s0, s1 = keys["s0"], keys["s1"]
+    v, w = 3, 2
+    wl = W.ram_workload(v=v, w=w, reads=1, flag=1, seed_off=7)
+    ca, ce = wl["cells"]
+    msg = ram_cells_msg(wl["contents"])
+    ram = np.array([[oracle.trlwe_encrypt_torus(s1, msg[i, A], ca[i, A], ce[i, A]) for A in range(2 ** v)]
+                    for i in range(w)])
+    sa, se = wl["wsel"]
+    sel = np.array([oracle.trgsw_encrypt(s1, (wl["waddr"] >> j) & 1, sa[j], se[j]) for j in range(v)])
+    fl = oracle.tlwe_encrypt_bits(s0, [1], *wl["fenc"])[0]
+    dat = oracle.tlwe_encrypt_bits(s0, wl["wdata"], *wl["denc"])
+    new = oracle.ram_write(keys["bk"], keys["ksk"], ram, sel, fl, dat).reshape(-1, 2, N)
+    rd = oracle.ram_read(keys["ksk"], ram, sel)
+    u = oracle.ram_control(keys["bk"], fl, dat, rd)
+    idx = W.rng(302).permutation(w * 2 ** v)
+    np.testing.assert_array_equal(oracle.ram_write_bars(keys["bk"], keys["ksk"], ram, sel, u, idx), new[idx])
+    few = np.array([idx[3], idx[0], idx[3]])
+    np.testing.assert_array_equal(oracle.ram_write_bars(keys["bk"], keys["ksk"], ram, sel, u, few), new[few])
+
+
 SMALL = oracle.Params(16, 64, 3, 6, 8, 2)
 
 
