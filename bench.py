@@ -78,6 +78,40 @@ BK_NTT_BYTES = N_LWE * 2 * GL * 2 * N_RING * 8  # key stream read by every gate 
 HBM_PEAK = 8.0e12                               # bytes/s
 
 
+# The method's own arithmetic per gate bootstrap (independent of how a kernel organises it):
+# 630 external products, each with 6 forward and 2 inverse negacyclic transforms of N = 1024
+# points (N/2 log2 N = 5,120 butterflies, one product and one sum and one difference mod p
+# each) and 12 pointwise key products of N points (one product and one sum each).
+BUTTERFLIES = N_RING // 2 * 10
+MULMOD_PER_GATE = STEPS_BR * (8 * BUTTERFLIES + 2 * 2 * GL * N_RING)      # 33.5 M
+ADDMOD_PER_GATE = STEPS_BR * (2 * 8 * BUTTERFLIES + 2 * 2 * GL * N_RING)  # 59.4 M
+
+
+def algorithmic(gates_per_s: float, ceiling):
+    """Gates/s against the method's work priced at the measured register-resident rates of a
+    product and of a sum mod p on the whole chip (`vsp_measure_modp`)."""
+    if ceiling is None:
+        return None
+    mul, add = ceiling
+    g_mul = mul / MULMOD_PER_GATE                                   # products alone
+    g_both = 1.0 / (MULMOD_PER_GATE / mul + ADDMOD_PER_GATE / add)  # products and sums, same VALU
+    return {"mulmod_per_gate": MULMOD_PER_GATE, "addmod_per_gate": ADDMOD_PER_GATE,
+            "mulmod_per_s": round(mul / 1e12, 4), "addmod_per_s": round(add / 1e12, 4), "unit": "T/s",
+            "ceiling_gates_per_s_mulmod_only": round(g_mul, 1), "frac_mulmod_only": round(gates_per_s / g_mul, 4),
+            "ceiling_gates_per_s": round(g_both, 1), "frac": round(gates_per_s / g_both, 4)}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def br_hbm_bytes(B: int) -> int:
     """Algorithmic HBM bytes of one blind-rotation launch over B gates: the key once, the
     opcodes and modulus-switched inputs read, the extracted TLWE rows written."""
@@ -142,18 +176,20 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--per-gate", type=int, default=8, help="gates timed in per-gate mode")
+    ap.add_argument("--per-gate", type=int, default=64, help="gates timed in per-gate mode")
     ap.add_argument("--no-circuit", action="store_true", help="skip the per-level circuit latency")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--cpu-gates", type=int, default=0, help="oracle sample size (default: about 12 s of work)")
     ap.add_argument("--no-memory", action="store_true", help="skip the CMUX-memory timings")
     ap.add_argument("--no-machine", action="store_true", help="skip the clocked-netlist cycle timing")
-    ap.add_argument("--serving", type=float, default=2.0, metavar="SECONDS",
+    ap.add_argument("--serving", type=float, default=10.0, metavar="SECONDS",
                     help="arrival window of the serving run at 50 circuits/s (0 skips it)")
     ap.add_argument("--serving-light", type=float, default=0.7, metavar="FRACTION",
                     help="also serve about 30 circuits offered at this fraction of the measured batched "
                          "throughput (0 skips it)")
+    ap.add_argument("--no-ntt-form", action="store_true",
+                    help="skip timing the 4096-gate batch in the NTT form when the tuning picks the matrix form")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run one plain device copy of MIB MiB (reference for HBM byte counters)")
     return ap.parse_args()
@@ -187,6 +223,7 @@ def cpu_baseline(s0, s1, bkd, kskd, cfg, in0, in1, ngates):
     oracle.rom_reads(ksk, rom, sel, threads=threads)
     rom_dt = time.perf_counter() - t2
     return {"value": round(ngates / dt, 2), "unit": "gate bootstraps/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": f"first {ngates} gates of the 4096-gate batch, {threads} threads, {dt:.1f} s",
             "single_thread_s_per_gate": round(single, 3), "rom_reads_per_s": round(16 / rom_dt, 1)}
 
@@ -372,7 +409,44 @@ def main():
     ms_per_step = dt * 1e3 / args.steps
     value = B_GATES * args.steps / dt
 
-    # per-gate mode: one launch sequence per gate
+    # register-resident throughput of a product and of a sum mod p on the whole chip
+    ceiling = nv.vsp_measure_modp(0, 4096)
+
+    # the same batch in the NTT form (the transform-domain method), when the tuning picked the
+    # matrix-core form for it
+    ntt_form = None
+    if br_waves == 32 and not args.no_ntt_form:
+        ctx.set_tuning(B_GATES, 8, ks_form)
+        ctx.gates(ops_d, a_d, b_d, out=out)
+        ctx.sync()
+        nv.vsp_profile_enable(ctx.handle, True)
+        reps = 3
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ctx.gates(ops_d, a_d, b_d, out=out)
+        torch.cuda.synchronize()
+        ndt = time.perf_counter() - t0
+        nbr_ms, nbr_n = nv.vsp_profile_read(ctx.handle, 0)
+        nv.vsp_profile_enable(ctx.handle, False)
+        ctx.set_tuning(B_GATES, 32, ks_form)
+        ctx.sync()
+        nrate = B_GATES * reps / ndt
+        navg = nbr_ms / max(nbr_n, 1)
+        nach = B_GATES * LANE_OPS_PER_GATE / (navg * 1e-3)
+        ntraffic, nsrc = measured_traffic(br_fingerprint())
+        ntt_form = {"kernel": "k_blind_rotate<8>", "value": round(nrate, 1), "unit": "gate bootstraps/s",
+                    "ms_per_step": round(ndt * 1e3 / reps, 3), "blind_rotation_avg_ms": round(navg, 3),
+                    "alu": {"achieved": round(nach / 1e12, 3), "peak": round(PEAK_LANE_OPS / 1e12, 3),
+                            "unit": "T int32 lane-ops/s (compiled-routine instruction model)",
+                            "frac": round(nach / PEAK_LANE_OPS, 4)},
+                    "algorithmic": algorithmic(B_GATES / (navg * 1e-3), ceiling),
+                    "hbm": {"algorithmic_bytes_per_launch": br_hbm_bytes(B_GATES),
+                            "frac": round(br_hbm_bytes(B_GATES) / (navg * 1e-3) / HBM_PEAK, 6),
+                            "measured_bytes_per_launch": ntraffic, "traffic_source": nsrc,
+                            "measured_GBps": None if ntraffic is None else round(ntraffic / (navg * 1e-3) / 1e9, 1)}}
+
+    # per-gate mode: one launch sequence per gate, each streaming the whole key
     per_gate = None
     pg = args.per_gate
     if pg > 0:
@@ -410,11 +484,27 @@ def main():
         c3 = W.config3()
         cin = client.tlwe_encrypt_bits(s0, c3["bits"], *c3["enc"])
         circ = ctx.circuit(c3["gates"], c3["ninputs"])
-        _, lv_ms = circ.run_timed(ctx.tensor(cin))
+        d_cin = ctx.tensor(cin)
+        _, lv_ms = circ.run_timed(d_cin)
         lv = np.array(lv_ms)
+        # the captured level sequence (one HIP graph launch), timed with events
+        wires = circ.run(d_cin)
+        st = torch.cuda.current_stream(ctx.device)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        circ.run(d_cin, wires)
+        e1.record(st)
+        e1.synchronize()
+        graph_ms = e0.elapsed_time(e1)
+        widths = np.asarray(c3["widths"])
         levels = {"levels": int(lv.size), "gates": int(len(c3["gates"])),
-                  "p50_ms": float(np.percentile(lv, 50)), "p99_ms": float(np.percentile(lv, 99)),
-                  "circuit_ms": float(lv.sum()), "gates_per_s": float(len(c3["gates"]) / (lv.sum() / 1e3))}
+                  "p50_ms": round(float(np.percentile(lv, 50)), 3), "p99_ms": round(float(np.percentile(lv, 99)), 3),
+                  "min_width": int(widths.min()), "max_width": int(widths.max()),
+                  "eager_circuit_ms": round(float(lv.sum()), 2),
+                  "eager_gates_per_s": round(float(len(c3["gates"]) / (lv.sum() / 1e3)), 1),
+                  "graph_circuit_ms": round(graph_ms, 2),
+                  "graph_gates_per_s": round(len(c3["gates"]) / (graph_ms / 1e3), 1)}
+        del wires
         circ.close()
 
     memory = None
@@ -435,6 +525,11 @@ def main():
         keyed["offered_fraction_of_batched_throughput"] = args.serving_light
         serving = dict(config=serving, light=light, light_4_key_sets=keyed)
 
+    per_gate_key = None
+    if per_gate is not None:
+        # each gate of the per-gate path streams the whole NTT-domain key once
+        per_gate_key = {"GBps": round(per_gate * BK_NTT_BYTES / 1e9, 2),
+                        "frac_of_hbm": round(per_gate * BK_NTT_BYTES / HBM_PEAK, 6), "gates_timed": pg}
     br_avg_ms = br_ms / max(br_n, 1)
     launch = {"br_shape": br_waves, "keyswitch": ["gather", "tiled", "split", "matrix"][ks_form], "autotune": tune}
     if br_waves == 32:
@@ -446,6 +541,9 @@ def main():
         hbm = mf_step_hbm_bytes(B_GATES) / (mf_avg * 1e-3)
         roof = {"bound": "mfma", "kernel": "k_mf_step", "achieved": round(achieved / 1e12, 1),
                 "peak": PEAK_INT8 / 1e12, "unit": "TOP/s (int8)", "frac": round(achieved / PEAK_INT8, 4),
+                "work": "issued int8 multiply-adds of the one-level Karatsuba Toeplitz products over four "
+                        "balanced byte planes (utilisation of issued work, not the method's arithmetic)",
+                "algorithmic": algorithmic(value, ceiling),
                 "traffic": traffic, "traffic_source": traffic_src, "avg_launch_ms": round(mf_avg, 4),
                 "launches_per_batch": N_LWE, "timed_launches": mf_n, "event_sample_period": PROF_PERIOD,
                 "int8_ops_per_launch": mf_step_ops(B_GATES),
@@ -459,6 +557,7 @@ def main():
         traffic, traffic_src = measured_traffic(br_fingerprint())
         hbm = br_hbm_bytes(B_GATES) / (br_avg_ms * 1e-3)
         roof = {"bound": "alu", "kernel": f"k_blind_rotate<{br_waves}>", "achieved": round(achieved, 3),
+                "algorithmic": algorithmic(B_GATES / (br_avg_ms * 1e-3), ceiling),
                 "peak": round(PEAK_LANE_OPS / 1e12, 3), "unit": "T int32 lane-ops/s",
                 "frac": round(achieved * 1e12 / PEAK_LANE_OPS, 4), "traffic": traffic, "traffic_source": traffic_src,
                 "avg_launch_ms": round(br_avg_ms, 3), "lane_ops_per_gate": LANE_OPS_PER_GATE,
@@ -476,12 +575,15 @@ def main():
         "metric": "gate bootstraps/sec on 1 MI355X, batched vs per-gate; p50/p99 per-level latency",
         "value": round(value, 1), "unit": "gate bootstraps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "int8" if br_waves == 32 else "u64", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "dtype_note": "exact torus arithmetic mod 2^32; " + ("int8 byte-plane MFMA operands with int32 "
+                      "accumulation" if br_waves == 32 else "NTT mod 2^64 - 2^32 + 1 in u64"),
         "config": {"workload": "4096 independent random gates (NAND/AND/OR/XOR/XNOR) on fresh TLWE, "
                                "n=630 N=1024 l=3 Bg=64 ks t=8 base=4, one batched launch",
                    "batch": B_GATES, "parallelism": "single GPU"},
         "per_gate_value": None if per_gate is None else round(per_gate, 2),
         "batched_over_per_gate": None if per_gate is None else round(value / per_gate, 1),
+        "per_gate_key_stream": per_gate_key, "ntt_form_4096": ntt_form,
         "mux_per_s": None if mux_rate is None else round(mux_rate, 1),
         "per_level": levels, "clocked_netlist": machine, "cmux_memory": memory, "serving": serving, "roofline": roof, "cpu_baseline": cpu,
     }
