@@ -110,6 +110,17 @@ vsp_status vsp_context_sync(vsp_context* ctx);
 vsp_status vsp_gates(vsp_context* ctx, const uint8_t* d_ops, const uint32_t* d_in0, const uint32_t* d_in1,
                      uint32_t* d_out, uint64_t B, int mode, void* stream);
 
+/* vsp_gates without any device allocation, for callers that cannot allocate (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc). Same arguments,
+ * results and errors as vsp_gates, bit for bit, with B <= 2048 (larger B: VSP_E_ARG, nothing
+ * enqueued). The intermediate ciphertexts live in one fixed 13.6 MB device array per GPU
+ * (2048 modulus-switched inputs and 2048 extracted TLWE rows), held until the process ends;
+ * the blind rotation runs in its NTT forms (the matrix-core form needs a larger workspace).
+ * Every call on one GPU shares that array, so calls that overlap on a GPU (other streams,
+ * other contexts or threads) race and must be ordered by the caller. */
+vsp_status vsp_gates_noalloc(vsp_context* ctx, const uint8_t* d_ops, const uint32_t* d_in0, const uint32_t* d_in1,
+                             uint32_t* d_out, uint64_t B, int mode, void* stream);
+
 /* Bootstrapping that returns a TRLWE (Sec. 2.1.2 "Bootstrapping in TFHE", without SE and
  * IKS): d_out[g] [2][N] is the blind-rotation accumulator of op_g(in0, in1) with the test
  * vector mu in every coefficient (constant coefficient encodes the gate's output bit).

@@ -50,6 +50,7 @@ SIGNATURES = {
     "vsp_context_destroy": (_st, [_vp]),
     "vsp_context_sync": (_st, [_vp]),
     "vsp_gates": (_st, [_vp, _vp, _vp, _vp, _vp, _u64, _i32, _vp]),
+    "vsp_gates_noalloc": (_st, [_vp, _vp, _vp, _vp, _vp, _u64, _i32, _vp]),
     "vsp_bootstrap_trlwe": (_st, [_vp, _vp, _vp, _vp, _vp, _u64, _vp]),
     "vsp_circuit_create": (_st, [_vp, ctypes.POINTER(vsp_gate_desc), _u64, _u64, ctypes.POINTER(_vp)]),
     "vsp_circuit_run": (_st, [_vp, _vp, _vp, _vp]),
@@ -128,6 +129,10 @@ def vsp_context_sync(ctx: int) -> None:
 
 def vsp_gates(ctx, d_ops, d_in0, d_in1, d_out, B, mode=VSP_BATCHED, stream=None) -> None:
     _call("vsp_gates", ctx, d_ops, d_in0, d_in1, d_out, B, mode, stream)
+
+
+def vsp_gates_noalloc(ctx, d_ops, d_in0, d_in1, d_out, B, mode=VSP_BATCHED, stream=None) -> None:
+    _call("vsp_gates_noalloc", ctx, d_ops, d_in0, d_in1, d_out, B, mode, stream)
 
 
 def vsp_bootstrap_trlwe(ctx, d_ops, d_in0, d_in1, d_out, B, stream=None) -> None:

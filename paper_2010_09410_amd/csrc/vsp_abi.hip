@@ -2,6 +2,7 @@
 // TRLWE-output bootstrapping and the test entry points. CMUX memory, circuits and the
 // server have their own files.
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -212,6 +213,37 @@ const char* vsp_status_str(vsp_status s) {
 
 const char* vsp_last_error(void) { return g_last_error.c_str(); }
 
+// ------------------------------------------------------------------ allocation-free gates
+// Fixed device scratch of vsp_gates_noalloc: the modulus-switched inputs ([kStaticGates][n+1])
+// and the extracted TLWE rows ([kStaticGates][N+1]) of one call. Each device holds its own
+// copy at its own address, resolved once per device (with that device current) when the first
+// context on it is created; host code uses only that address, never the array's name.
+constexpr uint64_t kStaticGates = 2048;
+constexpr size_t kStaticAbarBytes = (size_t)kStaticGates * TLWE0 * 4;
+constexpr size_t kStaticBytes = kStaticAbarBytes + (size_t)kStaticGates * TLWE1 * 4;
+static_assert(kStaticAbarBytes % 256 == 0, "the extracted rows start 256-byte aligned");
+static __device__ __align__(256) uint8_t scratch[kStaticBytes];
+
+static std::mutex g_scratch_mu;
+static std::vector<void*> g_scratch_ptr;  // indexed by device; null until resolved
+
+static vsp_status resolve_static_scratch(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((size_t)device < g_scratch_ptr.size() && g_scratch_ptr[device] != nullptr) return VSP_OK;
+  void* p = nullptr;
+  hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+  if (p == nullptr) return fail(VSP_E_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+  if ((size_t)device >= g_scratch_ptr.size()) g_scratch_ptr.resize((size_t)device + 1, nullptr);
+  g_scratch_ptr[device] = p;
+  return VSP_OK;
+}
+
+static void* static_scratch(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return (size_t)device < g_scratch_ptr.size() ? g_scratch_ptr[device] : nullptr;
+}
+
 vsp_status vsp_context_create(const vsp_params* params, const uint32_t* bk_host, const uint32_t* ksk_host, int device,
                               vsp_context** out) {
   if (out == nullptr) return fail(VSP_E_ARG, "out is NULL");
@@ -228,6 +260,7 @@ vsp_status vsp_context_create(const vsp_params* params, const uint32_t* bk_host,
   VSP_HIP(init_kernel_attributes());
   VSP_HIP(init_memory_kernel_attributes());
   VSP_HIP(init_mf_kernel_attributes());
+  if (vsp_status st = resolve_static_scratch(device)) return st;
   std::vector<u64> tw;
   if (!make_tables(tw)) return fail(VSP_E_HIP, "twiddle table construction failed");
 
@@ -282,14 +315,12 @@ vsp_status vsp_context_sync(vsp_context* ctx) {
   return VSP_OK;
 }
 
-static vsp_status gates_impl(vsp_context* ctx, const uint8_t* d_ops, const uint32_t* d_in0, const uint32_t* d_in1,
-                             uint32_t* d_out, uint64_t B, int mode, void* stream, bool trlwe_out) {
-  vsp_status s = check_ctx(ctx);
-  if (s) return s;
+// Argument checks shared by the gate entry points.
+static vsp_status check_gate_args(vsp_context* ctx, const uint8_t* d_ops, const uint32_t* d_in0, const uint32_t* d_in1,
+                                  uint32_t* d_out, uint64_t B, int mode, bool trlwe_out) {
+  vsp_status s;
   if (mode != VSP_BATCHED && mode != VSP_PER_GATE) return fail(VSP_E_ARG, "mode must be VSP_BATCHED or VSP_PER_GATE");
-  if (B == 0) return VSP_OK;
   if (B > (1ull << 31)) return fail(VSP_E_ARG, "B too large");
-  VSP_HIP(hipSetDevice(ctx->device));
   const size_t tl = (size_t)B * (LWE_N + 1) * 4;
   const size_t ob = trlwe_out ? (size_t)B * 2 * RING_N * 4 : tl;
   if ((s = check_device_range(ctx, d_ops, B, "d_ops"))) return s;
@@ -299,15 +330,16 @@ static vsp_status gates_impl(vsp_context* ctx, const uint8_t* d_ops, const uint3
   if ((s = check_no_overlap(d_out, ob, d_in0, tl, "d_out and d_in0"))) return s;
   if ((s = check_no_overlap(d_out, ob, d_in1, tl, "d_out and d_in1"))) return s;
   if ((s = check_no_overlap(d_out, ob, d_ops, B, "d_out and d_ops"))) return s;
-  const uint64_t chunk = (mode == VSP_BATCHED) ? std::min<uint64_t>(B, kMaxLaunch) : 1;
-  if ((s = scratch_reserve(ctx, ctx->abar, chunk * (LWE_N + 1) * 4))) return s;
-  if (!trlwe_out && (s = scratch_reserve(ctx, ctx->tlwe1, chunk * (RING_N + 1) * 4))) return s;
-  const bool matrix = ctx->tune.br_waves(chunk) == 32 || (B > chunk && ctx->tune.br_waves(B % chunk) == 32);
-  if (matrix && (s = scratch_reserve(ctx, ctx->mf_work, mf_work_bytes(chunk, !trlwe_out)))) return s;
-  void* mfw = matrix ? ctx->mf_work.ptr : nullptr;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  uint32_t* abar = static_cast<uint32_t*>(ctx->abar.ptr);
-  uint32_t* t1 = static_cast<uint32_t*>(ctx->tlwe1.ptr);
+  return VSP_OK;
+}
+
+// Enqueues prologue -> blind rotation -> key switch (or the TRLWE output) for B gates in
+// chunks of `chunk`, with the modulus-switched inputs in abar (chunk rows), the extracted rows
+// in t1 (chunk rows) and the matrix-core workspace mfw (NULL: the NTT forms).
+static vsp_status gates_enqueue(vsp_context* ctx, const uint8_t* d_ops, const uint32_t* d_in0, const uint32_t* d_in1,
+                                uint32_t* d_out, uint64_t B, uint64_t chunk, bool trlwe_out, uint32_t* abar,
+                                uint32_t* t1, void* mfw, hipStream_t st, bool prof) {
+  const vsp_context* pc = prof ? ctx : nullptr;
   for (uint64_t g0 = 0; g0 < B; g0 += chunk) {
     const uint64_t nb = (B - g0 < chunk) ? B - g0 : chunk;
     const uint8_t* ops = d_ops + g0;
@@ -318,29 +350,29 @@ static vsp_status gates_impl(vsp_context* ctx, const uint8_t* d_ops, const uint3
       uint32_t* o = d_out + g0 * 2 * RING_N;
       // NOT / invalid opcodes are reported through the device flag; their TRLWE stays untouched.
       {
-        ProfScope ps(ctx, 2, st);
+        ProfScope ps(pc, 2, st);
         e = launch_gate_prologue(ctx, ops, i0, i1, nullptr, nullptr, nullptr, abar, nullptr, nb, st, false);
       }
       if (e != hipSuccess) return hip_fail(e, "gate prologue");
       {
-        ProfScope ps(ctx, 0, st);
-        e = launch_blind_rotate(ctx, ops, abar, nullptr, o, nb, 0, st, nullptr, nullptr, nullptr, mfw, true);
+        ProfScope ps(pc, 0, st);
+        e = launch_blind_rotate(ctx, ops, abar, nullptr, o, nb, 0, st, nullptr, nullptr, nullptr, mfw, prof);
       }
       if (e != hipSuccess) return hip_fail(e, "blind rotation");
     } else {
       uint32_t* o = d_out + g0 * (LWE_N + 1);
       {
-        ProfScope ps(ctx, 2, st);
+        ProfScope ps(pc, 2, st);
         e = launch_gate_prologue(ctx, ops, i0, i1, nullptr, nullptr, nullptr, abar, o, nb, st);
       }
       if (e != hipSuccess) return hip_fail(e, "gate prologue");
       {
-        ProfScope ps(ctx, 0, st);
-        e = launch_blind_rotate(ctx, ops, abar, t1, nullptr, nb, 0, st, nullptr, nullptr, nullptr, mfw, true);
+        ProfScope ps(pc, 0, st);
+        e = launch_blind_rotate(ctx, ops, abar, t1, nullptr, nb, 0, st, nullptr, nullptr, nullptr, mfw, prof);
       }
       if (e != hipSuccess) return hip_fail(e, "blind rotation");
       {
-        ProfScope ps(ctx, 1, st);
+        ProfScope ps(pc, 1, st);
         e = launch_keyswitch(ctx, ops, t1, nullptr, o, nb, st);
       }
       if (e != hipSuccess) return hip_fail(e, "key switch");
@@ -349,9 +381,48 @@ static vsp_status gates_impl(vsp_context* ctx, const uint8_t* d_ops, const uint3
   return VSP_OK;
 }
 
+static vsp_status gates_impl(vsp_context* ctx, const uint8_t* d_ops, const uint32_t* d_in0, const uint32_t* d_in1,
+                             uint32_t* d_out, uint64_t B, int mode, void* stream, bool trlwe_out) {
+  vsp_status s = check_ctx(ctx);
+  if (s) return s;
+  if (mode != VSP_BATCHED && mode != VSP_PER_GATE) return fail(VSP_E_ARG, "mode must be VSP_BATCHED or VSP_PER_GATE");
+  if (B == 0) return VSP_OK;
+  VSP_HIP(hipSetDevice(ctx->device));
+  if ((s = check_gate_args(ctx, d_ops, d_in0, d_in1, d_out, B, mode, trlwe_out))) return s;
+  const uint64_t chunk = (mode == VSP_BATCHED) ? std::min<uint64_t>(B, kMaxLaunch) : 1;
+  if ((s = scratch_reserve(ctx, ctx->abar, chunk * (LWE_N + 1) * 4))) return s;
+  if (!trlwe_out && (s = scratch_reserve(ctx, ctx->tlwe1, chunk * (RING_N + 1) * 4))) return s;
+  const bool matrix = ctx->tune.br_waves(chunk) == 32 || (B > chunk && ctx->tune.br_waves(B % chunk) == 32);
+  if (matrix && (s = scratch_reserve(ctx, ctx->mf_work, mf_work_bytes(chunk, !trlwe_out)))) return s;
+  void* mfw = matrix ? ctx->mf_work.ptr : nullptr;
+  return gates_enqueue(ctx, d_ops, d_in0, d_in1, d_out, B, chunk, trlwe_out, static_cast<uint32_t*>(ctx->abar.ptr),
+                       static_cast<uint32_t*>(ctx->tlwe1.ptr), mfw, static_cast<hipStream_t>(stream), true);
+}
+
+
 vsp_status vsp_gates(vsp_context* ctx, const uint8_t* d_ops, const uint32_t* d_in0, const uint32_t* d_in1,
                      uint32_t* d_out, uint64_t B, int mode, void* stream) {
   return gates_impl(ctx, d_ops, d_in0, d_in1, d_out, B, mode, stream, false);
+}
+
+vsp_status vsp_gates_noalloc(vsp_context* ctx, const uint8_t* d_ops, const uint32_t* d_in0, const uint32_t* d_in1,
+                             uint32_t* d_out, uint64_t B, int mode, void* stream) {
+  vsp_status s = check_ctx(ctx);
+  if (s) return s;
+  if (mode != VSP_BATCHED && mode != VSP_PER_GATE) return fail(VSP_E_ARG, "mode must be VSP_BATCHED or VSP_PER_GATE");
+  if (B > kStaticGates)
+    return fail(VSP_E_ARG, "vsp_gates_noalloc takes at most " + std::to_string(kStaticGates) + " gates per call (got " +
+                               std::to_string(B) + ")");
+  if (B == 0) return VSP_OK;
+  VSP_HIP(hipSetDevice(ctx->device));
+  if ((s = check_gate_args(ctx, d_ops, d_in0, d_in1, d_out, B, mode, false))) return s;
+  uint8_t* base = static_cast<uint8_t*>(static_scratch(ctx->device));
+  if (base == nullptr) return fail(VSP_E_STATE, "the static scratch of this device was not resolved");
+  const uint64_t chunk = (mode == VSP_BATCHED) ? B : 1;
+  // no matrix-core workspace: the NTT forms of the blind rotation (the key switch needs none)
+  return gates_enqueue(ctx, d_ops, d_in0, d_in1, d_out, B, chunk, false, reinterpret_cast<uint32_t*>(base),
+                       reinterpret_cast<uint32_t*>(base + kStaticAbarBytes), nullptr,
+                       static_cast<hipStream_t>(stream), false);
 }
 
 vsp_status vsp_bootstrap_trlwe(vsp_context* ctx, const uint8_t* d_ops, const uint32_t* d_in0, const uint32_t* d_in1,
