@@ -1,7 +1,8 @@
 // Autotuner for the batched launches. On random ciphertexts it times one full round of gates
 // for each blind-rotation form (4 or 8 gates per workgroup at one wave per gate, one gate on
 // three waves, and the matrix-core form; a launch then picks the form with the fewest rounds x
-// round time for its batch) and the four key-switch forms (one workgroup per gate,
+// round time for its batch), the split matrix-core form at every bucket size with each
+// row-group count (the fastest count is kept per bucket) and the four key-switch forms (one workgroup per gate,
 // row-stationary tiles, LDS-staged split, matrix cores) per batch-size bucket. Every candidate
 // must produce bit-identical outputs. The result can be cached in a small JSON file keyed by
 // the GPU; a cache written for another list of forms is ignored.
@@ -47,8 +48,9 @@ std::string device_key(int dev) {
   return arch + "-" + std::to_string(p.multiProcessorCount) + "cu";
 }
 
-// Cache file: {"<device>": {"br_waves": [4, 8], "br_cap": [..], "br_round_ms": [..],
-//                          "buckets": [..], "ks_form": [..]}}
+// Cache file: {"<device>": {"br_waves": [4, 8, ..], "br_cap": [..], "br_round_ms": [..],
+//                          "buckets": [..], "ks_form": [..], "split_ms": [..],
+//                          "split_groups": [..]}}
 bool read_numbers(const std::string& s, size_t from, const char* name, double* out, int count) {
   const size_t p = s.find(std::string("\"") + name + "\"", from);
   if (p == std::string::npos) return false;
@@ -75,9 +77,11 @@ bool read_cache(const std::string& path, const std::string& key, Tuning& t) {
   const size_t at = s.find("\"" + key + "\"");
   if (at == std::string::npos) return false;
   double shapes[kBrShapes], cap[kBrShapes], ms[kBrShapes], ks[kTuneBuckets], buckets[kTuneBuckets];
+  double sms[kTuneBuckets], sg[kTuneBuckets];
   if (!read_numbers(s, at, "br_waves", shapes, kBrShapes) || !read_numbers(s, at, "br_cap", cap, kBrShapes) ||
       !read_numbers(s, at, "br_round_ms", ms, kBrShapes) || !read_numbers(s, at, "buckets", buckets, kTuneBuckets) ||
-      !read_numbers(s, at, "ks_form", ks, kTuneBuckets))
+      !read_numbers(s, at, "ks_form", ks, kTuneBuckets) || !read_numbers(s, at, "split_ms", sms, kTuneBuckets) ||
+      !read_numbers(s, at, "split_groups", sg, kTuneBuckets))
     return false;
   for (int i = 0; i < kBrShapes; i++)
     if (shapes[i] != kBrWaveChoices[i]) return false;  // written for another list of forms
@@ -92,6 +96,13 @@ bool read_cache(const std::string& path, const std::string& key, Tuning& t) {
   for (int b = 0; b < kTuneBuckets; b++) {
     if (!(ks[b] >= 0 && ks[b] < kKsForms && ks[b] == (double)(int)ks[b])) return false;
     n.ks_form[b] = (int)ks[b];
+  }
+  for (int b = 0; b < kTuneBuckets; b++) {
+    const int g = (int)sg[b];
+    if (!(sms[b] > 0 && sms[b] < 1e9) || (double)g != sg[b] || !(g == 0 || g == 1 || g == 2 || g == 3 || g == 6))
+      return false;
+    n.split_ms[b] = (float)sms[b];
+    n.split_groups[b] = g;
   }
   n.tuned = true;
   t = n;
@@ -116,6 +127,10 @@ bool write_cache(const std::string& path, const std::string& key, const Tuning& 
   list([](int i) { return kBucket[i]; }, kTuneBuckets);
   f << ", \"ks_form\": ";
   list([&](int i) { return t.ks_form[i]; }, kTuneBuckets);
+  f << ", \"split_ms\": ";
+  list([&](int i) { return t.split_ms[i]; }, kTuneBuckets);
+  f << ", \"split_groups\": ";
+  list([&](int i) { return t.split_groups[i]; }, kTuneBuckets);
   f << "}}\n";
   return (bool)f;
 }
@@ -202,6 +217,24 @@ vsp_status vsp_autotune(vsp_context* ctx, uint64_t max_batch, const char* cache_
     if (s > 0 && !same(t1ref.p, t1.p, std::min(t.br_cap[0], B) * T1))
       result = fail(VSP_E_HIP, "autotune: blind-rotation shapes disagree");
   }
+  // the split matrix-core form at every bucket size, with each row-group count
+  for (int b = 0; b < kTuneBuckets && result == VSP_OK && ctx->mf_key; b++) {
+    const uint64_t B = std::min<uint64_t>(kBucket[b], t.br_cap[3]);
+    float best = 1e30f;
+    for (int g : {1, 2, 3, 6}) {
+      const float ms = timed([&] {
+        (void)launch_blind_rotate_mfsplit(ctx, dops, dab, static_cast<uint32_t*>(t1.p), nullptr, B, ctx->mf_work.ptr,
+                                          g, st);
+      });
+      if (!same(t1ref.p, t1.p, std::min(t.br_cap[0], B) * T1))
+        result = fail(VSP_E_HIP, "autotune: blind-rotation shapes disagree");
+      if (ms < best) {
+        best = ms;
+        t.split_ms[b] = ms;
+        t.split_groups[b] = g;
+      }
+    }
+  }
   // Key switch on random TLWE1 rows, per bucket, at the bucket's largest batch.
   if (result == VSP_OK && (e = fill(static_cast<uint32_t*>(t1ref.p), S * (RING_N + 1), 0x7a11, 0, st)) != hipSuccess)
     result = hip_fail(e, "fill");
@@ -242,9 +275,9 @@ vsp_status vsp_tuning_get(const vsp_context* ctx, uint64_t B, int* br_waves, int
 
 vsp_status vsp_tuning_set(vsp_context* ctx, uint64_t B, int br_waves, int ks_form) {
   if (ctx == nullptr) return fail(VSP_E_ARG, "context is NULL");
-  if ((br_waves != 0 && br_waves != 3 && br_waves != 4 && br_waves != 8 && br_waves != 32) || ks_form < 0 ||
-      ks_form >= kKsForms)
-    return fail(VSP_E_ARG, "br_waves must be 0 (model), 3, 4, 8 or 32 and ks_form 0, 1, 2 or 3");
+  if ((br_waves != 0 && br_waves != 3 && br_waves != 4 && br_waves != 8 && br_waves != 32 && br_waves != 33) ||
+      ks_form < 0 || ks_form >= kKsForms)
+    return fail(VSP_E_ARG, "br_waves must be 0 (model), 3, 4, 8, 32 or 33 and ks_form 0, 1, 2 or 3");
   const int b = Tuning::bucket(B == 0 ? 1 : B);
   ctx->tune.br_force[b] = br_waves;
   ctx->tune.ks_form[b] = ks_form;

@@ -448,6 +448,144 @@ __global__ __launch_bounds__(MF_THREADS) void k_mf_step(const int8_t* __restrict
   }
 }
 
+// Split step for batches too small to fill the chip with (tile, output) workgroups: the work
+// of one step is cut into workgroups of four waves per (tile, output o, sub-product s, group
+// of TRGSW rows), wave q computing outputs [128 q, 128 q + 128) of P_s over the rows of its
+// group and all four byte planes (the same pass loop as k_mf_step with one operand segment
+// and one key sequence per pass). Each workgroup adds its share of y straight into ACC with
+// integer atomic adds (exact in any order: addition mod 2^32): P1 into both halves, P2 into
+// y0, P3 into y1. The next step's digits come from a separate launch of k_mf_digits, after
+// every share of the step has landed. Row groups: rows [rg * rows, rg * rows + rows) with
+// rows = 6 / groups (groups 1, 2, 3 or 6).
+constexpr int MFP_THREADS = 256;
+constexpr int MFP_A_U4 = MF_KB * 64;                                  // one segment of one row: 1024 operands
+constexpr size_t MFP_LDS = 2 * ((size_t)MFP_A_U4 * 16 + 4 * (size_t)MF_COPY_U32 * 4);
+static_assert(MFP_A_U4 == 4 * MFP_THREADS && MF_S / 4 == MFP_THREADS,
+              "four 16-byte operands and one key word per thread and pass");
+
+__global__ __launch_bounds__(MFP_THREADS, 3) void k_mf_part(const int8_t* __restrict__ Ek, const int8_t* __restrict__ A,
+                                                          u32* __restrict__ acc, const uint8_t* __restrict__ ops,
+                                                          uint64_t B, int groups) {
+  __shared__ uint4 abuf[2][MFP_A_U4];
+  __shared__ u32 ebuf[2][4 * MF_COPY_U32];
+  const uint64_t mt = blockIdx.x;
+  const int o = blockIdx.y;
+  const int sub = (int)blockIdx.z % MF_SUB, rg = (int)blockIdx.z / MF_SUB;
+  const int rows = MF_ROWS / groups, r0 = rg * rows, passes = MF_PLANES * rows;
+  const int tid = threadIdx.x, wl = tid >> 6, lane = tid & 63, n = lane & 31, kh = lane >> 5;
+  const int tb = MF_HALF + 128 * wl + n - 16 * kh - 15;
+  const int cp = tb & 3;
+  const int bofs = cp * MF_COPY_U32 + ((tb - cp) >> 2) - 8 * (MF_KB - 1);
+  const uint4* Ag = reinterpret_cast<const uint4*>(A + mt * MF_A_TILE) + sub * MFP_A_U4 + tid;
+  const u32* Eu = reinterpret_cast<const u32*>(Ek);
+  // pass p: plane 3 - p / rows, row r0 + p % rows (any row order gives the same plane sum)
+  auto a_row = [&](int pass) { return Ag + (size_t)(r0 + pass % rows) * (MF_A_ROW / 16); };
+  auto e_row = [&](int pass) {
+    const int r = r0 + pass % rows, b = MF_PLANES - 1 - pass / rows;
+    return Eu + ((((size_t)r * 2 + o) * MF_PLANES + b) * MF_SUB + sub) * (MF_S / 4);
+  };
+  auto stage_e = [&](u32* dst, u32 d0, u32 d1) {
+#pragma unroll
+    for (int c = 0; c < 4; c++) dst[c * MF_COPY_U32 + tid] = __builtin_amdgcn_alignbyte(d1, d0, c);
+  };
+  if (tid < 2 * 4 * 4) {  // the tails of all copies of both buffers
+    const int bufi = tid >> 4, rest = tid & 15;
+    ebuf[bufi][(rest >> 2) * MF_COPY_U32 + MF_S / 4 + (rest & 3)] = 0u;
+  }
+  {
+    const uint4* as = a_row(0);
+    const uint4 x0 = as[0], x1 = as[MFP_THREADS], x2 = as[2 * MFP_THREADS], x3 = as[3 * MFP_THREADS];
+    const u32* er = e_row(0);
+    const u32 d0 = er[tid], d1 = (tid + 1 < MF_S / 4) ? er[tid + 1] : 0u;
+    abuf[0][tid] = x0;
+    abuf[0][tid + MFP_THREADS] = x1;
+    abuf[0][tid + 2 * MFP_THREADS] = x2;
+    abuf[0][tid + 3 * MFP_THREADS] = x3;
+    stage_e(ebuf[0], d0, d1);
+  }
+  __syncthreads();
+  v16i c[4];
+#pragma unroll
+  for (int nb = 0; nb < 4; nb++)
+#pragma unroll
+    for (int x = 0; x < 16; x++) c[nb][x] = 0;
+  for (int pass = 0; pass < passes; pass++) {
+    const int buf = pass & 1;
+    const int nx = (pass + 1 < passes) ? pass + 1 : pass;  // the last pass fetches itself again, unused
+    const uint4* as = a_row(nx);
+    const uint4 p0 = as[0], p1 = as[MFP_THREADS], p2 = as[2 * MFP_THREADS], p3 = as[3 * MFP_THREADS];
+    u32 pd0, pd1;
+    {
+      const u32* er = e_row(nx);
+      pd0 = er[tid];
+      pd1 = (tid + 1 < MF_S / 4) ? er[tid + 1] : 0u;
+    }
+    const uint4* Ar = abuf[buf] + lane;
+    const u32* Bp = ebuf[buf] + bofs;
+    auto ldb = [&](int wofs) {
+      return v4i{(int)Bp[wofs], (int)Bp[wofs + 1], (int)Bp[wofs + 2], (int)Bp[wofs + 3]};
+    };
+    auto lda = [](const uint4& u) { return v4i{(int)u.x, (int)u.y, (int)u.z, (int)u.w}; };
+    v4i R[8], Av[4];
+#pragma unroll
+    for (int nb = 0; nb < 4; nb++) R[nb] = ldb(8 * (MF_KB - 1 + nb));
+    R[7] = ldb(8 * (MF_KB - 2));
+    Av[0] = lda(Ar[0]);
+    Av[1] = lda(Ar[64]);
+    for (int k8 = 0; k8 < MF_KB; k8 += 8) {
+#pragma unroll
+      for (int s8 = 0; s8 < 8; s8++) {
+        const int kb = k8 + s8;
+        const int kn = (kb + 2 < MF_KB) ? kb + 2 : MF_KB - 1;
+        Av[(s8 + 2) & 3] = lda(Ar[kn * 64]);
+        R[(6 - s8) & 7] = ldb(8 * (MF_KB - 1 - kn));
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int nb = 0; nb < 4; nb++)
+          c[nb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(Av[s8 & 3], R[(nb - s8) & 7], c[nb], 0, 0, 0);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+    if (pass % rows == rows - 1 && pass + 1 < passes) {
+#pragma unroll
+      for (int nb = 0; nb < 4; nb++)
+#pragma unroll
+        for (int x = 0; x < 16; x++) c[nb][x] = (int)((u32)c[nb][x] << 8);
+    }
+    if (pass + 1 < passes) {
+      uint4* ad = abuf[buf ^ 1] + tid;
+      ad[0] = p0;
+      ad[MFP_THREADS] = p1;
+      ad[2 * MFP_THREADS] = p2;
+      ad[3 * MFP_THREADS] = p3;
+      stage_e(ebuf[buf ^ 1], pd0, pd1);
+    }
+    __syncthreads();
+  }
+  // gates of the tile that bootstrap: bit m of `live` (lanes 0..31 test gate m = lane)
+  bool mine = false;
+  {
+    const uint64_t g = mt * MF_TILE + n;
+    const uint8_t op = ops ? ops[g < B ? g : 0] : (uint8_t)0;
+    mine = kh == 0 && g < B && op_bootstraps(op);
+  }
+  const uint64_t live = __ballot(mine);
+  // result (m, i): lane n + 32 kh, register x of block nb, m = 8 (x / 4) + 4 kh + x % 4,
+  // i = 128 q + 32 nb + n; P1 adds into outputs i and N/2 + i, P2 into i, P3 into N/2 + i
+#pragma unroll
+  for (int x = 0; x < 16; x++) {
+    const int m = 8 * (x >> 2) + 4 * kh + (x & 3);
+    if (!((live >> m) & 1)) continue;
+    u32* row = acc + ((mt * MF_TILE + m) * 2 + o) * RING_N + 128 * wl + n;
+#pragma unroll
+    for (int nb = 0; nb < 4; nb++) {
+      const u32 v = (u32)c[nb][x];
+      if (sub != 2) atomicAdd(row + 32 * nb, v);
+      if (sub != 1) atomicAdd(row + MF_HALF + 32 * nb, v);
+    }
+  }
+}
+
 hipError_t init_mf_kernel_attributes() {
   return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mf_step), hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)MF_STEP_LDS);
@@ -485,6 +623,35 @@ hipError_t launch_blind_rotate_mfma(const vsp_context* ctx, const uint8_t* ops, 
       hipLaunchKernelGGL(k_mf_step, dim3((unsigned)tiles, 2), dim3(MF_THREADS), MF_STEP_LDS, st,
                          ctx->mf_key + (size_t)i * MF_KEY_STEP, Ab[i & 1], acc, ops, B, Ab[(i + 1) & 1], abar,
                          i + 1 < LWE_N ? i + 1 : -1);
+  }
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && tlwe1) e = launch_sample_extract(acc, tlwe1, B, 1, st);
+  return e;
+}
+
+// Split form of the matrix-core blind rotation: per step one k_mf_part launch (shares of the
+// products added into ACC) and one k_mf_digits launch (the next step's operands from ACC).
+// groups (1, 2, 3 or 6) sets the TRGSW rows per workgroup; the workspace is that of the fused
+// form (the operands of one step and, without a caller TRLWE, the accumulators).
+hipError_t launch_blind_rotate_mfsplit(const vsp_context* ctx, const uint8_t* ops, const uint32_t* abar,
+                                       uint32_t* tlwe1, uint32_t* trlwe, uint64_t B, void* work, int groups,
+                                       hipStream_t st, bool instrument) {
+  if (B == 0) return hipSuccess;
+  if (groups != 1 && groups != 2 && groups != 3 && groups != 6) return hipErrorInvalidValue;
+  const uint64_t tiles = (B + MF_TILE - 1) / MF_TILE;
+  int8_t* Aop = static_cast<int8_t*>(work);
+  u32* acc = trlwe ? trlwe : reinterpret_cast<u32*>(Aop + 2 * tiles * MF_A_TILE);
+  hipLaunchKernelGGL(k_mf_init, dim3((unsigned)((B * 2 * RING_N + 255) / 256)), dim3(256), 0, st, ops, abar, acc, B);
+  const dim3 dgrid((unsigned)tiles, 2, MF_TILE / MF_DG);
+  hipLaunchKernelGGL(k_mf_digits, dgrid, dim3(256), 0, st, ops, abar, acc, Aop, B, 0);
+  {
+    ProfScope ps(instrument ? ctx : nullptr, 3, st, LWE_N);
+    for (int i = 0; i < LWE_N; i++) {
+      hipLaunchKernelGGL(k_mf_part, dim3((unsigned)tiles, 2, (unsigned)(MF_SUB * groups)), dim3(MFP_THREADS), 0, st,
+                         ctx->mf_key + (size_t)i * MF_KEY_STEP, Aop, acc, ops, B, groups);
+      if (i + 1 < LWE_N)
+        hipLaunchKernelGGL(k_mf_digits, dgrid, dim3(256), 0, st, ops, abar, acc, Aop, B, i + 1);
+    }
   }
   hipError_t e = hipGetLastError();
   if (e == hipSuccess && tlwe1) e = launch_sample_extract(acc, tlwe1, B, 1, st);

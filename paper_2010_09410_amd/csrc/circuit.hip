@@ -132,7 +132,7 @@ vsp_status vsp_circuit_create(vsp_context* ctx, const vsp_gate_desc* gates, uint
   if ((e = hipMalloc(&c->d_tlwe1, wmax * (RING_N + 1) * 4)) != hipSuccess) return bail(hip_fail(e, "hipMalloc"));
   bool matrix = false;  // the launch choice is fixed when the level sequence is captured below
   for (uint64_t L = 0; L < nlev && ctx->mf_key; L++)
-    matrix |= ctx->tune.br_waves(std::min<uint64_t>(kMaxLaunch, c->off[L + 1] - c->off[L])) == 32;
+    matrix |= br_matrix_form(ctx->tune.br_waves(std::min<uint64_t>(kMaxLaunch, c->off[L + 1] - c->off[L])));
   if (matrix && (e = hipMalloc(&c->d_mf, mf_work_bytes(wmax, true))) != hipSuccess) return bail(hip_fail(e, "hipMalloc"));
   if (ngates) {
     if ((e = hipMemcpy(c->d_ops, hops.data(), ngates, hipMemcpyHostToDevice)) != hipSuccess) return bail(hip_fail(e, "upload"));

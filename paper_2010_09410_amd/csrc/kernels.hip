@@ -183,13 +183,16 @@ hipError_t blind_rotate_capacity(int device, uint64_t (&cap)[kBrShapes]) {
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nw, reinterpret_cast<const void*>(&k_blind_rotate_wide),
                                                      BRW_WAVES * 64, brw_lds_bytes());
   if (e != hipSuccess) return e;
-  static_assert(kBrWaveChoices[0] == 4 && kBrWaveChoices[1] == 8 && kBrWaveChoices[2] == 3 && kBrWaveChoices[3] == 32,
+  static_assert(kBrWaveChoices[0] == 4 && kBrWaveChoices[1] == 8 && kBrWaveChoices[2] == 3 && kBrWaveChoices[3] == 32 &&
+                    kBrWaveChoices[4] == 33,
                 "shape order");
   cap[0] = (uint64_t)(n4 > 0 ? n4 : 1) * (uint64_t)cus * 4;
   cap[1] = (uint64_t)(n8 > 0 ? n8 : 1) * (uint64_t)cus * 8;
   cap[2] = (uint64_t)(nw > 0 ? nw : 1) * (uint64_t)cus;
   // matrix-core form: one workgroup per compute unit holds half a tile of MF_TILE gates
   cap[3] = (uint64_t)cus * MF_TILE / 2;
+  // split form: its shortest launch, one tile
+  cap[4] = MF_TILE;
   return hipSuccess;
 }
 
@@ -199,9 +202,11 @@ hipError_t launch_blind_rotate(const vsp_context* ctx, const uint8_t* ops, const
   if (B == 0) return hipSuccess;
   if (bkn == nullptr) bkn = ctx->bkn;
   if (waves <= 0) waves = ctx->tune.br_waves(B);
-  if (waves == 32) {
+  if (br_matrix_form(waves)) {
     if (keytab == nullptr && bkn == ctx->bkn && mf_work != nullptr && ctx->mf_key != nullptr)
-      return launch_blind_rotate_mfma(ctx, ops, abar, tlwe1, trlwe, B, mf_work, st, instrument);
+      return waves == 32 ? launch_blind_rotate_mfma(ctx, ops, abar, tlwe1, trlwe, B, mf_work, st, instrument)
+                         : launch_blind_rotate_mfsplit(ctx, ops, abar, tlwe1, trlwe, B, mf_work,
+                                                       ctx->tune.split_groups_for(B, ctx->cus), st, instrument);
     waves = 8;
   }
   if (waves == 3) {

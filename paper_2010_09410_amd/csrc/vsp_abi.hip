@@ -392,7 +392,8 @@ static vsp_status gates_impl(vsp_context* ctx, const uint8_t* d_ops, const uint3
   const uint64_t chunk = (mode == VSP_BATCHED) ? std::min<uint64_t>(B, kMaxLaunch) : 1;
   if ((s = scratch_reserve(ctx, ctx->abar, chunk * (LWE_N + 1) * 4))) return s;
   if (!trlwe_out && (s = scratch_reserve(ctx, ctx->tlwe1, chunk * (RING_N + 1) * 4))) return s;
-  const bool matrix = ctx->tune.br_waves(chunk) == 32 || (B > chunk && ctx->tune.br_waves(B % chunk) == 32);
+  const bool matrix =
+      br_matrix_form(ctx->tune.br_waves(chunk)) || (B > chunk && br_matrix_form(ctx->tune.br_waves(B % chunk)));
   if (matrix && (s = scratch_reserve(ctx, ctx->mf_work, mf_work_bytes(chunk, !trlwe_out)))) return s;
   void* mfw = matrix ? ctx->mf_work.ptr : nullptr;
   return gates_enqueue(ctx, d_ops, d_in0, d_in1, d_out, B, chunk, trlwe_out, static_cast<uint32_t*>(ctx->abar.ptr),

@@ -31,11 +31,23 @@ __host__ __device__ inline bool op_bootstraps(uint32_t op) { return op < 8 || op
 constexpr int DEVERR_BAD_OP = 1;
 
 // Blind-rotation forms: 4 or 8 gates per workgroup at one wave per gate, 3 for one gate per
-// workgroup on three waves (the latency form), and 32 for the matrix-core form (int8 MFMA
-// products over tiles of MF_TILE gates, two launches per step).
-constexpr int kBrShapes = 4;
-constexpr int kBrWaveChoices[kBrShapes] = {4, 8, 3, 32};
+// workgroup on three waves (the latency form), 32 for the matrix-core form (int8 MFMA products
+// over tiles of MF_TILE gates, one workgroup per tile and output polynomial, one launch per
+// step), and 33 for its split form (the products of a step cut into workgroups per tile,
+// output polynomial, sub-product and group of TRGSW rows, for batches too small to fill the
+// chip; two launches per step).
+constexpr int kBrShapes = 5;
+constexpr int kBrWaveChoices[kBrShapes] = {4, 8, 3, 32, 33};
 constexpr int MF_TILE = 32;
+inline bool br_matrix_form(int waves) { return waves == 32 || waves == 33; }
+// Row groups of the split form for B gates on a chip of `cus` compute units: the fewest that
+// give about three workgroups of four waves per compute unit.
+inline int mf_split_groups(uint64_t B, int cus) {
+  const uint64_t units = (B + MF_TILE - 1) / MF_TILE * 2 * 3;  // tiles x outputs x sub-products
+  for (int g : {1, 2, 3})
+    if (units * (uint64_t)g >= 3ull * (uint64_t)(cus > 0 ? cus : 256)) return g;
+  return 6;
+}
 
 // Batch-size buckets: bucket b holds batches with kBucket[b-1] < B <= kBucket[b]; the last
 // one also holds every larger batch.
@@ -47,15 +59,23 @@ constexpr uint64_t kBucket[kTuneBuckets] = {1, 16, 64, 256, 1024, 2048, 4096};
 //  * Blind rotation: a gate is one wave from start to end, so a batch of B gates takes
 //    ceil(B / br_cap[s]) rounds of br_round_ms[s] with shape s, where br_cap[s] is the number
 //    of gates the whole GPU holds at once (occupancy x compute units x gates per group) and
-//    br_round_ms[s] the time of one full round. The shape with the fewer milliseconds wins
-//    (ties: the 8-gate workgroup). br_force[b] != 0 pins the shape for bucket b.
+//    br_round_ms[s] the time of one full round. The split matrix-core form is timed instead
+//    at every bucket size (split_ms[b], with the fastest row-group count split_groups[b]) and
+//    estimated in between by linear interpolation (beyond the last bucket: in proportion).
+//    The shape with the fewer milliseconds wins (ties: the 8-gate workgroup). br_force[b] != 0
+//    pins the shape for bucket b.
 //  * Key switch: per bucket, form 0 gathers key rows per gate, 1 reads them once per tile of
 //    gates and selects in registers, 2 stages them through LDS for a tile of gates and splits
 //    the j range over workgroups, 3 runs on the matrix cores (one-hot digit rows times the
 //    key's byte planes).
 struct Tuning {
-  uint64_t br_cap[kBrShapes] = {1024, 2048, 512, 4096};
-  float br_round_ms[kBrShapes] = {1.0f, 1.48f, 0.8f, 2.66f};
+  uint64_t br_cap[kBrShapes] = {1024, 2048, 512, 4096, MF_TILE};
+  float br_round_ms[kBrShapes] = {1.0f, 1.48f, 0.75f, 2.31f, 0.34f};
+  // split form, per bucket: time in the same units as br_round_ms, and row groups (0: the
+  // count that fills the chip, mf_split_groups). The defaults are relative times measured on
+  // an MI355X (one 4-gate-workgroup round = 1).
+  float split_ms[kTuneBuckets] = {0.23f, 0.31f, 0.36f, 0.51f, 0.91f, 1.53f, 2.51f};
+  int split_groups[kTuneBuckets] = {6, 6, 6, 3, 2, 1, 1};
   int br_force[kTuneBuckets] = {0, 0, 0, 0, 0, 0, 0};
   int ks_form[kTuneBuckets] = {2, 2, 2, 2, 3, 3, 3};
   bool tuned = false;
@@ -69,9 +89,10 @@ struct Tuning {
     if (f) return f;
     int best = 1;
     double best_ms = 0;
-    for (int s : {1, 0, 2, 3}) {
+    for (int s : {1, 0, 2, 3, 4}) {
       const uint64_t cap = br_cap[s] ? br_cap[s] : 1;
-      const double ms = (double)((B + cap - 1) / cap) * br_round_ms[s];
+      double ms = (double)((B + cap - 1) / cap) * br_round_ms[s];
+      if (s == 4) ms = split_estimate(B);
       if (s == 1 || ms < best_ms) {
         best = s;
         best_ms = ms;
@@ -80,6 +101,17 @@ struct Tuning {
     return kBrWaveChoices[best];
   }
   int ks_form_for(uint64_t B) const { return ks_form[bucket(B)]; }
+  double split_estimate(uint64_t B) const {
+    const int b = bucket(B);
+    if (B >= kBucket[kTuneBuckets - 1]) return (double)split_ms[kTuneBuckets - 1] * (double)B / kBucket[b];
+    if (b == 0) return split_ms[0];
+    const double f = (double)(B - kBucket[b - 1]) / (double)(kBucket[b] - kBucket[b - 1]);
+    return split_ms[b - 1] + f * (split_ms[b] - split_ms[b - 1]);
+  }
+  int split_groups_for(uint64_t B, int cus) const {
+    const int g = split_groups[bucket(B)];
+    return g ? g : mf_split_groups(B, cus);
+  }
 };
 
 // Growable device scratch owned by a context.
@@ -187,9 +219,9 @@ hipError_t launch_mux_combine(uint32_t* t, uint64_t B, hipStream_t st);
 // Blind rotation of B gates (abar from the prologue). Writes SE_0 (TLWE1 [B][N+1]) and/or
 // the accumulator (TRLWE [B][2][N]). waves: a shape of kBrWaveChoices, <= 0 the tuned choice.
 // bkn: the bootstrapping key to use (NULL: the context's); with keytab non-NULL gate g uses
-// keytab[kid[g]] instead (device arrays). The matrix-core form (waves 32) needs the context's
-// own key and a workspace of mf_work_bytes(B, trlwe == NULL) bytes in mf_work; without them
-// the 8-gate form runs instead.
+// keytab[kid[g]] instead (device arrays). The matrix-core forms (waves 32 and 33) need the
+// context's own key and a workspace of mf_work_bytes(B, trlwe == NULL) bytes in mf_work;
+// without them the 8-gate form runs instead.
 hipError_t launch_blind_rotate(const vsp_context* ctx, const uint8_t* ops, const uint32_t* abar, uint32_t* tlwe1,
                                uint32_t* trlwe, uint64_t B, int waves, hipStream_t st, const uint64_t* bkn = nullptr,
                                const uint64_t* const* keytab = nullptr, const uint8_t* kid = nullptr,
@@ -205,6 +237,11 @@ size_t ks_mf_key_bytes();
 hipError_t launch_ks_mfkey(const uint32_t* ksk, int8_t* KB, hipStream_t st);
 hipError_t launch_keyswitch_mfma(const int8_t* KB, const uint8_t* ops, const uint32_t* tlwe1, const uint32_t* idxo,
                                  uint32_t* out, uint64_t B, hipStream_t st);
+// Split form (waves 33): two launches per step, `groups` (1, 2, 3 or 6) row groups per
+// (tile, output, sub-product); same workspace as the fused form.
+hipError_t launch_blind_rotate_mfsplit(const vsp_context* ctx, const uint8_t* ops, const uint32_t* abar,
+                                       uint32_t* tlwe1, uint32_t* trlwe, uint64_t B, void* work, int groups,
+                                       hipStream_t st, bool instrument = false);
 // With instrument set (eager calls from the caller's thread only), one event pair of class 3
 // brackets the step launches.
 hipError_t launch_blind_rotate_mfma(const vsp_context* ctx, const uint8_t* ops, const uint32_t* abar, uint32_t* tlwe1,

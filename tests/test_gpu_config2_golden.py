@@ -20,8 +20,8 @@ GOLDEN = os.path.join(HERE, "golden", "config2_oracle_digest.json")
 B = 4096
 
 # (blind-rotation shape, key-switch form): the matrix-core form, the 8-, 4- and 3-wave NTT
-# forms; key-switch forms 3 (matrix cores), 2 (LDS-staged split), 1 (row tiles), 0 (gather).
-FORMS = [(32, 3), (32, 2), (8, 3), (8, 2), (4, 1), (3, 0)]
+# forms, the split matrix-core form; key-switch forms 3 (matrix cores), 2 (LDS-staged split), 1 (row tiles), 0 (gather).
+FORMS = [(32, 3), (32, 2), (8, 3), (8, 2), (4, 1), (3, 0), (33, 3)]
 
 
 def row_digest(row) -> str:
@@ -56,3 +56,22 @@ def test_every_gate_matches_oracle(gpu, batch, waves, ks):
     bad = [k for k in range(B) if row_digest(out[k]) != want[k]]
     assert not bad, f"{len(bad)} of {B} gates differ from the oracle (shape {waves}, key switch {ks}); first {bad[:8]}"
     assert hashlib.sha256(out.astype("<u4").tobytes()).hexdigest() == doc["outputs_sha256"]
+
+
+@pytest.mark.parametrize("nb", [1, 16, 64, 1000, 2048])
+def test_split_matrix_form_prefixes_match_oracle(gpu, batch, nb):
+    """The split matrix-core form on the first nb gates (one tile, partial tiles, a ragged
+    1000-gate batch, a 2048-gate batch with fewer row groups) against the oracle's digests."""
+    cfg, in0, in1, doc = batch
+    d0, d1, dops = gpu.tensor(in0[:nb]), gpu.tensor(in1[:nb]), gpu.tensor(cfg["ops"][:nb])
+    saved = gpu.tuning(nb)
+    try:
+        gpu.set_tuning(nb, 33, 2)
+        assert gpu.tuning(nb) == (33, 2)
+        out = to_host(gpu.gates(dops, d0, d1))
+        gpu.sync()
+    finally:
+        gpu.set_tuning(nb, 0, saved[1])
+    want = doc["gate_sha256_prefix"]
+    bad = [k for k in range(nb) if row_digest(out[k]) != want[k]]
+    assert not bad, f"{len(bad)} of {nb} gates differ from the oracle; first {bad[:8]}"

@@ -12,7 +12,8 @@ from paper_2010_09410_amd import VspError, client
 from paper_2010_09410_amd.device import to_host
 
 pytestmark = pytest.mark.gpu
-SHAPES = [(4, 0), (4, 1), (4, 2), (8, 0), (8, 1), (8, 2), (3, 0), (3, 2), (32, 2), (32, 0), (8, 3), (32, 3)]
+SHAPES = [(4, 0), (4, 1), (4, 2), (8, 0), (8, 1), (8, 2), (3, 0), (3, 2), (32, 2), (32, 0), (8, 3), (32, 3),
+          (33, 2), (33, 3), (33, 0)]
 
 
 def batch(keys, B, seed):
@@ -27,7 +28,8 @@ def batch(keys, B, seed):
 @pytest.mark.parametrize("B,sample", [(37, None), (300, 12)])
 def test_every_launch_shape_bit_identical(gpu, keys, B, sample):
     """B=37 and B=300 are ragged for 4- and 8-gate workgroups, 16-gate key-switch tiles and
-    32-gate matrix-core tiles; shape 3 runs each gate on three waves, 32 on the matrix cores."""
+    32-gate matrix-core tiles; shape 3 runs each gate on three waves, 32 on the matrix cores, 33
+    on the matrix cores split by sub-product and row group."""
     _, saved_t = gpu.tuning(B)
     cfg, in0, in1 = batch(keys, B, 31 + B)
     d0, d1, dops = gpu.tensor(in0), gpu.tensor(in1), gpu.tensor(cfg["ops"])
@@ -58,6 +60,28 @@ def test_tuning_set_rejects_unknown_shapes(gpu):
 BUCKETS = (1, 16, 64, 256, 1024, 2048, 4096)
 
 
+def model_choice(entry, B):
+    """The launch rule: fewest rounds x round time for the one-wave-per-gate forms and the
+    matrix-core form, the interpolated per-bucket time for the split matrix-core form (ties:
+    the 8-gate workgroup, then the order 4, 3, 32, 33)."""
+    caps, ms, sms = entry["br_cap"], entry["br_round_ms"], entry["split_ms"]
+    def split(B):
+        b = next((i for i, k in enumerate(BUCKETS) if B <= k), len(BUCKETS) - 1)
+        if B >= BUCKETS[-1]:
+            return sms[-1] * B / BUCKETS[b]
+        if b == 0:
+            return sms[0]
+        f = (B - BUCKETS[b - 1]) / (BUCKETS[b] - BUCKETS[b - 1])
+        return sms[b - 1] + f * (sms[b] - sms[b - 1])
+    est = {s: -(-B // caps[s]) * ms[s] for s in range(4)}
+    est[4] = split(B)
+    best = 1
+    for s in (0, 2, 3, 4):
+        if est[s] < est[best]:
+            best = s
+    return [4, 8, 3, 32, 33][best]
+
+
 def test_autotune_model_and_cache_round_trip(gpu, tmp_path):
     saved = {b: gpu.tuning(b)[1] for b in BUCKETS}
     path = tmp_path / "tune.json"
@@ -65,21 +89,33 @@ def test_autotune_model_and_cache_round_trip(gpu, tmp_path):
         gpu.autotune(max_batch=64, cache_path=str(path))
         (key, entry), = json.loads(path.read_text()).items()
         assert key.startswith("gfx950")
-        assert entry["br_waves"] == [4, 8, 3, 32] and list(entry["buckets"]) == list(BUCKETS)
-        cap4, cap8, capw, capm = entry["br_cap"]
-        assert 256 <= cap4 < cap8 and capw >= 256 and capm >= cap8 and all(ms > 0 for ms in entry["br_round_ms"])
+        assert entry["br_waves"] == [4, 8, 3, 32, 33] and list(entry["buckets"]) == list(BUCKETS)
+        cap4, cap8, capw, capm, caps = entry["br_cap"]
+        assert 256 <= cap4 < cap8 and capw >= 256 and capm >= cap8 and caps == 32
+        assert all(ms > 0 for ms in entry["br_round_ms"]) and all(ms > 0 for ms in entry["split_ms"])
+        assert all(g in (1, 2, 3, 6) for g in entry["split_groups"])
         assert all(t in (0, 1, 2, 3) for t in entry["ks_form"])
         for b, t in zip(BUCKETS, entry["ks_form"]):
             assert gpu.tuning(b)[1] == t
-        # the launch follows rounds x round time; a cache entry for this GPU is read back
-        for ms, small, large in (([1.0, 100.0, 100.0, 100.0], 4, 4), ([100.0, 1.0, 100.0, 100.0], 8, 8),
-                                 ([1.0, 1.5, 100.0, 100.0], 4, 8), ([100.0, 100.0, 1.0, 100.0], 3, 3),
-                                 ([100.0, 100.0, 100.0, 1.0], 32, 32)):
+        # the measured entry, read back from the file, picks what the rule says at every size
+        gpu.autotune(max_batch=64, cache_path=str(path))
+        for B in (1, 16, 40, 64, 200, 256, 700, 1024, 1500, 2048, 3000, 4096, 5000):
+            assert gpu.tuning(B)[0] == model_choice(entry, B), B
+        # edited entries for this GPU are read back and followed
+        big = [100.0] * 7
+        for ms, sms, small, large in (([1.0, 100.0, 100.0, 100.0, 100.0], big, 4, 4),
+                                      ([100.0, 1.0, 100.0, 100.0, 100.0], big, 8, 8),
+                                      ([1.0, 1.5, 100.0, 100.0, 100.0], big, 4, 8),
+                                      ([100.0, 100.0, 1.0, 100.0, 100.0], big, 3, 3),
+                                      ([100.0, 100.0, 100.0, 1.0, 100.0], big, 32, 32),
+                                      ([100.0, 100.0, 100.0, 100.0, 100.0], [0.001] * 7, 33, 33),
+                                      ([100.0, 1.0, 100.0, 100.0, 100.0], [0.5] * 5 + [1000.0, 1000.0], None, None)):
             entry["br_round_ms"] = ms
+            entry["split_ms"] = sms
             path.write_text(json.dumps({key: entry}))
             gpu.autotune(max_batch=64, cache_path=str(path))
-            assert gpu.tuning(cap4)[0] == small
-            assert gpu.tuning(cap4 + 1)[0] == large
+            for B, want in ((cap4, small), (cap4 + 1, large)):
+                assert gpu.tuning(B)[0] == (want if want is not None else model_choice(entry, B)), (ms, sms, B)
     finally:
         for b, t in saved.items():
             gpu.set_tuning(b, 0, t)
