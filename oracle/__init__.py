@@ -43,6 +43,19 @@ class Params(ctypes.Structure):
 
 DEFAULT = Params(630, 1024, 3, 6, 8, 2)
 
+
+class Params2(ctypes.Structure):
+    """Level-2 parameters of circuit bootstrapping: ring degree, gadget rows and base bits on
+    the 2^64 torus, private key-switch digits and base bits."""
+    _fields_ = [("N", ctypes.c_int32), ("l", ctypes.c_int32), ("bgbit", ctypes.c_int32),
+                ("t", ctypes.c_int32), ("basebit", ctypes.c_int32)]
+
+    def __repr__(self):
+        return f"Params2(N={self.N}, l={self.l}, bgbit={self.bgbit}, t={self.t}, basebit={self.basebit})"
+
+
+DEFAULT2 = Params2(2048, 4, 9, 12, 2)
+
 _lib = None
 
 
@@ -61,6 +74,8 @@ _i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
 _u8p = np.ctypeslib.ndpointer(dtype=np.uint8, flags="C_CONTIGUOUS")
 _i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
 _P = ctypes.POINTER(Params)
+_Q = ctypes.POINTER(Params2)
+_u64p = np.ctypeslib.ndpointer(dtype=np.uint64, flags="C_CONTIGUOUS")
 _c = ctypes
 
 
@@ -103,6 +118,20 @@ def _declare(L):
         "or_rom_reads": (None, [_P, _u32p, _u32p, _c.c_int, _u32p, _c.c_int, _c.c_int, _u32p,
                                 _c.c_int64, _c.c_int]),
         "or_ram_reads": (None, [_P, _u32p, _u32p, _c.c_int, _c.c_int, _u32p, _u32p, _c.c_int64, _c.c_int]),
+        "or_polymul64": (None, [_c.c_int, _u64p, _u64p, _u64p]),
+        "or_rotate64": (None, [_c.c_int, _u64p, _c.c_uint32, _u64p]),
+        "or_trlwe64_encrypt_torus": (None, [_c.c_int, _u64p, _u64p, _i64p, _u64p, _u64p]),
+        "or_trlwe64_phase": (None, [_c.c_int, _u64p, _u64p, _u64p]),
+        "or_trgsw64_encrypt": (None, [_Q, _u64p, _u64p, _i64p, _c.c_int, _u64p]),
+        "or_bk2_gen": (None, [_c.c_int, _Q, _u32p, _u64p, _u64p, _i64p, _u64p, _c.c_int]),
+        "or_decompose64": (None, [_Q, _c.c_uint64, _i64p]),
+        "or_external_product64": (None, [_Q, _u64p, _u64p, _u64p]),
+        "or_blind_rotate64": (None, [_c.c_int, _Q, _u64p, _u32p, _u64p, _u64p]),
+        "or_sample_extract64": (None, [_c.c_int, _u64p, _u64p]),
+        "or_pksk_gen": (None, [_P, _Q, _u32p, _u64p, _u32p, _i32p, _u32p, _c.c_int]),
+        "or_private_keyswitch": (None, [_P, _Q, _u32p, _c.c_int, _u64p, _u32p]),
+        "or_circuit_bootstrap": (None, [_P, _Q, _u64p, _u32p, _u32p, _u32p]),
+        "or_circuit_bootstraps": (None, [_P, _Q, _u64p, _u32p, _u32p, _u32p, _c.c_int64, _c.c_int]),
         "or_cmux_count": (_c.c_uint64, []),
         "or_br_count": (_c.c_uint64, []),
         "or_reset_counters": (None, []),
@@ -403,3 +432,124 @@ def keyset(s0, s1, bkd, kskd, P=DEFAULT, threads=None):
     bk = bk_gen(s0, s1, bkd[0], bkd[1], P, threads)
     ksk = ksk_gen(s0, s1, kskd[0], kskd[1], P)
     return bk, ksk
+
+
+# ----------------------------------------------------------------- circuit bootstrapping
+def _u64(x):
+    return np.ascontiguousarray(x, dtype=np.uint64)
+
+
+def _i64(x):
+    return np.ascontiguousarray(x, dtype=np.int64)
+
+
+def polymul64(a, b):
+    """Negacyclic product mod 2^64 (schoolbook)."""
+    a, b = _u64(a), _u64(b)
+    out = np.zeros_like(a)
+    lib().or_polymul64(a.size, a, b, out)
+    return out
+
+
+def rotate64(p, k):
+    p = _u64(p)
+    out = np.zeros_like(p)
+    lib().or_rotate64(p.size, p, int(k) % (2 * p.size), out)
+    return out
+
+
+def trlwe64_encrypt_torus(s2, m, a, e):
+    a = _u64(a)
+    out = np.zeros(2 * a.size, dtype=np.uint64)
+    lib().or_trlwe64_encrypt_torus(a.size, _u64(s2), a, _i64(e), _u64(m), out)
+    return out.reshape(2, -1)
+
+
+def trlwe64_phase(s2, c):
+    c = _u64(c).reshape(-1)
+    out = np.zeros(c.size // 2, dtype=np.uint64)
+    lib().or_trlwe64_phase(c.size // 2, _u64(s2), c, out)
+    return out
+
+
+def trgsw64_encrypt(s2, m, masks, noise, Q=DEFAULT2):
+    out = np.zeros((2 * Q.l, 2, Q.N), dtype=np.uint64)
+    lib().or_trgsw64_encrypt(ctypes.byref(Q), _u64(s2), _u64(masks).reshape(-1), _i64(noise).reshape(-1), int(m),
+                             out.reshape(-1))
+    return out
+
+
+def bk2_gen(s0, s2, masks, noise, Q=DEFAULT2, threads=None):
+    """Level-2 bootstrapping key [n][2 l2][2][N2]: BK2[i] = TRGSW2_{s2}(s0[i])."""
+    n = len(s0)
+    out = np.zeros((n, 2 * Q.l, 2, Q.N), dtype=np.uint64)
+    lib().or_bk2_gen(n, ctypes.byref(Q), _u32(s0), _u64(s2), _u64(masks).reshape(-1), _i64(noise).reshape(-1),
+                     out.reshape(-1), threads or default_threads())
+    return out
+
+
+def decompose64(x, Q=DEFAULT2):
+    d = np.zeros(16, dtype=np.int64)
+    lib().or_decompose64(ctypes.byref(Q), int(x) & 0xFFFFFFFFFFFFFFFF, d)
+    return d[:Q.l].copy()
+
+
+def external_product64(C, x, Q=DEFAULT2):
+    out = np.zeros((2, Q.N), dtype=np.uint64)
+    lib().or_external_product64(ctypes.byref(Q), _u64(C).reshape(-1), _u64(x).reshape(-1), out.reshape(-1))
+    return out
+
+
+def blind_rotate64(bk2, c, tv, Q=DEFAULT2):
+    c = _u32(c)
+    out = np.zeros((2, Q.N), dtype=np.uint64)
+    lib().or_blind_rotate64(c.size - 1, ctypes.byref(Q), _u64(bk2).reshape(-1), c, _u64(tv), out.reshape(-1))
+    return out
+
+
+def sample_extract64(c):
+    c = _u64(c).reshape(-1)
+    N = c.size // 2
+    out = np.zeros(N + 1, dtype=np.uint64)
+    lib().or_sample_extract64(N, c, out)
+    return out
+
+
+def pksk_gen(s1, s2, masks, noise, P=DEFAULT, Q=DEFAULT2, threads=None):
+    """Private functional key-switching keys [2][N2+1][t2][base2-1][2][N]: function 0 is
+    x -> -s1 x, function 1 is x -> x."""
+    base = 1 << Q.basebit
+    out = np.zeros((2, Q.N + 1, Q.t, base - 1, 2, P.N), dtype=np.uint32)
+    lib().or_pksk_gen(ctypes.byref(P), ctypes.byref(Q), _u32(s1), _u64(s2), _u32(masks).reshape(-1),
+                      _i32(noise).reshape(-1), out.reshape(-1), threads or default_threads())
+    return out
+
+
+def private_keyswitch(pksk, u, c, P=DEFAULT, Q=DEFAULT2):
+    out = np.zeros((2, P.N), dtype=np.uint32)
+    lib().or_private_keyswitch(ctypes.byref(P), ctypes.byref(Q), _u32(pksk).reshape(-1), int(u), _u64(c),
+                               out.reshape(-1))
+    return out
+
+
+def circuit_bootstrap(bk2, pksk, c, P=DEFAULT, Q=DEFAULT2):
+    """Level-0 TLWE of a bit -> level-1 TRGSW [2l][2][N] of that bit."""
+    out = np.zeros((2 * P.l, 2, P.N), dtype=np.uint32)
+    lib().or_circuit_bootstrap(ctypes.byref(P), ctypes.byref(Q), _u64(bk2).reshape(-1), _u32(pksk).reshape(-1),
+                               _u32(c), out.reshape(-1))
+    return out
+
+
+def circuit_bootstraps(bk2, pksk, cs, P=DEFAULT, Q=DEFAULT2, threads=None):
+    cs = _u32(cs)
+    R = cs.shape[0]
+    out = np.zeros((R, 2 * P.l, 2, P.N), dtype=np.uint32)
+    lib().or_circuit_bootstraps(ctypes.byref(P), ctypes.byref(Q), _u64(bk2).reshape(-1), _u32(pksk).reshape(-1),
+                                cs.reshape(-1), out.reshape(-1), R, threads or default_threads())
+    return out
+
+
+def keyset2(s0, s1, s2, bk2d, pkskd, P=DEFAULT, Q=DEFAULT2, threads=None):
+    """Circuit-bootstrapping keys from the given draws: (level-2 bootstrapping key, private
+    key-switching keys)."""
+    return bk2_gen(s0, s2, bk2d[0], bk2d[1], Q, threads), pksk_gen(s1, s2, pkskd[0], pkskd[1], P, Q, threads)

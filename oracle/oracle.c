@@ -639,3 +639,260 @@ void or_ram_reads(const or_params *P, const uint32_t *ksk, const uint32_t *ram, 
   reads_ctx c = {P, ksk, ram, sel, out, v, w, 0};
   parallel_for(R, threads, ram_one, &c);
 }
+
+/* ================================================================== circuit bootstrapping
+ *
+ * TLWE (level 0, a bit as +-1/8) -> TRGSW (level 1, gadget l x Bg), the conversion the paper
+ * names "Circuit Bootstrapping" (Sec. 2.1.2, after Chillotti et al.) and applies to the
+ * address bits of the CMUX memory (Sec. 8.2). The paper fixes no parameters for it; the
+ * reading used here: a level-2 ring of degree N2 over the 2^64 torus (uint64), a level-2
+ * bootstrapping key BK2[i] = TRGSW2_{s2}(s0[i]) with gadget l2 x 2^bgbit2, and private
+ * functional key switching from level 2 to level-1 TRLWE with t2 digits of basebit2 bits.
+ * For each gadget level j = 1..l of the output: a level-2 blind rotation of c with the
+ * test vector 1/(2 Bg^j) in every coefficient, SampleExtract at 0, plus 1/(2 Bg^j) (so the
+ * TLWE2 holds m/Bg^j), then two private key switches: f(x) = -s1 x gives TRGSW row j-1 (the
+ * rows whose a part carries m/Bg^j, phase -m s1/Bg^j) and f(x) = x gives row l+j-1 (phase
+ * m/Bg^j), the row layout of or_trgsw_encrypt. */
+
+typedef struct {
+  int32_t N;       /* level-2 TRLWE degree */
+  int32_t l;       /* level-2 gadget rows per column */
+  int32_t bgbit;   /* log2 of the level-2 gadget base */
+  int32_t t;       /* private key-switch digits */
+  int32_t basebit; /* log2 of the private key-switch base */
+} or_params2;
+
+/* out += a * b in Z[X]/(X^N+1) mod 2^64 (schoolbook). */
+static void polymul64_acc(int N, const uint64_t *a, const uint64_t *b, uint64_t *out) {
+  for (int i = 0; i < N; i++) {
+    const uint64_t ai = a[i];
+    if (ai == 0) continue;
+    uint64_t *o = out + i;
+    for (int j = 0; j < N - i; j++) o[j] += ai * b[j];
+    uint64_t *w = out + i - N;
+    for (int j = N - i; j < N; j++) w[j] -= ai * b[j];
+  }
+}
+
+void or_polymul64(int N, const uint64_t *a, const uint64_t *b, uint64_t *out) {
+  memset(out, 0, sizeof(uint64_t) * N);
+  polymul64_acc(N, a, b, out);
+}
+
+/* out = X^k p, k in [0, 2N), over the 2^64 torus. */
+void or_rotate64(int N, const uint64_t *p, uint32_t k, uint64_t *out) {
+  k %= (uint32_t)(2 * N);
+  for (int j = 0; j < N; j++) {
+    int64_t src = (int64_t)j - (int64_t)k;
+    int neg = 0;
+    while (src < 0) { src += N; neg ^= 1; }
+    out[j] = neg ? (uint64_t)(0ull - p[src]) : p[src];
+  }
+}
+
+/* Level-2 TRLWE: (a, a s + m + e) over the 2^64 torus. */
+void or_trlwe64_encrypt_torus(int N, const uint64_t *s, const uint64_t *a, const int64_t *e,
+                              const uint64_t *m, uint64_t *c) {
+  memcpy(c, a, sizeof(uint64_t) * N);
+  or_polymul64(N, a, s, c + N);
+  for (int j = 0; j < N; j++) c[N + j] += m[j] + (uint64_t)e[j];
+}
+
+void or_trlwe64_phase(int N, const uint64_t *s, const uint64_t *c, uint64_t *ph) {
+  or_polymul64(N, c, s, ph);
+  for (int j = 0; j < N; j++) ph[j] = c[N + j] - ph[j];
+}
+
+static uint64_t gadget2(const or_params2 *Q, int j) { return 1ull << (64 - Q->bgbit * j); }
+
+/* Level-2 TRGSW of a bit (rows as in or_trgsw_encrypt). masks/noise [2 l2][N2]. */
+void or_trgsw64_encrypt(const or_params2 *Q, const uint64_t *s, const uint64_t *masks,
+                        const int64_t *noise, int m, uint64_t *C) {
+  const int N = Q->N, l = Q->l;
+  uint64_t *zero = xmalloc(sizeof(uint64_t) * N);
+  for (int r = 0; r < 2 * l; r++) {
+    uint64_t *row = C + (size_t)r * 2 * N;
+    or_trlwe64_encrypt_torus(N, s, masks + (size_t)r * N, noise + (size_t)r * N, zero, row);
+    if (m) {
+      if (r < l) row[0] += gadget2(Q, r + 1);
+      else row[N] += gadget2(Q, r - l + 1);
+    }
+  }
+  free(zero);
+}
+
+typedef struct { const or_params2 *Q; const uint32_t *s0; const uint64_t *s2, *masks; const int64_t *noise; uint64_t *out; } bk2_ctx;
+
+static void bk2_one(void *p, int64_t i) {
+  bk2_ctx *c = p;
+  const size_t rowsz = (size_t)2 * c->Q->l * c->Q->N;
+  or_trgsw64_encrypt(c->Q, c->s2, c->masks + i * rowsz, c->noise + i * rowsz, (int)c->s0[i],
+                     c->out + (size_t)i * rowsz * 2);
+}
+
+/* Level-2 bootstrapping key: BK2[i] = TRGSW2_{s2}(s0[i]), i < n. masks/noise [n][2 l2][N2];
+ * bk2 [n][2 l2][2][N2]. */
+void or_bk2_gen(int n, const or_params2 *Q, const uint32_t *s0, const uint64_t *s2, const uint64_t *masks,
+                const int64_t *noise, uint64_t *bk2, int threads) {
+  bk2_ctx c = {Q, s0, s2, masks, noise, bk2};
+  parallel_for(n, threads, bk2_one, &c);
+}
+
+/* Signed gadget decomposition on the 2^64 torus: x ~ sum_{r=1..l2} d_r / Bg2^r, d_r in
+ * [-Bg2/2, Bg2/2), rounding to the nearest multiple of 1/Bg2^l2. */
+void or_decompose64(const or_params2 *Q, uint64_t x, int64_t *d) {
+  const int l = Q->l, bgbit = Q->bgbit;
+  const uint64_t half = 1ull << (bgbit - 1), mask = (1ull << bgbit) - 1;
+  uint64_t offset = 0;
+  for (int r = 1; r <= l; r++) offset += half << (64 - r * bgbit);
+  offset += 1ull << (64 - l * bgbit - 1);
+  const uint64_t t = x + offset;
+  for (int r = 1; r <= l; r++) d[r - 1] = (int64_t)((t >> (64 - r * bgbit)) & mask) - (int64_t)half;
+}
+
+/* Level-2 external product (as or_external_product, mod 2^64). */
+void or_external_product64(const or_params2 *Q, const uint64_t *C, const uint64_t *in, uint64_t *out) {
+  const int N = Q->N, l = Q->l;
+  uint64_t *dig = xmalloc(sizeof(uint64_t) * 2 * l * N);
+  int64_t d[16];
+  for (int half = 0; half < 2; half++)
+    for (int j = 0; j < N; j++) {
+      or_decompose64(Q, in[half * N + j], d);
+      for (int r = 0; r < l; r++) dig[(size_t)(half * l + r) * N + j] = (uint64_t)d[r];
+    }
+  memset(out, 0, sizeof(uint64_t) * 2 * N);
+  for (int q = 0; q < 2 * l; q++) {
+    const uint64_t *row = C + (size_t)q * 2 * N;
+    polymul64_acc(N, dig + (size_t)q * N, row, out);
+    polymul64_acc(N, dig + (size_t)q * N, row + N, out + N);
+  }
+  free(dig);
+}
+
+/* Level-2 blind rotation of a level-0 TLWE c (n+1, 2^32 torus): modulus switch to Z/2N2,
+ * ACC = (0, X^{-bbar} tv), ACC <- ACC + BK2[i] (ext) (X^{abar_i} ACC - ACC) for i < n. */
+void or_blind_rotate64(int n, const or_params2 *Q, const uint64_t *bk2, const uint32_t *c, const uint64_t *tv,
+                       uint64_t *acc) {
+  const int N = Q->N;
+  const size_t trgsw = (size_t)2 * Q->l * 2 * N;
+  uint64_t *diff = xmalloc(sizeof(uint64_t) * 2 * N);
+  uint64_t *prod = xmalloc(sizeof(uint64_t) * 2 * N);
+  const uint32_t bbar = or_modswitch(c[n], N);
+  memset(acc, 0, sizeof(uint64_t) * N);
+  or_rotate64(N, tv, (uint32_t)(2 * N) - bbar, acc + N);
+  for (int i = 0; i < n; i++) {
+    const uint32_t abar = or_modswitch(c[i], N);
+    or_rotate64(N, acc, abar, diff);
+    or_rotate64(N, acc + N, abar, diff + N);
+    for (int j = 0; j < 2 * N; j++) diff[j] -= acc[j];
+    or_external_product64(Q, bk2 + i * trgsw, diff, prod);
+    for (int j = 0; j < 2 * N; j++) acc[j] += prod[j];
+  }
+  free(diff); free(prod);
+  __atomic_fetch_add(&g_br_count, 1, __ATOMIC_RELAXED);
+}
+
+/* SampleExtract at 0 over the 2^64 torus: TLWE2 (N2 + 1). */
+void or_sample_extract64(int N, const uint64_t *c, uint64_t *out) {
+  out[0] = c[0];
+  for (int j = 1; j < N; j++) out[j] = 0ull - c[N - j];
+  out[N] = c[N];
+}
+
+/* Private functional key-switching keys from the level-2 TLWE key to level-1 TRLWE under
+ * s1, for f_0(x) = -s1 x and f_1(x) = x: with z = (-s2[0], ..., -s2[N2-1], 1) (so that
+ * sum_k c_k z_k is the phase of a TLWE2 c = (a, b)),
+ *   PKSK[u][k][p][v-1] = TRLWE_{s1}(f_u(v z_k / base^(p+1))),  k <= N2, p < t2, v = 1..base-1,
+ * messages on the 2^32 torus. masks [2][N2+1][t2][base-1][N], noise the same shape (int32);
+ * pksk [2][N2+1][t2][base-1][2][N]. */
+typedef struct { const or_params *P; const or_params2 *Q; const uint32_t *s1; const uint64_t *s2;
+                 const uint32_t *masks; const int32_t *noise; uint32_t *out; } pksk_ctx;
+
+static void pksk_one(void *p, int64_t idx) {
+  pksk_ctx *c = p;
+  const int N = c->P->N, N2 = c->Q->N, t = c->Q->t, bb = c->Q->basebit, base = 1 << bb;
+  /* idx = ((u (N2+1) + k) t + pp) (base-1) + (v-1) */
+  int64_t r = idx;
+  const int v = (int)(r % (base - 1)) + 1; r /= (base - 1);
+  const int pp = (int)(r % t); r /= t;
+  const int k = (int)(r % (N2 + 1)); r /= (N2 + 1);
+  const int u = (int)r;
+  const uint32_t z = (k == N2) ? 1u : (uint32_t)(0u - (uint32_t)c->s2[k]);
+  const uint32_t x = (uint32_t)v * z * (1u << (32 - (pp + 1) * bb));   /* v z_k / base^(p+1) */
+  uint32_t *m = xmalloc(sizeof(uint32_t) * N);
+  if (u == 0) for (int j = 0; j < N; j++) m[j] = 0u - c->s1[j] * x;   /* -s1 x */
+  else m[0] = x;                                                      /* x      */
+  or_trlwe_encrypt_torus(N, c->s1, c->masks + (size_t)idx * N, c->noise + (size_t)idx * N, m,
+                         c->out + (size_t)idx * 2 * N);
+  free(m);
+}
+
+void or_pksk_gen(const or_params *P, const or_params2 *Q, const uint32_t *s1, const uint64_t *s2,
+                 const uint32_t *masks, const int32_t *noise, uint32_t *pksk, int threads) {
+  pksk_ctx c = {P, Q, s1, s2, masks, noise, pksk};
+  const int64_t count = (int64_t)2 * (Q->N + 1) * Q->t * ((1 << Q->basebit) - 1);
+  parallel_for(count, threads, pksk_one, &c);
+}
+
+/* Private functional key switch of a TLWE2 c (N2 + 1, 2^64 torus) with key u:
+ * out = sum_{k <= N2} sum_{p < t2} PKSK[u][k][p][v_{k,p}], v_{k,p} the p-th base-2^basebit2
+ * digit (most significant first) of c_k rounded to t2 basebit2 bits. out [2][N]. */
+void or_private_keyswitch(const or_params *P, const or_params2 *Q, const uint32_t *pksk, int u,
+                          const uint64_t *c, uint32_t *out) {
+  const int N = P->N, N2 = Q->N, t = Q->t, bb = Q->basebit, base = 1 << bb;
+  const uint64_t round = 1ull << (64 - t * bb - 1);
+  const uint32_t *key = pksk + (size_t)u * (N2 + 1) * t * (base - 1) * 2 * N;
+  memset(out, 0, sizeof(uint32_t) * 2 * N);
+  for (int k = 0; k <= N2; k++) {
+    const uint64_t chat = c[k] + round;
+    for (int p = 0; p < t; p++) {
+      const uint32_t v = (uint32_t)(chat >> (64 - (p + 1) * bb)) & (uint32_t)(base - 1);
+      if (v == 0) continue;
+      const uint32_t *e = key + (((size_t)k * t + p) * (base - 1) + (v - 1)) * 2 * N;
+      for (int j = 0; j < 2 * N; j++) out[j] += e[j];
+    }
+  }
+}
+
+/* Circuit bootstrapping of a level-0 TLWE c of a bit into a level-1 TRGSW C [2l][2][N]
+ * (P: the level-0/1 parameters and the output gadget; Q: level 2). */
+/* Gadget level j (1..l) of the conversion: TRGSW rows j-1 and l+j-1 of C. */
+static void cb_level(const or_params *P, const or_params2 *Q, const uint64_t *bk2, const uint32_t *pksk,
+                     const uint32_t *c, int j, uint32_t *C) {
+  const int N = P->N, l = P->l, N2 = Q->N;
+  uint64_t *tv = xmalloc(sizeof(uint64_t) * N2);
+  uint64_t *acc = xmalloc(sizeof(uint64_t) * 2 * N2);
+  uint64_t *ext = xmalloc(sizeof(uint64_t) * (N2 + 1));
+  const uint64_t half = 1ull << (63 - P->bgbit * j);       /* 1/(2 Bg^j) */
+  for (int i = 0; i < N2; i++) tv[i] = half;
+  or_blind_rotate64(P->n, Q, bk2, c, tv, acc);
+  or_sample_extract64(N2, acc, ext);
+  ext[N2] += half;                                          /* m / Bg^j */
+  or_private_keyswitch(P, Q, pksk, 0, ext, C + (size_t)(j - 1) * 2 * N);
+  or_private_keyswitch(P, Q, pksk, 1, ext, C + (size_t)(l + j - 1) * 2 * N);
+  free(tv); free(acc); free(ext);
+}
+
+void or_circuit_bootstrap(const or_params *P, const or_params2 *Q, const uint64_t *bk2, const uint32_t *pksk,
+                          const uint32_t *c, uint32_t *C) {
+  for (int j = 1; j <= P->l; j++) cb_level(P, Q, bk2, pksk, c, j, C);
+}
+
+typedef struct { const or_params *P; const or_params2 *Q; const uint64_t *bk2; const uint32_t *pksk;
+                 const uint32_t *in; uint32_t *out; } cb_ctx;
+
+static void cb_one(void *p, int64_t job) {
+  cb_ctx *c = p;
+  const int l = c->P->l;
+  const int64_t i = job / l;
+  const size_t trgsw = (size_t)2 * l * 2 * c->P->N;
+  cb_level(c->P, c->Q, c->bk2, c->pksk, c->in + (size_t)i * (c->P->n + 1), (int)(job % l) + 1, c->out + i * trgsw);
+}
+
+/* R circuit bootstraps, their R l gadget levels spread over `threads` threads.
+ * in [R][n+1], out [R][2l][2][N]. */
+void or_circuit_bootstraps(const or_params *P, const or_params2 *Q, const uint64_t *bk2, const uint32_t *pksk,
+                           const uint32_t *in, uint32_t *out, int64_t R, int threads) {
+  cb_ctx c = {P, Q, bk2, pksk, in, out};
+  parallel_for(R * P->l, threads, cb_one, &c);
+}

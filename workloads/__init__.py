@@ -15,7 +15,9 @@ computes them, and this module imports neither.
 
 Seeds: 0 secret keys (s0 then s1), 1 bootstrapping-key masks and noise, 2 key-switching
 key masks and noise, 10 + c plaintexts / circuits / arrivals of workload c, 20 + c the
-encryption randomness of workload c.
+encryption randomness of workload c; for circuit bootstrapping 3 the level-2 key s2,
+4 the level-2 bootstrapping-key masks and noise, 5 the private key-switching-key masks and
+noise.
 """
 from __future__ import annotations
 
@@ -29,6 +31,17 @@ KS_T = 8             # key-switch digits per coefficient
 KS_BASE = 4          # key-switch base (basebit = 2)
 SIGMA0 = 2.0 ** -15  # TLWE / key-switching-key noise sd (torus units)
 SIGMA1 = 2.0 ** -25  # TRLWE / TRGSW / bootstrapping-key noise sd (torus units)
+
+# Circuit bootstrapping (level 2, a reading: the paper names the operation but fixes no
+# parameters): ring degree, gadget, 2^64-torus noise of the level-2 bootstrapping key, and
+# the private key switch to level-1 TRLWE with its key's noise.
+RING_N2 = 2048
+GADGET_L2 = 4
+BG_BIT2 = 9
+PKS_T = 12
+PKS_BASE = 4          # basebit 2
+SIGMA2 = 2.0 ** -44   # level-2 bootstrapping-key noise sd (torus units)
+SIGMA_PKS = 2.0 ** -30  # private key-switching-key noise sd (torus units)
 
 # Gate opcodes as the C ABI numbers them.
 NAND, AND, OR, NOR, XOR, XNOR, ANDNOT, ORNOT, NOT = range(9)
@@ -73,6 +86,37 @@ def ksk_draws(seed: int = 2, n: int = LWE_N, N: int = RING_N, t: int = KS_T,
     masks = uniform_u32(g, (N, t, base - 1, n))
     noise = gaussian_i32(g, sigma, (N, t, base - 1))
     return masks, noise
+
+
+def uniform_u64(g: np.random.Generator, shape) -> np.ndarray:
+    return g.integers(0, 2 ** 64, size=shape, dtype=np.uint64)
+
+
+def gaussian_i64(g: np.random.Generator, sigma: float, shape) -> np.ndarray:
+    """Noise integers rint(sigma * 2^64 * z) on the 2^64 torus, z ~ N(0,1)."""
+    z = g.standard_normal(size=shape)
+    return np.rint(z * (sigma * 2.0 ** 64)).astype(np.int64)
+
+
+def secret_key2(seed: int = 3, N2: int = RING_N2):
+    """Binary level-2 TRLWE key (uint64 coefficients)."""
+    return rng(seed).integers(0, 2, size=N2, dtype=np.uint64)
+
+
+def bk2_draws(seed: int = 4, n: int = LWE_N, N2: int = RING_N2, l2: int = GADGET_L2, sigma: float = SIGMA2):
+    """Masks [n][2 l2][N2] (uint64) and noise [n][2 l2][N2] (int64) of the level-2
+    bootstrapping key."""
+    g = rng(seed)
+    return uniform_u64(g, (n, 2 * l2, N2)), gaussian_i64(g, sigma, (n, 2 * l2, N2))
+
+
+def pksk_draws(seed: int = 5, N: int = RING_N, N2: int = RING_N2, t: int = PKS_T, base: int = PKS_BASE,
+               sigma: float = SIGMA_PKS):
+    """Masks [2][N2+1][t][base-1][N] and noise of the same shape of the two private
+    key-switching keys (level-1 TRLWE rows)."""
+    g = rng(seed)
+    shape = (2, N2 + 1, t, base - 1, N)
+    return uniform_u32(g, shape), gaussian_i32(g, sigma, shape)
 
 
 def tlwe_draws(g: np.random.Generator, count: int, n: int = LWE_N, sigma: float = SIGMA0):
