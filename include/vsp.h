@@ -71,6 +71,7 @@ typedef struct vsp_circuit vsp_circuit;
 typedef struct vsp_server vsp_server;
 typedef struct vsp_keyset vsp_keyset;
 typedef struct vsp_machine vsp_machine;
+typedef struct vsp_cbkey vsp_cbkey;
 
 /* A gate of a circuit: opcode and the wire ids of its inputs (in1 ignored by NOT). Wires
  * 0..ninputs-1 are the circuit inputs; gate g writes wire ninputs + g. */
@@ -308,6 +309,31 @@ vsp_status vsp_debug_external_product(vsp_context* ctx, const uint32_t* d_trgsw,
  * p/2); d_b torus values. Arrays [J][N]. */
 vsp_status vsp_debug_polymul(vsp_context* ctx, const int32_t* d_a, const uint32_t* d_b, uint32_t* d_out,
                              uint64_t J, void* stream);
+
+/* ---------------------------------------------------------------- circuit bootstrapping
+ * TLWE -> TRGSW (Sec. 2.1.2 "Circuit Bootstrapping"), the conversion the CMUX memory applies
+ * to its address bits (Sec. 8.2). The paper fixes no parameters for it; this library reads
+ * them as a level-2 ring of degree N2 = 2048 over the 2^64 torus with an l2 = 4 x 2^9 gadget
+ * and private functional key switching to level-1 TRLWE with t2 = 12 digits of 2 bits.
+ *
+ * vsp_cbkey_create uploads the level-2 bootstrapping key bk2_host [n][2 l2][2][N2] (uint64
+ * torus words; BK2[i] = TRGSW2_{s2}(s0[i]), rows as the level-1 TRGSW) and the two private
+ * key-switching keys pksk_host [2][N2+1][t2][3][2][N] (uint32; entry [u][k][p][v-1] is a
+ * level-1 TRLWE of f_u(v z_k / 4^(p+1)) with z = (-s2[0..N2-1], 1), f_0(x) = -s1 x and
+ * f_1(x) = x), converts the first to its transformed layout on the device (about 645 MB; the
+ * second takes 1.2 GB) and returns the key in *out. Host arrays are copied. Synchronous.
+ * Destroy it before its context. */
+vsp_status vsp_cbkey_create(vsp_context* ctx, const uint64_t* bk2_host, const uint32_t* pksk_host, vsp_cbkey** out);
+vsp_status vsp_cbkey_destroy(vsp_cbkey* key);
+
+/* d_out[r] [2l][2][N] = the level-1 TRGSW of the bit that the level-0 TLWE d_in[r] [n+1]
+ * encrypts (+-1/8 encoding), for r < R: for each gadget level j = 1..l a level-2 blind
+ * rotation with test vector 1/(2 Bg^j), SampleExtract at 0 plus 1/(2 Bg^j), then the two
+ * private key switches, giving rows j-1 (f_0) and l+j-1 (f_1). The output is usable as a
+ * selector of vsp_rom_read / vsp_ram_read / vsp_ram_write. R = 0 is a no-op; R above 2^20 is
+ * VSP_E_ARG. The key's scratch grows on demand (allocation). */
+vsp_status vsp_circuit_bootstrap(vsp_context* ctx, vsp_cbkey* key, const uint32_t* d_in, uint32_t* d_out,
+                                 uint64_t R, void* stream);
 
 #ifdef __cplusplus
 }

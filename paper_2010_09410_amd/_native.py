@@ -70,6 +70,9 @@ SIGNATURES = {
     "vsp_machine_destroy": (_st, [_vp]),
     "vsp_keyset_create": (_st, [_vp, _vp, _vp, ctypes.POINTER(_vp)]),
     "vsp_keyset_destroy": (_st, [_vp]),
+    "vsp_cbkey_create": (_st, [_vp, _vp, _vp, ctypes.POINTER(_vp)]),
+    "vsp_cbkey_destroy": (_st, [_vp]),
+    "vsp_circuit_bootstrap": (_st, [_vp, _vp, _vp, _vp, _u64, _vp]),
     "vsp_server_submit_keyset": (_st, [_vp, _vp, ctypes.POINTER(vsp_gate_desc), _u64, _u64, _vp, ctypes.POINTER(_u64)]),
     "vsp_mux": (_st, [_vp, _vp, _vp, _vp, _vp, _u64, _vp]),
     "vsp_autotune": (_st, [_vp, _u64, ctypes.c_char_p]),
@@ -224,6 +227,21 @@ def vsp_keyset_create(ctx, bk_host, ksk_host) -> int:
 
 def vsp_keyset_destroy(k) -> None:
     _call("vsp_keyset_destroy", k)
+
+
+def vsp_cbkey_create(ctx, bk2_host, pksk_host) -> int:
+    """bk2_host: C-contiguous uint64 array [n][8][2][2048]; pksk_host: uint32 [2][2049][12][3][2][1024]."""
+    out = _vp()
+    _call("vsp_cbkey_create", ctx, bk2_host.ctypes.data, pksk_host.ctypes.data, ctypes.byref(out))
+    return out.value
+
+
+def vsp_cbkey_destroy(k) -> None:
+    _call("vsp_cbkey_destroy", k)
+
+
+def vsp_circuit_bootstrap(ctx, key, d_in, d_out, R, stream=None) -> None:
+    _call("vsp_circuit_bootstrap", ctx, key, d_in, d_out, R, stream)
 
 
 def vsp_server_submit_keyset(srv, keys, gates, ninputs: int, h_inputs) -> int:

@@ -165,3 +165,78 @@ def ram_cell_messages(contents, N: int = N_RING) -> np.ndarray:
     msg = np.full(contents.shape + (N,), NEG_MU, dtype=np.uint32)
     msg[..., 0] = bit_to_torus(contents)
     return msg
+
+
+# ------------------------------------------------------------------ circuit bootstrapping keys
+# Level 2 (the conversion TLWE -> TRGSW of Sec. 2.1.2 "Circuit Bootstrapping"): a binary key
+# s2 of degree N2 over the 2^64 torus, BK2[i] = TRGSW2_{s2}(s0[i]) with an l2 x 2^bg2 gadget,
+# and two private functional key-switching keys to level-1 TRLWE under s1.
+N2, L2, BG_BIT2, PKS_T, PKS_BASEBIT = 2048, 4, 9, 12, 2
+M64 = (1 << 64) - 1
+
+
+def mul_by_key64(a: np.ndarray, s: np.ndarray) -> np.ndarray:
+    """a(X) s(X) mod (X^N + 1, 2^64) for rows a [..., N] (uint64) and a binary key s [N], as
+    float64 matrix products on four 16-bit limbs (partial sums below 2^27: exact)."""
+    a = np.asarray(a, dtype=np.uint64)
+    shape = a.shape
+    a2 = a.reshape(-1, shape[-1])
+    M = _negacyclic_matrix(np.asarray(s))
+    r = np.zeros(a2.shape, dtype=np.uint64)
+    for q in range(4):
+        limb = ((a2 >> np.uint64(16 * q)) & np.uint64(0xFFFF)).astype(np.float64)
+        part = np.rint(limb @ M).astype(np.int64).astype(np.uint64)   # two's complement mod 2^64
+        r += part << np.uint64(16 * q)
+    return r.reshape(shape)
+
+
+def trlwe64_encrypt_torus(s2, m, masks, noise) -> np.ndarray:
+    masks = np.asarray(masks, dtype=np.uint64)
+    b = mul_by_key64(masks, s2) + np.asarray(m, dtype=np.uint64) + np.asarray(noise).astype(np.int64).astype(np.uint64)
+    return np.stack([masks, b], axis=-2)
+
+
+def trgsw64_encrypt(s2, m, masks, noise) -> np.ndarray:
+    """Level-2 TRGSW of bits m [...]: masks, noise [..., 2 l2, N2] -> [..., 2 l2, 2, N2] (rows as
+    trgsw_encrypt, gadget entries 2^(64 - bg2 (r+1)))."""
+    masks = np.asarray(masks, dtype=np.uint64)
+    C = trlwe64_encrypt_torus(s2, np.zeros_like(masks), masks, noise)
+    m = np.asarray(m, dtype=np.uint64)
+    for r in range(L2):
+        g = np.uint64(1 << (64 - BG_BIT2 * (r + 1)))
+        C[..., r, 0, 0] += m * g
+        C[..., L2 + r, 1, 0] += m * g
+    return C
+
+
+def private_keyswitching_keys(s1, s2, masks, noise, chunk: int = 8192) -> np.ndarray:
+    """PKSK[u][k][p][v-1] = TRLWE_{s1}(f_u(v z_k / 4^(p+1))) with z = (-s2, 1), f_0(x) = -s1 x,
+    f_1(x) = x: [2][N2+1][t][3][2][N] (uint32)."""
+    masks = np.asarray(masks, dtype=np.uint32)
+    _, K, t, B1, N = masks.shape
+    z = np.concatenate([(-np.asarray(s2, dtype=np.int64)), np.ones(1, np.int64)]) & M32      # [K]
+    v = np.arange(1, B1 + 1, dtype=np.uint64)
+    sh = np.uint64(32) - np.uint64(PKS_BASEBIT) * (np.arange(t, dtype=np.uint64) + np.uint64(1))
+    x = (z.astype(np.uint64)[:, None, None] * v[None, None, :] * (np.uint64(1) << sh)[None, :, None]) & M32  # [K][t][B1]
+    out = np.empty(masks.shape[:-1] + (2, N), dtype=np.uint32)
+    s1u = np.asarray(s1, dtype=np.uint64)
+    for u in range(2):
+        flat_m = masks[u].reshape(-1, N)
+        flat_e = np.asarray(noise[u]).reshape(-1, N)
+        flat_x = x.reshape(-1)
+        dst = out[u].reshape(-1, 2, N)
+        for lo in range(0, flat_m.shape[0], chunk):
+            hi = min(lo + chunk, flat_m.shape[0])
+            xs = flat_x[lo:hi].astype(np.uint64)
+            if u == 0:
+                msg = ((np.uint64(0) - s1u[None, :] * xs[:, None]) & M32).astype(np.uint32)
+            else:
+                msg = np.zeros((hi - lo, N), dtype=np.uint32)
+                msg[:, 0] = xs.astype(np.uint32)
+            dst[lo:hi] = trlwe_encrypt_torus(s1, msg, flat_m[lo:hi], flat_e[lo:hi])
+    return out
+
+
+def keyset2(s0, s1, s2, bk2d, pkskd):
+    """(BK2 [n][2 l2][2][N2] uint64, PKSK [2][N2+1][t][3][2][N] uint32)."""
+    return trgsw64_encrypt(s2, np.asarray(s0), *bk2d), private_keyswitching_keys(s1, s2, *pkskd)

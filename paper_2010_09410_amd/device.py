@@ -130,6 +130,9 @@ class Context:
     def keyset(self, bk: np.ndarray, ksk: np.ndarray) -> "Keyset":
         return Keyset(self, bk, ksk)
 
+    def cbkey(self, bk2: np.ndarray, pksk: np.ndarray) -> "CbKey":
+        return CbKey(self, bk2, pksk)
+
     def server(self, mem_budget_bytes: int, max_batch: int = 4096) -> "Server":
         return Server(self, mem_budget_bytes, max_batch)
 
@@ -207,6 +210,29 @@ class Machine:
     def close(self) -> None:
         if getattr(self, "handle", None):
             nv.vsp_machine_destroy(self.handle)
+            self.handle = None
+
+
+class CbKey:
+    """Circuit-bootstrapping keys on the context's GPU: level-2 bootstrapping key and the
+    private key-switching keys."""
+
+    def __init__(self, ctx: Context, bk2: np.ndarray, pksk: np.ndarray):
+        self.ctx = ctx
+        self.handle = nv.vsp_cbkey_create(ctx.handle, np.ascontiguousarray(bk2, dtype=np.uint64),
+                                          np.ascontiguousarray(pksk, dtype=np.uint32))
+
+    def bootstrap(self, tlwe: torch.Tensor, out=None) -> torch.Tensor:
+        """TLWE [R][n+1] -> TRGSW [R][2l][2][N]."""
+        R = tlwe.shape[0]
+        if out is None:
+            out = self.ctx.empty(R, 6, 2, 1024)
+        nv.vsp_circuit_bootstrap(self.ctx.handle, self.handle, _ptr(tlwe), _ptr(out), R, self.ctx.stream())
+        return out
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            nv.vsp_cbkey_destroy(self.handle)
             self.handle = None
 
 
