@@ -1,8 +1,8 @@
 // Autotuner for the batched launches. On random ciphertexts it times one full round of gates
 // for each blind-rotation form (4 or 8 gates per workgroup at one wave per gate, one gate on
 // three waves, and the matrix-core form; a launch then picks the form with the fewest rounds x
-// round time for its batch), the split matrix-core form at every bucket size with each
-// row-group count (the fastest count is kept per bucket) and the four key-switch forms (one workgroup per gate,
+// round time for its batch), the split matrix-core form at eleven batch sizes with each
+// row-group count (the fastest count is kept per size) and the four key-switch forms (one workgroup per gate,
 // row-stationary tiles, LDS-staged split, matrix cores) per batch-size bucket. Every candidate
 // must produce bit-identical outputs. The result can be cached in a small JSON file keyed by
 // the GPU; a cache written for another list of forms is ignored.
@@ -49,8 +49,8 @@ std::string device_key(int dev) {
 }
 
 // Cache file: {"<device>": {"br_waves": [4, 8, ..], "br_cap": [..], "br_round_ms": [..],
-//                          "buckets": [..], "ks_form": [..], "split_ms": [..],
-//                          "split_groups": [..]}}
+//                          "buckets": [..], "ks_form": [..], "split_at": [..],
+//                          "split_ms": [..], "split_groups": [..]}}
 bool read_numbers(const std::string& s, size_t from, const char* name, double* out, int count) {
   const size_t p = s.find(std::string("\"") + name + "\"", from);
   if (p == std::string::npos) return false;
@@ -77,11 +77,11 @@ bool read_cache(const std::string& path, const std::string& key, Tuning& t) {
   const size_t at = s.find("\"" + key + "\"");
   if (at == std::string::npos) return false;
   double shapes[kBrShapes], cap[kBrShapes], ms[kBrShapes], ks[kTuneBuckets], buckets[kTuneBuckets];
-  double sms[kTuneBuckets], sg[kTuneBuckets];
+  double sms[kSplitPts], sg[kSplitPts], spts[kSplitPts];
   if (!read_numbers(s, at, "br_waves", shapes, kBrShapes) || !read_numbers(s, at, "br_cap", cap, kBrShapes) ||
       !read_numbers(s, at, "br_round_ms", ms, kBrShapes) || !read_numbers(s, at, "buckets", buckets, kTuneBuckets) ||
-      !read_numbers(s, at, "ks_form", ks, kTuneBuckets) || !read_numbers(s, at, "split_ms", sms, kTuneBuckets) ||
-      !read_numbers(s, at, "split_groups", sg, kTuneBuckets))
+      !read_numbers(s, at, "ks_form", ks, kTuneBuckets) || !read_numbers(s, at, "split_at", spts, kSplitPts) ||
+      !read_numbers(s, at, "split_ms", sms, kSplitPts) || !read_numbers(s, at, "split_groups", sg, kSplitPts))
     return false;
   for (int i = 0; i < kBrShapes; i++)
     if (shapes[i] != kBrWaveChoices[i]) return false;  // written for another list of forms
@@ -97,12 +97,13 @@ bool read_cache(const std::string& path, const std::string& key, Tuning& t) {
     if (!(ks[b] >= 0 && ks[b] < kKsForms && ks[b] == (double)(int)ks[b])) return false;
     n.ks_form[b] = (int)ks[b];
   }
-  for (int b = 0; b < kTuneBuckets; b++) {
-    const int g = (int)sg[b];
-    if (!(sms[b] > 0 && sms[b] < 1e9) || (double)g != sg[b] || !(g == 0 || g == 1 || g == 2 || g == 3 || g == 6))
+  for (int k = 0; k < kSplitPts; k++) {
+    const int g = (int)sg[k];
+    if (spts[k] != (double)kSplitAt[k]) return false;  // written for other sizes
+    if (!(sms[k] > 0 && sms[k] < 1e9) || (double)g != sg[k] || !(g == 0 || g == 1 || g == 2 || g == 3 || g == 6))
       return false;
-    n.split_ms[b] = (float)sms[b];
-    n.split_groups[b] = g;
+    n.split_ms[k] = (float)sms[k];
+    n.split_groups[k] = g;
   }
   n.tuned = true;
   t = n;
@@ -127,10 +128,12 @@ bool write_cache(const std::string& path, const std::string& key, const Tuning& 
   list([](int i) { return kBucket[i]; }, kTuneBuckets);
   f << ", \"ks_form\": ";
   list([&](int i) { return t.ks_form[i]; }, kTuneBuckets);
+  f << ", \"split_at\": ";
+  list([](int i) { return kSplitAt[i]; }, kSplitPts);
   f << ", \"split_ms\": ";
-  list([&](int i) { return t.split_ms[i]; }, kTuneBuckets);
+  list([&](int i) { return t.split_ms[i]; }, kSplitPts);
   f << ", \"split_groups\": ";
-  list([&](int i) { return t.split_groups[i]; }, kTuneBuckets);
+  list([&](int i) { return t.split_groups[i]; }, kSplitPts);
   f << "}}\n";
   return (bool)f;
 }
@@ -217,9 +220,9 @@ vsp_status vsp_autotune(vsp_context* ctx, uint64_t max_batch, const char* cache_
     if (s > 0 && !same(t1ref.p, t1.p, std::min(t.br_cap[0], B) * T1))
       result = fail(VSP_E_HIP, "autotune: blind-rotation shapes disagree");
   }
-  // the split matrix-core form at every bucket size, with each row-group count
-  for (int b = 0; b < kTuneBuckets && result == VSP_OK && ctx->mf_key; b++) {
-    const uint64_t B = std::min<uint64_t>(kBucket[b], t.br_cap[3]);
+  // the split matrix-core form at each timed size, with each row-group count
+  for (int b = 0; b < kSplitPts && result == VSP_OK && ctx->mf_key; b++) {
+    const uint64_t B = std::min<uint64_t>(kSplitAt[b], t.br_cap[3]);
     float best = 1e30f;
     for (int g : {1, 2, 3, 6}) {
       const float ms = timed([&] {

@@ -207,7 +207,7 @@ hipError_t launch_blind_rotate(const vsp_context* ctx, const uint8_t* ops, const
       return waves == 32 ? launch_blind_rotate_mfma(ctx, ops, abar, tlwe1, trlwe, B, mf_work, st, instrument)
                          : launch_blind_rotate_mfsplit(ctx, ops, abar, tlwe1, trlwe, B, mf_work,
                                                        ctx->tune.split_groups_for(B, ctx->cus), st, instrument);
-    waves = 8;
+    waves = ctx->tune.br_waves(B, true);
   }
   if (waves == 3) {
     hipLaunchKernelGGL(k_blind_rotate_wide, dim3((unsigned)B), dim3(BRW_WAVES * 64), brw_lds_bytes(), st, bkn,

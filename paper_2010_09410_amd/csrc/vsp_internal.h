@@ -53,6 +53,9 @@ inline int mf_split_groups(uint64_t B, int cus) {
 // one also holds every larger batch.
 constexpr int kTuneBuckets = 7;
 constexpr uint64_t kBucket[kTuneBuckets] = {1, 16, 64, 256, 1024, 2048, 4096};
+// Batch sizes at which the split matrix-core form is timed (its time is interpolated between).
+constexpr int kSplitPts = 11;
+constexpr uint64_t kSplitAt[kSplitPts] = {1, 16, 64, 256, 512, 768, 1024, 1536, 2048, 3072, 4096};
 
 // Launch choices, set by vsp_autotune or left at the defaults. Every choice gives
 // bit-identical results.
@@ -60,8 +63,8 @@ constexpr uint64_t kBucket[kTuneBuckets] = {1, 16, 64, 256, 1024, 2048, 4096};
 //    ceil(B / br_cap[s]) rounds of br_round_ms[s] with shape s, where br_cap[s] is the number
 //    of gates the whole GPU holds at once (occupancy x compute units x gates per group) and
 //    br_round_ms[s] the time of one full round. The split matrix-core form is timed instead
-//    at every bucket size (split_ms[b], with the fastest row-group count split_groups[b]) and
-//    estimated in between by linear interpolation (beyond the last bucket: in proportion).
+//    at the sizes kSplitAt (split_ms[k], with the fastest row-group count split_groups[k]) and
+//    estimated in between by linear interpolation (beyond the last size: in proportion).
 //    The shape with the fewer milliseconds wins (ties: the 8-gate workgroup). br_force[b] != 0
 //    pins the shape for bucket b.
 //  * Key switch: per bucket, form 0 gathers key rows per gate, 1 reads them once per tile of
@@ -70,12 +73,12 @@ constexpr uint64_t kBucket[kTuneBuckets] = {1, 16, 64, 256, 1024, 2048, 4096};
 //    key's byte planes).
 struct Tuning {
   uint64_t br_cap[kBrShapes] = {1024, 2048, 512, 4096, MF_TILE};
-  float br_round_ms[kBrShapes] = {1.0f, 1.48f, 0.75f, 2.31f, 0.34f};
-  // split form, per bucket: time in the same units as br_round_ms, and row groups (0: the
-  // count that fills the chip, mf_split_groups). The defaults are relative times measured on
-  // an MI355X (one 4-gate-workgroup round = 1).
-  float split_ms[kTuneBuckets] = {0.23f, 0.31f, 0.36f, 0.51f, 0.91f, 1.53f, 2.51f};
-  int split_groups[kTuneBuckets] = {6, 6, 6, 3, 2, 1, 1};
+  float br_round_ms[kBrShapes] = {1.0f, 1.482f, 0.75f, 2.33f, 0.337f};
+  // split form, at the sizes kSplitAt: time in the same units as br_round_ms, and row groups
+  // (0: the count that fills the chip, mf_split_groups). The defaults are relative times
+  // measured on an MI355X (one 4-gate-workgroup round = 1).
+  float split_ms[kSplitPts] = {0.228f, 0.306f, 0.356f, 0.513f, 0.672f, 0.829f, 0.918f, 1.368f, 1.53f, 2.22f, 2.567f};
+  int split_groups[kSplitPts] = {6, 6, 6, 3, 2, 3, 2, 2, 1, 1, 1};
   int br_force[kTuneBuckets] = {0, 0, 0, 0, 0, 0, 0};
   int ks_form[kTuneBuckets] = {2, 2, 2, 2, 3, 3, 3};
   bool tuned = false;
@@ -84,12 +87,15 @@ struct Tuning {
     while (b + 1 < kTuneBuckets && B > kBucket[b]) b++;
     return b;
   }
-  int br_waves(uint64_t B) const {
+  // with ntt_only, the best of the NTT forms (for launches that cannot take the matrix-core
+  // forms: another key, or no workspace)
+  int br_waves(uint64_t B, bool ntt_only = false) const {
     const int f = br_force[bucket(B)];
-    if (f) return f;
+    if (f && !(ntt_only && br_matrix_form(f))) return f;
     int best = 1;
     double best_ms = 0;
     for (int s : {1, 0, 2, 3, 4}) {
+      if (ntt_only && s >= 3) continue;
       const uint64_t cap = br_cap[s] ? br_cap[s] : 1;
       double ms = (double)((B + cap - 1) / cap) * br_round_ms[s];
       if (s == 4) ms = split_estimate(B);
@@ -101,15 +107,20 @@ struct Tuning {
     return kBrWaveChoices[best];
   }
   int ks_form_for(uint64_t B) const { return ks_form[bucket(B)]; }
+  static int split_point(uint64_t B) {  // the first timed size at or above B (else the last)
+    int k = 0;
+    while (k + 1 < kSplitPts && B > kSplitAt[k]) k++;
+    return k;
+  }
   double split_estimate(uint64_t B) const {
-    const int b = bucket(B);
-    if (B >= kBucket[kTuneBuckets - 1]) return (double)split_ms[kTuneBuckets - 1] * (double)B / kBucket[b];
-    if (b == 0) return split_ms[0];
-    const double f = (double)(B - kBucket[b - 1]) / (double)(kBucket[b] - kBucket[b - 1]);
-    return split_ms[b - 1] + f * (split_ms[b] - split_ms[b - 1]);
+    const int k = split_point(B);
+    if (B >= kSplitAt[kSplitPts - 1]) return (double)split_ms[kSplitPts - 1] * (double)B / kSplitAt[k];
+    if (k == 0) return split_ms[0];
+    const double f = (double)(B - kSplitAt[k - 1]) / (double)(kSplitAt[k] - kSplitAt[k - 1]);
+    return split_ms[k - 1] + f * (split_ms[k] - split_ms[k - 1]);
   }
   int split_groups_for(uint64_t B, int cus) const {
-    const int g = split_groups[bucket(B)];
+    const int g = split_groups[split_point(B)];
     return g ? g : mf_split_groups(B, cus);
   }
 };
@@ -221,7 +232,7 @@ hipError_t launch_mux_combine(uint32_t* t, uint64_t B, hipStream_t st);
 // bkn: the bootstrapping key to use (NULL: the context's); with keytab non-NULL gate g uses
 // keytab[kid[g]] instead (device arrays). The matrix-core forms (waves 32 and 33) need the
 // context's own key and a workspace of mf_work_bytes(B, trlwe == NULL) bytes in mf_work;
-// without them the 8-gate form runs instead.
+// without them the best NTT form for B runs instead.
 hipError_t launch_blind_rotate(const vsp_context* ctx, const uint8_t* ops, const uint32_t* abar, uint32_t* tlwe1,
                                uint32_t* trlwe, uint64_t B, int waves, hipStream_t st, const uint64_t* bkn = nullptr,
                                const uint64_t* const* keytab = nullptr, const uint8_t* kid = nullptr,

@@ -64,14 +64,14 @@ def model_choice(entry, B):
     """The launch rule: fewest rounds x round time for the one-wave-per-gate forms and the
     matrix-core form, the interpolated per-bucket time for the split matrix-core form (ties:
     the 8-gate workgroup, then the order 4, 3, 32, 33)."""
-    caps, ms, sms = entry["br_cap"], entry["br_round_ms"], entry["split_ms"]
+    caps, ms, sms, at = entry["br_cap"], entry["br_round_ms"], entry["split_ms"], entry["split_at"]
     def split(B):
-        b = next((i for i, k in enumerate(BUCKETS) if B <= k), len(BUCKETS) - 1)
-        if B >= BUCKETS[-1]:
-            return sms[-1] * B / BUCKETS[b]
+        b = next((i for i, k in enumerate(at) if B <= k), len(at) - 1)
+        if B >= at[-1]:
+            return sms[-1] * B / at[b]
         if b == 0:
             return sms[0]
-        f = (B - BUCKETS[b - 1]) / (BUCKETS[b] - BUCKETS[b - 1])
+        f = (B - at[b - 1]) / (at[b] - at[b - 1])
         return sms[b - 1] + f * (sms[b] - sms[b - 1])
     est = {s: -(-B // caps[s]) * ms[s] for s in range(4)}
     est[4] = split(B)
@@ -102,14 +102,15 @@ def test_autotune_model_and_cache_round_trip(gpu, tmp_path):
         for B in (1, 16, 40, 64, 200, 256, 700, 1024, 1500, 2048, 3000, 4096, 5000):
             assert gpu.tuning(B)[0] == model_choice(entry, B), B
         # edited entries for this GPU are read back and followed
-        big = [100.0] * 7
+        big = [100.0] * 11
+        assert entry["split_at"] == [1, 16, 64, 256, 512, 768, 1024, 1536, 2048, 3072, 4096]
         for ms, sms, small, large in (([1.0, 100.0, 100.0, 100.0, 100.0], big, 4, 4),
                                       ([100.0, 1.0, 100.0, 100.0, 100.0], big, 8, 8),
                                       ([1.0, 1.5, 100.0, 100.0, 100.0], big, 4, 8),
                                       ([100.0, 100.0, 1.0, 100.0, 100.0], big, 3, 3),
                                       ([100.0, 100.0, 100.0, 1.0, 100.0], big, 32, 32),
-                                      ([100.0, 100.0, 100.0, 100.0, 100.0], [0.001] * 7, 33, 33),
-                                      ([100.0, 1.0, 100.0, 100.0, 100.0], [0.5] * 5 + [1000.0, 1000.0], None, None)):
+                                      ([100.0, 100.0, 100.0, 100.0, 100.0], [0.001] * 11, 33, 33),
+                                      ([100.0, 1.0, 100.0, 100.0, 100.0], [0.5] * 7 + [1000.0] * 4, None, None)):
             entry["br_round_ms"] = ms
             entry["split_ms"] = sms
             path.write_text(json.dumps({key: entry}))
