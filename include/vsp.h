@@ -194,6 +194,20 @@ vsp_status vsp_machine_run(vsp_machine* m, const uint32_t* d_inputs, uint32_t* d
                            uint64_t ncycles, void* stream);
 vsp_status vsp_machine_destroy(vsp_machine* m);
 
+/* Give a machine a one-cycle single-port RAM (the CMUX memory of Sec. 8.2, fed by the
+ * processor's wires as TLWE): d_ram [w][2^v][2][N] holds its cells (caller's device memory,
+ * updated in place by every cycle's write). Each cycle, after the DAG, the wires
+ * addr_wires[0..v) (address, least significant bit first), flag_wire (write flag) and
+ * data_wires[0..w) (write data) are staged; circuit bootstrapping turns the address bits into
+ * TRGSW selectors (key: vsp_cbkey_create); the RAM is read at that address (contents before
+ * the write) into flip-flops read_state[0..w) (their next_state entries are then ignored);
+ * and the write of vsp_ram_write runs with the staged flag and data. Wire ids as for
+ * vsp_machine_create (0..ninputs-1 inputs, then flip-flops, then gates). One RAM per machine
+ * (VSP_E_STATE for a second); the key and d_ram must outlive the machine. */
+vsp_status vsp_machine_attach_ram(vsp_machine* m, vsp_cbkey* key, uint32_t* d_ram, uint32_t v, uint32_t w,
+                                  const uint32_t* addr_wires, uint32_t flag_wire, const uint32_t* data_wires,
+                                  const uint32_t* read_state);
+
 /* Continuous-batching server over one context (Bob evaluating many clients' circuits,
  * Sec. 4.1): admits submitted circuits while their resident wire buffers fit in
  * mem_budget_bytes of device memory, and each iteration launches one batch of ready

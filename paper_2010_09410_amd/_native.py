@@ -71,6 +71,7 @@ SIGNATURES = {
     "vsp_keyset_create": (_st, [_vp, _vp, _vp, ctypes.POINTER(_vp)]),
     "vsp_keyset_destroy": (_st, [_vp]),
     "vsp_cbkey_create": (_st, [_vp, _vp, _vp, ctypes.POINTER(_vp)]),
+    "vsp_machine_attach_ram": (_st, [_vp, _vp, _vp, ctypes.c_uint32, ctypes.c_uint32, _vp, ctypes.c_uint32, _vp, _vp]),
     "vsp_cbkey_destroy": (_st, [_vp]),
     "vsp_circuit_bootstrap": (_st, [_vp, _vp, _vp, _vp, _u64, _vp]),
     "vsp_server_submit_keyset": (_st, [_vp, _vp, ctypes.POINTER(vsp_gate_desc), _u64, _u64, _vp, ctypes.POINTER(_u64)]),
@@ -234,6 +235,14 @@ def vsp_cbkey_create(ctx, bk2_host, pksk_host) -> int:
     out = _vp()
     _call("vsp_cbkey_create", ctx, bk2_host.ctypes.data, pksk_host.ctypes.data, ctypes.byref(out))
     return out.value
+
+
+def vsp_machine_attach_ram(m, key, d_ram, v, w, addr_wires, flag_wire, data_wires, read_state) -> None:
+    """addr_wires [v], data_wires [w], read_state [w]: sequences of ints (host)."""
+    a = np.ascontiguousarray(addr_wires, dtype=np.uint32)
+    d = np.ascontiguousarray(data_wires, dtype=np.uint32)
+    r = np.ascontiguousarray(read_state, dtype=np.uint32)
+    _call("vsp_machine_attach_ram", m, key, d_ram, v, w, a.ctypes.data, flag_wire, d.ctypes.data, r.ctypes.data)
 
 
 def vsp_cbkey_destroy(k) -> None:

@@ -207,6 +207,14 @@ class Machine:
                            None if wires is None else _ptr(wires), int(ncycles), self.ctx.stream())
         return wires
 
+    def attach_ram(self, key: "CbKey", ram: torch.Tensor, addr_wires, flag_wire: int, data_wires, read_state) -> None:
+        """RAM port: ram [w][2^v][2][N] (kept by the caller), updated every cycle."""
+        w, cells = ram.shape[0], ram.shape[1]
+        v = int(cells).bit_length() - 1
+        self.ram = ram
+        nv.vsp_machine_attach_ram(self.handle, key.handle, _ptr(ram), v, w, addr_wires, int(flag_wire), data_wires,
+                                  read_state)
+
     def close(self) -> None:
         if getattr(self, "handle", None):
             nv.vsp_machine_destroy(self.handle)

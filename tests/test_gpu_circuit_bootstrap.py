@@ -81,3 +81,74 @@ def test_circuit_bootstrap_argument_errors(gpu, cb):
     with pytest.raises(VspError) as ei:                                   # output overlaps the input
         nv.vsp_circuit_bootstrap(gpu.handle, cb["key"].handle, o.data_ptr(), o.data_ptr(), 2, gpu.stream())
     assert ei.value.status == nv.VSP_E_ARG
+
+
+def counter_machine_netlist():
+    """A clocked netlist with a RAM port (v = 4, w = 4): address register A (flip-flops 0-3)
+    counts up each cycle; the read port loads register D (flip-flops 4-7) with RAM[A]; the
+    write data is D XOR A under the external write-flag input. Wires: 0 the flag, 1-4 A,
+    5-8 D, then the gates."""
+    NOT, XOR, AND = 8, 4, 1
+    A, D = [1, 2, 3, 4], [5, 6, 7, 8]
+    gates = []
+    def gate(op, a, b):
+        gates.append((op, a, b))
+        return 9 + len(gates) - 1
+    s0 = gate(NOT, A[0], A[0])
+    c = A[0]
+    nxt = [s0]
+    for b in range(1, 4):
+        nxt.append(gate(XOR, A[b], c))
+        if b < 3:
+            c = gate(AND, A[b], c)
+    wd = [gate(XOR, D[b], A[b]) for b in range(4)]
+    next_state = nxt + D            # the D entries are taken over by the read port
+    return np.array(gates, np.int64), next_state, A, wd
+
+
+def test_clocked_netlist_with_ram_in_the_loop(gpu, keys, cb):
+    """Cycles of a netlist whose RAM is read and written every clock from TLWE wires (circuit
+    bootstrapping of the address): the state and the RAM follow the plaintext model for four
+    cycles; the first cycle's read and write are bit-exact against the oracle fed the same
+    ciphertexts."""
+    s0, s1 = keys["s0"], keys["s1"]
+    gates, next_state, A_w, wd_w = counter_machine_netlist()
+    g = W.rng(702)
+    contents = g.integers(0, 2, (4, 16))
+    a0, d0 = 13, int(g.integers(0, 16))
+    flags = [1, 0, 1, 1]
+    state_bits = [(a0 >> b) & 1 for b in range(4)] + [(d0 >> b) & 1 for b in range(4)]
+    state = client.tlwe_encrypt_bits(s0, state_bits, *W.tlwe_draws(g, 8))
+    ca, ce = W.trlwe_draws(g, 64)
+    ram0 = client.trlwe_encrypt_torus(s1, client.ram_cell_messages(contents), ca.reshape(4, 16, N), ce.reshape(4, 16, N))
+    fin = client.tlwe_encrypt_bits(s0, flags, *W.tlwe_draws(g, 4)).reshape(4, 1, n + 1)
+    m = gpu.machine(gates, 1, next_state)
+    d_ram = gpu.tensor(ram0)
+    m.attach_ram(cb["key"], d_ram, A_w, 0, wd_w, [4, 5, 6, 7])
+    d_state = gpu.tensor(state)
+    # cycle 1, then the oracle on the same ciphertexts: selectors from circuit bootstrapping
+    # of the address flip-flops, the read into D, the write of D xor A under the flag
+    m.run(d_state, 1, gpu.tensor(fin[:1]))
+    st1 = to_host(d_state)
+    ram1 = to_host(d_ram)
+    gpu.sync()
+    sel = oracle.circuit_bootstraps(cb["bk2"], cb["pksk"], state[:4])
+    np.testing.assert_array_equal(st1[4:8], oracle.ram_read(keys["ksk"], ram0, sel))
+    wdata = np.stack([oracle.gate(keys["bk"], keys["ksk"], 4, state[4 + b], state[b]) for b in range(4)])
+    np.testing.assert_array_equal(ram1, oracle.ram_write(keys["bk"], keys["ksk"], ram0, sel, fin[0, 0], wdata))
+    # three more cycles against the plaintext model
+    m.run(d_state, 3, gpu.tensor(fin[1:]))
+    st = client.tlwe_decrypt(s0, to_host(d_state))
+    ram = to_host(d_ram)
+    gpu.sync()
+    mem = contents.copy()
+    A, Dv = a0, d0
+    for f in flags:
+        rd = mem[:, A].copy()
+        if f:
+            mem[:, A] = [((Dv >> b) & 1) ^ ((A >> b) & 1) for b in range(4)]
+        A, Dv = (A + 1) % 16, int(sum(int(rd[b]) << b for b in range(4)))
+    assert [int(x) for x in st] == [(A >> b) & 1 for b in range(4)] + [(Dv >> b) & 1 for b in range(4)]
+    got = (client.trlwe_phase(s1, ram)[..., 0].view(np.int32) >= 0).astype(int)
+    np.testing.assert_array_equal(got, mem)
+    m.close()
