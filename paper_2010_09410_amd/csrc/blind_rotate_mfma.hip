@@ -229,11 +229,14 @@ __device__ __forceinline__ int mf_pass_row(int pass) {
 // next_step for rows 3o .. 3o + 2 of its tile into Anext: they depend only on the updated
 // polynomial o of its own 32 gates, which it has just written, so no other workgroup is
 // involved (the other output polynomial's workgroup writes rows 3(1 - o) ..).
-__global__ __launch_bounds__(MF_THREADS) void k_mf_step(const int8_t* __restrict__ Ek, const int8_t* __restrict__ A,
+__global__ __launch_bounds__(MF_THREADS) void k_mf_step(const int8_t* __restrict__ Ek0, const int8_t* __restrict__ A,
                                                          u32* __restrict__ acc, const uint8_t* __restrict__ ops,
                                                          uint64_t B, int8_t* __restrict__ Anext,
-                                                         const u32* __restrict__ abar, int next_step) {
+                                                         const u32* __restrict__ abar, int next_step,
+                                                         const int8_t* const* __restrict__ tkeys, uint64_t key_off) {
   extern __shared__ uint4 mf_lds[];
+  // the step's key: the context's (Ek0), or the tile's key set's
+  const int8_t* __restrict__ Ek = tkeys ? tkeys[blockIdx.x] + key_off : Ek0;
   uint4* abuf = mf_lds;                                            // [2][MF_A_PASS_U4]
   u32* ebuf = reinterpret_cast<u32*>(mf_lds + 2 * MF_A_PASS_U4);  // [2][3 sequences][4 copies][MF_COPY_U32]
   const uint64_t mt = blockIdx.x;
@@ -463,9 +466,11 @@ constexpr size_t MFP_LDS = 2 * ((size_t)MFP_A_U4 * 16 + 4 * (size_t)MF_COPY_U32 
 static_assert(MFP_A_U4 == 4 * MFP_THREADS && MF_S / 4 == MFP_THREADS,
               "four 16-byte operands and one key word per thread and pass");
 
-__global__ __launch_bounds__(MFP_THREADS, 3) void k_mf_part(const int8_t* __restrict__ Ek, const int8_t* __restrict__ A,
+__global__ __launch_bounds__(MFP_THREADS, 3) void k_mf_part(const int8_t* __restrict__ Ek0, const int8_t* __restrict__ A,
                                                           u32* __restrict__ acc, const uint8_t* __restrict__ ops,
-                                                          uint64_t B, int groups) {
+                                                          uint64_t B, int groups,
+                                                          const int8_t* const* __restrict__ tkeys, uint64_t key_off) {
+  const int8_t* __restrict__ Ek = tkeys ? tkeys[blockIdx.x] + key_off : Ek0;
   __shared__ uint4 abuf[2][MFP_A_U4];
   __shared__ u32 ebuf[2][4 * MF_COPY_U32];
   const uint64_t mt = blockIdx.x;
@@ -605,7 +610,8 @@ hipError_t launch_mf_key(const uint32_t* bk, int8_t* E, hipStream_t st) {
 }
 
 hipError_t launch_blind_rotate_mfma(const vsp_context* ctx, const uint8_t* ops, const uint32_t* abar, uint32_t* tlwe1,
-                                    uint32_t* trlwe, uint64_t B, void* work, hipStream_t st, bool instrument) {
+                                    uint32_t* trlwe, uint64_t B, void* work, hipStream_t st, bool instrument,
+                                    const int8_t* const* tkeys) {
   if (B == 0) return hipSuccess;
   const uint64_t tiles = (B + MF_TILE - 1) / MF_TILE;
   // operands of even steps in A[0], of odd steps in A[1]: step i reads A[i % 2] and writes
@@ -621,8 +627,8 @@ hipError_t launch_blind_rotate_mfma(const vsp_context* ctx, const uint8_t* ops, 
     ProfScope ps(instrument ? ctx : nullptr, 3, st, LWE_N);
     for (int i = 0; i < LWE_N; i++)
       hipLaunchKernelGGL(k_mf_step, dim3((unsigned)tiles, 2), dim3(MF_THREADS), MF_STEP_LDS, st,
-                         ctx->mf_key + (size_t)i * MF_KEY_STEP, Ab[i & 1], acc, ops, B, Ab[(i + 1) & 1], abar,
-                         i + 1 < LWE_N ? i + 1 : -1);
+                         tkeys ? nullptr : ctx->mf_key + (size_t)i * MF_KEY_STEP, Ab[i & 1], acc, ops, B,
+                         Ab[(i + 1) & 1], abar, i + 1 < LWE_N ? i + 1 : -1, tkeys, (uint64_t)i * MF_KEY_STEP);
   }
   hipError_t e = hipGetLastError();
   if (e == hipSuccess && tlwe1) e = launch_sample_extract(acc, tlwe1, B, 1, st);
@@ -635,7 +641,7 @@ hipError_t launch_blind_rotate_mfma(const vsp_context* ctx, const uint8_t* ops, 
 // form (the operands of one step and, without a caller TRLWE, the accumulators).
 hipError_t launch_blind_rotate_mfsplit(const vsp_context* ctx, const uint8_t* ops, const uint32_t* abar,
                                        uint32_t* tlwe1, uint32_t* trlwe, uint64_t B, void* work, int groups,
-                                       hipStream_t st, bool instrument) {
+                                       hipStream_t st, bool instrument, const int8_t* const* tkeys) {
   if (B == 0) return hipSuccess;
   if (groups != 1 && groups != 2 && groups != 3 && groups != 6) return hipErrorInvalidValue;
   const uint64_t tiles = (B + MF_TILE - 1) / MF_TILE;
@@ -648,7 +654,8 @@ hipError_t launch_blind_rotate_mfsplit(const vsp_context* ctx, const uint8_t* op
     ProfScope ps(instrument ? ctx : nullptr, 3, st, LWE_N);
     for (int i = 0; i < LWE_N; i++) {
       hipLaunchKernelGGL(k_mf_part, dim3((unsigned)tiles, 2, (unsigned)(MF_SUB * groups)), dim3(MFP_THREADS), 0, st,
-                         ctx->mf_key + (size_t)i * MF_KEY_STEP, Aop, acc, ops, B, groups);
+                         tkeys ? nullptr : ctx->mf_key + (size_t)i * MF_KEY_STEP, Aop, acc, ops, B, groups, tkeys,
+                         (uint64_t)i * MF_KEY_STEP);
       if (i + 1 < LWE_N)
         hipLaunchKernelGGL(k_mf_digits, dgrid, dim3(256), 0, st, ops, abar, acc, Aop, B, i + 1);
     }

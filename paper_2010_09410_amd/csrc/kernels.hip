@@ -75,6 +75,7 @@ __global__ __launch_bounds__(256) void k_gate_prologue(const uint8_t* __restrict
   const uint64_t g = i / TLWE0;
   const int c = (int)(i - g * TLWE0);
   const uint32_t op = ops ? ops[g] : uniform_op;
+  if (op == OP_SKIP) return;
   const uint64_t r0 = idx0 ? idx0[g] : g, r1 = idx1 ? idx1[g] : g;
   const u32 x = in0[r0 * TLWE0 + c];
   const bool one_input = (op == VSP_NOT || op == OP_IDENT || !op_bootstraps(op));
@@ -198,15 +199,18 @@ hipError_t blind_rotate_capacity(int device, uint64_t (&cap)[kBrShapes]) {
 
 hipError_t launch_blind_rotate(const vsp_context* ctx, const uint8_t* ops, const uint32_t* abar, uint32_t* tlwe1,
                                uint32_t* trlwe, uint64_t B, int waves, hipStream_t st, const uint64_t* bkn,
-                               const uint64_t* const* keytab, const uint8_t* kid, void* mf_work, bool instrument) {
+                               const uint64_t* const* keytab, const uint8_t* kid, void* mf_work, bool instrument,
+                               const int8_t* const* tile_mfkeys) {
   if (B == 0) return hipSuccess;
   if (bkn == nullptr) bkn = ctx->bkn;
   if (waves <= 0) waves = ctx->tune.br_waves(B);
   if (br_matrix_form(waves)) {
-    if (keytab == nullptr && bkn == ctx->bkn && mf_work != nullptr && ctx->mf_key != nullptr)
-      return waves == 32 ? launch_blind_rotate_mfma(ctx, ops, abar, tlwe1, trlwe, B, mf_work, st, instrument)
+    const bool own = keytab == nullptr && bkn == ctx->bkn && ctx->mf_key != nullptr;
+    if (mf_work != nullptr && (own || tile_mfkeys != nullptr))
+      return waves == 32 ? launch_blind_rotate_mfma(ctx, ops, abar, tlwe1, trlwe, B, mf_work, st, instrument, tile_mfkeys)
                          : launch_blind_rotate_mfsplit(ctx, ops, abar, tlwe1, trlwe, B, mf_work,
-                                                       ctx->tune.split_groups_for(B, ctx->cus), st, instrument);
+                                                       ctx->tune.split_groups_for(B, ctx->cus), st, instrument,
+                                                       tile_mfkeys);
     waves = ctx->tune.br_waves(B, true);
   }
   if (waves == 3) {
@@ -433,12 +437,14 @@ __global__ __launch_bounds__(256) void k_keyswitch_split(const u32* __restrict__
 }
 
 hipError_t launch_keyswitch(const vsp_context* ctx, const uint8_t* ops, const uint32_t* tlwe1, const uint32_t* idxo,
-                            uint32_t* out, uint64_t B, hipStream_t st, int form, const uint32_t* ksk) {
+                            uint32_t* out, uint64_t B, hipStream_t st, int form, const uint32_t* ksk,
+                            const int8_t* ks_mf) {
   if (B == 0) return hipSuccess;
   if (ksk == nullptr) ksk = ctx->ksk;
   if (form < 0) form = ctx->tune.ks_form_for(B);
   if (form == 3) {
     if (ksk == ctx->ksk && ctx->ks_mf != nullptr) return launch_keyswitch_mfma(ctx->ks_mf, ops, tlwe1, idxo, out, B, st);
+    if (ksk != ctx->ksk && ks_mf != nullptr) return launch_keyswitch_mfma(ks_mf, ops, tlwe1, idxo, out, B, st);
     form = 2;
   }
   if (form == 2) {

@@ -51,6 +51,8 @@ struct Slot {  // one in-flight batch
   uint32_t* d_idx = nullptr;
   uint8_t* d_kid = nullptr;
   const uint64_t** d_keytab = nullptr;
+  const int8_t** h_tilekeys = nullptr;  // matrix-core key of each tile of a padded batch
+  const int8_t** d_tilekeys = nullptr;
   uint32_t* d_abar = nullptr;
   uint32_t* d_tlwe1 = nullptr;
   hipEvent_t ev = nullptr;
@@ -63,6 +65,7 @@ struct Slot {  // one in-flight batch
 struct vsp_server {
   vsp_context* ctx = nullptr;
   uint64_t budget = 0, max_batch = 0, arena_rows = 0;
+  uint64_t cap = 0;  // launch entries per batch: max_batch plus tile padding of every key set
   uint32_t* arena = nullptr;
   std::map<uint64_t, uint64_t> free_rows;  // base -> length
   uint64_t resident = 0, peak = 0, gates_launched = 0, batches = 0, next_ticket = 1;
@@ -223,14 +226,26 @@ void worker_loop(vsp_server* s) {
       }
     }
     if (na) s->rr = (s->rr + 1) % na;
-    // lay the batch out grouped by key set (counting sort on the key index)
+    // lay the batch out grouped by key set (counting sort on the key index); when a key set
+    // other than the context's takes part and the batch size calls for a matrix-core form, each
+    // key set's range starts on a tile boundary (padding entries do nothing) and every tile
+    // names its key set's byte-plane key
     const size_t nk = kset.size();
-    std::vector<uint64_t> start(nk + 1, 0);
-    for (const auto& c : s->cand) start[c.key + 1]++;
-    for (size_t k = 0; k < nk; k++) start[k + 1] += start[k];
+    std::vector<uint64_t> count(nk, 0), start(nk + 1, 0);
+    for (const auto& c : s->cand) count[c.key]++;
+    const bool keyed = nk > 1 || (nk == 1 && kset[0] != nullptr);
+    bool padded = false;
+    if (keyed && s->mf_work) {
+      uint64_t nbp = 0;
+      for (size_t k = 0; k < nk; k++) nbp += (count[k] + MF_TILE - 1) / MF_TILE * MF_TILE;
+      padded = br_matrix_form(s->ctx->tune.br_waves(nbp));
+    }
+    for (size_t k = 0; k < nk; k++)
+      start[k + 1] = start[k] + (padded ? (count[k] + MF_TILE - 1) / MF_TILE * MF_TILE : count[k]);
+    const uint64_t nbl = start[nk];  // launched entries, padding included
     {
+      const uint64_t M = s->cap;
       std::vector<uint64_t> fill(start.begin(), start.end() - 1);
-      const uint64_t M = s->max_batch;
       for (const auto& c : s->cand) {
         const uint64_t i = fill[c.key]++;
         sl.h_ops[i] = c.op;
@@ -239,7 +254,17 @@ void worker_loop(vsp_server* s) {
         sl.h_idx[M + i] = c.i1;
         sl.h_idx[2 * M + i] = c.io;
       }
-      for (size_t k = 0; k < nk; k++) sl.h_keytab[k] = kset[k] ? kset[k]->bkn : s->ctx->bkn;
+      for (size_t k = 0; k < nk; k++) {
+        for (uint64_t i = fill[k]; i < start[k + 1]; i++) {
+          sl.h_ops[i] = OP_SKIP;
+          sl.h_kid[i] = (uint8_t)k;
+          sl.h_idx[i] = sl.h_idx[M + i] = sl.h_idx[2 * M + i] = 0;
+        }
+        sl.h_keytab[k] = kset[k] ? kset[k]->bkn : s->ctx->bkn;
+        if (padded)
+          for (uint64_t t = start[k] / MF_TILE; t < start[k + 1] / MF_TILE; t++)
+            sl.h_tilekeys[t] = kset[k] ? kset[k]->mf_key : s->ctx->mf_key;
+      }
     }
     if (nb == 0) {
       const bool inflight = s->slots[0].busy || s->slots[1].busy;
@@ -257,24 +282,27 @@ void worker_loop(vsp_server* s) {
     s->batches++;
     lk.unlock();
     hipStream_t st = s->st;
-    const uint64_t M = s->max_batch;
-    (void)hipMemcpyAsync(sl.d_ops, sl.h_ops, nb, hipMemcpyHostToDevice, st);
-    (void)hipMemcpyAsync(sl.d_idx, sl.h_idx, nb * 4, hipMemcpyHostToDevice, st);
-    (void)hipMemcpyAsync(sl.d_idx + M, sl.h_idx + M, nb * 4, hipMemcpyHostToDevice, st);
-    (void)hipMemcpyAsync(sl.d_idx + 2 * M, sl.h_idx + 2 * M, nb * 4, hipMemcpyHostToDevice, st);
+    const uint64_t M = s->cap;
+    (void)hipMemcpyAsync(sl.d_ops, sl.h_ops, nbl, hipMemcpyHostToDevice, st);
+    (void)hipMemcpyAsync(sl.d_idx, sl.h_idx, nbl * 4, hipMemcpyHostToDevice, st);
+    (void)hipMemcpyAsync(sl.d_idx + M, sl.h_idx + M, nbl * 4, hipMemcpyHostToDevice, st);
+    (void)hipMemcpyAsync(sl.d_idx + 2 * M, sl.h_idx + 2 * M, nbl * 4, hipMemcpyHostToDevice, st);
     if (nk > 1) {
-      (void)hipMemcpyAsync(sl.d_kid, sl.h_kid, nb, hipMemcpyHostToDevice, st);
+      (void)hipMemcpyAsync(sl.d_kid, sl.h_kid, nbl, hipMemcpyHostToDevice, st);
       (void)hipMemcpyAsync(sl.d_keytab, sl.h_keytab, nk * sizeof(void*), hipMemcpyHostToDevice, st);
     }
+    if (padded)
+      (void)hipMemcpyAsync(sl.d_tilekeys, sl.h_tilekeys, nbl / MF_TILE * sizeof(void*), hipMemcpyHostToDevice, st);
     hipError_t e = launch_gate_prologue(s->ctx, sl.d_ops, s->arena, s->arena, sl.d_idx, sl.d_idx + M, sl.d_idx + 2 * M,
-                                        sl.d_abar, s->arena, nb, st);
+                                        sl.d_abar, s->arena, nbl, st);
     if (e == hipSuccess)
-      e = launch_blind_rotate(s->ctx, sl.d_ops, sl.d_abar, sl.d_tlwe1, nullptr, nb, 0, st, sl.h_keytab[0],
-                              nk > 1 ? sl.d_keytab : nullptr, nk > 1 ? sl.d_kid : nullptr, s->mf_work);
+      e = launch_blind_rotate(s->ctx, sl.d_ops, sl.d_abar, sl.d_tlwe1, nullptr, nbl, 0, st, sl.h_keytab[0],
+                              nk > 1 ? sl.d_keytab : nullptr, nk > 1 ? sl.d_kid : nullptr, s->mf_work, false,
+                              padded ? sl.d_tilekeys : nullptr);
     for (size_t k = 0; k < nk && e == hipSuccess; k++) {
-      const uint64_t a = start[k], n = start[k + 1] - start[k];
-      e = launch_keyswitch(s->ctx, sl.d_ops + a, sl.d_tlwe1 + a * (RING_N + 1), sl.d_idx + 2 * M + a, s->arena, n, st,
-                           -1, kset[k] ? kset[k]->ksk : nullptr);
+      const uint64_t a = start[k];
+      e = launch_keyswitch(s->ctx, sl.d_ops + a, sl.d_tlwe1 + a * (RING_N + 1), sl.d_idx + 2 * M + a, s->arena, count[k],
+                           st, -1, kset[k] ? kset[k]->ksk : nullptr, kset[k] ? kset[k]->ks_mf : nullptr);
     }
     if (e == hipSuccess) e = hipEventRecord(sl.ev, st);
     if (e != hipSuccess) {
@@ -292,10 +320,10 @@ void free_server(vsp_server* s) {
   (void)hipSetDevice(s->ctx->device);
   (void)hipDeviceSynchronize();
   for (auto& sl : s->slots) {
-    for (void* p : {(void*)sl.h_ops, (void*)sl.h_idx, (void*)sl.h_kid, (void*)sl.h_keytab})
+    for (void* p : {(void*)sl.h_ops, (void*)sl.h_idx, (void*)sl.h_kid, (void*)sl.h_keytab, (void*)sl.h_tilekeys})
       if (p) (void)hipHostFree(p);
-    for (void* p : {(void*)sl.d_ops, (void*)sl.d_idx, (void*)sl.d_kid, (void*)sl.d_keytab, (void*)sl.d_abar,
-                    (void*)sl.d_tlwe1})
+    for (void* p : {(void*)sl.d_ops, (void*)sl.d_idx, (void*)sl.d_kid, (void*)sl.d_keytab, (void*)sl.d_tilekeys,
+                    (void*)sl.d_abar, (void*)sl.d_tlwe1})
       if (p) (void)hipFree(p);
     if (sl.ev) (void)hipEventDestroy(sl.ev);
   }
@@ -321,6 +349,7 @@ vsp_status vsp_server_create(vsp_context* ctx, uint64_t mem_budget_bytes, uint64
   s->ctx = ctx;
   s->budget = rows * ROWB;
   s->max_batch = max_batch;
+  s->cap = max_batch + (uint64_t)MF_TILE * kMaxBatchKeys;
   s->arena_rows = rows;
   s->free_rows[0] = rows;
   auto bail = [&](vsp_status st) {
@@ -331,21 +360,24 @@ vsp_status vsp_server_create(vsp_context* ctx, uint64_t mem_budget_bytes, uint64
   if ((e = hipSetDevice(ctx->device)) != hipSuccess) return bail(hip_fail(e, "hipSetDevice"));
   if ((e = hipMalloc(&s->arena, s->budget)) != hipSuccess) return bail(hip_fail(e, "hipMalloc(arena)"));
   if ((e = hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking)) != hipSuccess) return bail(hip_fail(e, "stream"));
+  const uint64_t C = s->cap, tiles = C / MF_TILE + 1;
   for (auto& sl : s->slots) {
-    if ((e = hipHostMalloc(&sl.h_ops, max_batch)) != hipSuccess) return bail(hip_fail(e, "hipHostMalloc"));
-    if ((e = hipHostMalloc(&sl.h_idx, 3 * max_batch * 4)) != hipSuccess) return bail(hip_fail(e, "hipHostMalloc"));
-    if ((e = hipHostMalloc(&sl.h_kid, max_batch)) != hipSuccess) return bail(hip_fail(e, "hipHostMalloc"));
+    if ((e = hipHostMalloc(&sl.h_ops, C)) != hipSuccess) return bail(hip_fail(e, "hipHostMalloc"));
+    if ((e = hipHostMalloc(&sl.h_idx, 3 * C * 4)) != hipSuccess) return bail(hip_fail(e, "hipHostMalloc"));
+    if ((e = hipHostMalloc(&sl.h_kid, C)) != hipSuccess) return bail(hip_fail(e, "hipHostMalloc"));
     if ((e = hipHostMalloc(&sl.h_keytab, kMaxBatchKeys * sizeof(void*))) != hipSuccess)
       return bail(hip_fail(e, "hipHostMalloc"));
-    if ((e = hipMalloc(&sl.d_kid, max_batch)) != hipSuccess) return bail(hip_fail(e, "hipMalloc"));
+    if ((e = hipHostMalloc(&sl.h_tilekeys, tiles * sizeof(void*))) != hipSuccess) return bail(hip_fail(e, "hipHostMalloc"));
+    if ((e = hipMalloc(&sl.d_kid, C)) != hipSuccess) return bail(hip_fail(e, "hipMalloc"));
     if ((e = hipMalloc(&sl.d_keytab, kMaxBatchKeys * sizeof(void*))) != hipSuccess) return bail(hip_fail(e, "hipMalloc"));
-    if ((e = hipMalloc(&sl.d_ops, max_batch)) != hipSuccess) return bail(hip_fail(e, "hipMalloc"));
-    if ((e = hipMalloc(&sl.d_idx, 3 * max_batch * 4)) != hipSuccess) return bail(hip_fail(e, "hipMalloc"));
-    if ((e = hipMalloc(&sl.d_abar, max_batch * ROWB)) != hipSuccess) return bail(hip_fail(e, "hipMalloc"));
-    if ((e = hipMalloc(&sl.d_tlwe1, max_batch * (RING_N + 1) * 4)) != hipSuccess) return bail(hip_fail(e, "hipMalloc"));
+    if ((e = hipMalloc(&sl.d_tilekeys, tiles * sizeof(void*))) != hipSuccess) return bail(hip_fail(e, "hipMalloc"));
+    if ((e = hipMalloc(&sl.d_ops, C)) != hipSuccess) return bail(hip_fail(e, "hipMalloc"));
+    if ((e = hipMalloc(&sl.d_idx, 3 * C * 4)) != hipSuccess) return bail(hip_fail(e, "hipMalloc"));
+    if ((e = hipMalloc(&sl.d_abar, C * ROWB)) != hipSuccess) return bail(hip_fail(e, "hipMalloc"));
+    if ((e = hipMalloc(&sl.d_tlwe1, C * (RING_N + 1) * 4)) != hipSuccess) return bail(hip_fail(e, "hipMalloc"));
     if ((e = hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming)) != hipSuccess) return bail(hip_fail(e, "event"));
   }
-  if (ctx->mf_key && (e = hipMalloc(&s->mf_work, mf_work_bytes(max_batch, true))) != hipSuccess)
+  if (ctx->mf_key && (e = hipMalloc(&s->mf_work, mf_work_bytes(C, true))) != hipSuccess)
     return bail(hip_fail(e, "hipMalloc(matrix-core workspace)"));
   s->worker = std::thread(worker_loop, s);
   *out = s;

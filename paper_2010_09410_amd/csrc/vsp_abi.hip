@@ -440,7 +440,7 @@ vsp_status vsp_keyset_create(vsp_context* ctx, const uint32_t* bk_host, const ui
   VSP_HIP(hipSetDevice(ctx->device));
   auto* k = new vsp_keyset();
   k->ctx = ctx;
-  if ((s = upload_keys(ctx, bk_host, ksk_host, &k->bkn, &k->ksk))) {
+  if ((s = upload_keys(ctx, bk_host, ksk_host, &k->bkn, &k->ksk, &k->mf_key, &k->ks_mf))) {
     delete k;
     return s;
   }
@@ -452,8 +452,8 @@ vsp_status vsp_keyset_destroy(vsp_keyset* k) {
   if (k == nullptr) return VSP_OK;
   (void)hipSetDevice(k->ctx->device);
   (void)hipDeviceSynchronize();
-  if (k->bkn) (void)hipFree(k->bkn);
-  if (k->ksk) (void)hipFree(k->ksk);
+  for (void* p : {(void*)k->bkn, (void*)k->ksk, (void*)k->mf_key, (void*)k->ks_mf})
+    if (p) (void)hipFree(p);
   delete k;
   return VSP_OK;
 }

@@ -24,6 +24,8 @@ constexpr uint64_t kMaxLaunch = 1ull << 22;
 
 // Internal opcode: bootstrap the first input unchanged (refresh of a noisy TLWE).
 constexpr uint8_t OP_IDENT = 16;
+// Internal opcode: a padding entry of a batch (no input read, no output written, no bootstrap).
+constexpr uint8_t OP_SKIP = 17;
 
 __host__ __device__ inline bool op_bootstraps(uint32_t op) { return op < 8 || op == OP_IDENT; }
 
@@ -54,8 +56,8 @@ inline int mf_split_groups(uint64_t B, int cus) {
 constexpr int kTuneBuckets = 7;
 constexpr uint64_t kBucket[kTuneBuckets] = {1, 16, 64, 256, 1024, 2048, 4096};
 // Batch sizes at which the split matrix-core form is timed (its time is interpolated between).
-constexpr int kSplitPts = 11;
-constexpr uint64_t kSplitAt[kSplitPts] = {1, 16, 64, 256, 512, 768, 1024, 1536, 2048, 3072, 4096};
+constexpr int kSplitPts = 13;
+constexpr uint64_t kSplitAt[kSplitPts] = {1, 16, 64, 256, 512, 768, 1024, 1280, 1536, 1792, 2048, 3072, 4096};
 
 // Launch choices, set by vsp_autotune or left at the defaults. Every choice gives
 // bit-identical results.
@@ -77,8 +79,9 @@ struct Tuning {
   // split form, at the sizes kSplitAt: time in the same units as br_round_ms, and row groups
   // (0: the count that fills the chip, mf_split_groups). The defaults are relative times
   // measured on an MI355X (one 4-gate-workgroup round = 1).
-  float split_ms[kSplitPts] = {0.228f, 0.306f, 0.356f, 0.513f, 0.672f, 0.829f, 0.918f, 1.368f, 1.53f, 2.22f, 2.567f};
-  int split_groups[kSplitPts] = {6, 6, 6, 3, 2, 3, 2, 2, 1, 1, 1};
+  float split_ms[kSplitPts] = {0.228f, 0.306f, 0.356f, 0.513f, 0.672f, 0.829f, 0.918f, 1.14f, 1.368f, 1.45f, 1.53f,
+                               2.22f, 2.567f};
+  int split_groups[kSplitPts] = {6, 6, 6, 3, 2, 3, 2, 2, 2, 1, 1, 1, 1};
   int br_force[kTuneBuckets] = {0, 0, 0, 0, 0, 0, 0};
   int ks_form[kTuneBuckets] = {2, 2, 2, 2, 3, 3, 3};
   bool tuned = false;
@@ -155,6 +158,8 @@ struct vsp_keyset {
   vsp_context* ctx = nullptr;
   uint64_t* bkn = nullptr;
   uint32_t* ksk = nullptr;
+  int8_t* mf_key = nullptr;  // byte-plane forms for the matrix-core blind rotation and key switch
+  int8_t* ks_mf = nullptr;
 };
 
 struct vsp_context {
@@ -233,10 +238,14 @@ hipError_t launch_mux_combine(uint32_t* t, uint64_t B, hipStream_t st);
 // keytab[kid[g]] instead (device arrays). The matrix-core forms (waves 32 and 33) need the
 // context's own key and a workspace of mf_work_bytes(B, trlwe == NULL) bytes in mf_work;
 // without them the best NTT form for B runs instead.
+// tile_mfkeys (device, one pointer per tile of MF_TILE gates, NULL for none): the byte-plane
+// key of each tile's key set, for batches whose key-set ranges start on tile boundaries; with
+// it the matrix-core forms also run batches of other key sets.
 hipError_t launch_blind_rotate(const vsp_context* ctx, const uint8_t* ops, const uint32_t* abar, uint32_t* tlwe1,
                                uint32_t* trlwe, uint64_t B, int waves, hipStream_t st, const uint64_t* bkn = nullptr,
                                const uint64_t* const* keytab = nullptr, const uint8_t* kid = nullptr,
-                               void* mf_work = nullptr, bool instrument = false);
+                               void* mf_work = nullptr, bool instrument = false,
+                               const int8_t* const* tile_mfkeys = nullptr);
 // Matrix-core form (blind_rotate_mfma.hip): key bytes, workspace bytes, key conversion from
 // the torus key [n][2l][2][N] on the device, and the launch sequence.
 hipError_t init_mf_kernel_attributes();
@@ -252,18 +261,22 @@ hipError_t launch_keyswitch_mfma(const int8_t* KB, const uint8_t* ops, const uin
 // (tile, output, sub-product); same workspace as the fused form.
 hipError_t launch_blind_rotate_mfsplit(const vsp_context* ctx, const uint8_t* ops, const uint32_t* abar,
                                        uint32_t* tlwe1, uint32_t* trlwe, uint64_t B, void* work, int groups,
-                                       hipStream_t st, bool instrument = false);
+                                       hipStream_t st, bool instrument = false,
+                                       const int8_t* const* tkeys = nullptr);
 // With instrument set (eager calls from the caller's thread only), one event pair of class 3
 // brackets the step launches.
 hipError_t launch_blind_rotate_mfma(const vsp_context* ctx, const uint8_t* ops, const uint32_t* abar, uint32_t* tlwe1,
-                                    uint32_t* trlwe, uint64_t B, void* work, hipStream_t st, bool instrument = false);
+                                    uint32_t* trlwe, uint64_t B, void* work, hipStream_t st, bool instrument = false,
+                                    const int8_t* const* tkeys = nullptr);
 // Identity key switch TLWE1 [B][N+1] -> TLWE0 [B][n+1] (outputs scattered by idxo if given).
 // form: 0 one workgroup per gate, 1 row-stationary tiles, 2 LDS-staged split, 3 matrix cores
 // (the context's own key only; other keys run form 2), -1 the tuned one.
 constexpr int kKsForms = 4;
-// ksk: the key-switching key to use (NULL: the context's).
+// ksk: the key-switching key to use (NULL: the context's); ks_mf: its byte-plane form (needed
+// for form 3 with a key other than the context's).
 hipError_t launch_keyswitch(const vsp_context* ctx, const uint8_t* ops, const uint32_t* tlwe1, const uint32_t* idxo,
-                            uint32_t* out, uint64_t B, hipStream_t st, int form = -1, const uint32_t* ksk = nullptr);
+                            uint32_t* out, uint64_t B, hipStream_t st, int form = -1, const uint32_t* ksk = nullptr,
+                            const int8_t* ks_mf = nullptr);
 // out[j] = C_j (ext) x_j, or with `x0` given: out[j] = x0_j + C_j (ext) (x_j - x0_j).
 hipError_t launch_ext_product(const vsp_context* ctx, const uint64_t* Cn, const uint32_t* x, uint32_t* out,
                               uint64_t J, hipStream_t st);

@@ -165,3 +165,47 @@ def test_served_trace_decrypts_and_matches_oracle(gpu, keys):
             got.append(wires[r["ninputs"] + k])
     ref = oracle.gates(keys["bk"], keys["ksk"], np.array(ops, np.uint8), np.array(a), np.array(b))
     np.testing.assert_array_equal(np.array(got), ref)
+
+
+def test_mixed_key_set_batches_on_the_matrix_cores(gpu, keys):
+    """Two clients with different key sets, each with a wide three-level circuit, served with
+    the matrix-core forms forced for large batches: batches hold both key sets (each key set's
+    range padded to whole 32-gate tiles, every tile naming its key), and every output of client
+    B equals the oracle under B's keys gate by gate (fed the served input wires), while client
+    A's equal the circuit executor."""
+    import oracle
+    from test_gpu_circuit import plaintext_eval
+    s0b, s1b = W.secret_keys(8)
+    bkd, kskd = W.bk_draws(9), W.ksk_draws(10)
+    kb = gpu.keyset(*client.keyset(s0b, s1b, bkd, kskd))
+    ca = W.small_circuit(seed=1200, levels=3, wmin=1100, wmax=1300, ninputs=64)
+    cb = W.small_circuit(seed=1201, levels=3, wmin=1100, wmax=1300, ninputs=64)
+    xa = client.tlwe_encrypt_bits(keys["s0"], ca["bits"], *ca["enc"])
+    xb = client.tlwe_encrypt_bits(s0b, cb["bits"], *cb["enc"])
+    saved = {B: gpu.tuning(B) for B in (1024, 2048, 4096)}
+    try:
+        for B in (1024, 2048, 4096):
+            gpu.set_tuning(B, 33, 3)
+        srv = gpu.server(mem_budget_bytes=256 << 20, max_batch=4096)
+        ta = srv.submit(ca["gates"], ca["ninputs"], xa)
+        tb = srv.submit(cb["gates"], cb["ninputs"], xb, keyset=kb)
+        oa, _ = wait(srv, ta, ca["ninputs"] + len(ca["gates"]))
+        ob, _ = wait(srv, tb, cb["ninputs"] + len(cb["gates"]))
+        gates_launched, batches, _ = srv.stats()
+        srv.close()
+    finally:
+        for B, (w, t) in saved.items():
+            gpu.set_tuning(B, 0, t)
+    assert batches < 6                                     # levels of both clients shared batches
+    np.testing.assert_array_equal(client.tlwe_decrypt(s0b, ob), plaintext_eval(cb["gates"], cb["bits"]))
+    np.testing.assert_array_equal(client.tlwe_decrypt(keys["s0"], oa), plaintext_eval(ca["gates"], ca["bits"]))
+    bk_b, ksk_b = oracle.keyset(s0b, s1b, bkd, kskd)
+    g = cb["gates"]
+    idx = np.unique(np.r_[0, len(g) - 1, W.rng(1202).choice(len(g), 30, replace=False)])
+    ref = oracle.gates(bk_b, ksk_b, g[idx, 0].astype(np.uint8), ob[g[idx, 1]], ob[g[idx, 2]])
+    np.testing.assert_array_equal(ob[cb["ninputs"] + idx], ref)
+    circ = gpu.circuit(ca["gates"], ca["ninputs"])
+    np.testing.assert_array_equal(oa, to_host(circ.run(gpu.tensor(xa))))
+    gpu.sync()
+    circ.close()
+    kb.close()

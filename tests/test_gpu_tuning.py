@@ -99,18 +99,18 @@ def test_autotune_model_and_cache_round_trip(gpu, tmp_path):
             assert gpu.tuning(b)[1] == t
         # the measured entry, read back from the file, picks what the rule says at every size
         gpu.autotune(max_batch=64, cache_path=str(path))
-        for B in (1, 16, 40, 64, 200, 256, 700, 1024, 1500, 2048, 3000, 4096, 5000):
+        for B in (1, 16, 40, 64, 200, 256, 700, 1024, 1200, 1500, 1900, 2048, 3000, 4096, 5000):
             assert gpu.tuning(B)[0] == model_choice(entry, B), B
         # edited entries for this GPU are read back and followed
-        big = [100.0] * 11
-        assert entry["split_at"] == [1, 16, 64, 256, 512, 768, 1024, 1536, 2048, 3072, 4096]
+        big = [100.0] * 13
+        assert entry["split_at"] == [1, 16, 64, 256, 512, 768, 1024, 1280, 1536, 1792, 2048, 3072, 4096]
         for ms, sms, small, large in (([1.0, 100.0, 100.0, 100.0, 100.0], big, 4, 4),
                                       ([100.0, 1.0, 100.0, 100.0, 100.0], big, 8, 8),
                                       ([1.0, 1.5, 100.0, 100.0, 100.0], big, 4, 8),
                                       ([100.0, 100.0, 1.0, 100.0, 100.0], big, 3, 3),
                                       ([100.0, 100.0, 100.0, 1.0, 100.0], big, 32, 32),
-                                      ([100.0, 100.0, 100.0, 100.0, 100.0], [0.001] * 11, 33, 33),
-                                      ([100.0, 1.0, 100.0, 100.0, 100.0], [0.5] * 7 + [1000.0] * 4, None, None)):
+                                      ([100.0, 100.0, 100.0, 100.0, 100.0], [0.001] * 13, 33, 33),
+                                      ([100.0, 1.0, 100.0, 100.0, 100.0], [0.5] * 7 + [1000.0] * 6, None, None)):
             entry["br_round_ms"] = ms
             entry["split_ms"] = sms
             path.write_text(json.dumps({key: entry}))
@@ -167,5 +167,35 @@ def test_profile_sampling(gpu, keys):
         assert nv.vsp_profile_read(gpu.handle, 0)[1] == 0
         with pytest.raises(VspError):
             nv.vsp_profile_enable(gpu.handle, -1)
+    finally:
+        nv.vsp_profile_enable(gpu.handle, 0)
+
+
+def test_profile_ignores_captured_and_server_launches(gpu, keys):
+    """With profiling on, a circuit created (its levels captured into a graph) and run, and a
+    server run on its worker thread, record no events: only eager calls on the caller's thread
+    are instrumented; an eager gate call afterwards is."""
+    from paper_2010_09410_amd import _native as nv
+    c = W.small_circuit(seed=1300, levels=3, wmin=4, wmax=40, ninputs=16)
+    x = client.tlwe_encrypt_bits(keys["s0"], c["bits"], *c["enc"])
+    try:
+        nv.vsp_profile_enable(gpu.handle, 1)
+        circ = gpu.circuit(c["gates"], c["ninputs"])
+        circ.run(gpu.tensor(x))
+        gpu.sync()
+        circ.close()
+        srv = gpu.server(mem_budget_bytes=16 << 20, max_batch=64)
+        t = srv.submit(c["gates"], c["ninputs"], x)
+        import time
+        t0 = time.time()
+        while not srv.poll(t, c["ninputs"] + len(c["gates"]))[0]:
+            assert time.time() - t0 < 120
+            time.sleep(0.005)
+        srv.close()
+        for which in range(4):
+            assert nv.vsp_profile_read(gpu.handle, which)[1] == 0, which
+        cfg, in0, in1 = batch(keys, 8, 7)
+        gpu.gates(gpu.tensor(cfg["ops"]), gpu.tensor(in0), gpu.tensor(in1))
+        assert nv.vsp_profile_read(gpu.handle, 0)[1] == 1
     finally:
         nv.vsp_profile_enable(gpu.handle, 0)
