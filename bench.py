@@ -278,6 +278,65 @@ def memory_run(ctx, s0, s1, reps: int = 3):
                         "2,048 refresh bootstraps"}
 
 
+def circuit_bootstrap_run(ctx, s0, s1, reps: int = 2):
+    """Circuit bootstrapping (TLWE -> TRGSW) of the address bits of 256 ROM reads (9 bits each,
+    2,304 conversions), then the ROM read from those selectors; and one cycle of the clocked
+    netlist's RAM port (v = 8, w = 8): 8 address bits converted, one read, one write."""
+    import torch
+
+    import workloads as W
+    from paper_2010_09410_amd import client
+    t0 = time.perf_counter()
+    bk2, pksk = client.keyset2(s0, s1, W.secret_key2(), W.bk2_draws(), W.pksk_draws())
+    keygen_s = time.perf_counter() - t0
+    key = ctx.cbkey(bk2, pksk)
+    del bk2, pksk
+    wl = W.rom_workload(reads=256)
+    rom = client.trlwe_encrypt_torus(s1, client.pack_rom(wl["words"]), *wl["cells"])
+    bits = (wl["addr"][:, None] >> np.arange(9)[None, :]) & 1
+    tl = client.tlwe_encrypt_bits(s0, bits.reshape(-1), *W.tlwe_draws(W.rng(44), bits.size))
+    d_rom, d_tl = ctx.tensor(rom), ctx.tensor(tl)
+    st = torch.cuda.current_stream(ctx.device)
+
+    def timed(fn):
+        fn()
+        ms = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            fn()
+            e1.record(st)
+            e1.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        return float(np.median(ms))
+
+    sel = ctx.empty(bits.size, 6, 2, 1024)
+    cb_ms = timed(lambda: key.bootstrap(d_tl, out=sel))
+    one_ms = timed(lambda: key.bootstrap(d_tl[:1], out=sel[:1]))
+    rom_ms = timed(lambda: ctx.rom_read(d_rom, sel.reshape(256, 9, 6, 2, 1024), 9, 32))
+    tl8 = ctx.tensor(client.tlwe_encrypt_bits(s0, bits[0, :8], *W.tlwe_draws(W.rng(45), 8)))
+    rw = W.ram_workload(v=8, w=8, reads=1, flag=1)
+    d_ram = ctx.tensor(client.trlwe_encrypt_torus(s1, client.ram_cell_messages(rw["contents"]), *rw["cells"]))
+    flag = ctx.tensor(client.tlwe_encrypt_bits(s0, [1], *rw["fenc"])[0])
+    data = ctx.tensor(client.tlwe_encrypt_bits(s0, rw["wdata"], *rw["denc"]))
+    rsel = ctx.empty(8, 6, 2, 1024)
+
+    def ram_cycle():
+        key.bootstrap(tl8, out=rsel)
+        ctx.ram_read(d_ram, rsel.reshape(1, 8, 6, 2, 1024))
+        ctx.ram_write(d_ram, rsel, flag, data)
+    cyc_ms = timed(ram_cycle)
+    ctx.sync()
+    key.close()
+    return {"conversions": int(bits.size), "batch_ms": round(cb_ms, 2),
+            "per_s": round(bits.size / (cb_ms / 1e3), 1), "single_ms": round(one_ms, 2),
+            "rom_256_reads_from_tlwe_addresses_ms": round(cb_ms + rom_ms, 2),
+            "ram_port_cycle_ms": round(cyc_ms, 2), "client_keygen_s": round(keygen_s, 1),
+            "params": "level 2: N2 = 2048, l2 = 4, Bg2 = 2^9 on the 2^64 torus; private key switch t = 12, base 4",
+            "workload": "address bits of 256 ROM reads (512 x 32-bit words, 9-bit addresses) as fresh TLWE; RAM "
+                        "port cycle v = 8, w = 8: 8 conversions, one read, one write"}
+
+
 def machine_run(ctx, s0, cycles: int = 3):
     """Clock cycles of a synthetic clocked netlist of a small processor's size (2,422 gates in
     32 levels, 256 flip-flops), one HIP graph replay per cycle, timed with events."""
@@ -513,6 +572,9 @@ def main():
     machine = None
     if not args.no_machine:
         machine = machine_run(ctx, s0)
+    cbs = None
+    if not args.no_memory:
+        cbs = circuit_bootstrap_run(ctx, s0, s1)
 
     serving = None
     if args.serving > 0:
@@ -585,7 +647,7 @@ def main():
         "batched_over_per_gate": None if per_gate is None else round(value / per_gate, 1),
         "per_gate_key_stream": per_gate_key, "ntt_form_4096": ntt_form,
         "mux_per_s": None if mux_rate is None else round(mux_rate, 1),
-        "per_level": levels, "clocked_netlist": machine, "cmux_memory": memory, "serving": serving, "roofline": roof, "cpu_baseline": cpu,
+        "per_level": levels, "clocked_netlist": machine, "cmux_memory": memory, "circuit_bootstrapping": cbs, "serving": serving, "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
 
