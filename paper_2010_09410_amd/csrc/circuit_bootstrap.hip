@@ -104,6 +104,7 @@ constexpr size_t CB_LDS_DIG = (size_t)4 * 32 * 64 * 8;         // 64 KiB (also t
 constexpr size_t CB_LDS_TW = (size_t)2048 * 8;                 // 16 KiB
 constexpr size_t CB_LDS_T = (size_t)4 * WAVE_T_U32 * 4;        // transpose regions
 constexpr size_t CB_LDS = CB_LDS_ACC + CB_LDS_DIG + CB_LDS_TW + CB_LDS_T;
+constexpr int CB_KCH = 8;  // key slots per chunk of the streamed key
 
 __global__ __launch_bounds__(CB_THREADS) void k_cb_rotate(const u64* __restrict__ key, const u64* __restrict__ tw,
                                                            const u32* __restrict__ in, u64* __restrict__ out,
@@ -156,15 +157,37 @@ __global__ __launch_bounds__(CB_THREADS) void k_cb_rotate(const u64* __restrict_
         for (int s = 0; s < 32; s++) dig[((size_t)wave * 32 + s) * 64 + lane] = x[s];
       }
       __syncthreads();
+      // key entries stream in chunks of CB_KCH slots, the next chunk (of this row or the
+      // next) in flight while the current one is used
+      auto key_row = [&](int r) {
+        return reinterpret_cast<const ulonglong2*>(kstep + ((((size_t)(h * CB_L2 + r)) * 2 + o) * 2 + wd) *
+                                                               CB_KEY_BLOCK) + lane;
+      };
+      ulonglong2 kc[CB_KCH];
+      {
+        const ulonglong2* kb = key_row(0);
+#pragma unroll
+        for (int q = 0; q < CB_KCH; q++) kc[q] = kb[q * 64];
+      }
 #pragma unroll 1
       for (int r = 0; r < CB_L2; r++) {
-        const ulonglong2* kb = reinterpret_cast<const ulonglong2*>(
-                                   kstep + ((((size_t)(h * CB_L2 + r)) * 2 + o) * 2 + wd) * CB_KEY_BLOCK) + lane;
+        const ulonglong2* kb = key_row(r);
+        const ulonglong2* kb_next = key_row(r + 1 < CB_L2 ? r + 1 : r);
         const u64* dr = dig + (size_t)r * 32 * 64;
 #pragma unroll
-        for (int s = 0; s < 32; s++) {
-          const ulonglong2 kk = kb[s * 64];
-          sum[s] = gl_add(sum[s], gl_dot2(dr[s * 64 + l], kk.x, dr[s * 64 + 32 + l], kk.y));
+        for (int c = 0; c < 32 / CB_KCH; c++) {
+          ulonglong2 kn[CB_KCH];
+#pragma unroll
+          for (int q = 0; q < CB_KCH; q++)
+            kn[q] = (c + 1 < 32 / CB_KCH) ? kb[(CB_KCH * (c + 1) + q) * 64] : kb_next[q * 64];
+#pragma unroll
+          for (int q = 0; q < CB_KCH; q++) {
+            const int sl = CB_KCH * c + q;
+            sum[sl] = gl_add(sum[sl], gl_dot2(dr[sl * 64 + l], kc[q].x, dr[sl * 64 + 32 + l], kc[q].y));
+          }
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int q = 0; q < CB_KCH; q++) kc[q] = kn[q];
         }
       }
       __syncthreads();
