@@ -92,33 +92,35 @@ __global__ __launch_bounds__(256) void k_cb_key(const u64* __restrict__ bk2, u64
 }
 
 // Level-2 blind rotation, one workgroup of four waves per job (circuit bootstrap c = job / l,
-// gadget level j = job % l + 1), the accumulator in LDS. Per step, for each ACC polynomial h:
-// wave r forms gadget digit r + 1 of X^abar ACC_h - ACC_h (lanes 0-31 the even coefficients,
-// 32-63 the odd ones) and transforms it; then wave q = 2 o + w accumulates, for output o and
-// key half-word w, sum_r (D_e, D_o) x (entries of its lane). After both polynomials, each
-// wave inverts its sums; the high-word waves pass theirs through LDS and the low-word waves
-// add lo + 2^32 hi to ACC_o. The result is SampleExtract_0 + 1/(2 Bg^j) as a TLWE2.
+// gadget level j = job % l + 1), the accumulator in global memory (L2-resident). Per step, for
+// each ACC polynomial h: wave r forms gadget digit r + 1 of X^abar ACC_h - ACC_h (lanes 0-31 the
+// even coefficients, 32-63 the odd ones) and transforms it into its LDS block; then wave
+// q = 2 o + w accumulates, for output o and key half-word w, sum_r (D_e, D_o) x (entries of its
+// lane). After both polynomials, each wave inverts its sums; the high-word waves pass theirs
+// through their own LDS blocks and the low-word waves add lo + 2^32 hi to ACC_o. A wave's
+// transpose region lies in its own LDS block (used before the block is filled, and after it
+// has been read), so a workgroup takes 80 KiB of LDS and two fit on a compute unit. The
+// result is SampleExtract_0 + 1/(2 Bg^j) as a TLWE2.
 constexpr int CB_THREADS = 256;
-constexpr size_t CB_LDS_ACC = (size_t)2 * CB_N2 * 8;           // 32 KiB
-constexpr size_t CB_LDS_DIG = (size_t)4 * 32 * 64 * 8;         // 64 KiB (also the high-word exchange)
-constexpr size_t CB_LDS_TW = (size_t)2048 * 8;                 // 16 KiB
-constexpr size_t CB_LDS_T = (size_t)4 * WAVE_T_U32 * 4;        // transpose regions
-constexpr size_t CB_LDS = CB_LDS_ACC + CB_LDS_DIG + CB_LDS_TW + CB_LDS_T;
-constexpr int CB_KCH = 8;  // key slots per chunk of the streamed key
+constexpr size_t CB_BLOCK_U64 = (size_t)32 * 64;              // one wave's transformed digits: 16 KiB
+constexpr size_t CB_LDS = (4 * CB_BLOCK_U64 + 2048) * 8;       // digit blocks + twiddle tables: 80 KiB
+static_assert((size_t)WAVE_T_U32 <= 2 * CB_BLOCK_U64 && (size_t)2 * CB_N2 / 2 <= 2 * CB_BLOCK_U64,
+              "transpose region and high-word exchange fit in one block");
+constexpr int CB_KCH = 4;  // key slots per chunk of the streamed key
 
-__global__ __launch_bounds__(CB_THREADS) void k_cb_rotate(const u64* __restrict__ key, const u64* __restrict__ tw,
-                                                           const u32* __restrict__ in, u64* __restrict__ out,
-                                                           int gadget_l, int bgbit) {
+__global__ __launch_bounds__(CB_THREADS, 2) void k_cb_rotate(const u64* __restrict__ key, const u64* __restrict__ tw,
+                                                           const u32* __restrict__ in, u64* __restrict__ accbuf,
+                                                           u64* __restrict__ out, int gadget_l, int bgbit) {
   extern __shared__ u64 cb_lds[];
-  u64* acc = cb_lds;                                           // [2][N2]
-  u64* dig = cb_lds + 2 * CB_N2;                               // [4][32][64]
-  u64* tws = dig + 4 * 32 * 64;                                // forward then inverse tables
-  u32* treg = reinterpret_cast<u32*>(tws + 2048);
+  u64* dig = cb_lds;                                           // [4][32][64]
+  u64* tws = dig + 4 * CB_BLOCK_U64;                           // forward then inverse tables
   const uint64_t job = blockIdx.x;
   const int j = (int)(job % (uint64_t)gadget_l) + 1;
   const u32* c = in + (job / (uint64_t)gadget_l) * TLWE0;
+  u64* acc = accbuf + job * 2 * CB_N2;                         // [2][N2]
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, l = lane & 31, half = lane >> 5;
-  u32* reg = treg + wave * WAVE_T_U32 + half * TREGION;
+  u64* myblock = dig + (size_t)wave * CB_BLOCK_U64;
+  u32* reg = reinterpret_cast<u32*>(myblock) + half * TREGION;
   const u64 tvv = 1ull << (63 - bgbit * j);                    // 1/(2 Bg^j)
   for (int i = tid; i < 2048; i += CB_THREADS) tws[i] = tw[i];
   {
@@ -144,17 +146,23 @@ __global__ __launch_bounds__(CB_THREADS) void k_cb_rotate(const u64* __restrict_
       {
         u64 x[32];
         const int sh = 64 - CB_BG2 * (wave + 1);
+        // the accumulator words come from L2 in four groups of eight coefficients (bounded
+        // registers in flight)
 #pragma unroll
-        for (int t = 0; t < 32; t++) {
-          const int m = 2 * (l + 32 * t) + half;
-          const int src = (m - abar) & (2 * CB_N2 - 1);
-          const u64 r = P[src & (CB_N2 - 1)];
-          const u64 d = ((src & CB_N2) ? (0ull - r) : r) - P[m];
-          x[t] = (u64)((int64_t)(((d + CB_DECOMP_OFFSET) >> sh) & ((1u << CB_BG2) - 1)) - (1 << (CB_BG2 - 1)));
+        for (int t8 = 0; t8 < 32; t8 += 8) {
+#pragma unroll
+          for (int t = t8; t < t8 + 8; t++) {
+            const int m = 2 * (l + 32 * t) + half;
+            const int src = (m - abar) & (2 * CB_N2 - 1);
+            const u64 r = P[src & (CB_N2 - 1)];
+            const u64 d = ((src & CB_N2) ? (0ull - r) : r) - P[m];
+            x[t] = (u64)((int64_t)(((d + CB_DECOMP_OFFSET) >> sh) & ((1u << CB_BG2) - 1)) - (1 << (CB_BG2 - 1)));
+          }
+          __builtin_amdgcn_sched_barrier(0);
         }
         ntt_forward<true>(x, tws, reg, l);
 #pragma unroll
-        for (int s = 0; s < 32; s++) dig[((size_t)wave * 32 + s) * 64 + lane] = x[s];
+        for (int s = 0; s < 32; s++) myblock[(size_t)s * 64 + lane] = x[s];
       }
       __syncthreads();
       // key entries stream in chunks of CB_KCH slots, the next chunk (of this row or the
@@ -173,16 +181,16 @@ __global__ __launch_bounds__(CB_THREADS) void k_cb_rotate(const u64* __restrict_
       for (int r = 0; r < CB_L2; r++) {
         const ulonglong2* kb = key_row(r);
         const ulonglong2* kb_next = key_row(r + 1 < CB_L2 ? r + 1 : r);
-        const u64* dr = dig + (size_t)r * 32 * 64;
+        const u64* dr = dig + (size_t)r * CB_BLOCK_U64;
 #pragma unroll
-        for (int c = 0; c < 32 / CB_KCH; c++) {
+        for (int cc = 0; cc < 32 / CB_KCH; cc++) {
           ulonglong2 kn[CB_KCH];
 #pragma unroll
           for (int q = 0; q < CB_KCH; q++)
-            kn[q] = (c + 1 < 32 / CB_KCH) ? kb[(CB_KCH * (c + 1) + q) * 64] : kb_next[q * 64];
+            kn[q] = (cc + 1 < 32 / CB_KCH) ? kb[(CB_KCH * (cc + 1) + q) * 64] : kb_next[q * 64];
 #pragma unroll
           for (int q = 0; q < CB_KCH; q++) {
-            const int sl = CB_KCH * c + q;
+            const int sl = CB_KCH * cc + q;
             sum[sl] = gl_add(sum[sl], gl_dot2(dr[sl * 64 + l], kc[q].x, dr[sl * 64 + 32 + l], kc[q].y));
           }
           __builtin_amdgcn_sched_barrier(0);
@@ -194,17 +202,19 @@ __global__ __launch_bounds__(CB_THREADS) void k_cb_rotate(const u64* __restrict_
     }
     u64 z[32];
     ntt_inverse_lift64(sum, tws + 1024, reg, l, z);
-    u32* xch = reinterpret_cast<u32*>(dig);  // [2 o][N2]
+    // the high word of output o goes through the LDS block of wave 2 o + 1 (its own)
+    u32* xch = reinterpret_cast<u32*>(dig + (size_t)(2 * o + 1) * CB_BLOCK_U64);
     if (wd == 1) {
 #pragma unroll
-      for (int t = 0; t < 32; t++) xch[o * CB_N2 + 2 * (l + 32 * t) + half] = (u32)z[t];
+      for (int t = 0; t < 32; t++) xch[2 * (l + 32 * t) + half] = (u32)z[t];
     }
     __syncthreads();
     if (wd == 0) {
+      u64* A = acc + o * CB_N2;
 #pragma unroll
       for (int t = 0; t < 32; t++) {
         const int m = 2 * (l + 32 * t) + half;
-        acc[o * CB_N2 + m] += z[t] + ((u64)xch[o * CB_N2 + m] << 32);
+        A[m] += z[t] + ((u64)xch[m] << 32);
       }
     }
     __syncthreads();
@@ -262,6 +272,7 @@ struct vsp_cbkey {
   u64* key = nullptr;   // transformed level-2 bootstrapping key
   u32* pksk = nullptr;  // private key-switching keys
   Scratch tl2;          // TLWE2 outputs of the blind rotations
+  Scratch acc;          // their accumulators [job][2][N2]
 };
 
 extern "C" {
@@ -307,7 +318,7 @@ vsp_status vsp_cbkey_destroy(vsp_cbkey* k) {
   if (k == nullptr) return VSP_OK;
   (void)hipSetDevice(k->ctx->device);
   (void)hipDeviceSynchronize();
-  for (void* p : {(void*)k->key, (void*)k->pksk, k->tl2.ptr})
+  for (void* p : {(void*)k->key, (void*)k->pksk, k->tl2.ptr, k->acc.ptr})
     if (p) (void)hipFree(p);
   delete k;
   return VSP_OK;
@@ -327,10 +338,11 @@ vsp_status vsp_circuit_bootstrap(vsp_context* ctx, vsp_cbkey* key, const uint32_
   if ((s = check_no_overlap(d_out, ob, d_in, ib, "d_out and d_in"))) return s;
   const uint64_t jobs = R * GADGET_L;
   if ((s = scratch_reserve(ctx, key->tl2, jobs * CB_TLWE2 * 8))) return s;
+  if ((s = scratch_reserve(ctx, key->acc, jobs * 2 * CB_N2 * 8))) return s;
   hipStream_t st = static_cast<hipStream_t>(stream);
   u64* tl2 = static_cast<u64*>(key->tl2.ptr);
-  hipLaunchKernelGGL(k_cb_rotate, dim3((unsigned)jobs), dim3(CB_THREADS), CB_LDS, st, key->key, ctx->tw, d_in, tl2,
-                     GADGET_L, BG_BIT);
+  hipLaunchKernelGGL(k_cb_rotate, dim3((unsigned)jobs), dim3(CB_THREADS), CB_LDS, st, key->key, ctx->tw, d_in,
+                     static_cast<u64*>(key->acc.ptr), tl2, GADGET_L, BG_BIT);
   hipLaunchKernelGGL(k_cb_privks, dim3((unsigned)jobs, 2), dim3(256), 0, st, key->pksk, tl2, d_out, GADGET_L);
   VSP_HIP(hipGetLastError());
   return VSP_OK;
