@@ -493,40 +493,13 @@ __global__ __launch_bounds__(MFP_THREADS, 3) void k_mf_part(const int8_t* __rest
 #pragma unroll
     for (int c = 0; c < 4; c++) dst[c * MF_COPY_U32 + tid] = __builtin_amdgcn_alignbyte(d1, d0, c);
   };
-  if (tid < 2 * 4 * 4) {  // the tails of all copies of both buffers
-    const int bufi = tid >> 4, rest = tid & 15;
-    ebuf[bufi][(rest >> 2) * MF_COPY_U32 + MF_S / 4 + (rest & 3)] = 0u;
-  }
-  {
-    const uint4* as = a_row(0);
-    const uint4 x0 = as[0], x1 = as[MFP_THREADS], x2 = as[2 * MFP_THREADS], x3 = as[3 * MFP_THREADS];
-    const u32* er = e_row(0);
-    const u32 d0 = er[tid], d1 = (tid + 1 < MF_S / 4) ? er[tid + 1] : 0u;
-    abuf[0][tid] = x0;
-    abuf[0][tid + MFP_THREADS] = x1;
-    abuf[0][tid + 2 * MFP_THREADS] = x2;
-    abuf[0][tid + 3 * MFP_THREADS] = x3;
-    stage_e(ebuf[0], d0, d1);
-  }
-  __syncthreads();
   v16i c[4];
 #pragma unroll
   for (int nb = 0; nb < 4; nb++)
 #pragma unroll
     for (int x = 0; x < 16; x++) c[nb][x] = 0;
-  for (int pass = 0; pass < passes; pass++) {
-    const int buf = pass & 1;
-    const int nx = (pass + 1 < passes) ? pass + 1 : pass;  // the last pass fetches itself again, unused
-    const uint4* as = a_row(nx);
-    const uint4 p0 = as[0], p1 = as[MFP_THREADS], p2 = as[2 * MFP_THREADS], p3 = as[3 * MFP_THREADS];
-    u32 pd0, pd1;
-    {
-      const u32* er = e_row(nx);
-      pd0 = er[tid];
-      pd1 = (tid + 1 < MF_S / 4) ? er[tid + 1] : 0u;
-    }
-    const uint4* Ar = abuf[buf] + lane;
-    const u32* Bp = ebuf[buf] + bofs;
+  // one pass: the 16 input blocks of this wave's four output blocks
+  auto run_pass = [&](const uint4* Ar, const u32* Bp) {
     auto ldb = [&](int wofs) {
       return v4i{(int)Bp[wofs], (int)Bp[wofs + 1], (int)Bp[wofs + 2], (int)Bp[wofs + 3]};
     };
@@ -551,21 +524,85 @@ __global__ __launch_bounds__(MFP_THREADS, 3) void k_mf_part(const int8_t* __rest
         __builtin_amdgcn_sched_barrier(0);
       }
     }
-    if (pass % rows == rows - 1 && pass + 1 < passes) {
+  };
+  auto horner_shift = [&]() {
 #pragma unroll
-      for (int nb = 0; nb < 4; nb++)
+    for (int nb = 0; nb < 4; nb++)
 #pragma unroll
-        for (int x = 0; x < 16; x++) c[nb][x] = (int)((u32)c[nb][x] << 8);
+      for (int x = 0; x < 16; x++) c[nb][x] = (int)((u32)c[nb][x] << 8);
+  };
+  if (rows == 1) {
+    // one TRGSW row: its operands serve all four planes, so they and the four planes' key
+    // sequences are staged once (planes 3 and 2 in ebuf, 1 and 0 in the second operand
+    // buffer) and the passes run without further loads or barriers
+    auto kbuf = [&](int p) -> u32* {
+      return p < 2 ? ebuf[p] : reinterpret_cast<u32*>(abuf[1]) + (p - 2) * 4 * MF_COPY_U32;
+    };
+    if (tid < MF_PLANES * 4 * 4) {  // the tails of all copies of the four key buffers
+      const int bufi = tid >> 4, rest = tid & 15;
+      kbuf(bufi)[(rest >> 2) * MF_COPY_U32 + MF_S / 4 + (rest & 3)] = 0u;
     }
-    if (pass + 1 < passes) {
-      uint4* ad = abuf[buf ^ 1] + tid;
-      ad[0] = p0;
-      ad[MFP_THREADS] = p1;
-      ad[2 * MFP_THREADS] = p2;
-      ad[3 * MFP_THREADS] = p3;
-      stage_e(ebuf[buf ^ 1], pd0, pd1);
+    const uint4* as = a_row(0);
+    const uint4 x0 = as[0], x1 = as[MFP_THREADS], x2 = as[2 * MFP_THREADS], x3 = as[3 * MFP_THREADS];
+    u32 d0[MF_PLANES], d1[MF_PLANES];
+#pragma unroll
+    for (int p = 0; p < MF_PLANES; p++) {
+      const u32* er = e_row(p);
+      d0[p] = er[tid];
+      d1[p] = (tid + 1 < MF_S / 4) ? er[tid + 1] : 0u;
+    }
+    abuf[0][tid] = x0;
+    abuf[0][tid + MFP_THREADS] = x1;
+    abuf[0][tid + 2 * MFP_THREADS] = x2;
+    abuf[0][tid + 3 * MFP_THREADS] = x3;
+#pragma unroll
+    for (int p = 0; p < MF_PLANES; p++) stage_e(kbuf(p), d0[p], d1[p]);
+    __syncthreads();
+#pragma unroll 1
+    for (int pass = 0; pass < MF_PLANES; pass++) {
+      run_pass(abuf[0] + lane, kbuf(pass) + bofs);
+      if (pass + 1 < MF_PLANES) horner_shift();
+    }
+  } else {
+    if (tid < 2 * 4 * 4) {  // the tails of all copies of both buffers
+      const int bufi = tid >> 4, rest = tid & 15;
+      ebuf[bufi][(rest >> 2) * MF_COPY_U32 + MF_S / 4 + (rest & 3)] = 0u;
+    }
+    {
+      const uint4* as = a_row(0);
+      const uint4 x0 = as[0], x1 = as[MFP_THREADS], x2 = as[2 * MFP_THREADS], x3 = as[3 * MFP_THREADS];
+      const u32* er = e_row(0);
+      const u32 d0 = er[tid], d1 = (tid + 1 < MF_S / 4) ? er[tid + 1] : 0u;
+      abuf[0][tid] = x0;
+      abuf[0][tid + MFP_THREADS] = x1;
+      abuf[0][tid + 2 * MFP_THREADS] = x2;
+      abuf[0][tid + 3 * MFP_THREADS] = x3;
+      stage_e(ebuf[0], d0, d1);
     }
     __syncthreads();
+    for (int pass = 0; pass < passes; pass++) {
+      const int buf = pass & 1;
+      const int nx = (pass + 1 < passes) ? pass + 1 : pass;  // the last pass fetches itself again, unused
+      const uint4* as = a_row(nx);
+      const uint4 p0 = as[0], p1 = as[MFP_THREADS], p2 = as[2 * MFP_THREADS], p3 = as[3 * MFP_THREADS];
+      u32 pd0, pd1;
+      {
+        const u32* er = e_row(nx);
+        pd0 = er[tid];
+        pd1 = (tid + 1 < MF_S / 4) ? er[tid + 1] : 0u;
+      }
+      run_pass(abuf[buf] + lane, ebuf[buf] + bofs);
+      if (pass % rows == rows - 1 && pass + 1 < passes) horner_shift();
+      if (pass + 1 < passes) {
+        uint4* ad = abuf[buf ^ 1] + tid;
+        ad[0] = p0;
+        ad[MFP_THREADS] = p1;
+        ad[2 * MFP_THREADS] = p2;
+        ad[3 * MFP_THREADS] = p3;
+        stage_e(ebuf[buf ^ 1], pd0, pd1);
+      }
+      __syncthreads();
+    }
   }
   // gates of the tile that bootstrap: bit m of `live` (lanes 0..31 test gate m = lane)
   bool mine = false;
