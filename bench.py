@@ -190,6 +190,8 @@ def parse():
                          "throughput (0 skips it)")
     ap.add_argument("--no-ntt-form", action="store_true",
                     help="skip timing the 4096-gate batch in the NTT form when the tuning picks the matrix form")
+    ap.add_argument("--no-key-reuse", action="store_true",
+                    help="skip the 4096-gate NTT-form batch without key reuse (one key copy per resident gate)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run one plain device copy of MIB MiB (reference for HBM byte counters)")
     return ap.parse_args()
@@ -505,6 +507,31 @@ def main():
                             "measured_bytes_per_launch": ntraffic, "traffic_source": nsrc,
                             "measured_GBps": None if ntraffic is None else round(ntraffic / (navg * 1e-3) / 1e9, 1)}}
 
+    # What key reuse contributes: the same batch in the eight-wave NTT form with one shared key,
+    # then with gate g reading its own device copy g mod C, C = the gates the form holds at once
+    # (eight per CU), so that no resident gate shares key bytes with another; and one gate alone
+    # in the three-wave latency form (occupancy: one workgroup on the chip).
+    key_reuse = None
+    if not args.no_key_reuse:
+        resident = 8 * torch.cuda.get_device_properties(ctx.device).multi_processor_count
+        kr = {"form": "k_blind_rotate<8>", "gates": B_GATES, "key_bytes_per_gate": BK_NTT_BYTES}
+        for name, copies in (("shared", 1), ("unshared", resident)):
+            ctx.gates_key_copies(ops_d[:16], a_d[:16], b_d[:16], waves=8, copies=1)
+            _, ms = ctx.gates_key_copies(ops_d, a_d, b_d, waves=8, copies=copies, out=out)
+            kb = B_GATES * BK_NTT_BYTES if copies > 1 else BK_NTT_BYTES
+            kr[name] = {"copies": copies, "blind_rotation_ms": round(ms, 3),
+                        "gates_per_s": round(B_GATES / (ms * 1e-3), 1),
+                        "key_bytes_requested": kb, "key_GBps": round(kb / (ms * 1e-3) / 1e9, 1),
+                        "key_frac_of_hbm": round(kb / (ms * 1e-3) / HBM_PEAK, 4)}
+        _, one = ctx.gates_key_copies(ops_d[:1], a_d[:1], b_d[:1], waves=3, copies=1)
+        kr["one_gate"] = {"form": "k_blind_rotate_wide", "blind_rotation_ms": round(one, 3),
+                          "gates_per_s": round(1e3 / one, 2),
+                          "key_GBps": round(BK_NTT_BYTES / (one * 1e-3) / 1e9, 2)}
+        kr["occupancy_gain"] = round(kr["unshared"]["gates_per_s"] / kr["one_gate"]["gates_per_s"], 1)
+        kr["reuse_gain"] = round(kr["shared"]["gates_per_s"] / kr["unshared"]["gates_per_s"], 3)
+        key_reuse = kr
+        torch.cuda.synchronize()
+
     # per-gate mode: one launch sequence per gate, each streaming the whole key
     per_gate = None
     pg = args.per_gate
@@ -589,9 +616,13 @@ def main():
 
     per_gate_key = None
     if per_gate is not None:
-        # each gate of the per-gate path streams the whole NTT-domain key once
-        per_gate_key = {"GBps": round(per_gate * BK_NTT_BYTES / 1e9, 2),
-                        "frac_of_hbm": round(per_gate * BK_NTT_BYTES / HBM_PEAK, 6), "gates_timed": pg}
+        # each gate of the per-gate path streams the whole key of its form once: the byte-plane
+        # key in the matrix-core forms, the NTT-domain key otherwise
+        pg_form = ctx.tuning(1)[0]
+        pg_bytes = N_LWE * MF_KEY_STEP_BYTES if pg_form in (32, 33) else BK_NTT_BYTES
+        per_gate_key = {"GBps": round(per_gate * pg_bytes / 1e9, 2),
+                        "frac_of_hbm": round(per_gate * pg_bytes / HBM_PEAK, 6), "gates_timed": pg,
+                        "form": pg_form, "key_bytes_per_gate": pg_bytes}
     br_avg_ms = br_ms / max(br_n, 1)
     launch = {"br_shape": br_waves, "keyswitch": ["gather", "tiled", "split", "matrix"][ks_form], "autotune": tune}
     if br_waves == 32:
@@ -645,7 +676,7 @@ def main():
                    "batch": B_GATES, "parallelism": "single GPU"},
         "per_gate_value": None if per_gate is None else round(per_gate, 2),
         "batched_over_per_gate": None if per_gate is None else round(value / per_gate, 1),
-        "per_gate_key_stream": per_gate_key, "ntt_form_4096": ntt_form,
+        "per_gate_key_stream": per_gate_key, "ntt_form_4096": ntt_form, "key_reuse": key_reuse,
         "mux_per_s": None if mux_rate is None else round(mux_rate, 1),
         "per_level": levels, "clocked_netlist": machine, "cmux_memory": memory, "circuit_bootstrapping": cbs, "serving": serving, "roofline": roof, "cpu_baseline": cpu,
     }

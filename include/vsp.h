@@ -122,6 +122,22 @@ vsp_status vsp_gates(vsp_context* ctx, const uint8_t* d_ops, const uint32_t* d_i
 vsp_status vsp_gates_noalloc(vsp_context* ctx, const uint8_t* d_ops, const uint32_t* d_in0, const uint32_t* d_in1,
                              uint32_t* d_out, uint64_t B, int mode, void* stream);
 
+/* Gate bootstrapping with the bootstrapping key read from per-gate copies: the measurement of
+ * what key reuse contributes to the batched path. The paper's gate evaluation engine hands
+ * each gate to a worker as a task of its own (Sec. 6.2(d), list scheduling), so every gate's
+ * bootstrap makes its own pass over the key; a batch here shares one pass among all its gates
+ * (Sec. 2.3: gates of one level are independent). Same results as vsp_gates in batched mode, bit for bit, with
+ * the blind rotation in the NTT form `waves` (3, 4 or 8) and gate g reading device copy
+ * g mod `copies` of the converted key: once `copies` reaches the number of gates the form
+ * holds at once, no two resident gates read the same key bytes and nothing of the key is
+ * reused through the caches; copies = 1 is the ordinary shared key. 1 <= copies <= 65536,
+ * B <= 2^22; *br_ms receives the blind rotation's time (HIP events on `stream`). Allocates
+ * copies x 61.9 MB (copies > 1) for the duration of the call (VSP_E_NOMEM when the device
+ * lacks it, nothing enqueued) and returns only after the stream has drained. */
+vsp_status vsp_gates_key_copies(vsp_context* ctx, const uint8_t* d_ops, const uint32_t* d_in0, const uint32_t* d_in1,
+                                uint32_t* d_out, uint64_t B, int waves, uint32_t copies, void* stream,
+                                double* br_ms);
+
 /* Bootstrapping that returns a TRLWE (Sec. 2.1.2 "Bootstrapping in TFHE", without SE and
  * IKS): d_out[g] [2][N] is the blind-rotation accumulator of op_g(in0, in1) with the test
  * vector mu in every coefficient (constant coefficient encodes the gate's output bit).

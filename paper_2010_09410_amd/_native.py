@@ -51,6 +51,8 @@ SIGNATURES = {
     "vsp_context_sync": (_st, [_vp]),
     "vsp_gates": (_st, [_vp, _vp, _vp, _vp, _vp, _u64, _i32, _vp]),
     "vsp_gates_noalloc": (_st, [_vp, _vp, _vp, _vp, _vp, _u64, _i32, _vp]),
+    "vsp_gates_key_copies": (_st, [_vp, _vp, _vp, _vp, _vp, _u64, _i32, ctypes.c_uint32, _vp,
+                                   ctypes.POINTER(ctypes.c_double)]),
     "vsp_bootstrap_trlwe": (_st, [_vp, _vp, _vp, _vp, _vp, _u64, _vp]),
     "vsp_circuit_create": (_st, [_vp, ctypes.POINTER(vsp_gate_desc), _u64, _u64, ctypes.POINTER(_vp)]),
     "vsp_circuit_run": (_st, [_vp, _vp, _vp, _vp]),
@@ -137,6 +139,13 @@ def vsp_gates(ctx, d_ops, d_in0, d_in1, d_out, B, mode=VSP_BATCHED, stream=None)
 
 def vsp_gates_noalloc(ctx, d_ops, d_in0, d_in1, d_out, B, mode=VSP_BATCHED, stream=None) -> None:
     _call("vsp_gates_noalloc", ctx, d_ops, d_in0, d_in1, d_out, B, mode, stream)
+
+
+def vsp_gates_key_copies(ctx, d_ops, d_in0, d_in1, d_out, B, waves, copies, stream=None) -> float:
+    """Blind-rotation milliseconds of a batch whose gate g reads key copy g mod copies."""
+    ms = ctypes.c_double()
+    _call("vsp_gates_key_copies", ctx, d_ops, d_in0, d_in1, d_out, B, waves, copies, stream, ctypes.byref(ms))
+    return ms.value
 
 
 def vsp_bootstrap_trlwe(ctx, d_ops, d_in0, d_in1, d_out, B, stream=None) -> None:

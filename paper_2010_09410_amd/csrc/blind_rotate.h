@@ -24,7 +24,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_blind_rotate(const u64* __restri
                                                              const u32* __restrict__ abar, u32* __restrict__ tlwe1,
                                                              u32* __restrict__ trlwe, uint64_t B,
                                                              const u64* const* __restrict__ keytab,
-                                                             const uint8_t* __restrict__ kid) {
+                                                             const uint16_t* __restrict__ kid) {
   extern __shared__ u64 lds[];
   u64* tws = lds;
   for (int i = threadIdx.x; i < 2048; i += WAVES * 64) tws[i] = tw[i];

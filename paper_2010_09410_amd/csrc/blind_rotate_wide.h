@@ -60,7 +60,7 @@ __global__ __launch_bounds__(BRW_WAVES * 64) void k_blind_rotate_wide(const u64*
                                                                       const u32* __restrict__ abar,
                                                                       u32* __restrict__ tlwe1, u32* __restrict__ trlwe,
                                                                       uint64_t B, const u64* const* __restrict__ keytab,
-                                                                      const uint8_t* __restrict__ kid) {
+                                                                      const uint16_t* __restrict__ kid) {
   extern __shared__ u64 lds[];
   u64* tws = lds;
   for (int i = threadIdx.x; i < 2048; i += BRW_WAVES * 64) tws[i] = tw[i];

@@ -199,7 +199,7 @@ hipError_t blind_rotate_capacity(int device, uint64_t (&cap)[kBrShapes]) {
 
 hipError_t launch_blind_rotate(const vsp_context* ctx, const uint8_t* ops, const uint32_t* abar, uint32_t* tlwe1,
                                uint32_t* trlwe, uint64_t B, int waves, hipStream_t st, const uint64_t* bkn,
-                               const uint64_t* const* keytab, const uint8_t* kid, void* mf_work, bool instrument,
+                               const uint64_t* const* keytab, const uint16_t* kid, void* mf_work, bool instrument,
                                const int8_t* const* tile_mfkeys) {
   if (B == 0) return hipSuccess;
   if (bkn == nullptr) bkn = ctx->bkn;

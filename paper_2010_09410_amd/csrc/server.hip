@@ -45,11 +45,11 @@ constexpr int kMaxBatchKeys = 64;  // distinct key sets in one batch
 struct Slot {  // one in-flight batch
   uint8_t* h_ops = nullptr;
   uint32_t* h_idx = nullptr;
-  uint8_t* h_kid = nullptr;
+  uint16_t* h_kid = nullptr;
   const uint64_t** h_keytab = nullptr;
   uint8_t* d_ops = nullptr;
   uint32_t* d_idx = nullptr;
-  uint8_t* d_kid = nullptr;
+  uint16_t* d_kid = nullptr;
   const uint64_t** d_keytab = nullptr;
   const int8_t** h_tilekeys = nullptr;  // matrix-core key of each tile of a padded batch
   const int8_t** d_tilekeys = nullptr;
@@ -249,7 +249,7 @@ void worker_loop(vsp_server* s) {
       for (const auto& c : s->cand) {
         const uint64_t i = fill[c.key]++;
         sl.h_ops[i] = c.op;
-        sl.h_kid[i] = c.key;
+        sl.h_kid[i] = (uint16_t)c.key;
         sl.h_idx[i] = c.i0;
         sl.h_idx[M + i] = c.i1;
         sl.h_idx[2 * M + i] = c.io;
@@ -257,7 +257,7 @@ void worker_loop(vsp_server* s) {
       for (size_t k = 0; k < nk; k++) {
         for (uint64_t i = fill[k]; i < start[k + 1]; i++) {
           sl.h_ops[i] = OP_SKIP;
-          sl.h_kid[i] = (uint8_t)k;
+          sl.h_kid[i] = (uint16_t)k;
           sl.h_idx[i] = sl.h_idx[M + i] = sl.h_idx[2 * M + i] = 0;
         }
         sl.h_keytab[k] = kset[k] ? kset[k]->bkn : s->ctx->bkn;
@@ -288,7 +288,7 @@ void worker_loop(vsp_server* s) {
     (void)hipMemcpyAsync(sl.d_idx + M, sl.h_idx + M, nbl * 4, hipMemcpyHostToDevice, st);
     (void)hipMemcpyAsync(sl.d_idx + 2 * M, sl.h_idx + 2 * M, nbl * 4, hipMemcpyHostToDevice, st);
     if (nk > 1) {
-      (void)hipMemcpyAsync(sl.d_kid, sl.h_kid, nbl, hipMemcpyHostToDevice, st);
+      (void)hipMemcpyAsync(sl.d_kid, sl.h_kid, nbl * sizeof(uint16_t), hipMemcpyHostToDevice, st);
       (void)hipMemcpyAsync(sl.d_keytab, sl.h_keytab, nk * sizeof(void*), hipMemcpyHostToDevice, st);
     }
     if (padded)
@@ -364,11 +364,11 @@ vsp_status vsp_server_create(vsp_context* ctx, uint64_t mem_budget_bytes, uint64
   for (auto& sl : s->slots) {
     if ((e = hipHostMalloc(&sl.h_ops, C)) != hipSuccess) return bail(hip_fail(e, "hipHostMalloc"));
     if ((e = hipHostMalloc(&sl.h_idx, 3 * C * 4)) != hipSuccess) return bail(hip_fail(e, "hipHostMalloc"));
-    if ((e = hipHostMalloc(&sl.h_kid, C)) != hipSuccess) return bail(hip_fail(e, "hipHostMalloc"));
+    if ((e = hipHostMalloc(&sl.h_kid, C * sizeof(uint16_t))) != hipSuccess) return bail(hip_fail(e, "hipHostMalloc"));
     if ((e = hipHostMalloc(&sl.h_keytab, kMaxBatchKeys * sizeof(void*))) != hipSuccess)
       return bail(hip_fail(e, "hipHostMalloc"));
     if ((e = hipHostMalloc(&sl.h_tilekeys, tiles * sizeof(void*))) != hipSuccess) return bail(hip_fail(e, "hipHostMalloc"));
-    if ((e = hipMalloc(&sl.d_kid, C)) != hipSuccess) return bail(hip_fail(e, "hipMalloc"));
+    if ((e = hipMalloc(&sl.d_kid, C * sizeof(uint16_t))) != hipSuccess) return bail(hip_fail(e, "hipMalloc"));
     if ((e = hipMalloc(&sl.d_keytab, kMaxBatchKeys * sizeof(void*))) != hipSuccess) return bail(hip_fail(e, "hipMalloc"));
     if ((e = hipMalloc(&sl.d_tilekeys, tiles * sizeof(void*))) != hipSuccess) return bail(hip_fail(e, "hipMalloc"));
     if ((e = hipMalloc(&sl.d_ops, C)) != hipSuccess) return bail(hip_fail(e, "hipMalloc"));

@@ -431,6 +431,79 @@ vsp_status vsp_bootstrap_trlwe(vsp_context* ctx, const uint8_t* d_ops, const uin
   return gates_impl(ctx, d_ops, d_in0, d_in1, d_out, B, VSP_BATCHED, stream, true);
 }
 
+vsp_status vsp_gates_key_copies(vsp_context* ctx, const uint8_t* d_ops, const uint32_t* d_in0, const uint32_t* d_in1,
+                                uint32_t* d_out, uint64_t B, int waves, uint32_t copies, void* stream,
+                                double* br_ms) {
+  vsp_status s = check_ctx(ctx);
+  if (s) return s;
+  if (waves != 3 && waves != 4 && waves != 8) return fail(VSP_E_ARG, "waves must be 3, 4 or 8 (an NTT form)");
+  if (copies == 0 || copies > 65536) return fail(VSP_E_ARG, "copies must be in [1, 65536]");
+  if (br_ms == nullptr) return fail(VSP_E_ARG, "br_ms must be non-NULL");
+  if (B > kMaxLaunch) return fail(VSP_E_ARG, "B above one launch (" + std::to_string(kMaxLaunch) + " gates)");
+  *br_ms = 0;
+  if (B == 0) return VSP_OK;
+  VSP_HIP(hipSetDevice(ctx->device));
+  if ((s = check_gate_args(ctx, d_ops, d_in0, d_in1, d_out, B, VSP_BATCHED, false))) return s;
+  const size_t key_bytes = (size_t)LWE_N * TRGSW_NTT_U64 * 8;
+  const size_t copy_bytes = copies > 1 ? (size_t)copies * key_bytes : 0;
+  size_t free_b = 0, total_b = 0;
+  VSP_HIP(hipMemGetInfo(&free_b, &total_b));
+  if (copy_bytes + (1ull << 30) > free_b)
+    return fail(VSP_E_NOMEM, std::to_string(copies) + " key copies need " + std::to_string(copy_bytes >> 20) +
+                                 " MiB; " + std::to_string(free_b >> 20) + " MiB free on the device");
+  if ((s = scratch_reserve(ctx, ctx->abar, B * (LWE_N + 1) * 4))) return s;
+  if ((s = scratch_reserve(ctx, ctx->tlwe1, B * (RING_N + 1) * 4))) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  uint64_t* keys = nullptr;
+  const uint64_t** d_tab = nullptr;
+  uint16_t* d_kid = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto undo = [&](vsp_status r) {
+    if (st) (void)hipStreamSynchronize(st);
+    else (void)hipDeviceSynchronize();
+    for (void* p : {(void*)keys, (void*)d_tab, (void*)d_kid})
+      if (p) (void)hipFree(p);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    return r;
+  };
+  hipError_t e;
+  std::vector<const uint64_t*> tab(copies, ctx->bkn);
+  if (copies > 1) {
+    if ((e = hipMalloc(&keys, copy_bytes)) != hipSuccess) return undo(hip_fail(e, "hipMalloc(key copies)"));
+    for (uint32_t c = 0; c < copies; c++) {
+      tab[c] = keys + (size_t)c * LWE_N * TRGSW_NTT_U64;
+      if ((e = hipMemcpyAsync(keys + (size_t)c * LWE_N * TRGSW_NTT_U64, ctx->bkn, key_bytes, hipMemcpyDeviceToDevice,
+                              st)) != hipSuccess)
+        return undo(hip_fail(e, "key copy"));
+    }
+  }
+  std::vector<uint16_t> kid(B);
+  for (uint64_t g = 0; g < B; g++) kid[g] = (uint16_t)(g % copies);
+  if ((e = hipMalloc(&d_tab, copies * sizeof(void*))) != hipSuccess) return undo(hip_fail(e, "hipMalloc(key table)"));
+  if ((e = hipMalloc(&d_kid, B * sizeof(uint16_t))) != hipSuccess) return undo(hip_fail(e, "hipMalloc(key index)"));
+  if ((e = hipMemcpyAsync(d_tab, tab.data(), copies * sizeof(void*), hipMemcpyHostToDevice, st)) != hipSuccess ||
+      (e = hipMemcpyAsync(d_kid, kid.data(), B * sizeof(uint16_t), hipMemcpyHostToDevice, st)) != hipSuccess)
+    return undo(hip_fail(e, "key table upload"));
+  if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess)
+    return undo(hip_fail(e, "hipEventCreate"));
+  uint32_t* abar = static_cast<uint32_t*>(ctx->abar.ptr);
+  uint32_t* t1 = static_cast<uint32_t*>(ctx->tlwe1.ptr);
+  if ((e = launch_gate_prologue(ctx, d_ops, d_in0, d_in1, nullptr, nullptr, nullptr, abar, d_out, B, st)) !=
+      hipSuccess)
+    return undo(hip_fail(e, "gate prologue"));
+  (void)hipEventRecord(e0, st);
+  e = launch_blind_rotate(ctx, d_ops, abar, t1, nullptr, B, waves, st, nullptr, d_tab, d_kid);
+  (void)hipEventRecord(e1, st);
+  if (e != hipSuccess) return undo(hip_fail(e, "blind rotation"));
+  if ((e = launch_keyswitch(ctx, d_ops, t1, nullptr, d_out, B, st)) != hipSuccess) return undo(hip_fail(e, "key switch"));
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return undo(hip_fail(e, "hipStreamSynchronize"));
+  float ms = 0;
+  if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) return undo(hip_fail(e, "hipEventElapsedTime"));
+  *br_ms = ms;
+  return undo(VSP_OK);
+}
+
 vsp_status vsp_keyset_create(vsp_context* ctx, const uint32_t* bk_host, const uint32_t* ksk_host, vsp_keyset** out) {
   if (out == nullptr) return fail(VSP_E_ARG, "out is NULL");
   *out = nullptr;

@@ -246,7 +246,7 @@ hipError_t launch_mux_combine(uint32_t* t, uint64_t B, hipStream_t st);
 // it the matrix-core forms also run batches of other key sets.
 hipError_t launch_blind_rotate(const vsp_context* ctx, const uint8_t* ops, const uint32_t* abar, uint32_t* tlwe1,
                                uint32_t* trlwe, uint64_t B, int waves, hipStream_t st, const uint64_t* bkn = nullptr,
-                               const uint64_t* const* keytab = nullptr, const uint8_t* kid = nullptr,
+                               const uint64_t* const* keytab = nullptr, const uint16_t* kid = nullptr,
                                void* mf_work = nullptr, bool instrument = false,
                                const int8_t* const* tile_mfkeys = nullptr);
 // Matrix-core form (blind_rotate_mfma.hip): key bytes, workspace bytes, key conversion from

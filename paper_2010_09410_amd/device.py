@@ -73,6 +73,15 @@ class Context:
         nv.vsp_gates(self.handle, _ptr(ops), _ptr(in0), _ptr(in1), _ptr(out), B, mode, self.stream())
         return out
 
+    def gates_key_copies(self, ops, in0, in1, waves: int, copies: int, out=None):
+        """(outputs, blind-rotation ms) of gates whose gate g reads its own key copy g mod copies."""
+        B = ops.numel()
+        if out is None:
+            out = self.empty(B, self.N_LWE + 1)
+        ms = nv.vsp_gates_key_copies(self.handle, _ptr(ops), _ptr(in0), _ptr(in1), _ptr(out), B, waves, copies,
+                                     self.stream())
+        return out, ms
+
     def mux(self, sel: torch.Tensor, in1: torch.Tensor, in0: torch.Tensor, out=None) -> torch.Tensor:
         """Encrypted sel ? in1 : in0, row by row."""
         B = sel.shape[0]

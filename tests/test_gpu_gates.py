@@ -105,6 +105,25 @@ def test_per_gate_mode_equals_batched(gpu, keys):
     np.testing.assert_array_equal(o_b, oracle.gates(keys["bk"], keys["ksk"], ops, in0, in1))
 
 
+def test_key_copies_equal_oracle(gpu, keys):
+    """Gates whose gate g reads its own device copy g mod c of the bootstrapping key (a batch
+    without key reuse): the same bits as the oracle in every NTT form and for several copy
+    counts (one per gate, fewer, one), with NOT gates and a ragged batch; bad forms and copy
+    counts are refused."""
+    from paper_2010_09410_amd import _native as nv
+    ops, A, Bb, in0, in1 = truth_table_inputs(keys, 505)
+    ref = oracle.gates(keys["bk"], keys["ksk"], ops, in0, in1)
+    d = [dev(gpu, x) for x in (ops, in0, in1)]
+    for waves, copies in ((8, 1), (8, ops.size), (4, 5), (3, ops.size), (8, 7)):
+        out, ms = gpu.gates_key_copies(*d, waves=waves, copies=copies)
+        assert ms > 0
+        np.testing.assert_array_equal(to_host(out), ref, err_msg=f"waves={waves} copies={copies}")
+    for waves, copies in ((32, 1), (8, 0), (8, 65537)):
+        with pytest.raises(VspError) as ei:
+            gpu.gates_key_copies(*d, waves=waves, copies=copies)
+        assert ei.value.status == nv.VSP_E_ARG
+
+
 def test_trivial_inputs_exact_closed_form(gpu):
     ops, A, Bb = [], [], []
     for op in ALL_OPS[:8]:
