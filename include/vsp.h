@@ -304,6 +304,15 @@ vsp_status vsp_tuning_get(const vsp_context* ctx, uint64_t B, int* br_waves, int
  * bucket to the round-time model), ks_form 0, 1, 2 or 3. Results are the same for every choice. */
 vsp_status vsp_tuning_set(vsp_context* ctx, uint64_t B, int br_waves, int ks_form);
 
+/* Pin how the split matrix-core form (the blind rotation's form 33) cuts a step at the timed
+ * batch size that covers B (1, 16, 64, 256, 512, 768, 1024, 1280, 1536, 1792, 2048, 3072,
+ * 4096 gates; batches up to that size and above the previous one use it): groups = 1, 2, 3
+ * or 6 groups of TRGSW rows per (tile, output, sub-product), 12 or 24 for one row per
+ * workgroup and the four byte planes in 2 or 4 ranges, 0 for the count that fills the chip.
+ * *previous (may be NULL) receives the value it replaces. Results are the same for every
+ * choice; vsp_autotune overwrites the setting. */
+vsp_status vsp_tuning_set_split(vsp_context* ctx, uint64_t B, int groups, int* previous);
+
 /* Kernel-time instrumentation (for benchmarks): with on >= 1, the blind-rotation, key-switch
  * and gate-prologue launches made by vsp_gates / vsp_bootstrap_trlwe / vsp_mux on the calling
  * thread are bracketed by HIP events on the stream they run on; for the matrix-core form one

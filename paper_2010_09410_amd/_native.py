@@ -80,6 +80,7 @@ SIGNATURES = {
     "vsp_mux": (_st, [_vp, _vp, _vp, _vp, _vp, _u64, _vp]),
     "vsp_autotune": (_st, [_vp, _u64, ctypes.c_char_p]),
     "vsp_tuning_get": (_st, [_vp, _u64, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+    "vsp_tuning_set_split": (_st, [_vp, _u64, _i32, ctypes.POINTER(ctypes.c_int)]),
     "vsp_tuning_set": (_st, [_vp, _u64, _i32, _i32]),
     "vsp_profile_enable": (_st, [_vp, _i32]),
     "vsp_profile_read": (_st, [_vp, _i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_u64)]),
@@ -305,6 +306,13 @@ def vsp_tuning_get(ctx, B: int):
 
 def vsp_tuning_set(ctx, B: int, br_waves: int, ks_form: int) -> None:
     _call("vsp_tuning_set", ctx, B, br_waves, ks_form)
+
+
+def vsp_tuning_set_split(ctx, B: int, groups: int) -> int:
+    """Pins the split form's workgroup count at the timed size covering B; returns the previous one."""
+    prev = ctypes.c_int()
+    _call("vsp_tuning_set_split", ctx, B, groups, ctypes.byref(prev))
+    return prev.value
 
 
 def vsp_profile_enable(ctx, on) -> None:

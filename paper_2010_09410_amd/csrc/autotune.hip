@@ -100,7 +100,7 @@ bool read_cache(const std::string& path, const std::string& key, Tuning& t) {
   for (int k = 0; k < kSplitPts; k++) {
     const int g = (int)sg[k];
     if (spts[k] != (double)kSplitAt[k]) return false;  // written for other sizes
-    if (!(sms[k] > 0 && sms[k] < 1e9) || (double)g != sg[k] || !(g == 0 || g == 1 || g == 2 || g == 3 || g == 6))
+    if (!(sms[k] > 0 && sms[k] < 1e9) || (double)g != sg[k] || !(g == 0 || split_groups_valid(g)))
       return false;
     n.split_ms[k] = (float)sms[k];
     n.split_groups[k] = g;
@@ -220,11 +220,12 @@ vsp_status vsp_autotune(vsp_context* ctx, uint64_t max_batch, const char* cache_
     if (s > 0 && !same(t1ref.p, t1.p, std::min(t.br_cap[0], B) * T1))
       result = fail(VSP_E_HIP, "autotune: blind-rotation shapes disagree");
   }
-  // the split matrix-core form at each timed size, with each row-group count
+  // the split matrix-core form at each timed size, with each workgroup count
   for (int b = 0; b < kSplitPts && result == VSP_OK && ctx->mf_key; b++) {
     const uint64_t B = std::min<uint64_t>(kSplitAt[b], t.br_cap[3]);
     float best = 1e30f;
-    for (int g : {1, 2, 3, 6}) {
+    for (int g : kSplitGroupChoices) {
+      if (g > 6 && B > 256) continue;  // plane ranges (12, 24) only pay while tiles are few
       const float ms = timed([&] {
         (void)launch_blind_rotate_mfsplit(ctx, dops, dab, static_cast<uint32_t*>(t1.p), nullptr, B, ctx->mf_work.ptr,
                                           g, st);
@@ -273,6 +274,16 @@ vsp_status vsp_tuning_get(const vsp_context* ctx, uint64_t B, int* br_waves, int
   if (ctx == nullptr || br_waves == nullptr || ks_form == nullptr) return fail(VSP_E_ARG, "NULL argument");
   *br_waves = ctx->tune.br_waves(B == 0 ? 1 : B);
   *ks_form = ctx->tune.ks_form_for(B == 0 ? 1 : B);
+  return VSP_OK;
+}
+
+vsp_status vsp_tuning_set_split(vsp_context* ctx, uint64_t B, int groups, int* previous) {
+  if (ctx == nullptr) return fail(VSP_E_ARG, "context is NULL");
+  if (groups != 0 && !split_groups_valid(groups))
+    return fail(VSP_E_ARG, "groups must be 0 (the count that fills the chip), 1, 2, 3, 6, 12 or 24");
+  const int k = Tuning::split_point(B == 0 ? 1 : B);
+  if (previous) *previous = ctx->tune.split_groups[k];
+  ctx->tune.split_groups[k] = groups;
   return VSP_OK;
 }
 

@@ -459,7 +459,11 @@ __global__ __launch_bounds__(MF_THREADS) void k_mf_step(const int8_t* __restrict
 // integer atomic adds (exact in any order: addition mod 2^32): P1 into both halves, P2 into
 // y0, P3 into y1. The next step's digits come from a separate launch of k_mf_digits, after
 // every share of the step has landed. Row groups: rows [rg * rows, rg * rows + rows) with
-// rows = 6 / groups (groups 1, 2, 3 or 6).
+// rows = 6 / groups (groups 1, 2, 3 or 6). With groups 12 or 24 every workgroup takes one row
+// and a range of 2 or 1 byte planes (planes bhi down to blo): Horner's rule over its own
+// planes, then its sum shifted left by 8 blo bits before the atomic add (exact mod 2^32, as
+// the full sum is that of the shifted plane sums), so that a single gate spreads over 144
+// workgroups.
 constexpr int MFP_THREADS = 256;
 constexpr int MFP_A_U4 = MF_KB * 64;                                  // one segment of one row: 1024 operands
 constexpr size_t MFP_LDS = 2 * ((size_t)MFP_A_U4 * 16 + 4 * (size_t)MF_COPY_U32 * 4);
@@ -476,17 +480,20 @@ __global__ __launch_bounds__(MFP_THREADS, 3) void k_mf_part(const int8_t* __rest
   const uint64_t mt = blockIdx.x;
   const int o = blockIdx.y;
   const int sub = (int)blockIdx.z % MF_SUB, rg = (int)blockIdx.z / MF_SUB;
-  const int rows = MF_ROWS / groups, r0 = rg * rows, passes = MF_PLANES * rows;
+  const int rgroups = groups > MF_ROWS ? MF_ROWS : groups;
+  const int planes = groups > MF_ROWS ? MF_PLANES * MF_ROWS / groups : MF_PLANES;
+  const int rows = MF_ROWS / rgroups, r0 = (rg % rgroups) * rows, passes = planes * rows;
+  const int bhi = MF_PLANES - 1 - (rg / rgroups) * planes, blo = bhi - planes + 1;
   const int tid = threadIdx.x, wl = tid >> 6, lane = tid & 63, n = lane & 31, kh = lane >> 5;
   const int tb = MF_HALF + 128 * wl + n - 16 * kh - 15;
   const int cp = tb & 3;
   const int bofs = cp * MF_COPY_U32 + ((tb - cp) >> 2) - 8 * (MF_KB - 1);
   const uint4* Ag = reinterpret_cast<const uint4*>(A + mt * MF_A_TILE) + sub * MFP_A_U4 + tid;
   const u32* Eu = reinterpret_cast<const u32*>(Ek);
-  // pass p: plane 3 - p / rows, row r0 + p % rows (any row order gives the same plane sum)
+  // pass p: plane bhi - p / rows, row r0 + p % rows (any row order gives the same plane sum)
   auto a_row = [&](int pass) { return Ag + (size_t)(r0 + pass % rows) * (MF_A_ROW / 16); };
   auto e_row = [&](int pass) {
-    const int r = r0 + pass % rows, b = MF_PLANES - 1 - pass / rows;
+    const int r = r0 + pass % rows, b = bhi - pass / rows;
     return Eu + ((((size_t)r * 2 + o) * MF_PLANES + b) * MF_SUB + sub) * (MF_S / 4);
   };
   auto stage_e = [&](u32* dst, u32 d0, u32 d1) {
@@ -532,9 +539,9 @@ __global__ __launch_bounds__(MFP_THREADS, 3) void k_mf_part(const int8_t* __rest
       for (int x = 0; x < 16; x++) c[nb][x] = (int)((u32)c[nb][x] << 8);
   };
   if (rows == 1) {
-    // one TRGSW row: its operands serve all four planes, so they and the four planes' key
-    // sequences are staged once (planes 3 and 2 in ebuf, 1 and 0 in the second operand
-    // buffer) and the passes run without further loads or barriers
+    // one TRGSW row: its operands serve all of the workgroup's planes, so they and those
+    // planes' key sequences are staged once (the first two in ebuf, the others in the second
+    // operand buffer) and the passes run without further loads or barriers
     auto kbuf = [&](int p) -> u32* {
       return p < 2 ? ebuf[p] : reinterpret_cast<u32*>(abuf[1]) + (p - 2) * 4 * MF_COPY_U32;
     };
@@ -547,21 +554,25 @@ __global__ __launch_bounds__(MFP_THREADS, 3) void k_mf_part(const int8_t* __rest
     u32 d0[MF_PLANES], d1[MF_PLANES];
 #pragma unroll
     for (int p = 0; p < MF_PLANES; p++) {
-      const u32* er = e_row(p);
-      d0[p] = er[tid];
-      d1[p] = (tid + 1 < MF_S / 4) ? er[tid + 1] : 0u;
+      d0[p] = d1[p] = 0u;
+      if (p < planes) {  // uniform
+        const u32* er = e_row(p);
+        d0[p] = er[tid];
+        d1[p] = (tid + 1 < MF_S / 4) ? er[tid + 1] : 0u;
+      }
     }
     abuf[0][tid] = x0;
     abuf[0][tid + MFP_THREADS] = x1;
     abuf[0][tid + 2 * MFP_THREADS] = x2;
     abuf[0][tid + 3 * MFP_THREADS] = x3;
 #pragma unroll
-    for (int p = 0; p < MF_PLANES; p++) stage_e(kbuf(p), d0[p], d1[p]);
+    for (int p = 0; p < MF_PLANES; p++)
+      if (p < planes) stage_e(kbuf(p), d0[p], d1[p]);
     __syncthreads();
 #pragma unroll 1
-    for (int pass = 0; pass < MF_PLANES; pass++) {
+    for (int pass = 0; pass < planes; pass++) {
       run_pass(abuf[0] + lane, kbuf(pass) + bofs);
-      if (pass + 1 < MF_PLANES) horner_shift();
+      if (pass + 1 < planes) horner_shift();
     }
   } else {
     if (tid < 2 * 4 * 4) {  // the tails of all copies of both buffers
@@ -621,7 +632,7 @@ __global__ __launch_bounds__(MFP_THREADS, 3) void k_mf_part(const int8_t* __rest
     u32* row = acc + ((mt * MF_TILE + m) * 2 + o) * RING_N + 128 * wl + n;
 #pragma unroll
     for (int nb = 0; nb < 4; nb++) {
-      const u32 v = (u32)c[nb][x];
+      const u32 v = (u32)c[nb][x] << (8 * blo);
       if (sub != 2) atomicAdd(row + 32 * nb, v);
       if (sub != 1) atomicAdd(row + MF_HALF + 32 * nb, v);
     }
@@ -674,13 +685,14 @@ hipError_t launch_blind_rotate_mfma(const vsp_context* ctx, const uint8_t* ops, 
 
 // Split form of the matrix-core blind rotation: per step one k_mf_part launch (shares of the
 // products added into ACC) and one k_mf_digits launch (the next step's operands from ACC).
-// groups (1, 2, 3 or 6) sets the TRGSW rows per workgroup; the workspace is that of the fused
-// form (the operands of one step and, without a caller TRLWE, the accumulators).
+// groups (kSplitGroupChoices) sets the TRGSW rows, or for one row the byte planes, per
+// workgroup; the workspace is that of the fused form (the operands of one step and, without a
+// caller TRLWE, the accumulators).
 hipError_t launch_blind_rotate_mfsplit(const vsp_context* ctx, const uint8_t* ops, const uint32_t* abar,
                                        uint32_t* tlwe1, uint32_t* trlwe, uint64_t B, void* work, int groups,
                                        hipStream_t st, bool instrument, const int8_t* const* tkeys) {
   if (B == 0) return hipSuccess;
-  if (groups != 1 && groups != 2 && groups != 3 && groups != 6) return hipErrorInvalidValue;
+  if (!split_groups_valid(groups)) return hipErrorInvalidValue;
   const uint64_t tiles = (B + MF_TILE - 1) / MF_TILE;
   int8_t* Aop = static_cast<int8_t*>(work);
   u32* acc = trlwe ? trlwe : reinterpret_cast<u32*>(Aop + 2 * tiles * MF_A_TILE);

@@ -36,12 +36,20 @@ constexpr int DEVERR_BAD_OP = 1;
 // workgroup on three waves (the latency form), 32 for the matrix-core form (int8 MFMA products
 // over tiles of MF_TILE gates, one workgroup per tile and output polynomial, one launch per
 // step), and 33 for its split form (the products of a step cut into workgroups per tile,
-// output polynomial, sub-product and group of TRGSW rows, for batches too small to fill the
-// chip; two launches per step).
+// output polynomial, sub-product and group of TRGSW rows, and for single rows also per range
+// of byte planes, for batches too small to fill the chip; two launches per step).
 constexpr int kBrShapes = 5;
 constexpr int kBrWaveChoices[kBrShapes] = {4, 8, 3, 32, 33};
 constexpr int MF_TILE = 32;
 inline bool br_matrix_form(int waves) { return waves == 32 || waves == 33; }
+// Workgroup counts per (tile, output, sub-product) of the split form: 1, 2, 3 or 6 groups of
+// TRGSW rows, or one row per workgroup with the four byte planes in 2 (12) or 4 (24) ranges.
+constexpr int kSplitGroupChoices[6] = {1, 2, 3, 6, 12, 24};
+inline bool split_groups_valid(int g) {
+  for (int c : kSplitGroupChoices)
+    if (g == c) return true;
+  return false;
+}
 // Row groups of the split form for B gates on a chip of `cus` compute units: the fewest that
 // give about three workgroups of four waves per compute unit.
 inline int mf_split_groups(uint64_t B, int cus) {
@@ -80,9 +88,9 @@ struct Tuning {
   // split form, at the sizes kSplitAt: time in the same units as br_round_ms, and row groups
   // (0: the count that fills the chip, mf_split_groups). The defaults are relative times
   // measured on an MI355X (one 4-gate-workgroup round = 1).
-  float split_ms[kSplitPts] = {0.201f, 0.278f, 0.326f, 0.513f, 0.672f, 0.829f, 0.918f, 1.14f, 1.368f, 1.45f, 1.53f,
+  float split_ms[kSplitPts] = {0.152f, 0.249f, 0.326f, 0.513f, 0.672f, 0.829f, 0.918f, 1.14f, 1.368f, 1.45f, 1.53f,
                                2.22f, 2.567f};
-  int split_groups[kSplitPts] = {6, 6, 6, 3, 2, 3, 2, 2, 2, 1, 1, 1, 1};
+  int split_groups[kSplitPts] = {24, 12, 6, 3, 2, 3, 2, 2, 2, 1, 1, 1, 1};
   int br_force[kTuneBuckets] = {0, 0, 0, 0, 0, 0, 0};
   int ks_form[kTuneBuckets] = {2, 2, 2, 2, 3, 3, 3};
   bool tuned = false;
@@ -260,7 +268,7 @@ size_t ks_mf_key_bytes();
 hipError_t launch_ks_mfkey(const uint32_t* ksk, int8_t* KB, hipStream_t st);
 hipError_t launch_keyswitch_mfma(const int8_t* KB, const uint8_t* ops, const uint32_t* tlwe1, const uint32_t* idxo,
                                  uint32_t* out, uint64_t B, hipStream_t st);
-// Split form (waves 33): two launches per step, `groups` (1, 2, 3 or 6) row groups per
+// Split form (waves 33): two launches per step, `groups` (kSplitGroupChoices) workgroups per
 // (tile, output, sub-product); same workspace as the fused form.
 hipError_t launch_blind_rotate_mfsplit(const vsp_context* ctx, const uint8_t* ops, const uint32_t* abar,
                                        uint32_t* tlwe1, uint32_t* trlwe, uint64_t B, void* work, int groups,

@@ -129,6 +129,9 @@ class Context:
     def set_tuning(self, B: int, br_waves: int, ks_form: int) -> None:
         nv.vsp_tuning_set(self.handle, B, br_waves, ks_form)
 
+    def set_split_groups(self, B: int, groups: int) -> int:
+        return nv.vsp_tuning_set_split(self.handle, B, groups)
+
     # -------------------------------------------------------------- circuits / serving
     def circuit(self, gates, ninputs: int) -> "Circuit":
         return Circuit(self, gates, ninputs)

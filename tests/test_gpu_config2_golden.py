@@ -75,3 +75,23 @@ def test_split_matrix_form_prefixes_match_oracle(gpu, batch, nb):
     want = doc["gate_sha256_prefix"]
     bad = [k for k in range(nb) if row_digest(out[k]) != want[k]]
     assert not bad, f"{len(bad)} of {nb} gates differ from the oracle; first {bad[:8]}"
+
+
+@pytest.mark.parametrize("nb,groups", [(1, 12), (1, 24), (16, 24), (37, 12), (64, 24), (64, 1), (256, 6)])
+def test_split_form_workgroup_counts_match_oracle(gpu, batch, nb, groups):
+    """Every way of cutting a step of the split form (row groups, single rows with the byte
+    planes in two or four ranges) on prefixes of the batch, against the oracle's digests."""
+    cfg, in0, in1, doc = batch
+    d0, d1, dops = gpu.tensor(in0[:nb]), gpu.tensor(in1[:nb]), gpu.tensor(cfg["ops"][:nb])
+    saved = gpu.tuning(nb)
+    prev = gpu.set_split_groups(nb, groups)
+    try:
+        gpu.set_tuning(nb, 33, 2)
+        out = to_host(gpu.gates(dops, d0, d1))
+        gpu.sync()
+    finally:
+        gpu.set_tuning(nb, 0, saved[1])
+        gpu.set_split_groups(nb, prev)
+    want = doc["gate_sha256_prefix"]
+    bad = [k for k in range(nb) if row_digest(out[k]) != want[k]]
+    assert not bad, f"{len(bad)} of {nb} gates differ from the oracle (groups {groups}); first {bad[:8]}"
