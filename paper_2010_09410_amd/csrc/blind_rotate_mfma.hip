@@ -84,11 +84,13 @@ __global__ __launch_bounds__(256) void k_mf_key(const u32* __restrict__ bk, int8
   }
 }
 
-// ACC = (0, X^{-bbar} (mu, ..., mu)) for the gates that bootstrap.
+// ACC = (0, X^{-bbar} (mu, ..., mu)) for the gates that bootstrap; with `zero` non-NULL also
+// clears the same rows there (the first step's target in the rotating-buffer split form).
 __global__ __launch_bounds__(256) void k_mf_init(const uint8_t* __restrict__ ops, const u32* __restrict__ abar,
-                                                  u32* __restrict__ acc, uint64_t B) {
+                                                  u32* __restrict__ acc, uint64_t B, u32* __restrict__ zero) {
   const uint64_t id = (uint64_t)blockIdx.x * 256 + threadIdx.x;
   if (id >= B * 2 * RING_N) return;
+  if (zero) zero[id] = 0u;
   const uint64_t g = id / (2 * RING_N);
   if (ops && !op_bootstraps(ops[g])) return;
   const int c = (int)(id - g * 2 * RING_N);
@@ -464,7 +466,15 @@ __global__ __launch_bounds__(MF_THREADS) void k_mf_step(const int8_t* __restrict
 // planes, then its sum shifted left by 8 blo bits before the atomic add (exact mod 2^32, as
 // the full sum is that of the shifted plane sums), so that a single gate spreads over 144
 // workgroups.
+// With acc_in non-NULL (batches of at most MFP_FUSE gates, one row per workgroup) the step
+// needs no digit launch: the accumulator rotates through three buffers, ACC_i in acc_in, the
+// target acc zeroed one step earlier, acc_zero (ACC_{i-1}, no longer read) cleared for the
+// next step. Each workgroup stages polynomial h of its row r = 3h + k for the batch's gates
+// in LDS and forms its own operand segment from it (the digits of X^{abar_i} ACC_h - ACC_h,
+// as k_mf_digits would), and the workgroups of sub-products P2 and P3 of the first row group
+// also add ACC_i's y0 and y1 halves to their shares, so that acc ends as ACC_{i+1}.
 constexpr int MFP_THREADS = 256;
+constexpr int MFP_FUSE = 4;  // largest batch whose digits the step kernel forms itself
 constexpr int MFP_A_U4 = MF_KB * 64;                                  // one segment of one row: 1024 operands
 constexpr size_t MFP_LDS = 2 * ((size_t)MFP_A_U4 * 16 + 4 * (size_t)MF_COPY_U32 * 4);
 static_assert(MFP_A_U4 == 4 * MFP_THREADS && MF_S / 4 == MFP_THREADS,
@@ -473,7 +483,9 @@ static_assert(MFP_A_U4 == 4 * MFP_THREADS && MF_S / 4 == MFP_THREADS,
 __global__ __launch_bounds__(MFP_THREADS, 3) void k_mf_part(const int8_t* __restrict__ Ek0, const int8_t* __restrict__ A,
                                                           u32* __restrict__ acc, const uint8_t* __restrict__ ops,
                                                           uint64_t B, int groups,
-                                                          const int8_t* const* __restrict__ tkeys, uint64_t key_off) {
+                                                          const int8_t* const* __restrict__ tkeys, uint64_t key_off,
+                                                          const u32* __restrict__ acc_in, u32* __restrict__ acc_zero,
+                                                          const u32* __restrict__ abar, int step) {
   const int8_t* __restrict__ Ek = tkeys ? tkeys[blockIdx.x] + key_off : Ek0;
   __shared__ uint4 abuf[2][MFP_A_U4];
   __shared__ u32 ebuf[2][4 * MF_COPY_U32];
@@ -488,6 +500,19 @@ __global__ __launch_bounds__(MFP_THREADS, 3) void k_mf_part(const int8_t* __rest
   const int tb = MF_HALF + 128 * wl + n - 16 * kh - 15;
   const int cp = tb & 3;
   const int bofs = cp * MF_COPY_U32 + ((tb - cp) >> 2) - 8 * (MF_KB - 1);
+  // rotating buffers: the first row group's P2 / P3 workgroups carry ACC_i's y0 / y1 halves
+  // into their shares (gates m < MFP_FUSE end in registers x = m of the lanes with kh = 0),
+  // fetched here so that their latency hides behind the products
+  const bool carry = acc_in != nullptr && rg == 0 && sub != 0;
+  u32 cyv[MFP_FUSE][4];
+#pragma unroll
+  for (int m = 0; m < MFP_FUSE; m++) {
+    const uint64_t g = mt * MF_TILE + m;
+    const bool fetch = carry && kh == 0 && g < B;
+#pragma unroll
+    for (int nb = 0; nb < 4; nb++)
+      cyv[m][nb] = fetch ? acc_in[(g * 2 + o) * RING_N + (sub == 2 ? MF_HALF : 0) + 128 * wl + 32 * nb + n] : 0u;
+  }
   const uint4* Ag = reinterpret_cast<const uint4*>(A + mt * MF_A_TILE) + sub * MFP_A_U4 + tid;
   const u32* Eu = reinterpret_cast<const u32*>(Ek);
   // pass p: plane bhi - p / rows, row r0 + p % rows (any row order gives the same plane sum)
@@ -545,12 +570,19 @@ __global__ __launch_bounds__(MFP_THREADS, 3) void k_mf_part(const int8_t* __rest
     auto kbuf = [&](int p) -> u32* {
       return p < 2 ? ebuf[p] : reinterpret_cast<u32*>(abuf[1]) + (p - 2) * 4 * MF_COPY_U32;
     };
-    if (tid < MF_PLANES * 4 * 4) {  // the tails of all copies of the four key buffers
+    const bool fuse = acc_in != nullptr;
+    if (!fuse && tid < MF_PLANES * 4 * 4) {  // the tails of all copies of the four key buffers
       const int bufi = tid >> 4, rest = tid & 15;
       kbuf(bufi)[(rest >> 2) * MF_COPY_U32 + MF_S / 4 + (rest & 3)] = 0u;
     }
-    const uint4* as = a_row(0);
-    const uint4 x0 = as[0], x1 = as[MFP_THREADS], x2 = as[2 * MFP_THREADS], x3 = as[3 * MFP_THREADS];
+    uint4 x0 = make_uint4(0u, 0u, 0u, 0u), x1 = x0, x2 = x0, x3 = x0;
+    if (!fuse) {
+      const uint4* as = a_row(0);
+      x0 = as[0];
+      x1 = as[MFP_THREADS];
+      x2 = as[2 * MFP_THREADS];
+      x3 = as[3 * MFP_THREADS];
+    }
     u32 d0[MF_PLANES], d1[MF_PLANES];
 #pragma unroll
     for (int p = 0; p < MF_PLANES; p++) {
@@ -561,10 +593,64 @@ __global__ __launch_bounds__(MFP_THREADS, 3) void k_mf_part(const int8_t* __rest
         d1[p] = (tid + 1 < MF_S / 4) ? er[tid + 1] : 0u;
       }
     }
-    abuf[0][tid] = x0;
-    abuf[0][tid + MFP_THREADS] = x1;
-    abuf[0][tid + 2 * MFP_THREADS] = x2;
-    abuf[0][tid + 3 * MFP_THREADS] = x3;
+    if (fuse) {
+      // this row's operand segment from ACC_i: stage polynomial h of the gates in LDS (the
+      // second operand buffer), zero the operands of gates without digits, then form the
+      // digit words of the others (gate m, block kb, half kh, word wi: four coefficients)
+      const int h = r0 / GADGET_L, k = r0 % GADGET_L, sh = 32 - BG_BIT * (k + 1);
+      const uint64_t g0 = mt * MF_TILE;
+      const int nb = (int)((B - g0 < (uint64_t)MFP_FUSE) ? B - g0 : (uint64_t)MFP_FUSE);
+      u32* pst = reinterpret_cast<u32*>(abuf[1]);  // [MFP_FUSE][N]
+      bool gl[MFP_FUSE];
+      uint4 pv[MFP_FUSE];
+#pragma unroll
+      for (int m = 0; m < MFP_FUSE; m++) {
+        gl[m] = m < nb && (!ops || op_bootstraps(ops[g0 + m]));
+        pv[m] = gl[m] ? reinterpret_cast<const uint4*>(acc_in + ((g0 + m) * 2 + h) * RING_N)[tid]
+                      : make_uint4(0u, 0u, 0u, 0u);
+      }
+#pragma unroll
+      for (int m = 0; m < MFP_FUSE; m++) reinterpret_cast<uint4*>(pst + m * RING_N)[tid] = pv[m];
+      __syncthreads();
+#pragma unroll
+      for (int v = 0; v < 4; v++) {
+        const int c = tid + MFP_THREADS * v, m = c & 31;
+        if (!(m < MFP_FUSE && gl[m])) abuf[0][c] = make_uint4(0u, 0u, 0u, 0u);
+      }
+#pragma unroll
+      for (int v = 0; v < 2; v++) {
+        const int u = tid + MFP_THREADS * v, m = u >> 7, kb = (u >> 3) & 15, kq = (u >> 2) & 1, wi = u & 3;
+        if (!gl[m]) continue;
+        const u32* P = pst + m * RING_N;
+        const int a = (int)abar[(g0 + m) * TLWE0 + step];
+        u32 w = 0;
+#pragma unroll
+        for (int q = 0; q < 4; q++) {  // byte q of the word: local coefficient j
+          const int j = 32 * kb + 16 * kq + 15 - 4 * wi - q;
+          u32 d[2];
+#pragma unroll
+          for (int half = 0; half < 2; half++) {
+            const int ix = (half * MF_HALF + j - a) & (2 * RING_N - 1);
+            const u32 r = P[ix & (RING_N - 1)];
+            const u32 x = ((ix & RING_N) ? 0u - r : r) - P[half * MF_HALF + j] + DECOMP_OFFSET;
+            d[half] = ((x >> sh) & 63u) - 32u;
+          }
+          const u32 byte = sub == 0 ? d[0] + d[1] : (sub == 1 ? d[1] : d[0]);
+          w |= (byte & 255u) << (8 * q);
+        }
+        reinterpret_cast<u32*>(&abuf[0][kb * 64 + m + 32 * kq])[wi] = w;
+      }
+      __syncthreads();  // the staged polynomials are read; the key buffers may now use abuf[1]
+      if (tid < MF_PLANES * 4 * 4) {
+        const int bufi = tid >> 4, rest = tid & 15;
+        kbuf(bufi)[(rest >> 2) * MF_COPY_U32 + MF_S / 4 + (rest & 3)] = 0u;
+      }
+    } else {
+      abuf[0][tid] = x0;
+      abuf[0][tid + MFP_THREADS] = x1;
+      abuf[0][tid + 2 * MFP_THREADS] = x2;
+      abuf[0][tid + 3 * MFP_THREADS] = x3;
+    }
 #pragma unroll
     for (int p = 0; p < MF_PLANES; p++)
       if (p < planes) stage_e(kbuf(p), d0[p], d1[p]);
@@ -623,18 +709,26 @@ __global__ __launch_bounds__(MFP_THREADS, 3) void k_mf_part(const int8_t* __rest
     mine = kh == 0 && g < B && op_bootstraps(op);
   }
   const uint64_t live = __ballot(mine);
+  // rotating buffers: the first row group's P1 workgroup clears the next step's target
+  if (acc_in != nullptr && rg == 0 && sub == 0) {  // rows of gates that do not bootstrap stay untouched
+    for (int m = 0; m < MFP_FUSE; m++)
+      if ((live >> m) & 1)
+        reinterpret_cast<uint4*>(acc_zero + ((mt * MF_TILE + m) * 2 + o) * RING_N)[tid] = make_uint4(0u, 0u, 0u, 0u);
+  }
   // result (m, i): lane n + 32 kh, register x of block nb, m = 8 (x / 4) + 4 kh + x % 4,
   // i = 128 q + 32 nb + n; P1 adds into outputs i and N/2 + i, P2 into i, P3 into N/2 + i
 #pragma unroll
   for (int x = 0; x < 16; x++) {
     const int m = 8 * (x >> 2) + 4 * kh + (x & 3);
     if (!((live >> m) & 1)) continue;
-    u32* row = acc + ((mt * MF_TILE + m) * 2 + o) * RING_N + 128 * wl + n;
+    const size_t ro = ((mt * MF_TILE + m) * 2 + o) * RING_N + 128 * wl + n;
+    u32* row = acc + ro;
 #pragma unroll
     for (int nb = 0; nb < 4; nb++) {
       const u32 v = (u32)c[nb][x] << (8 * blo);
-      if (sub != 2) atomicAdd(row + 32 * nb, v);
-      if (sub != 1) atomicAdd(row + MF_HALF + 32 * nb, v);
+      const u32 cy = (x < MFP_FUSE && carry) ? cyv[x < MFP_FUSE ? x : 0][nb] : 0u;
+      if (sub != 2) atomicAdd(row + 32 * nb, v + cy);
+      if (sub != 1) atomicAdd(row + MF_HALF + 32 * nb, v + cy);
     }
   }
 }
@@ -666,7 +760,8 @@ hipError_t launch_blind_rotate_mfma(const vsp_context* ctx, const uint8_t* ops, 
   // the operands of step i + 1 into the other one
   int8_t* Ab[2] = {static_cast<int8_t*>(work), static_cast<int8_t*>(work) + tiles * MF_A_TILE};
   u32* acc = trlwe ? trlwe : reinterpret_cast<u32*>(Ab[1] + tiles * MF_A_TILE);
-  hipLaunchKernelGGL(k_mf_init, dim3((unsigned)((B * 2 * RING_N + 255) / 256)), dim3(256), 0, st, ops, abar, acc, B);
+  hipLaunchKernelGGL(k_mf_init, dim3((unsigned)((B * 2 * RING_N + 255) / 256)), dim3(256), 0, st, ops, abar, acc, B,
+                     nullptr);
   hipLaunchKernelGGL(k_mf_digits, dim3((unsigned)tiles, 2, MF_TILE / MF_DG), dim3(256), 0, st, ops, abar, acc, Ab[0], B,
                      0);
   {
@@ -696,15 +791,31 @@ hipError_t launch_blind_rotate_mfsplit(const vsp_context* ctx, const uint8_t* op
   const uint64_t tiles = (B + MF_TILE - 1) / MF_TILE;
   int8_t* Aop = static_cast<int8_t*>(work);
   u32* acc = trlwe ? trlwe : reinterpret_cast<u32*>(Aop + 2 * tiles * MF_A_TILE);
-  hipLaunchKernelGGL(k_mf_init, dim3((unsigned)((B * 2 * RING_N + 255) / 256)), dim3(256), 0, st, ops, abar, acc, B);
-  const dim3 dgrid((unsigned)tiles, 2, MF_TILE / MF_DG);
-  hipLaunchKernelGGL(k_mf_digits, dgrid, dim3(256), 0, st, ops, abar, acc, Aop, B, 0);
-  {
+  const dim3 pgrid((unsigned)tiles, 2, (unsigned)(MF_SUB * groups));
+  if (B <= (uint64_t)MFP_FUSE && groups >= MF_ROWS) {
+    // one launch per step: ACC_i in buf[i mod 3], the step adds into buf[(i + 1) mod 3] and
+    // clears buf[(i + 2) mod 3]; n is a multiple of 3, so ACC_n ends in buf[0] = acc. The
+    // two spare buffers take the (unused) operand area of the workspace.
+    static_assert(LWE_N % 3 == 0, "the last step's target is the first buffer");
+    static_assert(2 * MFP_FUSE * 2 * RING_N * 4 <= 2 * MF_A_TILE, "spare buffers fit the operand area");
+    u32* buf[3] = {acc, reinterpret_cast<u32*>(Aop), reinterpret_cast<u32*>(Aop) + B * 2 * RING_N};
+    hipLaunchKernelGGL(k_mf_init, dim3((unsigned)((B * 2 * RING_N + 255) / 256)), dim3(256), 0, st, ops, abar, acc, B,
+                       buf[1]);
+    ProfScope ps(instrument ? ctx : nullptr, 3, st, LWE_N);
+    for (int i = 0; i < LWE_N; i++)
+      hipLaunchKernelGGL(k_mf_part, pgrid, dim3(MFP_THREADS), 0, st,
+                         tkeys ? nullptr : ctx->mf_key + (size_t)i * MF_KEY_STEP, Aop, buf[(i + 1) % 3], ops, B,
+                         groups, tkeys, (uint64_t)i * MF_KEY_STEP, buf[i % 3], buf[(i + 2) % 3], abar, i);
+  } else {
+    hipLaunchKernelGGL(k_mf_init, dim3((unsigned)((B * 2 * RING_N + 255) / 256)), dim3(256), 0, st, ops, abar, acc, B,
+                       nullptr);
+    const dim3 dgrid((unsigned)tiles, 2, MF_TILE / MF_DG);
+    hipLaunchKernelGGL(k_mf_digits, dgrid, dim3(256), 0, st, ops, abar, acc, Aop, B, 0);
     ProfScope ps(instrument ? ctx : nullptr, 3, st, LWE_N);
     for (int i = 0; i < LWE_N; i++) {
-      hipLaunchKernelGGL(k_mf_part, dim3((unsigned)tiles, 2, (unsigned)(MF_SUB * groups)), dim3(MFP_THREADS), 0, st,
+      hipLaunchKernelGGL(k_mf_part, pgrid, dim3(MFP_THREADS), 0, st,
                          tkeys ? nullptr : ctx->mf_key + (size_t)i * MF_KEY_STEP, Aop, acc, ops, B, groups, tkeys,
-                         (uint64_t)i * MF_KEY_STEP);
+                         (uint64_t)i * MF_KEY_STEP, nullptr, nullptr, nullptr, 0);
       if (i + 1 < LWE_N)
         hipLaunchKernelGGL(k_mf_digits, dgrid, dim3(256), 0, st, ops, abar, acc, Aop, B, i + 1);
     }

@@ -146,6 +146,34 @@ def test_bootstrap_trlwe_matches_oracle(gpu, keys):
         np.testing.assert_array_equal(out[k], oracle.bootstrap_to_trlwe(keys["bk"], lin), err_msg=f"k={k}")
 
 
+@pytest.mark.parametrize("groups", [6, 24])
+def test_tiny_split_batches_with_idle_gates(gpu, keys, groups):
+    """Batches of at most four gates in the split matrix-core form (digits formed inside the
+    step kernel, the accumulator rotating through three buffers), with a gate that does not
+    bootstrap among them: gate outputs and TRLWE accumulators equal the oracle."""
+    ops, A, Bb, in0, in1 = truth_table_inputs(keys, 506)
+    pick = [32, 1, 0]                      # NOT, NAND, NAND: the first gate does not bootstrap
+    ops3, a3, b3 = ops[pick], in0[pick], in1[pick]
+    assert ops3[0] == oracle.NOT
+    saved = {B: gpu.tuning(B) for B in (3, 4)}
+    prev = gpu.set_split_groups(3, groups)
+    try:
+        for B in (3, 4):
+            gpu.set_tuning(B, 33, 2)
+        out = to_host(gpu.gates(dev(gpu, ops3), dev(gpu, a3), dev(gpu, b3)))
+        np.testing.assert_array_equal(out, oracle.gates(keys["bk"], keys["ksk"], ops3, a3, b3))
+        t_ops, t0, t1 = ops[[1, 5, 9, 13]], in0[[1, 5, 9, 13]], in1[[1, 5, 9, 13]]
+        tr = to_host(gpu.bootstrap_trlwe(dev(gpu, t_ops), dev(gpu, t0), dev(gpu, t1)))
+        for k in range(4):
+            lin, _ = oracle.gate_linear(int(t_ops[k]), t0[k], t1[k])
+            np.testing.assert_array_equal(tr[k], oracle.bootstrap_to_trlwe(keys["bk"], lin), err_msg=f"k={k}")
+        gpu.sync()
+    finally:
+        for B, (w, t) in saved.items():
+            gpu.set_tuning(B, 0, t)
+        gpu.set_split_groups(3, prev)
+
+
 def test_empty_batch_is_noop(gpu):
     t = gpu.empty(1, n + 1)
     ops = torch.zeros(1, dtype=torch.uint8, device=gpu.device)
