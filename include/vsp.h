@@ -308,7 +308,10 @@ vsp_status vsp_tuning_set(vsp_context* ctx, uint64_t B, int br_waves, int ks_for
  * batch size that covers B (1, 16, 64, 256, 512, 768, 1024, 1280, 1536, 1792, 2048, 3072,
  * 4096 gates; batches up to that size and above the previous one use it): groups = 1, 2, 3
  * or 6 groups of TRGSW rows per (tile, output, sub-product), 12 or 24 for one row per
- * workgroup and the four byte planes in 2 or 4 ranges, 0 for the count that fills the chip.
+ * workgroup and the four byte planes in 2 or 4 ranges (shares added with integer atomics);
+ * -1, -2, -3 or -6 for those row groups with the shares stored as partial sums that the next
+ * digit launch adds up (batches above 3,072 gates fall back to atomics); 0 for the count that
+ * fills the chip.
  * *previous (may be NULL) receives the value it replaces. Results are the same for every
  * choice; vsp_autotune overwrites the setting. */
 vsp_status vsp_tuning_set_split(vsp_context* ctx, uint64_t B, int groups, int* previous);

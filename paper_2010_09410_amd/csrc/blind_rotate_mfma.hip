@@ -130,56 +130,97 @@ __device__ __forceinline__ void mf_digit_words(const u32 (&rot0)[4], const u32 (
 }
 
 constexpr int MF_DG = 8;  // gates per digit workgroup
+// Shares of one (tile, output, sub-product, workgroup group) in the partial-sum split form:
+// [gate m][local output i], N/2 words per gate.
+constexpr size_t MF_PART_U32 = (size_t)MF_TILE * MF_HALF;
 
+// With PG > 0 the step's shares are first added into ACC (the partial-sum split form, PG
+// workgroups per (tile, output, sub-product)): y0[i] = sum over groups of P1[i] + P2[i],
+// y1[i] = sum of P1[i] + P3[i] from the share blocks of output polynomial h, and ACC_h += y
+// is written back. The updated polynomials of the workgroup's gates are staged in LDS, where
+// the rotated coefficients are read. step == n: the shares of the last step only.
+template <int PG>
 __global__ __launch_bounds__(256) void k_mf_digits(const uint8_t* __restrict__ ops, const u32* __restrict__ abar,
-                                                    const u32* __restrict__ acc, int8_t* __restrict__ A, uint64_t B,
-                                                    int step) {
-  __shared__ u32 sA[GADGET_L][MF_SUB][MF_KB][2 * MF_DG][4];
+                                                    u32* __restrict__ acc, int8_t* __restrict__ A, uint64_t B,
+                                                    int step, const u32* __restrict__ part) {
+  // the gates' polynomials h [MF_DG][N] while digits are formed, then the operand words
+  // sA[k][segment][kb][lane][4] gathered in operand order
+  constexpr int SP_U4 = MF_DG * RING_N / 4, SA_U4 = GADGET_L * MF_SUB * MF_KB * 2 * MF_DG;
+  __shared__ uint4 lds[SP_U4 > SA_U4 ? SP_U4 : SA_U4];
   const uint64_t mt = blockIdx.x;
   const int h = blockIdx.y, e = blockIdx.z, t = threadIdx.x;
   const int jg = t & 127, kb = jg >> 3, kh = (jg >> 2) & 1, dw = 3 - (jg & 3);
   constexpr int ROUNDS = MF_DG / 2;
-  // all loads first (their latencies overlap), then the digits
   bool live[ROUNDS];
   uint4 own[ROUNDS][2];
-  u32 rot[ROUNDS][2][4];
 #pragma unroll
   for (int q = 0; q < ROUNDS; q++) {
     const int mm = 2 * q + (t >> 7);
     const uint64_t g = mt * MF_TILE + (uint64_t)e * MF_DG + mm;
     live[q] = g < B && (!ops || op_bootstraps(ops[g]));
-    const int a = live[q] ? (int)abar[g * TLWE0 + step] : 0;
-    const u32* p = acc + (g * 2 + h) * RING_N;
+    uint4* p = reinterpret_cast<uint4*>(acc + (g * 2 + h) * RING_N);
 #pragma unroll
-    for (int half = 0; half < 2; half++) {
-      own[q][half] = live[q] ? reinterpret_cast<const uint4*>(p)[half * (MF_HALF / 4) + jg] : make_uint4(0u, 0u, 0u, 0u);
+    for (int half = 0; half < 2; half++)
+      own[q][half] = live[q] ? p[half * (MF_HALF / 4) + jg] : make_uint4(0u, 0u, 0u, 0u);
+    if (PG > 0 && live[q]) {
+      const uint4* Q = reinterpret_cast<const uint4*>(part) +
+                       ((mt * 2 + h) * MF_SUB * PG * MF_TILE + (uint64_t)e * MF_DG + mm) * (MF_HALF / 4) + jg;
+      constexpr size_t SUB_U4 = (size_t)PG * MF_PART_U32 / 4, RG_U4 = MF_PART_U32 / 4;
 #pragma unroll
-      for (int s = 0; s < 4; s++) {
-        const int idx = (half * MF_HALF + 4 * jg + 3 - s - a) & (2 * RING_N - 1);
-        const u32 r = live[q] ? p[idx & (RING_N - 1)] : 0u;
-        rot[q][half][s] = (idx & RING_N) ? 0u - r : r;
+      for (int rg = 0; rg < (PG > 0 ? PG : 1); rg++) {
+        const uint4 p1 = Q[rg * RG_U4], p2 = Q[SUB_U4 + rg * RG_U4], p3 = Q[2 * SUB_U4 + rg * RG_U4];
+        own[q][0].x += p1.x + p2.x; own[q][0].y += p1.y + p2.y; own[q][0].z += p1.z + p2.z; own[q][0].w += p1.w + p2.w;
+        own[q][1].x += p1.x + p3.x; own[q][1].y += p1.y + p3.y; own[q][1].z += p1.z + p3.z; own[q][1].w += p1.w + p3.w;
       }
+      p[jg] = own[q][0];
+      p[MF_HALF / 4 + jg] = own[q][1];
     }
+    lds[mm * (RING_N / 4) + jg] = own[q][0];
+    lds[mm * (RING_N / 4) + MF_HALF / 4 + jg] = own[q][1];
   }
+  if (step >= LWE_N) return;  // uniform: the last step's shares only
+  __syncthreads();
+  u32 w[ROUNDS][GADGET_L][MF_SUB];
 #pragma unroll
   for (int q = 0; q < ROUNDS; q++) {
     const int mm = 2 * q + (t >> 7);
-    u32 w[GADGET_L][MF_SUB] = {};
-    if (live[q]) {
-      const u32 ov0[4] = {own[q][0].x, own[q][0].y, own[q][0].z, own[q][0].w};
-      const u32 ov1[4] = {own[q][1].x, own[q][1].y, own[q][1].z, own[q][1].w};
-      mf_digit_words(rot[q][0], ov0, rot[q][1], ov1, w);
-    }
+    const uint64_t g = mt * MF_TILE + (uint64_t)e * MF_DG + mm;
 #pragma unroll
     for (int k = 0; k < GADGET_L; k++)
 #pragma unroll
-      for (int sg = 0; sg < MF_SUB; sg++) sA[k][sg][kb][mm + MF_DG * kh][dw] = w[k][sg];
+      for (int sg = 0; sg < MF_SUB; sg++) w[q][k][sg] = 0u;
+    if (live[q]) {
+      const int a = (int)abar[g * TLWE0 + step];
+      const u32* P = reinterpret_cast<const u32*>(lds + mm * (RING_N / 4));
+      u32 rot[2][4];
+#pragma unroll
+      for (int half = 0; half < 2; half++)
+#pragma unroll
+        for (int s = 0; s < 4; s++) {
+          const int idx = (half * MF_HALF + 4 * jg + 3 - s - a) & (2 * RING_N - 1);
+          const u32 r = P[idx & (RING_N - 1)];
+          rot[half][s] = (idx & RING_N) ? 0u - r : r;
+        }
+      const u32 ov0[4] = {own[q][0].x, own[q][0].y, own[q][0].z, own[q][0].w};
+      const u32 ov1[4] = {own[q][1].x, own[q][1].y, own[q][1].z, own[q][1].w};
+      mf_digit_words(rot[0], ov0, rot[1], ov1, w[q]);
+    }
+  }
+  __syncthreads();  // the staged polynomials are read: the region now gathers operand words
+  u32(*sA)[MF_SUB][MF_KB][2 * MF_DG][4] = reinterpret_cast<u32(*)[MF_SUB][MF_KB][2 * MF_DG][4]>(lds);
+#pragma unroll
+  for (int q = 0; q < ROUNDS; q++) {
+    const int mm = 2 * q + (t >> 7);
+#pragma unroll
+    for (int k = 0; k < GADGET_L; k++)
+#pragma unroll
+      for (int sg = 0; sg < MF_SUB; sg++) sA[k][sg][kb][mm + MF_DG * kh][dw] = w[q][k][sg];
   }
   __syncthreads();
   // out: rows 3h .. 3h + 2, every segment and block, lanes e*8 + (0..7) and 32 + e*8 + (0..7)
-  const uint4* src = reinterpret_cast<const uint4*>(&sA[0][0][0][0][0]);
+  const uint4* src = lds;
   uint4* dst = reinterpret_cast<uint4*>(A + mt * MF_A_TILE + (size_t)GADGET_L * h * MF_A_ROW);
-  for (int c = t; c < GADGET_L * MF_SUB * MF_KB * 2 * MF_DG; c += 256) {
+  for (int c = t; c < SA_U4; c += 256) {
     const int ll = c % (2 * MF_DG), rk = c / (2 * MF_DG);  // rk = (k * 3 + segment) * MF_KB + kb
     const int lane = (ll % MF_DG) + MF_DG * e + 32 * (ll / MF_DG);
     dst[(size_t)rk * 64 + lane] = src[c];
@@ -485,7 +526,8 @@ __global__ __launch_bounds__(MFP_THREADS, 3) void k_mf_part(const int8_t* __rest
                                                           uint64_t B, int groups,
                                                           const int8_t* const* __restrict__ tkeys, uint64_t key_off,
                                                           const u32* __restrict__ acc_in, u32* __restrict__ acc_zero,
-                                                          const u32* __restrict__ abar, int step) {
+                                                          const u32* __restrict__ abar, int step,
+                                                          u32* __restrict__ part) {
   const int8_t* __restrict__ Ek = tkeys ? tkeys[blockIdx.x] + key_off : Ek0;
   __shared__ uint4 abuf[2][MFP_A_U4];
   __shared__ u32 ebuf[2][4 * MF_COPY_U32];
@@ -717,12 +759,22 @@ __global__ __launch_bounds__(MFP_THREADS, 3) void k_mf_part(const int8_t* __rest
   }
   // result (m, i): lane n + 32 kh, register x of block nb, m = 8 (x / 4) + 4 kh + x % 4,
   // i = 128 q + 32 nb + n; P1 adds into outputs i and N/2 + i, P2 into i, P3 into N/2 + i
+  if (part) {  // partial-sum form: plain stores of the share, added up by the digit launch
+    u32* q = part + (((mt * 2 + o) * MF_SUB + sub) * (uint64_t)groups + rg) * MF_PART_U32 + 128 * wl + n;
+#pragma unroll
+    for (int x = 0; x < 16; x++) {
+      const int m = 8 * (x >> 2) + 4 * kh + (x & 3);
+      if (!((live >> m) & 1)) continue;
+#pragma unroll
+      for (int nb = 0; nb < 4; nb++) q[(size_t)m * MF_HALF + 32 * nb] = (u32)c[nb][x] << (8 * blo);
+    }
+    return;
+  }
 #pragma unroll
   for (int x = 0; x < 16; x++) {
     const int m = 8 * (x >> 2) + 4 * kh + (x & 3);
     if (!((live >> m) & 1)) continue;
-    const size_t ro = ((mt * MF_TILE + m) * 2 + o) * RING_N + 128 * wl + n;
-    u32* row = acc + ro;
+    u32* row = acc + ((mt * MF_TILE + m) * 2 + o) * RING_N + 128 * wl + n;
 #pragma unroll
     for (int nb = 0; nb < 4; nb++) {
       const u32 v = (u32)c[nb][x] << (8 * blo);
@@ -742,7 +794,9 @@ size_t mf_key_bytes() { return (size_t)LWE_N * MF_KEY_STEP; }
 
 size_t mf_work_bytes(uint64_t B, bool need_acc) {
   const uint64_t tiles = (B + MF_TILE - 1) / MF_TILE;
-  return 2 * tiles * MF_A_TILE + (need_acc ? (size_t)B * 2 * RING_N * 4 : 0);
+  const uint64_t ptiles = tiles < (uint64_t)kPartTiles ? tiles : (uint64_t)kPartTiles;
+  return 2 * tiles * MF_A_TILE + (need_acc ? (size_t)B * 2 * RING_N * 4 : 0) +
+         (size_t)ptiles * 2 * MF_SUB * 6 * MF_PART_U32 * 4;  // partial sums of up to six groups
 }
 
 hipError_t launch_mf_key(const uint32_t* bk, int8_t* E, hipStream_t st) {
@@ -762,8 +816,8 @@ hipError_t launch_blind_rotate_mfma(const vsp_context* ctx, const uint8_t* ops, 
   u32* acc = trlwe ? trlwe : reinterpret_cast<u32*>(Ab[1] + tiles * MF_A_TILE);
   hipLaunchKernelGGL(k_mf_init, dim3((unsigned)((B * 2 * RING_N + 255) / 256)), dim3(256), 0, st, ops, abar, acc, B,
                      nullptr);
-  hipLaunchKernelGGL(k_mf_digits, dim3((unsigned)tiles, 2, MF_TILE / MF_DG), dim3(256), 0, st, ops, abar, acc, Ab[0], B,
-                     0);
+  hipLaunchKernelGGL(k_mf_digits<0>, dim3((unsigned)tiles, 2, MF_TILE / MF_DG), dim3(256), 0, st, ops, abar, acc, Ab[0],
+                     B, 0, nullptr);
   {
     // one event pair around the whole step sequence: its duration / LWE_N is the average step
     // launch including the gaps between launches (an upper bound on the kernel's own time)
@@ -781,23 +835,50 @@ hipError_t launch_blind_rotate_mfma(const vsp_context* ctx, const uint8_t* ops, 
 // Split form of the matrix-core blind rotation: per step one k_mf_part launch (shares of the
 // products added into ACC) and one k_mf_digits launch (the next step's operands from ACC).
 // groups (kSplitGroupChoices) sets the TRGSW rows, or for one row the byte planes, per
-// workgroup; the workspace is that of the fused form (the operands of one step and, without a
-// caller TRLWE, the accumulators).
+// workgroup; a negative count -g (g = 1, 2, 3 or 6) stores the shares as partial sums that
+// the digit launch adds up, instead of integer atomics. The workspace is mf_work_bytes(B, .):
+// the operands of one step, without a caller TRLWE the accumulators, then the partial sums.
+template <int PG>
+static void launch_split_partial_steps(const vsp_context* ctx, const uint8_t* ops, const uint32_t* abar, u32* acc,
+                                       int8_t* Aop, u32* Q, uint64_t B, uint64_t tiles, hipStream_t st,
+                                       bool instrument, const int8_t* const* tkeys) {
+  const dim3 dgrid((unsigned)tiles, 2, MF_TILE / MF_DG), pgrid((unsigned)tiles, 2, (unsigned)(MF_SUB * PG));
+  hipLaunchKernelGGL(k_mf_digits<0>, dgrid, dim3(256), 0, st, ops, abar, acc, Aop, B, 0, nullptr);
+  ProfScope ps(instrument ? ctx : nullptr, 3, st, LWE_N);
+  for (int i = 0; i < LWE_N; i++) {
+    hipLaunchKernelGGL(k_mf_part, pgrid, dim3(MFP_THREADS), 0, st,
+                       tkeys ? nullptr : ctx->mf_key + (size_t)i * MF_KEY_STEP, Aop, acc, ops, B, PG, tkeys,
+                       (uint64_t)i * MF_KEY_STEP, nullptr, nullptr, nullptr, 0, Q);
+    hipLaunchKernelGGL(k_mf_digits<PG>, dgrid, dim3(256), 0, st, ops, abar, acc, Aop, B, i + 1, Q);
+  }
+}
+
 hipError_t launch_blind_rotate_mfsplit(const vsp_context* ctx, const uint8_t* ops, const uint32_t* abar,
                                        uint32_t* tlwe1, uint32_t* trlwe, uint64_t B, void* work, int groups,
                                        hipStream_t st, bool instrument, const int8_t* const* tkeys) {
   if (B == 0) return hipSuccess;
   if (!split_groups_valid(groups)) return hipErrorInvalidValue;
   const uint64_t tiles = (B + MF_TILE - 1) / MF_TILE;
+  if (groups < 0 && tiles > (uint64_t)kPartTiles) groups = -groups;  // no room for the partial sums
   int8_t* Aop = static_cast<int8_t*>(work);
   u32* acc = trlwe ? trlwe : reinterpret_cast<u32*>(Aop + 2 * tiles * MF_A_TILE);
-  const dim3 pgrid((unsigned)tiles, 2, (unsigned)(MF_SUB * groups));
-  if (B <= (uint64_t)MFP_FUSE && groups >= MF_ROWS) {
+  u32* Q = reinterpret_cast<u32*>(Aop + 2 * tiles * MF_A_TILE + (trlwe ? 0 : B * 2 * RING_N * 4));
+  if (groups < 0) {
+    hipLaunchKernelGGL(k_mf_init, dim3((unsigned)((B * 2 * RING_N + 255) / 256)), dim3(256), 0, st, ops, abar, acc, B,
+                       nullptr);
+    switch (-groups) {
+      case 1: launch_split_partial_steps<1>(ctx, ops, abar, acc, Aop, Q, B, tiles, st, instrument, tkeys); break;
+      case 2: launch_split_partial_steps<2>(ctx, ops, abar, acc, Aop, Q, B, tiles, st, instrument, tkeys); break;
+      case 3: launch_split_partial_steps<3>(ctx, ops, abar, acc, Aop, Q, B, tiles, st, instrument, tkeys); break;
+      default: launch_split_partial_steps<6>(ctx, ops, abar, acc, Aop, Q, B, tiles, st, instrument, tkeys); break;
+    }
+  } else if (B <= (uint64_t)MFP_FUSE && groups >= MF_ROWS) {
     // one launch per step: ACC_i in buf[i mod 3], the step adds into buf[(i + 1) mod 3] and
     // clears buf[(i + 2) mod 3]; n is a multiple of 3, so ACC_n ends in buf[0] = acc. The
     // two spare buffers take the (unused) operand area of the workspace.
     static_assert(LWE_N % 3 == 0, "the last step's target is the first buffer");
     static_assert(2 * MFP_FUSE * 2 * RING_N * 4 <= 2 * MF_A_TILE, "spare buffers fit the operand area");
+    const dim3 pgrid((unsigned)tiles, 2, (unsigned)(MF_SUB * groups));
     u32* buf[3] = {acc, reinterpret_cast<u32*>(Aop), reinterpret_cast<u32*>(Aop) + B * 2 * RING_N};
     hipLaunchKernelGGL(k_mf_init, dim3((unsigned)((B * 2 * RING_N + 255) / 256)), dim3(256), 0, st, ops, abar, acc, B,
                        buf[1]);
@@ -805,19 +886,19 @@ hipError_t launch_blind_rotate_mfsplit(const vsp_context* ctx, const uint8_t* op
     for (int i = 0; i < LWE_N; i++)
       hipLaunchKernelGGL(k_mf_part, pgrid, dim3(MFP_THREADS), 0, st,
                          tkeys ? nullptr : ctx->mf_key + (size_t)i * MF_KEY_STEP, Aop, buf[(i + 1) % 3], ops, B,
-                         groups, tkeys, (uint64_t)i * MF_KEY_STEP, buf[i % 3], buf[(i + 2) % 3], abar, i);
+                         groups, tkeys, (uint64_t)i * MF_KEY_STEP, buf[i % 3], buf[(i + 2) % 3], abar, i, nullptr);
   } else {
+    const dim3 dgrid((unsigned)tiles, 2, MF_TILE / MF_DG), pgrid((unsigned)tiles, 2, (unsigned)(MF_SUB * groups));
     hipLaunchKernelGGL(k_mf_init, dim3((unsigned)((B * 2 * RING_N + 255) / 256)), dim3(256), 0, st, ops, abar, acc, B,
                        nullptr);
-    const dim3 dgrid((unsigned)tiles, 2, MF_TILE / MF_DG);
-    hipLaunchKernelGGL(k_mf_digits, dgrid, dim3(256), 0, st, ops, abar, acc, Aop, B, 0);
+    hipLaunchKernelGGL(k_mf_digits<0>, dgrid, dim3(256), 0, st, ops, abar, acc, Aop, B, 0, nullptr);
     ProfScope ps(instrument ? ctx : nullptr, 3, st, LWE_N);
     for (int i = 0; i < LWE_N; i++) {
       hipLaunchKernelGGL(k_mf_part, pgrid, dim3(MFP_THREADS), 0, st,
                          tkeys ? nullptr : ctx->mf_key + (size_t)i * MF_KEY_STEP, Aop, acc, ops, B, groups, tkeys,
-                         (uint64_t)i * MF_KEY_STEP, nullptr, nullptr, nullptr, 0);
+                         (uint64_t)i * MF_KEY_STEP, nullptr, nullptr, nullptr, 0, nullptr);
       if (i + 1 < LWE_N)
-        hipLaunchKernelGGL(k_mf_digits, dgrid, dim3(256), 0, st, ops, abar, acc, Aop, B, i + 1);
+        hipLaunchKernelGGL(k_mf_digits<0>, dgrid, dim3(256), 0, st, ops, abar, acc, Aop, B, i + 1, nullptr);
     }
   }
   hipError_t e = hipGetLastError();
