@@ -138,25 +138,27 @@ constexpr size_t MF_PART_U32 = (size_t)MF_TILE * MF_HALF;
 // workgroups per (tile, output, sub-product)): y0[i] = sum over groups of P1[i] + P2[i],
 // y1[i] = sum of P1[i] + P3[i] from the share blocks of output polynomial h, and ACC_h += y
 // is written back. The updated polynomials of the workgroup's gates are staged in LDS, where
-// the rotated coefficients are read. step == n: the shares of the last step only.
-template <int PG>
+// the rotated coefficients are read. step == n: the shares of the last step only. DG gates
+// per workgroup (8 for the first step of the fused form; the split form takes 4, or 2 with
+// partial sums, for more workgroups on its latency-bound launches).
+template <int PG, int DG = MF_DG>
 __global__ __launch_bounds__(256) void k_mf_digits(const uint8_t* __restrict__ ops, const u32* __restrict__ abar,
                                                     u32* __restrict__ acc, int8_t* __restrict__ A, uint64_t B,
                                                     int step, const u32* __restrict__ part) {
-  // the gates' polynomials h [MF_DG][N] while digits are formed, then the operand words
+  // the gates' polynomials h [DG][N] while digits are formed, then the operand words
   // sA[k][segment][kb][lane][4] gathered in operand order
-  constexpr int SP_U4 = MF_DG * RING_N / 4, SA_U4 = GADGET_L * MF_SUB * MF_KB * 2 * MF_DG;
+  constexpr int SP_U4 = DG * RING_N / 4, SA_U4 = GADGET_L * MF_SUB * MF_KB * 2 * DG;
   __shared__ uint4 lds[SP_U4 > SA_U4 ? SP_U4 : SA_U4];
   const uint64_t mt = blockIdx.x;
   const int h = blockIdx.y, e = blockIdx.z, t = threadIdx.x;
   const int jg = t & 127, kb = jg >> 3, kh = (jg >> 2) & 1, dw = 3 - (jg & 3);
-  constexpr int ROUNDS = MF_DG / 2;
+  constexpr int ROUNDS = DG / 2;
   bool live[ROUNDS];
   uint4 own[ROUNDS][2];
 #pragma unroll
   for (int q = 0; q < ROUNDS; q++) {
     const int mm = 2 * q + (t >> 7);
-    const uint64_t g = mt * MF_TILE + (uint64_t)e * MF_DG + mm;
+    const uint64_t g = mt * MF_TILE + (uint64_t)e * DG + mm;
     live[q] = g < B && (!ops || op_bootstraps(ops[g]));
     uint4* p = reinterpret_cast<uint4*>(acc + (g * 2 + h) * RING_N);
 #pragma unroll
@@ -164,7 +166,7 @@ __global__ __launch_bounds__(256) void k_mf_digits(const uint8_t* __restrict__ o
       own[q][half] = live[q] ? p[half * (MF_HALF / 4) + jg] : make_uint4(0u, 0u, 0u, 0u);
     if (PG > 0 && live[q]) {
       const uint4* Q = reinterpret_cast<const uint4*>(part) +
-                       ((mt * 2 + h) * MF_SUB * PG * MF_TILE + (uint64_t)e * MF_DG + mm) * (MF_HALF / 4) + jg;
+                       ((mt * 2 + h) * MF_SUB * PG * MF_TILE + (uint64_t)e * DG + mm) * (MF_HALF / 4) + jg;
       constexpr size_t SUB_U4 = (size_t)PG * MF_PART_U32 / 4, RG_U4 = MF_PART_U32 / 4;
 #pragma unroll
       for (int rg = 0; rg < (PG > 0 ? PG : 1); rg++) {
@@ -184,7 +186,7 @@ __global__ __launch_bounds__(256) void k_mf_digits(const uint8_t* __restrict__ o
 #pragma unroll
   for (int q = 0; q < ROUNDS; q++) {
     const int mm = 2 * q + (t >> 7);
-    const uint64_t g = mt * MF_TILE + (uint64_t)e * MF_DG + mm;
+    const uint64_t g = mt * MF_TILE + (uint64_t)e * DG + mm;
 #pragma unroll
     for (int k = 0; k < GADGET_L; k++)
 #pragma unroll
@@ -207,22 +209,22 @@ __global__ __launch_bounds__(256) void k_mf_digits(const uint8_t* __restrict__ o
     }
   }
   __syncthreads();  // the staged polynomials are read: the region now gathers operand words
-  u32(*sA)[MF_SUB][MF_KB][2 * MF_DG][4] = reinterpret_cast<u32(*)[MF_SUB][MF_KB][2 * MF_DG][4]>(lds);
+  u32(*sA)[MF_SUB][MF_KB][2 * DG][4] = reinterpret_cast<u32(*)[MF_SUB][MF_KB][2 * DG][4]>(lds);
 #pragma unroll
   for (int q = 0; q < ROUNDS; q++) {
     const int mm = 2 * q + (t >> 7);
 #pragma unroll
     for (int k = 0; k < GADGET_L; k++)
 #pragma unroll
-      for (int sg = 0; sg < MF_SUB; sg++) sA[k][sg][kb][mm + MF_DG * kh][dw] = w[q][k][sg];
+      for (int sg = 0; sg < MF_SUB; sg++) sA[k][sg][kb][mm + DG * kh][dw] = w[q][k][sg];
   }
   __syncthreads();
   // out: rows 3h .. 3h + 2, every segment and block, lanes e*8 + (0..7) and 32 + e*8 + (0..7)
   const uint4* src = lds;
   uint4* dst = reinterpret_cast<uint4*>(A + mt * MF_A_TILE + (size_t)GADGET_L * h * MF_A_ROW);
   for (int c = t; c < SA_U4; c += 256) {
-    const int ll = c % (2 * MF_DG), rk = c / (2 * MF_DG);  // rk = (k * 3 + segment) * MF_KB + kb
-    const int lane = (ll % MF_DG) + MF_DG * e + 32 * (ll / MF_DG);
+    const int ll = c % (2 * DG), rk = c / (2 * DG);  // rk = (k * 3 + segment) * MF_KB + kb
+    const int lane = (ll % DG) + DG * e + 32 * (ll / DG);
     dst[(size_t)rk * 64 + lane] = src[c];
   }
 }
@@ -843,13 +845,15 @@ static void launch_split_partial_steps(const vsp_context* ctx, const uint8_t* op
                                        int8_t* Aop, u32* Q, uint64_t B, uint64_t tiles, hipStream_t st,
                                        bool instrument, const int8_t* const* tkeys) {
   const dim3 dgrid((unsigned)tiles, 2, MF_TILE / MF_DG), pgrid((unsigned)tiles, 2, (unsigned)(MF_SUB * PG));
+  constexpr int DG = 2;
+  const dim3 rgrid((unsigned)tiles, 2, MF_TILE / DG);
   hipLaunchKernelGGL(k_mf_digits<0>, dgrid, dim3(256), 0, st, ops, abar, acc, Aop, B, 0, nullptr);
   ProfScope ps(instrument ? ctx : nullptr, 3, st, LWE_N);
   for (int i = 0; i < LWE_N; i++) {
     hipLaunchKernelGGL(k_mf_part, pgrid, dim3(MFP_THREADS), 0, st,
                        tkeys ? nullptr : ctx->mf_key + (size_t)i * MF_KEY_STEP, Aop, acc, ops, B, PG, tkeys,
                        (uint64_t)i * MF_KEY_STEP, nullptr, nullptr, nullptr, 0, Q);
-    hipLaunchKernelGGL(k_mf_digits<PG>, dgrid, dim3(256), 0, st, ops, abar, acc, Aop, B, i + 1, Q);
+    hipLaunchKernelGGL((k_mf_digits<PG, DG>), rgrid, dim3(256), 0, st, ops, abar, acc, Aop, B, i + 1, Q);
   }
 }
 
@@ -888,17 +892,18 @@ hipError_t launch_blind_rotate_mfsplit(const vsp_context* ctx, const uint8_t* op
                          tkeys ? nullptr : ctx->mf_key + (size_t)i * MF_KEY_STEP, Aop, buf[(i + 1) % 3], ops, B,
                          groups, tkeys, (uint64_t)i * MF_KEY_STEP, buf[i % 3], buf[(i + 2) % 3], abar, i, nullptr);
   } else {
-    const dim3 dgrid((unsigned)tiles, 2, MF_TILE / MF_DG), pgrid((unsigned)tiles, 2, (unsigned)(MF_SUB * groups));
+    constexpr int DG = 4;
+    const dim3 dgrid((unsigned)tiles, 2, MF_TILE / DG), pgrid((unsigned)tiles, 2, (unsigned)(MF_SUB * groups));
     hipLaunchKernelGGL(k_mf_init, dim3((unsigned)((B * 2 * RING_N + 255) / 256)), dim3(256), 0, st, ops, abar, acc, B,
                        nullptr);
-    hipLaunchKernelGGL(k_mf_digits<0>, dgrid, dim3(256), 0, st, ops, abar, acc, Aop, B, 0, nullptr);
+    hipLaunchKernelGGL((k_mf_digits<0, DG>), dgrid, dim3(256), 0, st, ops, abar, acc, Aop, B, 0, nullptr);
     ProfScope ps(instrument ? ctx : nullptr, 3, st, LWE_N);
     for (int i = 0; i < LWE_N; i++) {
       hipLaunchKernelGGL(k_mf_part, pgrid, dim3(MFP_THREADS), 0, st,
                          tkeys ? nullptr : ctx->mf_key + (size_t)i * MF_KEY_STEP, Aop, acc, ops, B, groups, tkeys,
                          (uint64_t)i * MF_KEY_STEP, nullptr, nullptr, nullptr, 0, nullptr);
       if (i + 1 < LWE_N)
-        hipLaunchKernelGGL(k_mf_digits<0>, dgrid, dim3(256), 0, st, ops, abar, acc, Aop, B, i + 1, nullptr);
+        hipLaunchKernelGGL((k_mf_digits<0, DG>), dgrid, dim3(256), 0, st, ops, abar, acc, Aop, B, i + 1, nullptr);
     }
   }
   hipError_t e = hipGetLastError();
