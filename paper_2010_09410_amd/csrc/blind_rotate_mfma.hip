@@ -892,7 +892,7 @@ hipError_t launch_blind_rotate_mfsplit(const vsp_context* ctx, const uint8_t* op
                          tkeys ? nullptr : ctx->mf_key + (size_t)i * MF_KEY_STEP, Aop, buf[(i + 1) % 3], ops, B,
                          groups, tkeys, (uint64_t)i * MF_KEY_STEP, buf[i % 3], buf[(i + 2) % 3], abar, i, nullptr);
   } else {
-    constexpr int DG = 4;
+    constexpr int DG = 2;
     const dim3 dgrid((unsigned)tiles, 2, MF_TILE / DG), pgrid((unsigned)tiles, 2, (unsigned)(MF_SUB * groups));
     hipLaunchKernelGGL(k_mf_init, dim3((unsigned)((B * 2 * RING_N + 255) / 256)), dim3(256), 0, st, ops, abar, acc, B,
                        nullptr);

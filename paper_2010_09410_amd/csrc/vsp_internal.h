@@ -92,9 +92,9 @@ struct Tuning {
   // split form, at the sizes kSplitAt: time in the same units as br_round_ms, and row groups
   // (0: the count that fills the chip, mf_split_groups). The defaults are relative times
   // measured on an MI355X (one 4-gate-workgroup round = 1).
-  float split_ms[kSplitPts] = {0.113f, 0.259f, 0.336f, 0.427f, 0.568f, 0.700f, 0.886f, 0.972f, 1.287f, 1.329f, 1.433f,
-                               2.144f, 2.505f};
-  int split_groups[kSplitPts] = {24, 12, 6, -6, -2, -3, -2, -1, -2, -2, -2, -2, -1};
+  float split_ms[kSplitPts] = {0.114f, 0.190f, 0.246f, 0.355f, 0.505f, 0.670f, 0.857f, 0.916f, 1.253f, 1.333f, 1.399f,
+                               2.180f, 2.530f};
+  int split_groups[kSplitPts] = {24, 12, -6, -6, -2, -3, -2, -1, -2, -2, -2, -2, 1};
   int br_force[kTuneBuckets] = {0, 0, 0, 0, 0, 0, 0};
   int ks_form[kTuneBuckets] = {2, 2, 2, 2, 3, 3, 3};
   bool tuned = false;
