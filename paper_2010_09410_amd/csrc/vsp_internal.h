@@ -79,7 +79,7 @@ constexpr uint64_t kSplitAt[kSplitPts] = {1, 16, 64, 256, 512, 768, 1024, 1280, 
 //    br_round_ms[s] the time of one full round. The split matrix-core form is timed instead
 //    at the sizes kSplitAt (split_ms[k], with the fastest row-group count split_groups[k]) and
 //    estimated in between by linear interpolation (beyond the last size: in proportion), with
-//    a 10% margin above 1,280 gates.
+//    a 3% margin above 1,280 gates.
 //    The shape with the fewer milliseconds wins (ties: the 8-gate workgroup). br_force[b] != 0
 //    pins the shape for bucket b.
 //  * Key switch: per bucket, form 0 gathers key rows per gate, 1 reads them once per tile of
@@ -114,9 +114,9 @@ struct Tuning {
       if (ntt_only && s >= 3) continue;
       const uint64_t cap = br_cap[s] ? br_cap[s] : 1;
       double ms = (double)((B + cap - 1) / cap) * br_round_ms[s];
-      // above 1,280 gates the split form's time varies by up to 10% between neighbouring sizes
-      // (measured; workgroup balance and atomics), so it must win by that much
-      if (s == 4) ms = split_estimate(B) * (B > kSplitAt[7] ? 1.1 : 1.0);
+      // above 1,280 gates the split form's time deviates from the interpolation by a few
+      // percent between neighbouring sizes (measured: workgroup balance), so it must win by 3%
+      if (s == 4) ms = split_estimate(B) * (B > kSplitAt[7] ? 1.03 : 1.0);
       if (s == 1 || ms < best_ms) {
         best = s;
         best_ms = ms;

@@ -74,7 +74,7 @@ def model_choice(entry, B):
         f = (B - at[b - 1]) / (at[b] - at[b - 1])
         return sms[b - 1] + f * (sms[b] - sms[b - 1])
     est = {s: -(-B // caps[s]) * ms[s] for s in range(4)}
-    est[4] = split(B) * (1.1 if B > 1280 else 1.0)
+    est[4] = split(B) * (1.03 if B > 1280 else 1.0)
     best = 1
     for s in (0, 2, 3, 4):
         if est[s] < est[best]:
