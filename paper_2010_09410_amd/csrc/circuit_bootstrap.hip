@@ -224,38 +224,65 @@ __global__ __launch_bounds__(CB_THREADS, 2) void k_cb_rotate(const u64* __restri
   if (tid == 0) dst[CB_N2] = acc[CB_N2] + tvv;
 }
 
-// Private functional key switch: workgroup (job, u), thread t owning output words t + 256 q of
-// the TRLWE [2][N]; out = sum_{k <= N2, p < t2} PKSK[u][k][p][v_{k,p} - 1] over the nonzero
-// base-4 digits v_{k,p} (most significant first) of c_k rounded to 24 bits. Row u = 0 is
-// TRGSW row j - 1, u = 1 row l + j - 1.
-__global__ __launch_bounds__(256) void k_cb_privks(const u32* __restrict__ pksk, const u64* __restrict__ tl2,
-                                                   u32* __restrict__ out, int gadget_l) {
-  const uint64_t job = blockIdx.x;
-  const int u = blockIdx.y, tid = threadIdx.x;
-  const int j = (int)(job % (uint64_t)gadget_l) + 1;
-  const u64* c = tl2 + job * CB_TLWE2;
-  const u32* key = pksk + (size_t)u * CB_PKS_U + tid;
+// Private functional key switch: out = sum_{k <= N2, p < t2} PKSK[u][k][p][v_{k,p} - 1] over the
+// nonzero base-4 digits v_{k,p} (most significant first) of c_k rounded to 24 bits. Row u = 0
+// is TRGSW row j - 1, u = 1 row l + j - 1. Row-stationary: workgroup (tile of G jobs, u, slice
+// of 256 output words), thread t owning word 256 slice + t; for every (k, p) it loads the three
+// key words of its column once and adds the one each job's digit selects, so the key is read
+// once per tile instead of once per job (sums mod 2^32 in any order: the same bits). The
+// rounded coefficients of the tile's jobs are staged in LDS a chunk of k at a time.
+constexpr int CBP_CHUNK = 32;
+template <int G>
+__global__ __launch_bounds__(256, 2) void k_cb_privks(const u32* __restrict__ pksk, const u64* __restrict__ tl2,
+                                                   u32* __restrict__ out, int gadget_l, uint64_t jobs) {
+  __shared__ u32 chat[CBP_CHUNK][G];
+  const uint64_t j0 = (uint64_t)blockIdx.x * G;
+  const int u = blockIdx.y, tid = threadIdx.x, col = (int)blockIdx.z * 256 + tid;
+  const int ng = (int)((jobs - j0 < (uint64_t)G) ? jobs - j0 : (uint64_t)G);
   constexpr int TB = CB_T * CB_BB;
-  u32 a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (int k = 0; k < CB_TLWE2; k++) {
-    const u64 chat = (c[k] + (1ull << (64 - TB - 1))) >> (64 - TB);
-    const u32* kk = key + (size_t)k * CB_T * 3 * CB_PKS_ROW;
+  const u32* key = pksk + (size_t)u * CB_PKS_U + col;
+  u32 a[G];
 #pragma unroll
-    for (int p = 0; p < CB_T; p++) {
-      const u32 v = (u32)(chat >> (CB_BB * (CB_T - 1 - p))) & 3u;
-      const u32 mask = v ? 0xFFFFFFFFu : 0u;
-      const u32* row = kk + ((size_t)p * 3 + (v ? v - 1 : 0)) * CB_PKS_ROW;
-      u32 w[8];
+  for (int g = 0; g < G; g++) a[g] = 0u;
+  for (int k0 = 0; k0 < CB_TLWE2; k0 += CBP_CHUNK) {
+    __syncthreads();  // the previous chunk is consumed
+    for (int i = tid; i < CBP_CHUNK * G; i += 256) {
+      const int kk = i / G, g = i % G;
+      u32 v = 0u;
+      if (g < ng && k0 + kk < CB_TLWE2)
+        v = (u32)((tl2[(j0 + g) * CB_TLWE2 + k0 + kk] + (1ull << (64 - TB - 1))) >> (64 - TB));
+      chat[kk][g] = v;
+    }
+    __syncthreads();
+    const int kn = (CB_TLWE2 - k0 < CBP_CHUNK) ? CB_TLWE2 - k0 : CBP_CHUNK;
+    for (int kk = 0; kk < kn; kk++) {
+      const u32* kr = key + (size_t)(k0 + kk) * CB_T * 3 * CB_PKS_ROW;
+      u32 c[G];  // the jobs' rounded coefficients: the same in every lane
 #pragma unroll
-      for (int q = 0; q < 8; q++) w[q] = row[q * 256];
+      for (int g = 0; g < G; g++) c[g] = __builtin_amdgcn_readfirstlane(chat[kk][g]);
 #pragma unroll
-      for (int q = 0; q < 8; q++) a[q] += w[q] & mask;
+      for (int p = 0; p < CB_T; p++) {
+        const u32 r0 = kr[(size_t)(p * 3) * CB_PKS_ROW], r1 = kr[(size_t)(p * 3 + 1) * CB_PKS_ROW],
+                  r2 = kr[(size_t)(p * 3 + 2) * CB_PKS_ROW];
+#pragma unroll
+        for (int g = 0; g < G; g++) {
+          // digit v = 2 b1 + b0 as all-ones / zero masks; row v - 1 (none for v = 0) picked with
+          // two bit-field selects, without branches
+          const u32 v = (c[g] >> (CB_BB * (CB_T - 1 - p))) & 3u;
+          const u32 m0 = 0u - (v & 1u), m1 = 0u - (v >> 1);
+          const u32 odd = (m1 & r2) | (~m1 & r0);  // v = 3 or 1
+          const u32 even = m1 & r1;                // v = 2 or 0
+          a[g] += (m0 & odd) | (~m0 & even);
+        }
+      }
     }
   }
-  const int row = u == 0 ? j - 1 : gadget_l + j - 1;
-  u32* dst = out + ((job / (uint64_t)gadget_l) * 2 * gadget_l + row) * CB_PKS_ROW + tid;
-#pragma unroll
-  for (int q = 0; q < 8; q++) dst[q * 256] = a[q];
+  for (int g = 0; g < ng; g++) {
+    const uint64_t job = j0 + g;
+    const int j = (int)(job % (uint64_t)gadget_l) + 1;
+    const int row = u == 0 ? j - 1 : gadget_l + j - 1;
+    out[((job / (uint64_t)gadget_l) * 2 * gadget_l + row) * CB_PKS_ROW + col] = a[g];
+  }
 }
 
 hipError_t init_cb_kernel_attributes() {
@@ -343,7 +370,22 @@ vsp_status vsp_circuit_bootstrap(vsp_context* ctx, vsp_cbkey* key, const uint32_
   u64* tl2 = static_cast<u64*>(key->tl2.ptr);
   hipLaunchKernelGGL(k_cb_rotate, dim3((unsigned)jobs), dim3(CB_THREADS), CB_LDS, st, key->key, ctx->tw, d_in,
                      static_cast<u64*>(key->acc.ptr), tl2, GADGET_L, BG_BIT);
-  hipLaunchKernelGGL(k_cb_privks, dim3((unsigned)jobs, 2), dim3(256), 0, st, key->pksk, tl2, d_out, GADGET_L);
+  // tiles as large as keep about four workgroups per compute unit busy (16 per tile and u)
+  const uint64_t slices = CB_PKS_ROW / 256;
+  auto tiles = [&](uint64_t g) { return (jobs + g - 1) / g; };
+  const uint64_t want = 4ull * (uint64_t)(ctx->cus > 0 ? ctx->cus : 256);
+  if (tiles(32) * 2 * slices >= want)
+    hipLaunchKernelGGL(k_cb_privks<32>, dim3((unsigned)tiles(32), 2, (unsigned)slices), dim3(256), 0, st, key->pksk,
+                       tl2, d_out, GADGET_L, jobs);
+  else if (tiles(16) * 2 * slices >= want)
+    hipLaunchKernelGGL(k_cb_privks<16>, dim3((unsigned)tiles(16), 2, (unsigned)slices), dim3(256), 0, st, key->pksk,
+                       tl2, d_out, GADGET_L, jobs);
+  else if (tiles(8) * 2 * slices >= want)
+    hipLaunchKernelGGL(k_cb_privks<8>, dim3((unsigned)tiles(8), 2, (unsigned)slices), dim3(256), 0, st, key->pksk,
+                       tl2, d_out, GADGET_L, jobs);
+  else
+    hipLaunchKernelGGL(k_cb_privks<2>, dim3((unsigned)tiles(2), 2, (unsigned)slices), dim3(256), 0, st, key->pksk,
+                       tl2, d_out, GADGET_L, jobs);
   VSP_HIP(hipGetLastError());
   return VSP_OK;
 }
