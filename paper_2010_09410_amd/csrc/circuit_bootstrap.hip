@@ -236,6 +236,7 @@ template <int G>
 __global__ __launch_bounds__(256, 2) void k_cb_privks(const u32* __restrict__ pksk, const u64* __restrict__ tl2,
                                                    u32* __restrict__ out, int gadget_l, uint64_t jobs) {
   __shared__ u32 chat[CBP_CHUNK][G];
+  __shared__ u32 tab[CB_T][4][256];  // thread t's column: entry v of digit p (v = 0: zero)
   const uint64_t j0 = (uint64_t)blockIdx.x * G;
   const int u = blockIdx.y, tid = threadIdx.x, col = (int)blockIdx.z * 256 + tid;
   const int ng = (int)((jobs - j0 < (uint64_t)G) ? jobs - j0 : (uint64_t)G);
@@ -244,6 +245,8 @@ __global__ __launch_bounds__(256, 2) void k_cb_privks(const u32* __restrict__ pk
   u32 a[G];
 #pragma unroll
   for (int g = 0; g < G; g++) a[g] = 0u;
+#pragma unroll
+  for (int p = 0; p < CB_T; p++) tab[p][0][tid] = 0u;
   for (int k0 = 0; k0 < CB_TLWE2; k0 += CBP_CHUNK) {
     __syncthreads();  // the previous chunk is consumed
     for (int i = tid; i < CBP_CHUNK * G; i += 256) {
@@ -260,21 +263,16 @@ __global__ __launch_bounds__(256, 2) void k_cb_privks(const u32* __restrict__ pk
       u32 c[G];  // the jobs' rounded coefficients: the same in every lane
 #pragma unroll
       for (int g = 0; g < G; g++) c[g] = __builtin_amdgcn_readfirstlane(chat[kk][g]);
+      // the thread's own column goes to LDS, where a wave-uniform digit indexes it (no compare
+      // and select per job and digit; each thread reads only what it wrote, so no barrier)
 #pragma unroll
-      for (int p = 0; p < CB_T; p++) {
-        const u32 r0 = kr[(size_t)(p * 3) * CB_PKS_ROW], r1 = kr[(size_t)(p * 3 + 1) * CB_PKS_ROW],
-                  r2 = kr[(size_t)(p * 3 + 2) * CB_PKS_ROW];
+      for (int p = 0; p < CB_T; p++)
 #pragma unroll
-        for (int g = 0; g < G; g++) {
-          // digit v = 2 b1 + b0 as all-ones / zero masks; row v - 1 (none for v = 0) picked with
-          // two bit-field selects, without branches
-          const u32 v = (c[g] >> (CB_BB * (CB_T - 1 - p))) & 3u;
-          const u32 m0 = 0u - (v & 1u), m1 = 0u - (v >> 1);
-          const u32 odd = (m1 & r2) | (~m1 & r0);  // v = 3 or 1
-          const u32 even = m1 & r1;                // v = 2 or 0
-          a[g] += (m0 & odd) | (~m0 & even);
-        }
-      }
+        for (int v = 0; v < 3; v++) tab[p][v + 1][tid] = kr[(size_t)(p * 3 + v) * CB_PKS_ROW];
+#pragma unroll
+      for (int p = 0; p < CB_T; p++)
+#pragma unroll
+        for (int g = 0; g < G; g++) a[g] += tab[p][(c[g] >> (CB_BB * (CB_T - 1 - p))) & 3u][tid];
     }
   }
   for (int g = 0; g < ng; g++) {
