@@ -515,6 +515,13 @@ vsp_status vsp_ram_write(vsp_context* ctx, uint32_t* d_ram, uint32_t v, uint32_t
   // mem_d: tlwe0 [cells] then abar [cells]
   if ((s = scratch_reserve(ctx, ctx->mem_d, cells * T0 * 2))) return s;
   if ((s = scratch_reserve(ctx, ctx->tlwe1, cells * T1))) return s;
+  // matrix-core workspace for the control and refresh bootstraps where the tuning picks those
+  // forms (both write TRLWE outputs, so no accumulator area)
+  const uint64_t nbr = std::max<uint64_t>(2 * (uint64_t)w, cells);
+  const bool matrix =
+      br_matrix_form(ctx->tune.br_waves(2 * (uint64_t)w)) || br_matrix_form(ctx->tune.br_waves(cells));
+  if (matrix && (s = scratch_reserve(ctx, ctx->mf_work, mf_work_bytes(nbr, false)))) return s;
+  void* mfw = matrix ? ctx->mf_work.ptr : nullptr;
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* mc = static_cast<char*>(ctx->mem_c.ptr);
   uint64_t* sel = static_cast<uint64_t*>(ctx->ntt_sel.ptr);
@@ -549,14 +556,16 @@ vsp_status vsp_ram_write(vsp_context* ctx, uint32_t* d_ram, uint32_t v, uint32_t
   if ((e = launch_gate_prologue(ctx, ops, src, src, idx, idx + 2 * w, nullptr, abar, nullptr, 2 * (uint64_t)w, st,
                                 false)) != hipSuccess)
     return hip_fail(e, "control prologue");
-  if ((e = launch_blind_rotate(ctx, ops, abar, nullptr, acc2, 2 * (uint64_t)w, 0, st)) != hipSuccess)
+  if ((e = launch_blind_rotate(ctx, ops, abar, nullptr, acc2, 2 * (uint64_t)w, 0, st, nullptr, nullptr, nullptr,
+                              mfw)) != hipSuccess)
     return hip_fail(e, "control bootstraps");
   if ((e = launch_ram_control(acc2, u, (int)w, st)) != hipSuccess) return hip_fail(e, "control combine");
   // write unit: bars, then refresh every cell with a bootstrap back to TRLWE, in place
   if ((e = launch_ram_bars(ctx, sel, selneg, d_ram, u, t1, (int)v, (int)w, st)) != hipSuccess) return hip_fail(e, "write bars");
   if ((e = launch_keyswitch(ctx, nullptr, t1, nullptr, t0, cells, st)) != hipSuccess) return hip_fail(e, "refresh key switch");
   if ((e = launch_gate_prologue_uniform(ctx, OP_IDENT, t0, abar, cells, st)) != hipSuccess) return hip_fail(e, "refresh prologue");
-  if ((e = launch_blind_rotate(ctx, nullptr, abar, nullptr, d_ram, cells, 0, st)) != hipSuccess)
+  if ((e = launch_blind_rotate(ctx, nullptr, abar, nullptr, d_ram, cells, 0, st, nullptr, nullptr, nullptr, mfw)) !=
+      hipSuccess)
     return hip_fail(e, "refresh bootstraps");
   return VSP_OK;
 }

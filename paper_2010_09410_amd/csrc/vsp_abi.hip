@@ -549,6 +549,11 @@ vsp_status vsp_mux(vsp_context* ctx, const uint32_t* d_sel, const uint32_t* d_in
   const uint64_t chunk = std::min<uint64_t>(B, kMaxLaunch / 2);
   if ((s = scratch_reserve(ctx, ctx->abar, 2 * chunk * (LWE_N + 1) * 4))) return s;
   if ((s = scratch_reserve(ctx, ctx->tlwe1, 2 * chunk * (RING_N + 1) * 4))) return s;
+  // the 2B bootstraps take the matrix-core forms where the tuning picks them (one workspace)
+  const bool matrix = br_matrix_form(ctx->tune.br_waves(2 * chunk)) ||
+                      (B > chunk && br_matrix_form(ctx->tune.br_waves(2 * (B % chunk))));
+  if (matrix && (s = scratch_reserve(ctx, ctx->mf_work, mf_work_bytes(2 * chunk, true)))) return s;
+  void* mfw = matrix ? ctx->mf_work.ptr : nullptr;
   hipStream_t st = static_cast<hipStream_t>(stream);
   uint32_t* abar = static_cast<uint32_t*>(ctx->abar.ptr);
   uint32_t* t1 = static_cast<uint32_t*>(ctx->tlwe1.ptr);
@@ -563,7 +568,7 @@ vsp_status vsp_mux(vsp_context* ctx, const uint32_t* d_sel, const uint32_t* d_in
     if (e != hipSuccess) return hip_fail(e, "mux prologue");
     {
       ProfScope ps(ctx, 0, st);
-      e = launch_blind_rotate(ctx, nullptr, abar, t1, nullptr, 2 * nb, 0, st);
+      e = launch_blind_rotate(ctx, nullptr, abar, t1, nullptr, 2 * nb, 0, st, nullptr, nullptr, nullptr, mfw);
     }
     if (e != hipSuccess) return hip_fail(e, "blind rotation");
     if ((e = launch_mux_combine(t1, nb, st)) != hipSuccess) return hip_fail(e, "mux combine");
