@@ -368,6 +368,13 @@ vsp_status vsp_debug_polymul(vsp_context* ctx, const int32_t* d_a, const uint32_
 vsp_status vsp_cbkey_create(vsp_context* ctx, const uint64_t* bk2_host, const uint32_t* pksk_host, vsp_cbkey** out);
 vsp_status vsp_cbkey_destroy(vsp_cbkey* key);
 
+/* The level-2 blind rotation's form for later vsp_circuit_bootstrap calls with this key: 0 (the
+ * default) picks by batch size, 1 forces one workgroup of four waves per (conversion, gadget
+ * level) job, two per compute unit (throughput), 2 forces eight waves per job, one per compute
+ * unit, with a step's eight digit rows transformed at once (latency). Results are the same
+ * for every form; form outside [0, 2] is VSP_E_ARG. */
+vsp_status vsp_cbkey_set_form(vsp_cbkey* key, int form);
+
 /* d_out[r] [2l][2][N] = the level-1 TRGSW of the bit that the level-0 TLWE d_in[r] [n+1]
  * encrypts (+-1/8 encoding), for r < R: for each gadget level j = 1..l a level-2 blind
  * rotation with test vector 1/(2 Bg^j), SampleExtract at 0 plus 1/(2 Bg^j), then the two

@@ -75,6 +75,7 @@ SIGNATURES = {
     "vsp_cbkey_create": (_st, [_vp, _vp, _vp, ctypes.POINTER(_vp)]),
     "vsp_machine_attach_ram": (_st, [_vp, _vp, _vp, ctypes.c_uint32, ctypes.c_uint32, _vp, ctypes.c_uint32, _vp, _vp]),
     "vsp_cbkey_destroy": (_st, [_vp]),
+    "vsp_cbkey_set_form": (_st, [_vp, _i32]),
     "vsp_circuit_bootstrap": (_st, [_vp, _vp, _vp, _vp, _u64, _vp]),
     "vsp_server_submit_keyset": (_st, [_vp, _vp, ctypes.POINTER(vsp_gate_desc), _u64, _u64, _vp, ctypes.POINTER(_u64)]),
     "vsp_mux": (_st, [_vp, _vp, _vp, _vp, _vp, _u64, _vp]),
@@ -257,6 +258,10 @@ def vsp_machine_attach_ram(m, key, d_ram, v, w, addr_wires, flag_wire, data_wire
 
 def vsp_cbkey_destroy(k) -> None:
     _call("vsp_cbkey_destroy", k)
+
+
+def vsp_cbkey_set_form(k, form: int) -> None:
+    _call("vsp_cbkey_set_form", k, form)
 
 
 def vsp_circuit_bootstrap(ctx, key, d_in, d_out, R, stream=None) -> None:

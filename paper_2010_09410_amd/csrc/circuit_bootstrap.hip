@@ -224,6 +224,140 @@ __global__ __launch_bounds__(CB_THREADS, 2) void k_cb_rotate(const u64* __restri
   if (tid == 0) dst[CB_N2] = acc[CB_N2] + tvv;
 }
 
+// Latency form of the level-2 blind rotation: one workgroup of eight waves per job, so that a
+// step's eight digit rows are transformed at once (wave w: polynomial h = w / 4, digit
+// w % 4 + 1, into its own LDS block) and the key products are split by polynomial (wave w:
+// output o and half-word wd of c = w % 4 = 2 o + wd over the rows of h = w / 4). The sums of
+// h = 1 then go through the LDS blocks of waves 4-7 to waves 0-3, which invert them and update
+// ACC as in k_cb_rotate. 144 KiB of LDS, one workgroup per compute unit: for batches that the
+// four-wave form would run in a single round anyway, where each step's critical path is then
+// one transform and four rows of key products instead of two and eight.
+constexpr int CBW_THREADS = 512;
+constexpr size_t CBW_LDS = (8 * CB_BLOCK_U64 + 2048) * 8;  // digit blocks + twiddle tables: 144 KiB
+
+__global__ __launch_bounds__(CBW_THREADS, 1) void k_cb_rotate_wide(const u64* __restrict__ key,
+                                                                  const u64* __restrict__ tw,
+                                                                  const u32* __restrict__ in,
+                                                                  u64* __restrict__ accbuf, u64* __restrict__ out,
+                                                                  int gadget_l, int bgbit) {
+  extern __shared__ u64 cb_lds[];
+  u64* dig = cb_lds;                                           // [8][32][64]
+  u64* tws = dig + 8 * CB_BLOCK_U64;                           // forward then inverse tables
+  const uint64_t job = blockIdx.x;
+  const int j = (int)(job % (uint64_t)gadget_l) + 1;
+  const u32* c = in + (job / (uint64_t)gadget_l) * TLWE0;
+  u64* acc = accbuf + job * 2 * CB_N2;                         // [2][N2]
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, l = lane & 31, half = lane >> 5;
+  u64* myblock = dig + (size_t)wave * CB_BLOCK_U64;
+  u32* reg = reinterpret_cast<u32*>(myblock) + half * TREGION;
+  const u64 tvv = 1ull << (63 - bgbit * j);                    // 1/(2 Bg^j)
+  for (int i = tid; i < 2048; i += CBW_THREADS) tws[i] = tw[i];
+  {
+    const u32 bbar = ((c[LWE_N] + (1u << 19)) >> 20) & (2 * CB_N2 - 1);
+    const int k = (int)((2 * CB_N2 - bbar) & (2 * CB_N2 - 1));
+    for (int m = tid; m < CB_N2; m += CBW_THREADS) {
+      const bool neg = (m < (k & (CB_N2 - 1))) != (k >= CB_N2);
+      acc[m] = 0;
+      acc[CB_N2 + m] = neg ? (0ull - tvv) : tvv;
+    }
+  }
+  __syncthreads();
+  const int h = wave >> 2, cw = wave & 3, o = cw >> 1, wd = cw & 1;
+  for (int i = 0; i < LWE_N; i++) {
+    const int abar = (int)(((c[i] + (1u << 19)) >> 20) & (2 * CB_N2 - 1));
+    const u64* kstep = key + (size_t)i * CB_KEY_STEP;
+    {
+      const u64* P = acc + h * CB_N2;
+      u64 x[32];
+      const int sh = 64 - CB_BG2 * (cw + 1);
+#pragma unroll
+      for (int t8 = 0; t8 < 32; t8 += 8) {
+#pragma unroll
+        for (int t = t8; t < t8 + 8; t++) {
+          const int m = 2 * (l + 32 * t) + half;
+          const int src = (m - abar) & (2 * CB_N2 - 1);
+          const u64 r = P[src & (CB_N2 - 1)];
+          const u64 d = ((src & CB_N2) ? (0ull - r) : r) - P[m];
+          x[t] = (u64)((int64_t)(((d + CB_DECOMP_OFFSET) >> sh) & ((1u << CB_BG2) - 1)) - (1 << (CB_BG2 - 1)));
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      ntt_forward<true>(x, tws, reg, l);
+#pragma unroll
+      for (int s = 0; s < 32; s++) myblock[(size_t)s * 64 + lane] = x[s];
+    }
+    __syncthreads();
+    u64 sum[32];
+#pragma unroll
+    for (int s = 0; s < 32; s++) sum[s] = 0;
+    {
+      auto key_row = [&](int r) {
+        return reinterpret_cast<const ulonglong2*>(kstep + ((((size_t)(h * CB_L2 + r)) * 2 + o) * 2 + wd) *
+                                                               CB_KEY_BLOCK) + lane;
+      };
+      ulonglong2 kc[CB_KCH];
+      {
+        const ulonglong2* kb = key_row(0);
+#pragma unroll
+        for (int q = 0; q < CB_KCH; q++) kc[q] = kb[q * 64];
+      }
+#pragma unroll 1
+      for (int r = 0; r < CB_L2; r++) {
+        const ulonglong2* kb = key_row(r);
+        const ulonglong2* kb_next = key_row(r + 1 < CB_L2 ? r + 1 : r);
+        const u64* dr = dig + (size_t)(h * CB_L2 + r) * CB_BLOCK_U64;
+#pragma unroll
+        for (int cc = 0; cc < 32 / CB_KCH; cc++) {
+          ulonglong2 kn[CB_KCH];
+#pragma unroll
+          for (int q = 0; q < CB_KCH; q++)
+            kn[q] = (cc + 1 < 32 / CB_KCH) ? kb[(CB_KCH * (cc + 1) + q) * 64] : kb_next[q * 64];
+#pragma unroll
+          for (int q = 0; q < CB_KCH; q++) {
+            const int sl = CB_KCH * cc + q;
+            sum[sl] = gl_add(sum[sl], gl_dot2(dr[sl * 64 + l], kc[q].x, dr[sl * 64 + 32 + l], kc[q].y));
+          }
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int q = 0; q < CB_KCH; q++) kc[q] = kn[q];
+        }
+      }
+    }
+    __syncthreads();  // every digit block is read
+    if (h == 1) {
+#pragma unroll
+      for (int s = 0; s < 32; s++) myblock[(size_t)s * 64 + lane] = sum[s];
+    }
+    __syncthreads();
+    u64 z[32];
+    u32* xch = reinterpret_cast<u32*>(dig + (size_t)(2 * o + 1) * CB_BLOCK_U64);
+    if (h == 0) {
+      const u64* other = dig + (size_t)(4 + cw) * CB_BLOCK_U64;
+#pragma unroll
+      for (int s = 0; s < 32; s++) sum[s] = gl_add(sum[s], other[(size_t)s * 64 + lane]);
+      ntt_inverse_lift64(sum, tws + 1024, reg, l, z);
+      // the high word of output o goes through the LDS block of wave 2 o + 1 (its own)
+      if (wd == 1) {
+#pragma unroll
+        for (int t = 0; t < 32; t++) xch[2 * (l + 32 * t) + half] = (u32)z[t];
+      }
+    }
+    __syncthreads();
+    if (h == 0 && wd == 0) {
+      u64* A = acc + o * CB_N2;
+#pragma unroll
+      for (int t = 0; t < 32; t++) {
+        const int m = 2 * (l + 32 * t) + half;
+        A[m] += z[t] + ((u64)xch[m] << 32);
+      }
+    }
+    __syncthreads();
+  }
+  u64* dst = out + job * CB_TLWE2;
+  for (int m = tid; m < CB_N2; m += CBW_THREADS) dst[m] = (m == 0) ? acc[0] : (0ull - acc[CB_N2 - m]);
+  if (tid == 0) dst[CB_N2] = acc[CB_N2] + tvv;
+}
+
 // Private functional key switch: out = sum_{k <= N2, p < t2} PKSK[u][k][p][v_{k,p} - 1] over the
 // nonzero base-4 digits v_{k,p} (most significant first) of c_k rounded to 24 bits. Row u = 0
 // is TRGSW row j - 1, u = 1 row l + j - 1. Row-stationary: workgroup (tile of G jobs, u, slice
@@ -284,8 +418,12 @@ __global__ __launch_bounds__(256, 2) void k_cb_privks(const u32* __restrict__ pk
 }
 
 hipError_t init_cb_kernel_attributes() {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cb_rotate), hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)CB_LDS);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cb_rotate),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)CB_LDS);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cb_rotate_wide), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)CBW_LDS);
+  return e;
 }
 
 }  // namespace vsp
@@ -298,6 +436,7 @@ struct vsp_cbkey {
   u32* pksk = nullptr;  // private key-switching keys
   Scratch tl2;          // TLWE2 outputs of the blind rotations
   Scratch acc;          // their accumulators [job][2][N2]
+  int form = 0;         // level-2 blind rotation: 0 by batch size, 1 four-wave form, 2 eight-wave form
 };
 
 extern "C" {
@@ -349,6 +488,13 @@ vsp_status vsp_cbkey_destroy(vsp_cbkey* k) {
   return VSP_OK;
 }
 
+vsp_status vsp_cbkey_set_form(vsp_cbkey* key, int form) {
+  if (key == nullptr) return fail(VSP_E_ARG, "key is NULL");
+  if (form < 0 || form > 2) return fail(VSP_E_ARG, "form must be 0 (by batch size), 1 (four waves) or 2 (eight waves)");
+  key->form = form;
+  return VSP_OK;
+}
+
 vsp_status vsp_circuit_bootstrap(vsp_context* ctx, vsp_cbkey* key, const uint32_t* d_in, uint32_t* d_out, uint64_t R,
                                  void* stream) {
   if (ctx == nullptr) return fail(VSP_E_ARG, "context is NULL");
@@ -366,8 +512,15 @@ vsp_status vsp_circuit_bootstrap(vsp_context* ctx, vsp_cbkey* key, const uint32_
   if ((s = scratch_reserve(ctx, key->acc, jobs * 2 * CB_N2 * 8))) return s;
   hipStream_t st = static_cast<hipStream_t>(stream);
   u64* tl2 = static_cast<u64*>(key->tl2.ptr);
-  hipLaunchKernelGGL(k_cb_rotate, dim3((unsigned)jobs), dim3(CB_THREADS), CB_LDS, st, key->key, ctx->tw, d_in,
-                     static_cast<u64*>(key->acc.ptr), tl2, GADGET_L, BG_BIT);
+  // the eight-wave form while the jobs fit one workgroup per compute unit (the four-wave form,
+  // two per compute unit, would run them in one round too, each step on half the waves)
+  const bool wide = key->form == 2 || (key->form == 0 && jobs <= (uint64_t)(ctx->cus > 0 ? ctx->cus : 256));
+  if (wide)
+    hipLaunchKernelGGL(k_cb_rotate_wide, dim3((unsigned)jobs), dim3(CBW_THREADS), CBW_LDS, st, key->key, ctx->tw, d_in,
+                       static_cast<u64*>(key->acc.ptr), tl2, GADGET_L, BG_BIT);
+  else
+    hipLaunchKernelGGL(k_cb_rotate, dim3((unsigned)jobs), dim3(CB_THREADS), CB_LDS, st, key->key, ctx->tw, d_in,
+                       static_cast<u64*>(key->acc.ptr), tl2, GADGET_L, BG_BIT);
   // tiles as large as keep about four workgroups per compute unit busy (16 per tile and u)
   const uint64_t slices = CB_PKS_ROW / 256;
   auto tiles = [&](uint64_t g) { return (jobs + g - 1) / g; };

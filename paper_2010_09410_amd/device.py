@@ -242,6 +242,10 @@ class CbKey:
         self.handle = nv.vsp_cbkey_create(ctx.handle, np.ascontiguousarray(bk2, dtype=np.uint64),
                                           np.ascontiguousarray(pksk, dtype=np.uint32))
 
+    def set_form(self, form: int) -> None:
+        """Level-2 blind rotation: 0 by batch size, 1 four-wave form, 2 eight-wave form."""
+        nv.vsp_cbkey_set_form(self.handle, form)
+
     def bootstrap(self, tlwe: torch.Tensor, out=None) -> torch.Tensor:
         """TLWE [R][n+1] -> TRGSW [R][2l][2][N]."""
         R = tlwe.shape[0]

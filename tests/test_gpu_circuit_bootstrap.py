@@ -29,15 +29,22 @@ def cb(gpu, keys):
 
 
 def test_circuit_bootstrap_matches_oracle(gpu, keys, cb):
+    """Five conversions against the oracle in both forms of the level-2 blind rotation (one
+    four-wave workgroup per job, and eight waves per job), and in the form picked by size."""
     g = W.rng(700)
     bits = np.array([1, 0, 1, 1, 0])
     cs = client.tlwe_encrypt_bits(keys["s0"], bits, *W.tlwe_draws(g, bits.size))
     cs[4] = client.trivial_tlwe_bits([0])[0]          # a noise-free, mask-free input
-    out = to_host(cb["key"].bootstrap(gpu.tensor(cs)))
-    gpu.sync()
     want = oracle.circuit_bootstraps(cb["bk2"], cb["pksk"], cs)
-    for r in range(bits.size):
-        np.testing.assert_array_equal(out[r].reshape(6, 2, N), want[r], err_msg=f"input {r}")
+    try:
+        for form in (1, 2, 0):
+            cb["key"].set_form(form)
+            out = to_host(cb["key"].bootstrap(gpu.tensor(cs)))
+            gpu.sync()
+            for r in range(bits.size):
+                np.testing.assert_array_equal(out[r].reshape(6, 2, N), want[r], err_msg=f"form {form}, input {r}")
+    finally:
+        cb["key"].set_form(0)
     # every row's phase is the gadget TRGSW's phase of the bit, within the noise
     s1 = keys["s1"]
     for r, b in enumerate(bits):
@@ -81,6 +88,10 @@ def test_circuit_bootstrap_argument_errors(gpu, cb):
     with pytest.raises(VspError) as ei:                                   # output overlaps the input
         nv.vsp_circuit_bootstrap(gpu.handle, cb["key"].handle, o.data_ptr(), o.data_ptr(), 2, gpu.stream())
     assert ei.value.status == nv.VSP_E_ARG
+    for bad in (-1, 3):
+        with pytest.raises(VspError) as ei:                               # unknown level-2 form
+            cb["key"].set_form(bad)
+        assert ei.value.status == nv.VSP_E_ARG
 
 
 def counter_machine_netlist():
