@@ -516,6 +516,9 @@ __global__ __launch_bounds__(MF_THREADS) void k_mf_step(const int8_t* __restrict
 // in LDS and forms its own operand segment from it (the digits of X^{abar_i} ACC_h - ACC_h,
 // as k_mf_digits would), and the workgroups of sub-products P2 and P3 of the first row group
 // also add ACC_i's y0 and y1 halves to their shares, so that acc ends as ACC_{i+1}.
+// With part non-NULL (the partial-sum form, groups 1, 2, 3 or 6) the shares are not added but
+// stored, P_s of group rg at part[tile][o][s][rg][gate][N/2], and the next digit launch adds
+// them into ACC (k_mf_digits with PG = groups).
 constexpr int MFP_THREADS = 256;
 constexpr int MFP_FUSE = 4;  // largest batch whose digits the step kernel forms itself
 constexpr int MFP_A_U4 = MF_KB * 64;                                  // one segment of one row: 1024 operands
