@@ -135,9 +135,9 @@ def mf_step_ops(B: int) -> int:
 
 
 def mf_step_hbm_bytes(B: int) -> int:
-    """Algorithmic HBM bytes of one step kernel launch: the digit operands and the step's key
-    read once, the accumulators read and written."""
-    return (B + MF_TILE - 1) // MF_TILE * MF_A_TILE_BYTES + MF_KEY_STEP_BYTES + B * 2 * N_RING * 4 * 2
+    """Compulsory HBM bytes of one step kernel launch: the step's digit operands read once and
+    the next step's written once, the step's key read once, the accumulators read and written."""
+    return 2 * ((B + MF_TILE - 1) // MF_TILE * MF_A_TILE_BYTES) + MF_KEY_STEP_BYTES + B * 2 * N_RING * 4 * 2
 
 
 def src_fingerprint(files) -> str:
