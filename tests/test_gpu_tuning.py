@@ -55,6 +55,18 @@ def test_tuning_set_rejects_unknown_shapes(gpu):
         gpu.set_tuning(64, 2, 0)
     with pytest.raises(VspError):
         gpu.set_tuning(64, 8, 4)
+    # split-form workgroup counts: the valid ones round-trip, others are refused
+    prev = gpu.set_split_groups(300, 2)
+    try:
+        for g in (1, 3, 6, 12, 24, -1, -2, -3, -6, 0):
+            assert gpu.set_split_groups(300, g) in (1, 2, 3, 6, 12, 24, -1, -2, -3, -6, 0)
+        assert gpu.set_split_groups(300, 2) == 0
+        for bad in (4, 5, 7, -12, -24, 48, -4):
+            with pytest.raises(VspError):
+                gpu.set_split_groups(300, bad)
+        assert gpu.set_split_groups(300, 2) == 2      # a refused value changes nothing
+    finally:
+        gpu.set_split_groups(300, prev)
 
 
 BUCKETS = (1, 16, 64, 256, 1024, 2048, 4096)
