@@ -60,6 +60,30 @@ def test_circuit_bootstrap_matches_oracle(gpu, keys, cb):
             assert np.abs(dev).max() < 1 << 16, (r, row, int(np.abs(dev).max()))
 
 
+def test_circuit_bootstrap_forms_agree_on_a_larger_batch(gpu, keys, cb):
+    """90 conversions (270 jobs, beyond one eight-wave round, so the default takes the four-wave
+    form): every output equals the eight-wave form's, and two sampled conversions equal the
+    oracle's."""
+    g = W.rng(701)
+    R = 90
+    bits = g.integers(0, 2, R)
+    cs = client.tlwe_encrypt_bits(keys["s0"], bits, *W.tlwe_draws(g, R))
+    d = gpu.tensor(cs)
+    try:
+        cb["key"].set_form(0)
+        auto = to_host(cb["key"].bootstrap(d))
+        cb["key"].set_form(2)
+        wide = to_host(cb["key"].bootstrap(d))
+        gpu.sync()
+    finally:
+        cb["key"].set_form(0)
+    np.testing.assert_array_equal(auto, wide)
+    pick = [0, R - 1]
+    want = oracle.circuit_bootstraps(cb["bk2"], cb["pksk"], cs[pick])
+    for k, r in enumerate(pick):
+        np.testing.assert_array_equal(auto[r].reshape(6, 2, N), want[k], err_msg=f"input {r}")
+
+
 def test_circuit_bootstrapped_address_drives_a_ram_read(gpu, keys, cb):
     """A RAM read (v = 8, w = 8) whose address arrives as level-0 TLWE bits: circuit
     bootstrapping gives the selectors, the read returns the stored bits."""
