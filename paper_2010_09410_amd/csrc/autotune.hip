@@ -225,7 +225,7 @@ vsp_status vsp_autotune(vsp_context* ctx, uint64_t max_batch, const char* cache_
     const uint64_t B = std::min<uint64_t>(kSplitAt[b], t.br_cap[3]);
     float best = 1e30f;
     for (int g : kSplitGroupChoices) {
-      if (g > 6 && B > 256) continue;  // plane ranges (12, 24) only pay while tiles are few
+      if ((g > 6 || g < -6) && B > 256) continue;  // plane ranges (12, 24) only pay while tiles are few
       if (g < 0 && B < 16) continue;   // partial sums only pay once atomics pile up
       const float ms = timed([&] {
         (void)launch_blind_rotate_mfsplit(ctx, dops, dab, static_cast<uint32_t*>(t1.p), nullptr, B, ctx->mf_work.ptr,
@@ -281,7 +281,7 @@ vsp_status vsp_tuning_get(const vsp_context* ctx, uint64_t B, int* br_waves, int
 vsp_status vsp_tuning_set_split(vsp_context* ctx, uint64_t B, int groups, int* previous) {
   if (ctx == nullptr) return fail(VSP_E_ARG, "context is NULL");
   if (groups != 0 && !split_groups_valid(groups))
-    return fail(VSP_E_ARG, "groups must be 0 (the count that fills the chip), 1, 2, 3, 6, 12, 24, -1, -2, -3 or -6");
+    return fail(VSP_E_ARG, "groups must be 0 (the count that fills the chip), 1, 2, 3, 6, 12, 24, -1, -2, -3, -6, -12 or -24");
   const int k = Tuning::split_point(B == 0 ? 1 : B);
   if (previous) *previous = ctx->tune.split_groups[k];
   ctx->tune.split_groups[k] = groups;

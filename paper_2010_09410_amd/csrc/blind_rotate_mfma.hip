@@ -516,7 +516,7 @@ __global__ __launch_bounds__(MF_THREADS) void k_mf_step(const int8_t* __restrict
 // in LDS and forms its own operand segment from it (the digits of X^{abar_i} ACC_h - ACC_h,
 // as k_mf_digits would), and the workgroups of sub-products P2 and P3 of the first row group
 // also add ACC_i's y0 and y1 halves to their shares, so that acc ends as ACC_{i+1}.
-// With part non-NULL (the partial-sum form, groups 1, 2, 3 or 6) the shares are not added but
+// With part non-NULL (the partial-sum form, any of the counts) the shares are not added but
 // stored, P_s of group rg at part[tile][o][s][rg][gate][N/2], and the next digit launch adds
 // them into ACC (k_mf_digits with PG = groups).
 constexpr int MFP_THREADS = 256;
@@ -800,8 +800,10 @@ size_t mf_key_bytes() { return (size_t)LWE_N * MF_KEY_STEP; }
 size_t mf_work_bytes(uint64_t B, bool need_acc) {
   const uint64_t tiles = (B + MF_TILE - 1) / MF_TILE;
   const uint64_t ptiles = tiles < (uint64_t)kPartTiles ? tiles : (uint64_t)kPartTiles;
+  const uint64_t stiles = tiles < (uint64_t)kPartSmallTiles ? tiles : (uint64_t)kPartSmallTiles;
+  const uint64_t blocks = std::max<uint64_t>(ptiles * 6, stiles * 24);  // share blocks per (output, sub-product)
   return 2 * tiles * MF_A_TILE + (need_acc ? (size_t)B * 2 * RING_N * 4 : 0) +
-         (size_t)ptiles * 2 * MF_SUB * 6 * MF_PART_U32 * 4;  // partial sums of up to six groups
+         (size_t)blocks * 2 * MF_SUB * MF_PART_U32 * 4;
 }
 
 hipError_t launch_mf_key(const uint32_t* bk, int8_t* E, hipStream_t st) {
@@ -840,8 +842,8 @@ hipError_t launch_blind_rotate_mfma(const vsp_context* ctx, const uint8_t* ops, 
 // Split form of the matrix-core blind rotation: per step one k_mf_part launch (shares of the
 // products added into ACC) and one k_mf_digits launch (the next step's operands from ACC).
 // groups (kSplitGroupChoices) sets the TRGSW rows, or for one row the byte planes, per
-// workgroup; a negative count -g (g = 1, 2, 3 or 6) stores the shares as partial sums that
-// the digit launch adds up, instead of integer atomics. The workspace is mf_work_bytes(B, .):
+// workgroup; a negative count -g (g = 1, 2, 3, 6, or 12 and 24 for at most eight tiles) stores
+// the shares as partial sums that the digit launch adds up, instead of integer atomics. The workspace is mf_work_bytes(B, .):
 // the operands of one step, without a caller TRLWE the accumulators, then the partial sums.
 template <int PG>
 static void launch_split_partial_steps(const vsp_context* ctx, const uint8_t* ops, const uint32_t* abar, u32* acc,
@@ -866,7 +868,8 @@ hipError_t launch_blind_rotate_mfsplit(const vsp_context* ctx, const uint8_t* op
   if (B == 0) return hipSuccess;
   if (!split_groups_valid(groups)) return hipErrorInvalidValue;
   const uint64_t tiles = (B + MF_TILE - 1) / MF_TILE;
-  if (groups < 0 && tiles > (uint64_t)kPartTiles) groups = -groups;  // no room for the partial sums
+  if (groups < 0 && tiles > (uint64_t)(groups < -6 ? kPartSmallTiles : kPartTiles))
+    groups = -groups;  // no room for the partial sums
   int8_t* Aop = static_cast<int8_t*>(work);
   u32* acc = trlwe ? trlwe : reinterpret_cast<u32*>(Aop + 2 * tiles * MF_A_TILE);
   u32* Q = reinterpret_cast<u32*>(Aop + 2 * tiles * MF_A_TILE + (trlwe ? 0 : B * 2 * RING_N * 4));
@@ -877,7 +880,9 @@ hipError_t launch_blind_rotate_mfsplit(const vsp_context* ctx, const uint8_t* op
       case 1: launch_split_partial_steps<1>(ctx, ops, abar, acc, Aop, Q, B, tiles, st, instrument, tkeys); break;
       case 2: launch_split_partial_steps<2>(ctx, ops, abar, acc, Aop, Q, B, tiles, st, instrument, tkeys); break;
       case 3: launch_split_partial_steps<3>(ctx, ops, abar, acc, Aop, Q, B, tiles, st, instrument, tkeys); break;
-      default: launch_split_partial_steps<6>(ctx, ops, abar, acc, Aop, Q, B, tiles, st, instrument, tkeys); break;
+      case 6: launch_split_partial_steps<6>(ctx, ops, abar, acc, Aop, Q, B, tiles, st, instrument, tkeys); break;
+      case 12: launch_split_partial_steps<12>(ctx, ops, abar, acc, Aop, Q, B, tiles, st, instrument, tkeys); break;
+      default: launch_split_partial_steps<24>(ctx, ops, abar, acc, Aop, Q, B, tiles, st, instrument, tkeys); break;
     }
   } else if (B <= (uint64_t)MFP_FUSE && groups >= MF_ROWS) {
     // one launch per step: ACC_i in buf[i mod 3], the step adds into buf[(i + 1) mod 3] and

@@ -44,11 +44,12 @@ constexpr int MF_TILE = 32;
 inline bool br_matrix_form(int waves) { return waves == 32 || waves == 33; }
 // Workgroup counts per (tile, output, sub-product) of the split form: 1, 2, 3 or 6 groups of
 // TRGSW rows, or one row per workgroup with the four byte planes in 2 (12) or 4 (24) ranges;
-// the shares go into ACC with integer atomics. -1, -2, -3, -6: the same row groups with the
-// shares stored as partial sums and added up by the next digit launch (batches of at most
-// kPartTiles tiles; larger ones use the atomics).
-constexpr int kSplitGroupChoices[10] = {1, 2, 3, 6, 12, 24, -1, -2, -3, -6};
+// the shares go into ACC with integer atomics. -1, -2, -3, -6, -12, -24: the same workgroups
+// with the shares stored as partial sums and added up by the next digit launch (batches of at
+// most kPartTiles tiles, kPartSmallTiles for -12 and -24; larger ones use the atomics).
+constexpr int kSplitGroupChoices[12] = {1, 2, 3, 6, 12, 24, -1, -2, -3, -6, -12, -24};
 constexpr int kPartTiles = 96;
+constexpr int kPartSmallTiles = 8;
 inline bool split_groups_valid(int g) {
   for (int c : kSplitGroupChoices)
     if (g == c) return true;

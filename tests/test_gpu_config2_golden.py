@@ -79,12 +79,14 @@ def test_split_matrix_form_prefixes_match_oracle(gpu, batch, nb):
 
 @pytest.mark.parametrize("nb,groups", [(1, 6), (1, 12), (1, 24), (2, 12), (3, 24), (4, 6), (5, 24), (16, 24),
                                        (37, 12), (64, 24), (64, 1), (256, 6), (1, -6), (16, -6), (37, -3),
-                                       (64, -6), (256, -3), (1000, -2), (2048, -1)])
+                                       (64, -6), (256, -3), (1000, -2), (2048, -1), (16, -12), (37, -24),
+                                       (256, -12), (300, -24)])
 def test_split_form_workgroup_counts_match_oracle(gpu, batch, nb, groups):
     """Every way of cutting a step of the split form (row groups, single rows with the byte
     planes in two or four ranges; up to four gates with the digits formed inside the step
     kernel, five gates just above; negative counts: shares stored as partial sums and added by
-    the digit launch) on prefixes of the batch, against the oracle's digests."""
+    the digit launch, 300 gates with -24 falling back to atomics) on prefixes of the batch,
+    against the oracle's digests."""
     cfg, in0, in1, doc = batch
     d0, d1, dops = gpu.tensor(in0[:nb]), gpu.tensor(in1[:nb]), gpu.tensor(cfg["ops"][:nb])
     saved = gpu.tuning(nb)

@@ -58,10 +58,10 @@ def test_tuning_set_rejects_unknown_shapes(gpu):
     # split-form workgroup counts: the valid ones round-trip, others are refused
     prev = gpu.set_split_groups(300, 2)
     try:
-        for g in (1, 3, 6, 12, 24, -1, -2, -3, -6, 0):
-            assert gpu.set_split_groups(300, g) in (1, 2, 3, 6, 12, 24, -1, -2, -3, -6, 0)
+        for g in (1, 3, 6, 12, 24, -1, -2, -3, -6, -12, -24, 0):
+            assert gpu.set_split_groups(300, g) in (1, 2, 3, 6, 12, 24, -1, -2, -3, -6, -12, -24, 0)
         assert gpu.set_split_groups(300, 2) == 0
-        for bad in (4, 5, 7, -12, -24, 48, -4):
+        for bad in (4, 5, 7, -5, 48, -48, -4):
             with pytest.raises(VspError):
                 gpu.set_split_groups(300, bad)
         assert gpu.set_split_groups(300, 2) == 2      # a refused value changes nothing
@@ -105,7 +105,7 @@ def test_autotune_model_and_cache_round_trip(gpu, tmp_path):
         cap4, cap8, capw, capm, caps = entry["br_cap"]
         assert 256 <= cap4 < cap8 and capw >= 256 and capm >= cap8 and caps == 32
         assert all(ms > 0 for ms in entry["br_round_ms"]) and all(ms > 0 for ms in entry["split_ms"])
-        assert all(g in (1, 2, 3, 6, 12, 24, -1, -2, -3, -6) for g in entry["split_groups"])
+        assert all(g in (1, 2, 3, 6, 12, 24, -1, -2, -3, -6, -12, -24) for g in entry["split_groups"])
         assert all(t in (0, 1, 2, 3) for t in entry["ks_form"])
         for b, t in zip(BUCKETS, entry["ks_form"]):
             assert gpu.tuning(b)[1] == t
