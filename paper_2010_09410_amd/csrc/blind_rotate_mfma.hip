@@ -522,7 +522,6 @@ __global__ __launch_bounds__(MF_THREADS) void k_mf_step(const int8_t* __restrict
 constexpr int MFP_THREADS = 256;
 constexpr int MFP_FUSE = 4;  // largest batch whose digits the step kernel forms itself
 constexpr int MFP_A_U4 = MF_KB * 64;                                  // one segment of one row: 1024 operands
-constexpr size_t MFP_LDS = 2 * ((size_t)MFP_A_U4 * 16 + 4 * (size_t)MF_COPY_U32 * 4);
 static_assert(MFP_A_U4 == 4 * MFP_THREADS && MF_S / 4 == MFP_THREADS,
               "four 16-byte operands and one key word per thread and pass");
 
