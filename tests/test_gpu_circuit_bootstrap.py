@@ -145,7 +145,9 @@ def test_clocked_netlist_with_ram_in_the_loop(gpu, keys, cb):
     """Cycles of a netlist whose RAM is read and written every clock from TLWE wires (circuit
     bootstrapping of the address): the state and the RAM follow the plaintext model for four
     cycles; the first cycle's read and write are bit-exact against the oracle fed the same
-    ciphertexts."""
+    ciphertexts; and a fresh machine resumed from the host snapshot taken after the first cycle
+    (flip-flops and RAM, the paper's snapshot for resumption) runs the other three cycles to the
+    same bits."""
     s0, s1 = keys["s0"], keys["s1"]
     gates, next_state, A_w, wd_w = counter_machine_netlist()
     g = W.rng(702)
@@ -173,9 +175,20 @@ def test_clocked_netlist_with_ram_in_the_loop(gpu, keys, cb):
     np.testing.assert_array_equal(ram1, oracle.ram_write(keys["bk"], keys["ksk"], ram0, sel, fin[0, 0], wdata))
     # three more cycles against the plaintext model
     m.run(d_state, 3, gpu.tensor(fin[1:]))
-    st = client.tlwe_decrypt(s0, to_host(d_state))
+    st_full = to_host(d_state)
+    st = client.tlwe_decrypt(s0, st_full)
     ram = to_host(d_ram)
     gpu.sync()
+    # resumption: a new machine from the snapshot after cycle 1
+    m2 = gpu.machine(gates, 1, next_state)
+    d_ram2 = gpu.tensor(ram1)
+    m2.attach_ram(cb["key"], d_ram2, A_w, 0, wd_w, [4, 5, 6, 7])
+    d_state2 = gpu.tensor(st1)
+    m2.run(d_state2, 3, gpu.tensor(fin[1:]))
+    np.testing.assert_array_equal(to_host(d_state2), st_full)
+    np.testing.assert_array_equal(to_host(d_ram2), ram)
+    gpu.sync()
+    m2.close()
     mem = contents.copy()
     A, Dv = a0, d0
     for f in flags:
