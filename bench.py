@@ -125,7 +125,8 @@ def br_hbm_bytes(B: int) -> int:
 MF_TILE = 32
 MF_OPS_PER_TILE = 2 * MF_TILE * 2 * 3 * (N_RING // 2) ** 2 * 2 * GL * 4
 MF_A_TILE_BYTES = 2 * GL * 3 * (N_RING // 2) * MF_TILE      # digit operands of a tile (int8)
-MF_KEY_STEP_BYTES = 2 * GL * 2 * 4 * 3 * N_RING             # three key sequences per row, output, plane
+MF_KEY_STEP_BYTES = (2 * GL * 2 * 4 * 3 * N_RING             # three key sequences per row, output, plane,
+                     + 2 * N_RING * 4)                      # and the digit-offset correction per output
 PEAK_INT8 = 5.0e15                                          # dense int8 MFMA, ops/s
 PROF_PERIOD = 16                                            # event-timed launches: one in PROF_PERIOD
 
@@ -136,7 +137,8 @@ def mf_step_ops(B: int) -> int:
 
 def mf_step_hbm_bytes(B: int) -> int:
     """Compulsory HBM bytes of one step kernel launch: the step's digit operands read once and
-    the next step's written once, the step's key read once, the accumulators read and written."""
+    the next step's written once, the step's key (with its offset correction) read once, the
+    accumulators read and written."""
     return 2 * ((B + MF_TILE - 1) // MF_TILE * MF_A_TILE_BYTES) + MF_KEY_STEP_BYTES + B * 2 * N_RING * 4 * 2
 
 

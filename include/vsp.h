@@ -89,8 +89,9 @@ const char* vsp_last_error(void);
  * bk_host [n][2l][2][N] (BK[i] = TRGSW_{s1}(s0[i]), Sec. 2.1.2 "Bootstrapping Key") and the
  * key-switching key ksk_host [N][t][base-1][n+1] (entry [j][p][v-1] = TLWE_{s0}(v s1[j] /
  * base^(p+1))), converts the bootstrapping key to the NTT domain and to the byte-plane forms
- * of the matrix-core blind rotation and key switch on the device (about 300 MB of device
- * memory in all), and returns it in *out. Host arrays are copied; the caller keeps them.
+ * of the matrix-core blind rotation and key switch on the device (about 330 MB of device
+ * memory in all: 62 MB NTT-domain, 98 MB byte-plane and 84 MB key-switch byte-plane forms, and
+ * the 83 MB key-switching key), and returns it in *out. Host arrays are copied; the caller keeps them.
  * Synchronous. */
 vsp_status vsp_context_create(const vsp_params* params, const uint32_t* bk_host, const uint32_t* ksk_host,
                               int device, vsp_context** out);
@@ -244,8 +245,8 @@ vsp_status vsp_server_poll(vsp_server* s, uint64_t ticket, uint32_t* h_wires, in
 
 /* A further client's key set on the context's GPU (the protocol gives every client its own
  * keys, Sec. 4.1): bk_host [n][2l][2][N] and ksk_host [N][t][base-1][n+1] as for
- * vsp_context_create, converted and copied to the device (about 145 MB); the caller keeps its
- * arrays. Synchronous. A key set must outlive every request submitted with it. */
+ * vsp_context_create, converted and copied to the device in the same forms (about 330 MB); the
+ * caller keeps its arrays. Synchronous. A key set must outlive every request submitted with it. */
 vsp_status vsp_keyset_create(vsp_context* ctx, const uint32_t* bk_host, const uint32_t* ksk_host, vsp_keyset** out);
 vsp_status vsp_keyset_destroy(vsp_keyset* k);
 

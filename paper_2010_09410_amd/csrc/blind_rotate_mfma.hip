@@ -15,11 +15,18 @@
 // S3[t] = Kt[t + N/2] - Kt[t] for t in (-N/2, N/2). Over a batch the operands (x0 + x1, x1,
 // x0) of all gates form the rows of A, and the three Toeplitz blocks per (row, output) form
 // a block-diagonal B: 3/4 of the multiply-adds of the plain product.
-// Exactness: digits are in [-32, 31], so x0 + x1 is in [-64, 62]; key words are split into
-// four balanced signed bytes Kt = sum_b 2^{8b} c_b (c_b in [-128, 127], mod 2^32); per byte
-// plane the int32 sums are below 6 x 512 x 64 x 128 < 2^25, and the planes are folded by
-// Horner's rule in the accumulators (plane 3 first, shift by 8 bits between planes), the
-// int32 wrap-around of the matrix cores being arithmetic mod 2^32.
+// Exactness: the operands carry the digits plus 32, x' = x + 32 in [0, 63] (x0' + x1' in
+// [0, 126]), which keeps the top bits of every operand byte clear and so lowers the switching
+// activity, and with it the power, of the matrix pipes; key words are split into four balanced
+// signed bytes Kt = sum_b 2^{8b} c_b (c_b in [-128, 127], mod 2^32); per byte plane the int32
+// sums stay below 6 x 512 x 126 x 128 < 2^26, and the planes are folded by Horner's rule in
+// the accumulators (plane 3 first, shift by 8 bits between planes), the int32 wrap-around of
+// the matrix cores being arithmetic mod 2^32. The offset adds 32 times the product of the row
+// key with the all-ones polynomial to each row's product, a vector that depends on the key
+// only: with K' the sum of the six row keys of output o, (K' (1 + X + .. + X^{N-1}))[i] =
+// 2 S_i - S_{N-1} in Z[X]/(X^N + 1) for the prefix sums S_i = K'[0] + .. + K'[i], so
+// C[i] = 64 S_i - 32 S_{N-1} is stored per (step, output) with the key and taken off where a
+// step's shares are combined.
 //
 // A step is one launch of k_mf_step: for one tile of 32 gates and one output polynomial per
 // workgroup it computes P1, P2 and P3, combines them, adds y to ACC, and writes the next
@@ -48,8 +55,19 @@ constexpr int MF_KB = MF_HALF / 32;     // 32-coefficient blocks of a sub-produc
 constexpr size_t MF_A_ROW = (size_t)MF_SUB * MF_KB * 64 * 16;
 constexpr size_t MF_A_TILE = (size_t)MF_ROWS * MF_A_ROW;
 
-// Key bytes per step: [row r][output o][plane b][sub-product s][t].
+// Key bytes per step: [row r][output o][plane b][sub-product s][t]; after the n steps, the
+// offset corrections C[step][o][N] (uint32).
 constexpr size_t MF_KEY_STEP = (size_t)MF_ROWS * 2 * MF_PLANES * MF_SUB * MF_S;
+constexpr size_t MF_KEY_BYTES = (size_t)LWE_N * MF_KEY_STEP;
+constexpr int MF_CORR_STEP_U32 = 2 * RING_N;
+constexpr int MF_OFS = 1 << (BG_BIT - 1);  // added to every digit in the operands: (x >> sh) & 63 is digit + 32
+
+// The correction words of output o of the step whose key bytes start key_off bytes into the
+// key at base.
+__device__ __forceinline__ const u32* mf_corr(const int8_t* base, uint64_t key_off, int o) {
+  return reinterpret_cast<const u32*>(base + MF_KEY_BYTES) + (key_off / MF_KEY_STEP) * MF_CORR_STEP_U32 +
+         (size_t)o * RING_N;
+}
 
 // The three sequences of every (step, row, output) in balanced bytes, from the torus key
 // bk [n][2l][2][N]: E[i][r][o][b][s][t] = byte b of S_s[t - N/2].
@@ -84,6 +102,42 @@ __global__ __launch_bounds__(256) void k_mf_key(const u32* __restrict__ bk, int8
   }
 }
 
+// Offset corrections: workgroup (step, o) sums the six row keys of output o (K'), scans the
+// sum, and writes C[i] = 64 S_i - 32 S_{N-1} (S_i = K'[0] + .. + K'[i], all mod 2^32).
+// Thread t takes coefficients 4t .. 4t + 3.
+static_assert(RING_N == 4 * 256, "four coefficients per thread");
+__global__ __launch_bounds__(256) void k_mf_corr(const u32* __restrict__ bk, u32* __restrict__ C) {
+  __shared__ u32 part[256];
+  const int step = blockIdx.x, o = blockIdx.y, t = threadIdx.x;
+  u32 v[4] = {0u, 0u, 0u, 0u};
+  for (int r = 0; r < MF_ROWS; r++) {
+    const uint4 k = reinterpret_cast<const uint4*>(bk + (((size_t)step * MF_ROWS + r) * 2 + o) * RING_N)[t];
+    v[0] += k.x;
+    v[1] += k.y;
+    v[2] += k.z;
+    v[3] += k.w;
+  }
+  v[1] += v[0];
+  v[2] += v[1];
+  v[3] += v[2];
+  part[t] = v[3];
+  __syncthreads();
+  for (int d = 1; d < 256; d <<= 1) {  // inclusive scan of the per-thread sums
+    const u32 add = t >= d ? part[t - d] : 0u;
+    __syncthreads();
+    part[t] += add;
+    __syncthreads();
+  }
+  const u32 before = t > 0 ? part[t - 1] : 0u, total = part[255];
+  uint4 c;
+  constexpr u32 two = 2u * MF_OFS, one = MF_OFS;
+  c.x = two * (before + v[0]) - one * total;
+  c.y = two * (before + v[1]) - one * total;
+  c.z = two * (before + v[2]) - one * total;
+  c.w = two * (before + v[3]) - one * total;
+  reinterpret_cast<uint4*>(C + ((size_t)step * 2 + o) * RING_N)[t] = c;
+}
+
 // ACC = (0, X^{-bbar} (mu, ..., mu)) for the gates that bootstrap; with `zero` non-NULL also
 // clears the same rows there (the first step's target in the rotating-buffer split form).
 __global__ __launch_bounds__(256) void k_mf_init(const uint8_t* __restrict__ ops, const u32* __restrict__ abar,
@@ -100,11 +154,11 @@ __global__ __launch_bounds__(256) void k_mf_init(const uint8_t* __restrict__ ops
 }
 
 // Digits of step i: for gate g, row r = 3h + k and coefficient j, digit k + 1 of
-// x = (X^{abar_i} ACC_h - ACC_h), written as the A operand of the step's products: segment
-// 1 holds x1 = x[N/2 ..], segment 2 x0 = x[.. N/2], segment 0 their sum. In a segment, byte
-// q of lane (m, kh) of block kb holds local coefficient j = 32 kb + 16 kh + 15 - q of gate
+// x = (X^{abar_i} ACC_h - ACC_h) plus MF_OFS, written as the A operand of the step's products:
+// segment 1 holds x1 = x[N/2 ..], segment 2 x0 = x[.. N/2], segment 0 their sum. In a segment,
+// byte q of lane (m, kh) of block kb holds local coefficient j = 32 kb + 16 kh + 15 - q of gate
 // 32 mt + m (the order that makes the B bytes of a lane ascend in the key sequence). Gates
-// at or above B and gates that do not bootstrap get zero digits.
+// at or above B and gates that do not bootstrap get zero bytes (their products are dropped).
 // Workgroup (mt, h, eighth e of the gates): thread t takes local coefficients 4 jg .. 4 jg + 3
 // (jg = t mod 128) of both halves for gates t / 128, t / 128 + 2, ... (coalesced reads of ACC
 // and of its rotation); the bytes are gathered in LDS in operand order, then written out as
@@ -121,7 +175,7 @@ __device__ __forceinline__ void mf_digit_words(const u32 (&rot0)[4], const u32 (
 #pragma unroll
     for (int k = 0; k < GADGET_L; k++) {
       const int sh = 32 - BG_BIT * (k + 1);
-      const u32 d0 = ((x0 >> sh) & 63u) - 32u, d1 = ((x1 >> sh) & 63u) - 32u;
+      const u32 d0 = (x0 >> sh) & 63u, d1 = (x1 >> sh) & 63u;  // digits plus MF_OFS
       w[k][0] |= ((d0 + d1) & 255u) << (8 * s);
       w[k][1] |= (d1 & 255u) << (8 * s);
       w[k][2] |= (d0 & 255u) << (8 * s);
@@ -229,6 +283,46 @@ __global__ __launch_bounds__(256) void k_mf_digits(const uint8_t* __restrict__ o
   }
 }
 
+// The 64 products of one pass for a wave's four output blocks nb over the 16 input blocks kb
+// of its segment. Block (nb, kb) takes the A operand of block kb (lane bytes at Ar[64 kb]) and
+// the B operand of diagonal d = nb - kb (ldb(8 (MF_KB - 1 + d)): the Toeplitz tile depends on
+// d only). The products are issued along diagonals: group t = 0..15 takes kb = t + nb for the
+// four nb, four independent accumulators that share one B operand (d = -t) while A changes,
+// A being the operand with the fewer switching bits (digits plus offset, against random key
+// bytes); the products with kb >= 16 wrap to kb - 16 (d = 16 - t: 3, 2, 1 in the last three
+// groups; the order of the integer sums does not matter). Each group loads the A operand of
+// block t + 4 (first used by the next group) and the B operand of group t + 2; the wrapped
+// products' operands are loaded two groups ahead.
+template <typename LDB, typename LDA>
+__device__ __forceinline__ void mf_pass_products(v16i (&c)[4], const uint4* __restrict__ Ar, LDB&& ldb, LDA&& lda) {
+  v4i Av[8], Bm[3], Aw[3], Bx[3];
+#pragma unroll
+  for (int k = 0; k < 4; k++) Av[k] = lda(Ar[k * 64]);
+  Bm[0] = ldb(8 * (MF_KB - 1));
+  Bm[1] = ldb(8 * (MF_KB - 2));
+#pragma unroll
+  for (int t = 0; t < MF_KB; t++) {
+    if (t + 4 < MF_KB) Av[(t + 4) & 7] = lda(Ar[(t + 4) * 64]);
+    if (t + 2 < MF_KB) Bm[(t + 2) % 3] = ldb(8 * (MF_KB - 3 - t));
+    if (t >= MF_KB - 5 && t < MF_KB - 2) {
+      const int w = t - (MF_KB - 5);  // wrapped block w, diagonal 3 - w
+      Aw[w] = lda(Ar[w * 64]);
+      Bx[w] = ldb(8 * (MF_KB + 2 - w));
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int nb = 0; nb < 4; nb++) {
+      const int kb = t + nb;
+      if (kb < MF_KB)
+        c[nb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(Av[kb & 7], Bm[t % 3], c[nb], 0, 0, 0);
+      else
+        c[nb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(Aw[kb >= MF_KB ? kb - MF_KB : 0],
+                                                      Bx[t >= MF_KB - 3 ? t - (MF_KB - 3) : 0], c[nb], 0, 0, 0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
 // ACC[g][o] += y for the 32 gates of tile blockIdx.x and output polynomial o = blockIdx.y.
 // Twelve waves: wave w computes sub-product s = w / 4 for local outputs
 // [128 (w mod 4), 128 (w mod 4) + 128) as four 32 x 32 blocks nb. Lane (n, kh) of the B
@@ -241,11 +335,10 @@ __global__ __launch_bounds__(256) void k_mf_digits(const uint8_t* __restrict__ o
 // The 24 passes (plane b from 3 down, the six rows r) each stage the tile's 48 KB of row-r operands and
 // the copies of the three sequences (r, o, b); the next pass's data is loaded into registers
 // while the current pass computes, and stored to the other buffer after it. Within a pass the
-// LDS reads of block kb + 2 are issued before the four products of block kb; the B operands
-// live in a ring of eight registers (block nb at kb in slot (nb - kb) mod 8), so the Toeplitz
-// shift costs no moves. At the end P1 goes through LDS to the waves of P2 and P3, which form
-// y0 = P1 + P2 and y1 = P1 + P3 in LDS; the workgroup adds y to ACC and keeps the updated
-// polynomial in LDS, where the next step's digits are formed.
+// products run in the diagonal order of mf_pass_products. At the end P1 goes through LDS to
+// the waves of P2 and P3, which form y0 = P1 + P2 and y1 = P1 + P3, take off the offset
+// correction and write y to LDS; the workgroup adds y to ACC and keeps the updated polynomial
+// in LDS, where the next step's digits are formed.
 constexpr int MF_WAVES = 12;
 constexpr int MF_THREADS = MF_WAVES * 64;
 constexpr int MF_A_PASS_U4 = (int)(MF_A_ROW / 16);      // 3072 16-byte operands per row and tile
@@ -270,7 +363,8 @@ __device__ __forceinline__ int mf_pass_row(int pass) {
   return ((pass / MF_ROWS) & 1) ? MF_ROWS - 1 - r : r;
 }
 
-// Step kernel. With next_step >= 0 the workgroup then writes the digit operands of step
+// Step kernel (Ek0, or the tile's tkeys entry, is the start of a whole key; key_off selects the
+// step). With next_step >= 0 the workgroup then writes the digit operands of step
 // next_step for rows 3o .. 3o + 2 of its tile into Anext: they depend only on the updated
 // polynomial o of its own 32 gates, which it has just written, so no other workgroup is
 // involved (the other output polynomial's workgroup writes rows 3(1 - o) ..).
@@ -281,7 +375,8 @@ __global__ __launch_bounds__(MF_THREADS) void k_mf_step(const int8_t* __restrict
                                                          const int8_t* const* __restrict__ tkeys, uint64_t key_off) {
   extern __shared__ uint4 mf_lds[];
   // the step's key: the context's (Ek0), or the tile's key set's
-  const int8_t* __restrict__ Ek = tkeys ? tkeys[blockIdx.x] + key_off : Ek0;
+  const int8_t* __restrict__ Kb = tkeys ? tkeys[blockIdx.x] : Ek0;
+  const int8_t* __restrict__ Ek = Kb + key_off;
   uint4* abuf = mf_lds;                                            // [2][MF_A_PASS_U4]
   u32* ebuf = reinterpret_cast<u32*>(mf_lds + 2 * MF_A_PASS_U4);  // [2][3 sequences][4 copies][MF_COPY_U32]
   const uint64_t mt = blockIdx.x;
@@ -343,27 +438,7 @@ __global__ __launch_bounds__(MF_THREADS) void k_mf_step(const int8_t* __restrict
       return v4i{(int)Bp[wofs], (int)Bp[wofs + 1], (int)Bp[wofs + 2], (int)Bp[wofs + 3]};
     };
     auto lda = [](const uint4& u) { return v4i{(int)u.x, (int)u.y, (int)u.z, (int)u.w}; };
-    v4i R[8], Av[4];
-#pragma unroll
-    for (int nb = 0; nb < 4; nb++) R[nb] = ldb(8 * (MF_KB - 1 + nb));
-    R[7] = ldb(8 * (MF_KB - 2));  // B_0 of block 1
-    Av[0] = lda(Ar[0]);
-    Av[1] = lda(Ar[64]);
-    for (int k8 = 0; k8 < MF_KB; k8 += 8) {
-#pragma unroll
-      for (int s8 = 0; s8 < 8; s8++) {
-        // reads for block kb + 2 (the last two blocks re-read the last one, unused)
-        const int kb = k8 + s8;
-        const int kn = (kb + 2 < MF_KB) ? kb + 2 : MF_KB - 1;
-        Av[(s8 + 2) & 3] = lda(Ar[kn * 64]);
-        R[(6 - s8) & 7] = ldb(8 * (MF_KB - 1 - kn));
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int nb = 0; nb < 4; nb++)
-          c[nb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(Av[s8 & 3], R[(nb - s8) & 7], c[nb], 0, 0, 0);
-        __builtin_amdgcn_sched_barrier(0);
-      }
-    }
+    mf_pass_products(c, Ar, ldb, lda);
     if (pass % MF_ROWS == MF_ROWS - 1 && pass + 1 < MF_PASSES) {
 #pragma unroll
       for (int nb = 0; nb < 4; nb++)
@@ -381,6 +456,13 @@ __global__ __launch_bounds__(MF_THREADS) void k_mf_step(const int8_t* __restrict
     }
     __syncthreads();
   }
+  // the offset correction of the outputs this wave forms (i below), taken off with P1
+  u32 cv[4] = {0u, 0u, 0u, 0u};
+  if (sub != 0) {
+    const u32* C = mf_corr(Kb, key_off, o) + (sub - 1) * MF_HALF + 128 * wl + n;
+#pragma unroll
+    for (int nb = 0; nb < 4; nb++) cv[nb] = C[32 * nb];
+  }
   // P1 to LDS ([w mod 4][nb][x][lane]); the P2 and P3 waves add it: y0 = P1 + P2 (sub 1,
   // outputs [0, N/2)), y1 = P1 + P3 (sub 2, outputs [N/2, N)).
   u32* p1buf = reinterpret_cast<u32*>(mf_lds);
@@ -395,7 +477,8 @@ __global__ __launch_bounds__(MF_THREADS) void k_mf_step(const int8_t* __restrict
 #pragma unroll
     for (int nb = 0; nb < 4; nb++)
 #pragma unroll
-      for (int x = 0; x < 16; x++) c[nb][x] = (int)((u32)c[nb][x] + p1buf[((wl * 4 + nb) * 16 + x) * 64 + lane]);
+      for (int x = 0; x < 16; x++)
+        c[nb][x] = (int)((u32)c[nb][x] + p1buf[((wl * 4 + nb) * 16 + x) * 64 + lane] - cv[nb]);
   }
   __syncthreads();
   // y to LDS as rows of MF_PROW words per gate: result (m, i) is lane n + 32 kh, register x of
@@ -479,7 +562,7 @@ __global__ __launch_bounds__(MF_THREADS) void k_mf_step(const int8_t* __restrict
 #pragma unroll
             for (int k = 0; k < GADGET_L; k++) {
               const int sh = 32 - BG_BIT * (k + 1);
-              const u32 d0 = ((x[0] >> sh) & 63u) - 32u, d1 = ((x[1] >> sh) & 63u) - 32u;
+              const u32 d0 = (x[0] >> sh) & 63u, d1 = (x[1] >> sh) & 63u;  // digits plus MF_OFS
               w[k][0][wi] |= ((d0 + d1) & 255u) << (8 * s);
               w[k][1][wi] |= (d1 & 255u) << (8 * s);
               w[k][2][wi] |= (d0 & 255u) << (8 * s);
@@ -518,7 +601,9 @@ __global__ __launch_bounds__(MF_THREADS) void k_mf_step(const int8_t* __restrict
 // also add ACC_i's y0 and y1 halves to their shares, so that acc ends as ACC_{i+1}.
 // With part non-NULL (the partial-sum form, any of the counts) the shares are not added but
 // stored, P_s of group rg at part[tile][o][s][rg][gate][N/2], and the next digit launch adds
-// them into ACC (k_mf_digits with PG = groups).
+// them into ACC (k_mf_digits with PG = groups). In every form the P2 and P3 workgroups of the
+// first group take the operand offset's correction of their outputs off their shares.
+// Ek0 (and each tkeys entry) is the start of a whole key; key_off selects the step.
 constexpr int MFP_THREADS = 256;
 constexpr int MFP_FUSE = 4;  // largest batch whose digits the step kernel forms itself
 constexpr int MFP_A_U4 = MF_KB * 64;                                  // one segment of one row: 1024 operands
@@ -532,7 +617,8 @@ __global__ __launch_bounds__(MFP_THREADS, 3) void k_mf_part(const int8_t* __rest
                                                           const u32* __restrict__ acc_in, u32* __restrict__ acc_zero,
                                                           const u32* __restrict__ abar, int step,
                                                           u32* __restrict__ part) {
-  const int8_t* __restrict__ Ek = tkeys ? tkeys[blockIdx.x] + key_off : Ek0;
+  const int8_t* __restrict__ Kb = tkeys ? tkeys[blockIdx.x] : Ek0;
+  const int8_t* __restrict__ Ek = Kb + key_off;
   __shared__ uint4 abuf[2][MFP_A_U4];
   __shared__ u32 ebuf[2][4 * MF_COPY_U32];
   const uint64_t mt = blockIdx.x;
@@ -582,6 +668,10 @@ __global__ __launch_bounds__(MFP_THREADS, 3) void k_mf_part(const int8_t* __rest
       return v4i{(int)Bp[wofs], (int)Bp[wofs + 1], (int)Bp[wofs + 2], (int)Bp[wofs + 3]};
     };
     auto lda = [](const uint4& u) { return v4i{(int)u.x, (int)u.y, (int)u.z, (int)u.w}; };
+    // block order (the diagonal order of the step kernel needs more registers than this
+    // kernel has to spare): the B operands in a ring of eight registers, block nb at input
+    // block kb in slot (nb - kb) mod 8, the reads of block kb + 2 issued before the products
+    // of block kb
     v4i R[8], Av[4];
 #pragma unroll
     for (int nb = 0; nb < 4; nb++) R[nb] = ldb(8 * (MF_KB - 1 + nb));
@@ -679,7 +769,7 @@ __global__ __launch_bounds__(MFP_THREADS, 3) void k_mf_part(const int8_t* __rest
             const int ix = (half * MF_HALF + j - a) & (2 * RING_N - 1);
             const u32 r = P[ix & (RING_N - 1)];
             const u32 x = ((ix & RING_N) ? 0u - r : r) - P[half * MF_HALF + j] + DECOMP_OFFSET;
-            d[half] = ((x >> sh) & 63u) - 32u;
+            d[half] = (x >> sh) & 63u;  // digit plus MF_OFS
           }
           const u32 byte = sub == 0 ? d[0] + d[1] : (sub == 1 ? d[1] : d[0]);
           w |= (byte & 255u) << (8 * q);
@@ -747,6 +837,13 @@ __global__ __launch_bounds__(MFP_THREADS, 3) void k_mf_part(const int8_t* __rest
       __syncthreads();
     }
   }
+  // the first group's P2 / P3 workgroups also take the offset correction of their outputs off
+  u32 cv[4] = {0u, 0u, 0u, 0u};
+  if (rg == 0 && sub != 0) {
+    const u32* C = mf_corr(Kb, key_off, o) + (sub - 1) * MF_HALF + 128 * wl + n;
+#pragma unroll
+    for (int nb = 0; nb < 4; nb++) cv[nb] = C[32 * nb];
+  }
   // gates of the tile that bootstrap: bit m of `live` (lanes 0..31 test gate m = lane)
   bool mine = false;
   {
@@ -770,7 +867,7 @@ __global__ __launch_bounds__(MFP_THREADS, 3) void k_mf_part(const int8_t* __rest
       const int m = 8 * (x >> 2) + 4 * kh + (x & 3);
       if (!((live >> m) & 1)) continue;
 #pragma unroll
-      for (int nb = 0; nb < 4; nb++) q[(size_t)m * MF_HALF + 32 * nb] = (u32)c[nb][x] << (8 * blo);
+      for (int nb = 0; nb < 4; nb++) q[(size_t)m * MF_HALF + 32 * nb] = ((u32)c[nb][x] << (8 * blo)) - cv[nb];
     }
     return;
   }
@@ -781,7 +878,7 @@ __global__ __launch_bounds__(MFP_THREADS, 3) void k_mf_part(const int8_t* __rest
     u32* row = acc + ((mt * MF_TILE + m) * 2 + o) * RING_N + 128 * wl + n;
 #pragma unroll
     for (int nb = 0; nb < 4; nb++) {
-      const u32 v = (u32)c[nb][x] << (8 * blo);
+      const u32 v = ((u32)c[nb][x] << (8 * blo)) - cv[nb];
       const u32 cy = (x < MFP_FUSE && carry) ? cyv[x < MFP_FUSE ? x : 0][nb] : 0u;
       if (sub != 2) atomicAdd(row + 32 * nb, v + cy);
       if (sub != 1) atomicAdd(row + MF_HALF + 32 * nb, v + cy);
@@ -794,7 +891,7 @@ hipError_t init_mf_kernel_attributes() {
                              (int)MF_STEP_LDS);
 }
 
-size_t mf_key_bytes() { return (size_t)LWE_N * MF_KEY_STEP; }
+size_t mf_key_bytes() { return MF_KEY_BYTES + (size_t)LWE_N * MF_CORR_STEP_U32 * 4; }
 
 size_t mf_work_bytes(uint64_t B, bool need_acc) {
   const uint64_t tiles = (B + MF_TILE - 1) / MF_TILE;
@@ -808,6 +905,8 @@ size_t mf_work_bytes(uint64_t B, bool need_acc) {
 hipError_t launch_mf_key(const uint32_t* bk, int8_t* E, hipStream_t st) {
   const uint64_t rows = (uint64_t)LWE_N * MF_ROWS * 2;
   hipLaunchKernelGGL(k_mf_key, dim3((unsigned)((rows * MF_S + 255) / 256)), dim3(256), 0, st, bk, E, rows);
+  hipLaunchKernelGGL(k_mf_corr, dim3((unsigned)LWE_N, 2), dim3(256), 0, st, bk,
+                     reinterpret_cast<u32*>(E + MF_KEY_BYTES));
   return hipGetLastError();
 }
 
@@ -830,7 +929,7 @@ hipError_t launch_blind_rotate_mfma(const vsp_context* ctx, const uint8_t* ops, 
     ProfScope ps(instrument ? ctx : nullptr, 3, st, LWE_N);
     for (int i = 0; i < LWE_N; i++)
       hipLaunchKernelGGL(k_mf_step, dim3((unsigned)tiles, 2), dim3(MF_THREADS), MF_STEP_LDS, st,
-                         tkeys ? nullptr : ctx->mf_key + (size_t)i * MF_KEY_STEP, Ab[i & 1], acc, ops, B,
+                         tkeys ? nullptr : ctx->mf_key, Ab[i & 1], acc, ops, B,
                          Ab[(i + 1) & 1], abar, i + 1 < LWE_N ? i + 1 : -1, tkeys, (uint64_t)i * MF_KEY_STEP);
   }
   hipError_t e = hipGetLastError();
@@ -855,7 +954,7 @@ static void launch_split_partial_steps(const vsp_context* ctx, const uint8_t* op
   ProfScope ps(instrument ? ctx : nullptr, 3, st, LWE_N);
   for (int i = 0; i < LWE_N; i++) {
     hipLaunchKernelGGL(k_mf_part, pgrid, dim3(MFP_THREADS), 0, st,
-                       tkeys ? nullptr : ctx->mf_key + (size_t)i * MF_KEY_STEP, Aop, acc, ops, B, PG, tkeys,
+                       tkeys ? nullptr : ctx->mf_key, Aop, acc, ops, B, PG, tkeys,
                        (uint64_t)i * MF_KEY_STEP, nullptr, nullptr, nullptr, 0, Q);
     hipLaunchKernelGGL((k_mf_digits<PG, DG>), rgrid, dim3(256), 0, st, ops, abar, acc, Aop, B, i + 1, Q);
   }
@@ -896,7 +995,7 @@ hipError_t launch_blind_rotate_mfsplit(const vsp_context* ctx, const uint8_t* op
     ProfScope ps(instrument ? ctx : nullptr, 3, st, LWE_N);
     for (int i = 0; i < LWE_N; i++)
       hipLaunchKernelGGL(k_mf_part, pgrid, dim3(MFP_THREADS), 0, st,
-                         tkeys ? nullptr : ctx->mf_key + (size_t)i * MF_KEY_STEP, Aop, buf[(i + 1) % 3], ops, B,
+                         tkeys ? nullptr : ctx->mf_key, Aop, buf[(i + 1) % 3], ops, B,
                          groups, tkeys, (uint64_t)i * MF_KEY_STEP, buf[i % 3], buf[(i + 2) % 3], abar, i, nullptr);
   } else {
     constexpr int DG = 2;
@@ -907,7 +1006,7 @@ hipError_t launch_blind_rotate_mfsplit(const vsp_context* ctx, const uint8_t* op
     ProfScope ps(instrument ? ctx : nullptr, 3, st, LWE_N);
     for (int i = 0; i < LWE_N; i++) {
       hipLaunchKernelGGL(k_mf_part, pgrid, dim3(MFP_THREADS), 0, st,
-                         tkeys ? nullptr : ctx->mf_key + (size_t)i * MF_KEY_STEP, Aop, acc, ops, B, groups, tkeys,
+                         tkeys ? nullptr : ctx->mf_key, Aop, acc, ops, B, groups, tkeys,
                          (uint64_t)i * MF_KEY_STEP, nullptr, nullptr, nullptr, 0, nullptr);
       if (i + 1 < LWE_N)
         hipLaunchKernelGGL((k_mf_digits<0, DG>), dgrid, dim3(256), 0, st, ops, abar, acc, Aop, B, i + 1, nullptr);
