@@ -2,8 +2,9 @@
 // for each blind-rotation form (4 or 8 gates per workgroup at one wave per gate, one gate on
 // three waves, and the matrix-core form; a launch then picks the form with the fewest rounds x
 // round time for its batch), the split matrix-core form at thirteen batch sizes with each
-// workgroup-group count (row groups or byte-plane ranges, atomics or partial sums; the fastest is kept per size) and the four key-switch forms (one workgroup per gate,
-// row-stationary tiles, LDS-staged split, matrix cores) per batch-size bucket. Every candidate
+// workgroup-group count (row groups or byte-plane ranges, atomics or partial sums; the fastest
+// is kept per size) and the four key-switch forms (one workgroup per gate, row-stationary
+// tiles, LDS-staged split, matrix cores) per batch-size bucket. Every candidate
 // must produce bit-identical outputs. The result can be cached in a small JSON file keyed by
 // the GPU; a cache written for another list of forms is ignored.
 #include <cstdio>
