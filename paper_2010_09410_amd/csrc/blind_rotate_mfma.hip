@@ -31,7 +31,9 @@
 // A step is one launch of k_mf_step: for one tile of 32 gates and one output polynomial per
 // workgroup it computes P1, P2 and P3, combines them, adds y to ACC, and writes the next
 // step's A rows that depend on that polynomial (bytes in the lane order of the MFMA
-// operands). k_mf_digits writes the first step's A. B is never stored
+// operands; segments 1 and 2 only, segment 0 being their bytewise sum, formed when a step
+// stages its operands). k_mf_digits writes the first step's A (all three segments, which the
+// split form reads). B is never stored
 // as a matrix: a 32 x 32 tile of a Toeplitz block depends only on its diagonal offset, so a
 // lane reads its sixteen bytes straight from the sequence (staged in LDS), and moving to the
 // next 32 input coefficients turns the tile of output block nb into that of block nb - 1,
@@ -404,15 +406,39 @@ __global__ __launch_bounds__(MF_THREADS) void k_mf_step(const int8_t* __restrict
     const int bufi = tid / (MF_SUB * 16), rest = tid % (MF_SUB * 16);
     ebuf[bufi * MF_ECOPIES_U32 + (rest >> 2) * MF_COPY_U32 + MF_S / 4 + (rest & 3)] = 0u;
   }
+  // Only segments 1 and 2 (x1, x0 plus offset) are read from A: segment 0, their sum, is formed
+  // while staging, a 32-bit add of packed bytes that cannot carry (each byte sum is at most
+  // 126), so a row moves 32 KiB instead of 48 and the tile's rows stay in L2 across planes.
+  // Thread t stages operand i = t of each segment, and threads t < 256 also i = t + 768.
+  constexpr int SEG_U4 = MF_KB * 64;
+  const bool two = tid < SEG_U4 - MF_THREADS;  // wave-uniform
+  auto load_row = [&](const uint4* row, uint4 (&v)[4]) {
+    v[0] = row[SEG_U4 + tid];
+    v[1] = row[2 * SEG_U4 + tid];
+    v[2] = v[3] = make_uint4(0u, 0u, 0u, 0u);
+    if (two) {
+      v[2] = row[SEG_U4 + MF_THREADS + tid];
+      v[3] = row[2 * SEG_U4 + MF_THREADS + tid];
+    }
+  };
+  auto store_row = [&](uint4* dst, const uint4 (&v)[4]) {
+    auto sum = [](const uint4& a, const uint4& b) { return make_uint4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w); };
+    dst[tid] = sum(v[0], v[1]);
+    dst[SEG_U4 + tid] = v[0];
+    dst[2 * SEG_U4 + tid] = v[1];
+    if (two) {
+      dst[MF_THREADS + tid] = sum(v[2], v[3]);
+      dst[SEG_U4 + MF_THREADS + tid] = v[2];
+      dst[2 * SEG_U4 + MF_THREADS + tid] = v[3];
+    }
+  };
+  static_assert(MF_A_PASS_U4 == MF_SUB * SEG_U4 && SEG_U4 - MF_THREADS <= MF_THREADS, "two rounds cover a segment");
   {
-    const uint4* as = Ag + tid;
-    const uint4 x0 = as[0], x1 = as[MF_THREADS], x2 = as[2 * MF_THREADS], x3 = as[3 * MF_THREADS];
+    uint4 x[4];
+    load_row(Ag, x);
     const u32* er = e_row(0);
     const u32 d0 = er[ew], d1 = (ew + 1 < MF_S / 4) ? er[ew + 1] : 0u;
-    abuf[tid] = x0;
-    abuf[tid + MF_THREADS] = x1;
-    abuf[tid + 2 * MF_THREADS] = x2;
-    abuf[tid + 3 * MF_THREADS] = x3;
+    store_row(abuf, x);
     stage_e(ebuf, d0, d1);
   }
   __syncthreads();
@@ -424,8 +450,8 @@ __global__ __launch_bounds__(MF_THREADS) void k_mf_step(const int8_t* __restrict
   for (int pass = 0; pass < MF_PASSES; pass++) {
     const int buf = pass & 1;
     const int nx = (pass + 1 < MF_PASSES) ? pass + 1 : pass;  // the last pass fetches itself again, unused
-    const uint4* as = Ag + (size_t)mf_pass_row(nx) * MF_A_PASS_U4 + tid;
-    const uint4 p0 = as[0], p1 = as[MF_THREADS], p2 = as[2 * MF_THREADS], p3 = as[3 * MF_THREADS];
+    uint4 pa[4];
+    load_row(Ag + (size_t)mf_pass_row(nx) * MF_A_PASS_U4, pa);
     u32 pd0, pd1;
     {
       const u32* er = e_row(nx);
@@ -447,11 +473,7 @@ __global__ __launch_bounds__(MF_THREADS) void k_mf_step(const int8_t* __restrict
     }
     // the other buffer was last read in the previous pass, before the barrier that ended it
     if (pass + 1 < MF_PASSES) {
-      uint4* ad = abuf + (buf ^ 1) * MF_A_PASS_U4 + tid;
-      ad[0] = p0;
-      ad[MF_THREADS] = p1;
-      ad[2 * MF_THREADS] = p2;
-      ad[3 * MF_THREADS] = p3;
+      store_row(abuf + (buf ^ 1) * MF_A_PASS_U4, pa);
       stage_e(ebuf + (buf ^ 1) * MF_ECOPIES_U32, pd0, pd1);
     }
     __syncthreads();
@@ -532,9 +554,9 @@ __global__ __launch_bounds__(MF_THREADS) void k_mf_step(const int8_t* __restrict
   __syncthreads();
   // Digits of step next_step for rows 3o .. 3o + 2: a 64-lane group per input block kb, lane
   // (m, kh) forming the 16-byte operand of gate m (local coefficients j = 32 kb + 16 kh + 15 - q,
-  // q = 0..15, of both halves) for the three levels and segments from the polynomial in LDS;
-  // each group writes nine 1 KiB operand rows. Gates at or above B and gates that do not
-  // bootstrap get zero digits.
+  // q = 0..15, of both halves) for the three levels from the polynomial in LDS, segments 1 and
+  // 2 only (the next step forms segment 0 when it stages them); each group writes six 1 KiB
+  // operand rows. Gates at or above B and gates that do not bootstrap get zero bytes.
   {
     const int m = lane & 31;
     const uint64_t g = mt * MF_TILE + m;
@@ -563,7 +585,6 @@ __global__ __launch_bounds__(MF_THREADS) void k_mf_step(const int8_t* __restrict
             for (int k = 0; k < GADGET_L; k++) {
               const int sh = 32 - BG_BIT * (k + 1);
               const u32 d0 = (x[0] >> sh) & 63u, d1 = (x[1] >> sh) & 63u;  // digits plus MF_OFS
-              w[k][0][wi] |= ((d0 + d1) & 255u) << (8 * s);
               w[k][1][wi] |= (d1 & 255u) << (8 * s);
               w[k][2][wi] |= (d0 & 255u) << (8 * s);
             }
@@ -573,7 +594,7 @@ __global__ __launch_bounds__(MF_THREADS) void k_mf_step(const int8_t* __restrict
 #pragma unroll
       for (int k = 0; k < GADGET_L; k++)
 #pragma unroll
-        for (int sg = 0; sg < MF_SUB; sg++)
+        for (int sg = 1; sg < MF_SUB; sg++)  // segment 0 is formed from these when staged
           dst[((k * MF_SUB + sg) * MF_KB + kb) * 64] = make_uint4(w[k][sg][0], w[k][sg][1], w[k][sg][2], w[k][sg][3]);
     }
   }
