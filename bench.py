@@ -137,9 +137,11 @@ def mf_step_ops(B: int) -> int:
 
 def mf_step_hbm_bytes(B: int) -> int:
     """Compulsory HBM bytes of one step kernel launch: the step's digit operands read once and
-    the next step's written once, the step's key (with its offset correction) read once, the
-    accumulators read and written."""
-    return 2 * ((B + MF_TILE - 1) // MF_TILE * MF_A_TILE_BYTES) + MF_KEY_STEP_BYTES + B * 2 * N_RING * 4 * 2
+    the next step's written once (segments x1 and x0 only: the step forms their sum segment
+    itself), the step's key (with its offset correction) read once, the accumulators read and
+    written."""
+    operands = (B + MF_TILE - 1) // MF_TILE * MF_A_TILE_BYTES * 2 // 3
+    return 2 * operands + MF_KEY_STEP_BYTES + B * 2 * N_RING * 4 * 2
 
 
 def src_fingerprint(files) -> str:
