@@ -603,8 +603,8 @@ __global__ __launch_bounds__(MF_THREADS) void k_mf_step(const int8_t* __restrict
 // Split step for batches too small to fill the chip with (tile, output) workgroups: the work
 // of one step is cut into workgroups of four waves per (tile, output o, sub-product s, group
 // of TRGSW rows), wave q computing outputs [128 q, 128 q + 128) of P_s over the rows of its
-// group and all four byte planes (the same pass loop as k_mf_step with one operand segment
-// and one key sequence per pass). Each workgroup adds its share of y straight into ACC with
+// group and all four byte planes (the pass loop of k_mf_step with one operand segment and one
+// key sequence per pass, its products in a diagonal order without the wrap). Each workgroup adds its share of y straight into ACC with
 // integer atomic adds (exact in any order: addition mod 2^32): P1 into both halves, P2 into
 // y0, P3 into y1. The next step's digits come from a separate launch of k_mf_digits, after
 // every share of the step has landed. Row groups: rows [rg * rows, rg * rows + rows) with
@@ -689,29 +689,28 @@ __global__ __launch_bounds__(MFP_THREADS, 3) void k_mf_part(const int8_t* __rest
       return v4i{(int)Bp[wofs], (int)Bp[wofs + 1], (int)Bp[wofs + 2], (int)Bp[wofs + 3]};
     };
     auto lda = [](const uint4& u) { return v4i{(int)u.x, (int)u.y, (int)u.z, (int)u.w}; };
-    // block order (the diagonal order of the step kernel needs more registers than this
-    // kernel has to spare): the B operands in a ring of eight registers, block nb at input
-    // block kb in slot (nb - kb) mod 8, the reads of block kb + 2 issued before the products
-    // of block kb
-    v4i R[8], Av[4];
-#pragma unroll
-    for (int nb = 0; nb < 4; nb++) R[nb] = ldb(8 * (MF_KB - 1 + nb));
-    R[7] = ldb(8 * (MF_KB - 2));
+    // diagonal order without the step kernel's wrap (which needs more registers than this
+    // kernel has to spare): group t = 0..18 takes kb = t - 3 + nb for the nb with kb in
+    // [0, 16), all with the B operand of diagonal 3 - t, so the key operand stays while the
+    // digits change; A blocks are loaded two groups ahead into a ring of eight registers, B
+    // operands two groups ahead into a ring of four
+    v4i Av[8], Bd[4];
     Av[0] = lda(Ar[0]);
     Av[1] = lda(Ar[64]);
-    for (int k8 = 0; k8 < MF_KB; k8 += 8) {
+    Bd[0] = ldb(8 * (MF_KB + 2));
+    Bd[1] = ldb(8 * (MF_KB + 1));
 #pragma unroll
-      for (int s8 = 0; s8 < 8; s8++) {
-        const int kb = k8 + s8;
-        const int kn = (kb + 2 < MF_KB) ? kb + 2 : MF_KB - 1;
-        Av[(s8 + 2) & 3] = lda(Ar[kn * 64]);
-        R[(6 - s8) & 7] = ldb(8 * (MF_KB - 1 - kn));
-        __builtin_amdgcn_sched_barrier(0);
+    for (int t = 0; t < MF_KB + 3; t++) {
+      if (t + 2 < MF_KB) Av[(t + 2) & 7] = lda(Ar[(t + 2) * 64]);
+      if (t + 2 < MF_KB + 3) Bd[(t + 2) & 3] = ldb(8 * (MF_KB - t));
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int nb = 0; nb < 4; nb++)
-          c[nb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(Av[s8 & 3], R[(nb - s8) & 7], c[nb], 0, 0, 0);
-        __builtin_amdgcn_sched_barrier(0);
+      for (int nb = 0; nb < 4; nb++) {
+        const int kb = t - 3 + nb;
+        if (kb >= 0 && kb < MF_KB)
+          c[nb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(Av[kb & 7], Bd[t & 3], c[nb], 0, 0, 0);
       }
+      __builtin_amdgcn_sched_barrier(0);
     }
   };
   auto horner_shift = [&]() {
